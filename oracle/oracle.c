@@ -1,0 +1,283 @@
+/*
+ * oracle.c -- plain FP64 CPU reference for the additive-kernel fast summation
+ * of "Preconditioned Additive Gaussian Processes with Fourier Acceleration"
+ * (Wagner, Xu, Nestler, Xi, Stoll).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * execute this file: it exists so that tests, the smoke check and the CPU
+ * baseline leg of the benchmark can compare the GPU library against a slow,
+ * obviously correct evaluation.  It shares no code, header, table or helper
+ * with the GPU library.
+ *
+ * Two results are computed here, both straight from their definitions:
+ *
+ *   O1  the exact additive kernel product
+ *         y_i = sigma_f^2 sum_s sum_j kappa_s(x_i^{W_s} - x_j^{W_s}) v_j
+ *               + sigma_eps^2 v_i
+ *       (Sec. 2.1, eq. additive_kernel / def_additive_kernel, regularised
+ *       matrix K + sigma_eps^2 I of Sec. 1) and the length-scale derivative
+ *       blocks sigma_f^2 sum_j kappa_s^der(...) v_j (eq. def_der_additive_kernels).
+ *
+ *   O2  the product with each sub-kernel replaced by its N^d-term
+ *       trigonometric interpolant (Sec. 3.1, eq. nfftkappa, eq. Fourier_sum):
+ *         h_i = Re sum_{k in I_N} b_k ( sum_j v_j e^{-2 pi i k.x~_j} ) e^{2 pi i k.x~_i}
+ *       evaluated either pairwise (tiny n) or through the inner sums
+ *       a_k = sum_j v_j e^{-2 pi i k.x~_j} (direct non-equispaced DFT).
+ *       The coefficients b_k are an input (computed by oracle/coefficients.py
+ *       from eq. discrete_fourier_coefficients1).
+ *
+ * Layouts: X is row-major n x p (leading dimension ldx), V is row-major
+ * n x nrhs, windows are given in CSR form (win_ptr[P+1], win_idx[...],
+ * 0-based feature indices).  Coefficient arrays for window s hold N_s^d_s
+ * real values, index (k_1+N/2, ..., k_d+N/2) row-major (last fastest).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846264338327950288
+
+enum { ORC_GAUSS = 0, ORC_MATERN12 = 1 };
+
+/* Kernel value and its derivative with respect to ell, for distance r >= 0.
+ * Gaussian:   exp(-r^2/(2 ell^2)),   derivative (r^2/ell^3) exp(...)
+ * Matern-1/2: exp(-r/ell),           derivative (r/ell^2)   exp(...)
+ * (eq. kernel_definition with unit variance, eq. def_der_additive_kernels). */
+void orc_kernel(int type, double r, double ell, double *val, double *dval)
+{
+    if (type == ORC_GAUSS) {
+        double e = exp(-(r * r) / (2.0 * ell * ell));
+        *val = e;
+        *dval = (r * r) / (ell * ell * ell) * e;
+    } else {
+        double e = exp(-r / ell);
+        *val = e;
+        *dval = r / (ell * ell) * e;
+    }
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
+/* O1: exact dense product for the target rows rows[0..nrows).
+ *   Y    [nrows x nrhs]          sigma_f^2 sum_s K_s V + sigma_eps^2 V (rows only)
+ *   DL   [P x nrows x nrhs] or 0 sigma_f^2 K_s^der V   (one block per window)
+ *   KS   [P x nrows x nrhs] or 0 K_s V (unscaled, per window)
+ * O(nrows * n * sum_s d_s); OpenMP over target rows. */
+void orc_dense_apply(int64_t n, int32_t p, const double *X, int64_t ldx,
+                     int32_t P, const int32_t *win_ptr, const int32_t *win_idx,
+                     const int32_t *ktype, const double *ell,
+                     double sigma_f, double sigma_eps,
+                     const double *V, int32_t nrhs,
+                     const int64_t *rows, int64_t nrows,
+                     double *Y, double *DL, double *KS)
+{
+    (void)p;
+    const double sf2 = sigma_f * sigma_f, se2 = sigma_eps * sigma_eps;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < nrows; ++t) {
+        const int64_t i = rows[t];
+        double *y = Y + t * nrhs;
+        for (int r = 0; r < nrhs; ++r) y[r] = se2 * V[i * nrhs + r];
+        double acc[64], dacc[64];
+        for (int32_t s = 0; s < P; ++s) {
+            for (int r = 0; r < nrhs; ++r) { acc[r] = 0.0; dacc[r] = 0.0; }
+            for (int64_t j = 0; j < n; ++j) {
+                double r2 = 0.0;
+                for (int32_t q = win_ptr[s]; q < win_ptr[s + 1]; ++q) {
+                    double diff = X[i * ldx + win_idx[q]] - X[j * ldx + win_idx[q]];
+                    r2 += diff * diff;
+                }
+                double kv, dkv;
+                orc_kernel(ktype[s], sqrt(r2), ell[s], &kv, &dkv);
+                for (int r = 0; r < nrhs; ++r) {
+                    acc[r] += kv * V[j * nrhs + r];
+                    dacc[r] += dkv * V[j * nrhs + r];
+                }
+            }
+            for (int r = 0; r < nrhs; ++r) {
+                y[r] += sf2 * acc[r];
+                if (DL) DL[((int64_t)s * nrows + t) * nrhs + r] = sf2 * dacc[r];
+                if (KS) KS[((int64_t)s * nrows + t) * nrhs + r] = acc[r];
+            }
+        }
+    }
+}
+
+/* Dense kernel matrix of one window (or its ell-derivative), n x n row-major:
+ * M_ij = kappa_s(x_i - x_j) (deriv = 0) or kappa_s^der(x_i - x_j) (deriv = 1). */
+void orc_dense_matrix(int64_t n, const double *X, int64_t ldx,
+                      int32_t nfeat, const int32_t *feat, int32_t ktype,
+                      double ell, int deriv, double *M)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+            double r2 = 0.0;
+            for (int32_t q = 0; q < nfeat; ++q) {
+                double diff = X[i * ldx + feat[q]] - X[j * ldx + feat[q]];
+                r2 += diff * diff;
+            }
+            double kv, dkv;
+            orc_kernel(ktype, sqrt(r2), ell, &kv, &dkv);
+            M[i * n + j] = deriv ? dkv : kv;
+        }
+    }
+}
+
+/* O2, pairwise form, one window: for target rows,
+ *   h_i = sum_j v_j sum_{k in I_N} b_k cos(2 pi k.(x~_i - x~_j))
+ * (eq. Fourier_sum, real part).  Xs holds the scaled window coordinates
+ * (n x d row-major).  O(nrows * n * N^d): tiny inputs only. */
+void orc_rf_pairwise(int64_t n, int32_t d, const double *Xs, int32_t N,
+                     const double *b, const double *V, int32_t nrhs,
+                     const int64_t *rows, int64_t nrows, double *H)
+{
+    int64_t K = 1;
+    for (int q = 0; q < d; ++q) K *= N;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nrows; ++t) {
+        const int64_t i = rows[t];
+        for (int r = 0; r < nrhs; ++r) H[t * nrhs + r] = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double kappa_rf = 0.0;
+            for (int64_t kk = 0; kk < K; ++kk) {
+                int64_t rem = kk;
+                double phase = 0.0;
+                for (int q = d - 1; q >= 0; --q) {
+                    int64_t kq = rem % N - N / 2;
+                    rem /= N;
+                    phase += (double)kq * (Xs[i * d + q] - Xs[j * d + q]);
+                }
+                kappa_rf += b[kk] * cos(2.0 * ORC_PI * phase);
+            }
+            for (int r = 0; r < nrhs; ++r) H[t * nrhs + r] += kappa_rf * V[j * nrhs + r];
+        }
+    }
+}
+
+/* Inner sums of eq. Fourier_sum (adjoint non-equispaced DFT), one window:
+ *   A[k][r] = sum_j v_j^r e^{-2 pi i k.x~_j},  k in I_N^d,
+ * stored interleaved (re, im) as A[(kk * nrhs + r) * 2 + {0,1}].
+ * Only points with a non-zero row in V contribute, so a sparse V is cheap.
+ * The exponential of the sum k.x is formed as the product of the d
+ * one-dimensional exponentials e^{-2 pi i k_q x_q}.  Each thread sums a
+ * disjoint range of points into a private array; the partial arrays are then
+ * added in thread order. */
+void orc_ndft_adjoint(int64_t n, int32_t d, const double *Xs, int32_t N,
+                      const double *V, int32_t nrhs, double *A)
+{
+    int64_t K = 1;
+    for (int q = 0; q < d; ++q) K *= N;
+    const int64_t len = K * nrhs * 2;
+    memset(A, 0, sizeof(double) * len);
+    int nt = orc_num_threads();
+    double *part = (double *)calloc((size_t)nt * len, sizeof(double));
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *acc = part + (int64_t)tid * len;
+        double *ec = (double *)malloc(sizeof(double) * 3 * N);
+        double *es = (double *)malloc(sizeof(double) * 3 * N);
+#pragma omp for schedule(static)
+        for (int64_t j = 0; j < n; ++j) {
+            int nz = 0;
+            for (int r = 0; r < nrhs; ++r) nz |= (V[j * nrhs + r] != 0.0);
+            if (!nz) continue;
+            for (int q = 0; q < d; ++q)
+                for (int k = 0; k < N; ++k) {
+                    double ang = -2.0 * ORC_PI * (double)(k - N / 2) * Xs[j * d + q];
+                    ec[q * N + k] = cos(ang);
+                    es[q * N + k] = sin(ang);
+                }
+            for (int64_t kk = 0; kk < K; ++kk) {
+                int64_t rem = kk;
+                double er = 1.0, ei = 0.0;
+                for (int q = d - 1; q >= 0; --q) {
+                    int k = (int)(rem % N);
+                    rem /= N;
+                    double cr = ec[q * N + k], ci = es[q * N + k];
+                    double tr = er * cr - ei * ci;
+                    ei = er * ci + ei * cr;
+                    er = tr;
+                }
+                for (int r = 0; r < nrhs; ++r) {
+                    double v = V[j * nrhs + r];
+                    acc[(kk * nrhs + r) * 2 + 0] += v * er;
+                    acc[(kk * nrhs + r) * 2 + 1] += v * ei;
+                }
+            }
+        }
+        free(ec);
+        free(es);
+    }
+    for (int t = 0; t < nt; ++t)
+        for (int64_t e = 0; e < len; ++e) A[e] += part[(int64_t)t * len + e];
+    free(part);
+}
+
+/* Outer sums of eq. Fourier_sum (real part), one window, target rows:
+ *   H[t][r] = Re sum_k b_k A[k][r] e^{2 pi i k.x~_i},  i = rows[t]. */
+void orc_ndft_forward(int32_t d, const double *Xs, int32_t N, const double *b,
+                      const double *A, int32_t nrhs,
+                      const int64_t *rows, int64_t nrows, double *H)
+{
+    int64_t K = 1;
+    for (int q = 0; q < d; ++q) K *= N;
+#pragma omp parallel
+    {
+        double *ec = (double *)malloc(sizeof(double) * 3 * N);
+        double *es = (double *)malloc(sizeof(double) * 3 * N);
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t t = 0; t < nrows; ++t) {
+            const int64_t i = rows[t];
+            for (int q = 0; q < d; ++q)
+                for (int k = 0; k < N; ++k) {
+                    double ang = 2.0 * ORC_PI * (double)(k - N / 2) * Xs[i * d + q];
+                    ec[q * N + k] = cos(ang);
+                    es[q * N + k] = sin(ang);
+                }
+            for (int r = 0; r < nrhs; ++r) H[t * nrhs + r] = 0.0;
+            for (int64_t kk = 0; kk < K; ++kk) {
+                int64_t rem = kk;
+                double er = 1.0, ei = 0.0;
+                for (int q = d - 1; q >= 0; --q) {
+                    int k = (int)(rem % N);
+                    rem /= N;
+                    double cr = ec[q * N + k], ci = es[q * N + k];
+                    double tr = er * cr - ei * ci;
+                    ei = er * ci + ei * cr;
+                    er = tr;
+                }
+                for (int r = 0; r < nrhs; ++r) {
+                    double ar = A[(kk * nrhs + r) * 2 + 0], ai = A[(kk * nrhs + r) * 2 + 1];
+                    H[t * nrhs + r] += b[kk] * (ar * er - ai * ei);
+                }
+            }
+        }
+        free(ec);
+        free(es);
+    }
+}
