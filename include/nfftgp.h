@@ -1,0 +1,184 @@
+/*
+ * nfftgp.h -- C ABI of the MI355X (gfx950) additive-kernel fast summation.
+ *
+ * The library applies the regularised additive kernel matrix of
+ * "Preconditioned Additive Gaussian Processes with Fourier Acceleration"
+ * (Wagner, Xu, Nestler, Xi, Stoll) and its hyper-parameter derivatives to
+ * blocks of vectors, and runs CG on it:
+ *
+ *   Khat = sigma_f^2 (K_1 + ... + K_P) + sigma_eps^2 I          (Sec. 2.1, Sec. 1)
+ *   (K_s)_ij = kappa_s(x_i^{W_s} - x_j^{W_s})                  (eq. def_additive_kernel)
+ *   kappa_s = exp(-r^2/(2 ell_s^2)) or exp(-r/ell_s)          (Gaussian / Matern-1/2)
+ *
+ * Each K_s is replaced by the matrix of the N_s^d-term trigonometric
+ * interpolant of its periodically continued kernel (Sec. 3.1, eq. nfftkappa,
+ * eq. discrete_fourier_coefficients1) and applied by the NFFT-based fast
+ * summation (eq. Fourier_sum; Appendix A): window spreading onto a (2N)^d
+ * grid, FFT, a diagonal multiply by the kernel's Fourier coefficients divided
+ * by the squared window coefficients, inverse FFT, window interpolation.
+ * Derivative products reuse the same pipeline with the coefficients of the
+ * sampled ell-derivative (Sec. 3.2, eq. exact_derivative).
+ *
+ * Conventions for every call:
+ *  - All matrices are row-major.  Device pointers point to memory allocated
+ *    on the device the plan was created on; host pointers are ordinary host
+ *    memory.  The caller owns every buffer it passes; the plan owns its own
+ *    workspaces and frees them in nfftgp_plan_destroy.
+ *  - Floating point buffers passed to a plan have the plan's precision
+ *    (float for NFFTGP_F32, double for NFFTGP_F64).  CG scalars, dot
+ *    products and the Lanczos history are always double.
+ *  - Work is enqueued on the stream given at plan creation (NULL = the null
+ *    stream).  nfftgp_apply allocates nothing and does not synchronise the
+ *    host, so it can be captured into a HIP graph.
+ *  - Argument errors are detected before any work is enqueued and leave the
+ *    plan unchanged.  Every call returns NFFTGP_OK or a negative status;
+ *    nfftgp_last_error() then gives a message (thread-local, valid until the
+ *    next call on the same thread).
+ *  - One plan must not be used from two threads at once.
+ */
+#ifndef NFFTGP_H
+#define NFFTGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NFFTGP_OK = 0,
+    NFFTGP_E_ARG = -1,    /* invalid argument (null pointer, size, overlap, ...)   */
+    NFFTGP_E_DIM = -2,    /* unsupported window dimension, bandwidth or cutoff     */
+    NFFTGP_E_BOX = -3,    /* SCALE_NONE but a point lies outside [-1/4, 1/4)^d     */
+    NFFTGP_E_HIP = -4,    /* a HIP runtime call failed                             */
+    NFFTGP_E_NOMEM = -5,  /* device allocation failed                              */
+    NFFTGP_E_NOTPD = -6,  /* CG met p^T Khat p <= 0: the operator is not definite  */
+    NFFTGP_E_NOCONV = -7, /* CG stopped at maxit before reaching tol               */
+    NFFTGP_E_STATE = -8   /* call order violated (e.g. apply before set_hyper)     */
+} nfftgp_status;
+
+typedef enum { NFFTGP_GAUSS = 0, NFFTGP_MATERN12 = 1 } nfftgp_kernel;
+typedef enum { NFFTGP_F32 = 0, NFFTGP_F64 = 1 } nfftgp_prec;
+
+/* Scaling of each window into the box [-1/4, 1/4)^d required by Sec. 3.1.
+ * AUTO: centre c0 = per-feature midrange, one isotropic factor
+ *       c = (1/4)(1 - 2^-20) / max_j ||x_j - c0||_inf, so x~ = c (x - c0);
+ *       a window whose coordinates already lie in [-1/4, 1/4) is kept as is
+ *       (c = 1, c0 = 0).
+ * NONE: c = 1, c0 = 0; every coordinate must lie in [-1/4, 1/4) (else E_BOX).
+ * Length-scales are always given in the caller's units; the box kernel is
+ * kappa(r~ / c; ell). */
+enum { NFFTGP_SCALE_AUTO = 0, NFFTGP_SCALE_NONE = 1 };
+
+/* Limits of this build. */
+#define NFFTGP_MAX_WINDOWS 64
+#define NFFTGP_MAX_WINDOW_DIM 3
+
+typedef struct nfftgp_plan_s *nfftgp_plan;
+
+/* Create a plan for fixed points and windows (Sec. 2.1: the points stay fixed
+ * while the hyper-parameters change).
+ *   X_dev    device, n x p row-major, leading dimension ldx >= p, precision prec.
+ *            Read during this call only (the plan keeps scaled, sorted copies).
+ *   n        number of points, 0 <= n < 2^31.
+ *   P        number of windows, 1..NFFTGP_MAX_WINDOWS.
+ *   win_ptr  host, P+1 offsets into win_idx; window s has d_s = win_ptr[s+1]-win_ptr[s]
+ *            features, 1 <= d_s <= 3.
+ *   win_idx  host, 0-based feature indices; windows must be disjoint (eq. additive_kernel).
+ *   kernel   host, P entries of nfftgp_kernel.
+ *   N        host, P bandwidths: powers of two, 8..64 for d_s = 3, 8..128 otherwise.
+ *            The index set is I_N = {-N/2, ..., N/2-1}^d (eq. nfftkappa) and the
+ *            oversampled FFT grid has (2N)^d points.
+ *   m        window cutoff (Kaiser-Bessel support m/(2N) per dimension, Appendix A),
+ *            2 <= m <= 8 and m < N/2.
+ *   max_nrhs largest nrhs that nfftgp_apply / nfftgp_cg will be given (1..64);
+ *            workspaces are sized for it here.
+ *   stream   hipStream_t to enqueue on (NULL = null stream).
+ * On success *out receives the plan.  Synchronises the stream once. */
+nfftgp_status nfftgp_plan_create(nfftgp_plan *out,
+                                 const void *X_dev, int64_t n, int32_t p, int64_t ldx,
+                                 int32_t P, const int32_t *win_ptr, const int32_t *win_idx,
+                                 const int32_t *kernel, const int32_t *N, int32_t m,
+                                 nfftgp_prec prec, int32_t scale_mode, int32_t max_nrhs,
+                                 void *stream);
+
+/* Set the hyper-parameters theta = (sigma_f, ell, sigma_eps) (Sec. 1).
+ *   ell   host, P length-scales in caller units (one per window; the paper's
+ *         shared ell is the case of P equal values), each > 0.
+ *   sigma_f, sigma_eps >= 0.
+ * Computes, on the device in FP64, the coefficients b_k and b^der_k of every
+ * window (eq. discrete_fourier_coefficients1, eq. exact_derivative) and the
+ * diagonal applied between the two FFTs.  Synchronises the stream once (to
+ * read back min_k b_k per window, see nfftgp_get_window_info). */
+nfftgp_status nfftgp_set_hyper(nfftgp_plan plan, double sigma_f, const double *ell,
+                               double sigma_eps);
+
+/* Apply the operator to nrhs vectors (eq. Fourier_sum, summed over windows as
+ * in Sec. 3.1, last paragraph).
+ *   V_dev        device, n x nrhs, leading dimension ldv >= nrhs.
+ *   KV_dev       device, n x nrhs (leading dimension nrhs), required:
+ *                sigma_f^2 sum_s K_s V + sigma_eps^2 V.
+ *   dKV_dell_dev device or NULL: P blocks of n x nrhs, block s =
+ *                dKhat/d ell_s V = sigma_f^2 K_s^der V (eq. def_der_additive_kernels).
+ *   dKV_dsf_dev  device or NULL: dKhat/d sigma_f V = 2 sigma_f sum_s K_s V.
+ *   dKV_dse_dev  device or NULL: dKhat/d sigma_eps V = 2 sigma_eps V.
+ * Output buffers must not overlap V.  1 <= nrhs <= max_nrhs.  Asynchronous. */
+nfftgp_status nfftgp_apply(nfftgp_plan plan, const void *V_dev, int64_t ldv, int32_t nrhs,
+                           void *KV_dev, void *dKV_dell_dev, void *dKV_dsf_dev,
+                           void *dKV_dse_dev);
+
+/* Solve Khat X = B column by column with CG (Sec. 1; Sec. 2.3) from a zero
+ * start; column c stops when ||r_c||_2 <= tol ||b_c||_2 or after maxit steps.
+ * Dot products, step lengths and residual norms are FP64 on the device.
+ *   B_dev, X_dev   device, n x nrhs (leading dimension nrhs), prec of the plan.
+ *   iters_host     host or NULL: nrhs iteration counts.
+ *   alpha_beta_host host or NULL: maxit x nrhs x 2 doubles; entry [j][c] holds
+ *                  (alpha_j, beta_j) of column c for j < iters[c] -- the Lanczos
+ *                  coefficients used by stochastic Lanczos quadrature.
+ *   resid_host     host or NULL: nrhs final relative residuals ||r||/||b||.
+ * Returns NFFTGP_E_NOTPD if some column met p^T Khat p <= 0 (that column is
+ * frozen at its last iterate), NFFTGP_E_NOCONV if a column did not reach tol,
+ * NFFTGP_OK otherwise.  Synchronises the stream every check_every iterations
+ * (check_every <= 0 means 8). */
+nfftgp_status nfftgp_cg(nfftgp_plan plan, const void *B_dev, int32_t nrhs, void *X_dev,
+                        double tol, int32_t maxit, int32_t check_every,
+                        int32_t *iters_host, double *alpha_beta_host, double *resid_host);
+
+/* Column dot products out[c] = sum_i A[i][c] * B[i][c] accumulated in FP64
+ * (Sec. 1 eq. div needs alpha^T dKhat alpha and z_i^T (...) terms).
+ *   A_dev, B_dev device, n x ncol with leading dimensions lda, ldb, precision prec.
+ *   out_host     host, ncol doubles.  Synchronises the stream. */
+nfftgp_status nfftgp_col_dots(nfftgp_plan plan, const void *A_dev, int64_t lda,
+                              const void *B_dev, int64_t ldb, int64_t n, int32_t ncol,
+                              double *out_host);
+
+/* Stochastic Lanczos quadrature (Sec. 1): for each column c,
+ *   out[c] = znorm2[c] * e_1^T log(T_c) e_1,
+ * where T_c is the Lanczos tridiagonal matrix built from the CG coefficients
+ * (alpha_j, beta_j), j < iters[c], in the layout nfftgp_cg writes.  Host-only
+ * FP64 computation (symmetric tridiagonal QL eigen-solver).  Returns
+ * NFFTGP_E_NOTPD if some T_c has a non-positive eigenvalue. */
+nfftgp_status nfftgp_slq_logquad(const double *alpha_beta_host, const int32_t *iters,
+                                 int32_t ncol, int32_t maxit, const double *znorm2,
+                                 double *out_host);
+
+/* Per-window information: centre c0 (d_s doubles), factor c, dimension, bandwidth,
+ * and the smallest coefficients min_k b_k and min_k b^der_k from the last
+ * set_hyper (min_b < 0 means K_{s,RF} can be indefinite).  Any output may be NULL. */
+nfftgp_status nfftgp_get_window_info(nfftgp_plan plan, int32_t s, double *c0, double *c,
+                                     int32_t *d, int32_t *N, double *min_b, double *min_bder);
+
+/* Device bytes the plan holds. */
+nfftgp_status nfftgp_get_workspace_bytes(nfftgp_plan plan, size_t *bytes);
+
+/* Free the plan and everything it owns (NULL is allowed).  Synchronises. */
+void nfftgp_plan_destroy(nfftgp_plan plan);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *nfftgp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NFFTGP_H */

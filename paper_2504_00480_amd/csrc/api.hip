@@ -1,0 +1,579 @@
+// C ABI of libnfftgp: plan creation (window scaling and sorting), per-theta
+// coefficients, the additive apply, CG, dot products and the Lanczos
+// quadrature.  See include/nfftgp.h for the contract of every entry point.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "nfftgp_impl.h"
+
+namespace nfftgp {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+}  // namespace nfftgp
+
+using namespace nfftgp;
+
+namespace {
+
+nfftgp_status fail(nfftgp_status st, const std::string &m)
+{
+    set_error(m);
+    return st;
+}
+
+size_t prec_bytes(int prec) { return prec == NFFTGP_F32 ? sizeof(float) : sizeof(double); }
+
+nfftgp_status dalloc(nfftgp_plan p, void **ptr, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(NFFTGP_E_NOMEM, "hipMalloc(" + std::to_string(bytes) + " bytes) failed: " +
+                                        hipGetErrorString(e));
+    }
+    p->allocs.push_back(*ptr);
+    p->bytes += bytes;
+    return NFFTGP_OK;
+}
+
+void free_plan(nfftgp_plan p)
+{
+    if (!p) return;
+    if (p->stream || true) (void)hipStreamSynchronize(p->stream);
+    for (void *a : p->allocs) (void)hipFree(a);
+    delete p;
+}
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+WindowGeom make_geom(int d, int N, int m)
+{
+    WindowGeom g;
+    g.d = d;
+    g.N = N;
+    g.ng = 2 * N;
+    int tb = d == 3 ? 8 : (d == 2 ? 16 : 64);
+    g.tb = std::min(tb, g.ng);
+    g.nb = g.ng / g.tb;
+    g.nbins = 1;
+    g.pd = g.tb + 2 * m;
+    g.pc = 1;
+    g.cells = 1;
+    g.dcells = 1;
+    for (int q = 0; q < d; ++q) {
+        g.nbins *= g.nb;
+        g.pc *= g.pd;
+        g.cells *= g.ng;
+        g.dcells *= (N + 1);
+    }
+    return g;
+}
+
+// Temporary device buffers of plan creation, freed on every exit path.
+struct Scratch {
+    std::vector<void *> p;
+    ~Scratch()
+    {
+        for (void *x : p) (void)hipFree(x);
+    }
+    hipError_t get(void **ptr, size_t bytes)
+    {
+        if (bytes == 0) bytes = 256;
+        hipError_t e = hipMalloc(ptr, bytes);
+        if (e == hipSuccess) p.push_back(*ptr);
+        return e;
+    }
+};
+
+#define TRYS(expr)                                                 \
+    do {                                                           \
+        nfftgp_status st_ = (expr);                                \
+        if (st_ != NFFTGP_OK) {                                    \
+            free_plan(plan);                                       \
+            return st_;                                            \
+        }                                                          \
+    } while (0)
+
+#define TRYH(expr)                                                                  \
+    do {                                                                            \
+        hipError_t e_ = (expr);                                                     \
+        if (e_ != hipSuccess) {                                                     \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));           \
+            free_plan(plan);                                                        \
+            return NFFTGP_E_HIP;                                                    \
+        }                                                                           \
+    } while (0)
+
+// Enqueue one additive apply; no validation, no allocation, no host sync.
+nfftgp_status apply_impl(nfftgp_plan p, const void *V, int64_t ldv, int nrhs, void *KV,
+                         void *dell, void *dsf, void *dse)
+{
+    const hipStream_t s = p->stream;
+    const bool with_der = dell != nullptr;
+    const int64_t tot = p->n * nrhs;
+    if (p->n == 0) return NFFTGP_OK;
+    NFFTGP_HIP_TRY(launch_fill(p->prec, p->acc, tot, s));
+    NFFTGP_HIP_TRY(launch_fill(p->prec, p->comp, tot, s));
+    const size_t eb = prec_bytes(p->prec);
+    for (int w = 0; w < p->P; ++w) {
+        const Window &win = p->win[w];
+        NFFTGP_HIP_TRY(launch_spread(p->prec, win, p->m, p->n, V, ldv, nrhs, p->tilebuf, s));
+        NFFTGP_HIP_TRY(launch_fold(p->prec, win, p->m, nrhs, p->tilebuf, p->grid, s));
+        NFFTGP_HIP_TRY(launch_fft(p->prec, win.g, p->grid, nrhs, false, s));
+        NFFTGP_HIP_TRY(launch_diag(p->prec, win, nrhs, p->grid, with_der, s));
+        NFFTGP_HIP_TRY(launch_fft(p->prec, win.g, p->grid, nrhs * (with_der ? 2 : 1), true, s));
+        void *dout = with_der ? (void *)((char *)dell + (size_t)w * tot * eb) : nullptr;
+        NFFTGP_HIP_TRY(launch_interp(p->prec, win, p->m, p->n, nrhs, p->grid, with_der, p->acc,
+                                     p->comp, dout, p->sigma_f * p->sigma_f, s));
+    }
+    NFFTGP_HIP_TRY(launch_assemble(p->prec, p->n, nrhs, V, ldv, p->acc, p->comp, p->sigma_f,
+                                   p->sigma_eps, KV, dsf, dse, s));
+    return NFFTGP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nfftgp_last_error(void) { return g_err.c_str(); }
+
+nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n, int32_t p,
+                                 int64_t ldx, int32_t P, const int32_t *win_ptr,
+                                 const int32_t *win_idx, const int32_t *kernel, const int32_t *N,
+                                 int32_t m, nfftgp_prec prec, int32_t scale_mode,
+                                 int32_t max_nrhs, void *stream)
+{
+    set_error("");
+    if (!out) return fail(NFFTGP_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(NFFTGP_E_ARG, "n out of range");
+    if (n > 0 && !X_dev) return fail(NFFTGP_E_ARG, "X_dev is NULL");
+    if (p < 1 || ldx < p) return fail(NFFTGP_E_ARG, "need p >= 1 and ldx >= p");
+    if (P < 1 || P > NFFTGP_MAX_WINDOWS) return fail(NFFTGP_E_ARG, "P out of range");
+    if (!win_ptr || !win_idx || !kernel || !N) return fail(NFFTGP_E_ARG, "window arrays are NULL");
+    if (prec != NFFTGP_F32 && prec != NFFTGP_F64) return fail(NFFTGP_E_ARG, "bad precision");
+    if (scale_mode != NFFTGP_SCALE_AUTO && scale_mode != NFFTGP_SCALE_NONE)
+        return fail(NFFTGP_E_ARG, "bad scale_mode");
+    if (max_nrhs < 1 || max_nrhs > 64) return fail(NFFTGP_E_ARG, "max_nrhs must be in 1..64");
+    if (!(m == 2 || m == 4 || m == 6 || m == 8))
+        return fail(NFFTGP_E_DIM, "cutoff m must be 2, 4, 6 or 8");
+    if (win_ptr[0] != 0) return fail(NFFTGP_E_ARG, "win_ptr[0] must be 0");
+    std::vector<char> seen(p, 0);
+    for (int s = 0; s < P; ++s) {
+        int d = win_ptr[s + 1] - win_ptr[s];
+        if (d < 1 || d > 3) return fail(NFFTGP_E_DIM, "window dimension must be 1..3");
+        for (int q = win_ptr[s]; q < win_ptr[s + 1]; ++q) {
+            int f = win_idx[q];
+            if (f < 0 || f >= p) return fail(NFFTGP_E_ARG, "feature index out of range");
+            if (seen[f]) return fail(NFFTGP_E_ARG, "windows overlap");
+            seen[f] = 1;
+        }
+        if (kernel[s] != NFFTGP_GAUSS && kernel[s] != NFFTGP_MATERN12)
+            return fail(NFFTGP_E_ARG, "unknown kernel type");
+        int Nmax = d == 3 ? 64 : 128;
+        if (!is_pow2(N[s]) || N[s] < 8 || N[s] > Nmax)
+            return fail(NFFTGP_E_DIM, "bandwidth must be a power of two in 8..64 (d=3) or 8..128");
+        if (2 * m >= N[s]) return fail(NFFTGP_E_DIM, "cutoff must satisfy m < N/2");
+    }
+
+    nfftgp_plan plan = new nfftgp_plan_s();
+    plan->n = n;
+    plan->p = p;
+    plan->P = P;
+    plan->m = m;
+    plan->prec = prec;
+    plan->max_nrhs = max_nrhs;
+    plan->scale_mode = scale_mode;
+    plan->stream = (hipStream_t)stream;
+    TRYH(hipGetDevice(&plan->device));
+    const hipStream_t st = plan->stream;
+    const size_t eb = prec_bytes(prec);
+    int max_lds = 0;
+    TRYH(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, plan->device));
+    for (int s = 0; s < P; ++s) {
+        WindowGeom g = make_geom(win_ptr[s + 1] - win_ptr[s], N[s], m);
+        if ((size_t)2 * g.pc * eb > (size_t)max_lds) {
+            free_plan(plan);
+            return fail(NFFTGP_E_DIM, "window tile needs " + std::to_string(2 * g.pc * eb) +
+                                          " bytes of LDS, device allows " + std::to_string(max_lds));
+        }
+    }
+
+    Scratch tmp;
+    double *part = nullptr, *mm = nullptr;
+    int *flags = nullptr, *keys = nullptr, *hist = nullptr, *scan_tmp = nullptr, *bin_start = nullptr;
+    void *t_uns = nullptr;
+    int nblk = (int)std::max<int64_t>(1, (n + kSortBlock - 1) / kSortBlock);
+    int max_bins = 1;
+    for (int s = 0; s < P; ++s) max_bins = std::max(max_bins, make_geom(win_ptr[s + 1] - win_ptr[s], N[s], m).nbins);
+    int64_t hist_len = (int64_t)max_bins * nblk;
+    TRYH(tmp.get((void **)&part, kPartBlocks * 6 * sizeof(double)));
+    TRYH(tmp.get((void **)&mm, 8 * sizeof(double)));
+    TRYH(tmp.get((void **)&flags, 4 * sizeof(int)));
+    TRYH(tmp.get((void **)&keys, std::max<int64_t>(n, 1) * sizeof(int)));
+    TRYH(tmp.get((void **)&hist, (hist_len + 1) * sizeof(int)));
+    TRYH(tmp.get((void **)&scan_tmp, scan_scratch_ints(hist_len) * sizeof(int)));
+    TRYH(tmp.get((void **)&bin_start, (max_bins + 1) * sizeof(int)));
+    TRYH(tmp.get(&t_uns, std::max<int64_t>(n, 1) * 3 * eb));
+
+    size_t tile_need = 0;
+    int64_t max_cells = 1, maxK = 1;
+    plan->win.resize(P);
+    for (int s = 0; s < P; ++s) {
+        Window &w = plan->win[s];
+        const int d = win_ptr[s + 1] - win_ptr[s];
+        w.g = make_geom(d, N[s], m);
+        w.kernel = kernel[s];
+        for (int q = 0; q < d; ++q) w.feat[q] = win_idx[win_ptr[s] + q];
+        // --- scaling into [-1/4, 1/4)^d
+        double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        int hflags[2] = {0, 0};
+        TRYH(hipMemsetAsync(flags, 0, 4 * sizeof(int), st));
+        if (n > 0) {
+            TRYH(launch_minmax(prec, X_dev, n, ldx, d, w.feat, part, mm, flags, st));
+            double hm[6];
+            TRYH(hipMemcpyAsync(hm, mm, 2 * d * sizeof(double), hipMemcpyDeviceToHost, st));
+            TRYH(hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+            TRYH(hipStreamSynchronize(st));
+            if (hflags[0]) {
+                free_plan(plan);
+                return fail(NFFTGP_E_ARG, "X holds NaN or Inf in window " + std::to_string(s));
+            }
+            for (int q = 0; q < d; ++q) {
+                lo[q] = hm[q];
+                hi[q] = hm[d + q];
+            }
+        }
+        w.c = 1.0;
+        if (scale_mode == NFFTGP_SCALE_AUTO && n > 0) {
+            bool inside = true;
+            for (int q = 0; q < d; ++q) inside = inside && lo[q] >= -0.25 && hi[q] < 0.25;
+            if (!inside) {
+                double h = 0.0;
+                for (int q = 0; q < d; ++q) {
+                    w.c0[q] = (lo[q] + hi[q]) * 0.5;
+                    h = std::max(h, std::max(hi[q] - w.c0[q], w.c0[q] - lo[q]));
+                }
+                if (h > 0.0) w.c = 0.25 * (1.0 - std::ldexp(1.0, -20)) / h;
+            }
+        }
+        // --- grid coordinates, keys, sort
+        TRYS(dalloc(plan, &w.t_sorted, std::max<int64_t>(n, 1) * d * eb));
+        TRYS(dalloc(plan, (void **)&w.perm, std::max<int64_t>(n, 1) * sizeof(int)));
+        TRYH(launch_coords(prec, X_dev, n, ldx, d, w.feat, w.c0, w.c, w.g, t_uns, keys, flags + 1, st));
+        TRYH(launch_sort(prec, n, d, w.g.nbins, keys, t_uns, hist, scan_tmp, w.perm, w.t_sorted,
+                         bin_start, st));
+        std::vector<int> bs(w.g.nbins + 1);
+        TRYH(hipMemcpyAsync(bs.data(), bin_start, (w.g.nbins + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+        TRYH(hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        TRYH(hipStreamSynchronize(st));
+        if (hflags[1]) {
+            free_plan(plan);
+            return fail(NFFTGP_E_BOX, "window " + std::to_string(s) +
+                                          ": a scaled point lies outside [-1/4, 1/4)^d");
+        }
+        // --- subproblems: runs of at most kMaxSubPoints points of one bin
+        std::vector<int> sb, ss, sc, bsp(w.g.nbins + 1, 0);
+        for (int b = 0; b < w.g.nbins; ++b) {
+            int cnt = bs[b + 1] - bs[b];
+            for (int off = 0; off < cnt; off += kMaxSubPoints) {
+                sb.push_back(b);
+                ss.push_back(bs[b] + off);
+                sc.push_back(std::min(kMaxSubPoints, cnt - off));
+            }
+            bsp[b + 1] = (int)sb.size();
+        }
+        w.nsub = (int)sb.size();
+        TRYS(dalloc(plan, (void **)&w.sub_bin, std::max(1, w.nsub) * sizeof(int)));
+        TRYS(dalloc(plan, (void **)&w.sub_start, std::max(1, w.nsub) * sizeof(int)));
+        TRYS(dalloc(plan, (void **)&w.sub_count, std::max(1, w.nsub) * sizeof(int)));
+        TRYS(dalloc(plan, (void **)&w.bin_sub_ptr, (w.g.nbins + 1) * sizeof(int)));
+        if (w.nsub > 0) {
+            TRYH(hipMemcpy(w.sub_bin, sb.data(), w.nsub * sizeof(int), hipMemcpyHostToDevice));
+            TRYH(hipMemcpy(w.sub_start, ss.data(), w.nsub * sizeof(int), hipMemcpyHostToDevice));
+            TRYH(hipMemcpy(w.sub_count, sc.data(), w.nsub * sizeof(int), hipMemcpyHostToDevice));
+        }
+        TRYH(hipMemcpy(w.bin_sub_ptr, bsp.data(), (w.g.nbins + 1) * sizeof(int), hipMemcpyHostToDevice));
+        TRYS(dalloc(plan, &w.Dk, w.g.dcells * eb));
+        TRYS(dalloc(plan, &w.Dder, w.g.dcells * eb));
+        tile_need = std::max(tile_need, (size_t)w.nsub * w.g.pc);
+        max_cells = std::max(max_cells, w.g.cells);
+        int64_t K = 1;
+        for (int q = 0; q < d; ++q) K *= N[s];
+        maxK = std::max(maxK, K);
+    }
+    TRYS(dalloc(plan, &plan->tilebuf, std::max<size_t>(tile_need, 1) * max_nrhs * eb));
+    TRYS(dalloc(plan, &plan->grid, (size_t)max_cells * 2 * max_nrhs * 2 * eb));
+    const size_t vec_bytes = std::max<int64_t>(n, 1) * max_nrhs * eb;
+    TRYS(dalloc(plan, &plan->acc, vec_bytes));
+    TRYS(dalloc(plan, &plan->comp, vec_bytes));
+    TRYS(dalloc(plan, (void **)&plan->coef, (size_t)8 * maxK * sizeof(double)));
+    TRYS(dalloc(plan, (void **)&plan->bbar, (size_t)2 * maxK * sizeof(double)));
+    TRYS(dalloc(plan, (void **)&plan->minb, (size_t)2 * P * sizeof(double)));
+    TRYS(dalloc(plan, (void **)&plan->dot_part, (size_t)kDotBlocks * 64 * sizeof(double) + 64 * sizeof(double)));
+    TRYS(dalloc(plan, (void **)&plan->cg_scal, (size_t)kCgSlots * 64 * sizeof(double)));
+    TRYS(dalloc(plan, &plan->cg_r, vec_bytes));
+    TRYS(dalloc(plan, &plan->cg_p, vec_bytes));
+    TRYS(dalloc(plan, &plan->cg_ap, vec_bytes));
+    TRYH(hipStreamSynchronize(st));
+    *out = plan;
+    return NFFTGP_OK;
+}
+
+nfftgp_status nfftgp_set_hyper(nfftgp_plan plan, double sigma_f, const double *ell,
+                               double sigma_eps)
+{
+    set_error("");
+    if (!plan) return fail(NFFTGP_E_ARG, "plan is NULL");
+    if (!ell) return fail(NFFTGP_E_ARG, "ell is NULL");
+    if (!(sigma_f >= 0.0) || !std::isfinite(sigma_f) || !(sigma_eps >= 0.0) || !std::isfinite(sigma_eps))
+        return fail(NFFTGP_E_ARG, "sigma_f and sigma_eps must be finite and >= 0");
+    for (int s = 0; s < plan->P; ++s)
+        if (!(ell[s] > 0.0) || !std::isfinite(ell[s])) return fail(NFFTGP_E_ARG, "ell must be finite and > 0");
+    const hipStream_t st = plan->stream;
+    for (int s = 0; s < plan->P; ++s) {
+        Window &w = plan->win[s];
+        NFFTGP_HIP_TRY(launch_coefficients(plan->prec, w.g, plan->m, w.kernel, ell[s], w.c, plan->coef,
+                                           plan->bbar, w.Dk, w.Dder, plan->minb + 2 * s, st));
+    }
+    std::vector<double> mb(2 * plan->P);
+    NFFTGP_HIP_TRY(hipMemcpyAsync(mb.data(), plan->minb, 2 * plan->P * sizeof(double),
+                                  hipMemcpyDeviceToHost, st));
+    NFFTGP_HIP_TRY(hipStreamSynchronize(st));
+    for (int s = 0; s < plan->P; ++s) {
+        plan->win[s].ell = ell[s];
+        plan->win[s].min_b = mb[2 * s];
+        plan->win[s].min_bder = mb[2 * s + 1];
+    }
+    plan->sigma_f = sigma_f;
+    plan->sigma_eps = sigma_eps;
+    plan->have_hyper = true;
+    return NFFTGP_OK;
+}
+
+nfftgp_status nfftgp_apply(nfftgp_plan plan, const void *V_dev, int64_t ldv, int32_t nrhs,
+                           void *KV_dev, void *dKV_dell_dev, void *dKV_dsf_dev, void *dKV_dse_dev)
+{
+    set_error("");
+    if (!plan) return fail(NFFTGP_E_ARG, "plan is NULL");
+    if (!plan->have_hyper) return fail(NFFTGP_E_STATE, "nfftgp_set_hyper has not been called");
+    if (nrhs < 1 || nrhs > plan->max_nrhs) return fail(NFFTGP_E_ARG, "nrhs out of range 1..max_nrhs");
+    if (ldv < nrhs) return fail(NFFTGP_E_ARG, "ldv < nrhs");
+    if (plan->n > 0 && (!V_dev || !KV_dev)) return fail(NFFTGP_E_ARG, "V or KV is NULL");
+    return apply_impl(plan, V_dev, ldv, nrhs, KV_dev, dKV_dell_dev, dKV_dsf_dev, dKV_dse_dev);
+}
+
+nfftgp_status nfftgp_col_dots(nfftgp_plan plan, const void *A_dev, int64_t lda, const void *B_dev,
+                              int64_t ldb, int64_t n, int32_t ncol, double *out_host)
+{
+    set_error("");
+    if (!plan) return fail(NFFTGP_E_ARG, "plan is NULL");
+    if (ncol < 1 || ncol > 64 || n < 0 || lda < ncol || ldb < ncol || !out_host)
+        return fail(NFFTGP_E_ARG, "bad col_dots arguments");
+    if (n > 0 && (!A_dev || !B_dev)) return fail(NFFTGP_E_ARG, "A or B is NULL");
+    double *outd = plan->dot_part + kDotBlocks * 64;
+    NFFTGP_HIP_TRY(launch_coldots(plan->prec, A_dev, lda, B_dev, ldb, n, ncol, plan->dot_part, outd,
+                                  plan->stream));
+    NFFTGP_HIP_TRY(hipMemcpyAsync(out_host, outd, ncol * sizeof(double), hipMemcpyDeviceToHost,
+                                  plan->stream));
+    NFFTGP_HIP_TRY(hipStreamSynchronize(plan->stream));
+    return NFFTGP_OK;
+}
+
+nfftgp_status nfftgp_cg(nfftgp_plan plan, const void *B_dev, int32_t nrhs, void *X_dev, double tol,
+                        int32_t maxit, int32_t check_every, int32_t *iters_host,
+                        double *alpha_beta_host, double *resid_host)
+{
+    set_error("");
+    if (!plan) return fail(NFFTGP_E_ARG, "plan is NULL");
+    if (!plan->have_hyper) return fail(NFFTGP_E_STATE, "nfftgp_set_hyper has not been called");
+    if (nrhs < 1 || nrhs > plan->max_nrhs) return fail(NFFTGP_E_ARG, "nrhs out of range 1..max_nrhs");
+    if (maxit < 0 || !(tol >= 0.0)) return fail(NFFTGP_E_ARG, "bad tol or maxit");
+    if (plan->n > 0 && (!B_dev || !X_dev)) return fail(NFFTGP_E_ARG, "B or X is NULL");
+    if (check_every <= 0) check_every = 8;
+    const hipStream_t st = plan->stream;
+    const int64_t n = plan->n;
+    double *sc = plan->cg_scal;
+    if (alpha_beta_host && maxit > 0 && (int64_t)maxit * nrhs > plan->cg_hist_cap) {
+        void *h = nullptr;
+        nfftgp_status e = dalloc(plan, &h, (size_t)maxit * nrhs * 2 * sizeof(double));
+        if (e != NFFTGP_OK) return e;
+        plan->cg_hist = (double *)h;
+        plan->cg_hist_cap = maxit * nrhs;
+    }
+    double *hist = alpha_beta_host ? plan->cg_hist : nullptr;
+    NFFTGP_HIP_TRY(launch_cg_init(plan->prec, n, nrhs, B_dev, X_dev, plan->cg_r, plan->cg_p, st));
+    NFFTGP_HIP_TRY(launch_coldots(plan->prec, plan->cg_r, nrhs, plan->cg_r, nrhs, n, nrhs,
+                                  plan->dot_part, sc + kRR * nrhs, st));
+    NFFTGP_HIP_TRY(launch_cg_start(nrhs, sc, st));
+    std::vector<double> act(nrhs);
+    int it = 0;
+    for (; it < maxit; ++it) {
+        nfftgp_status e = apply_impl(plan, plan->cg_p, nrhs, nrhs, plan->cg_ap, nullptr, nullptr, nullptr);
+        if (e != NFFTGP_OK) return e;
+        NFFTGP_HIP_TRY(launch_coldots(plan->prec, plan->cg_p, nrhs, plan->cg_ap, nrhs, n, nrhs,
+                                      plan->dot_part, sc + kPAP * nrhs, st));
+        NFFTGP_HIP_TRY(launch_cg_alpha(nrhs, sc, st));
+        NFFTGP_HIP_TRY(launch_cg_xr(plan->prec, n, nrhs, sc, X_dev, plan->cg_r, plan->cg_p, plan->cg_ap, st));
+        NFFTGP_HIP_TRY(launch_coldots(plan->prec, plan->cg_r, nrhs, plan->cg_r, nrhs, n, nrhs,
+                                      plan->dot_part, sc + kRRNew * nrhs, st));
+        NFFTGP_HIP_TRY(launch_cg_beta(nrhs, sc, tol, it, hist, st));
+        NFFTGP_HIP_TRY(launch_cg_p(plan->prec, n, nrhs, sc, plan->cg_r, plan->cg_p, st));
+        if ((it + 1) % check_every == 0 || it + 1 == maxit) {
+            NFFTGP_HIP_TRY(hipMemcpyAsync(act.data(), sc + kActive * nrhs, nrhs * sizeof(double),
+                                          hipMemcpyDeviceToHost, st));
+            NFFTGP_HIP_TRY(hipStreamSynchronize(st));
+            bool any = false;
+            for (int c = 0; c < nrhs; ++c) any = any || act[c] != 0.0;
+            if (!any) {
+                ++it;
+                break;
+            }
+        }
+    }
+    std::vector<double> all((size_t)kCgSlots * nrhs);
+    NFFTGP_HIP_TRY(hipMemcpyAsync(all.data(), sc, all.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (alpha_beta_host && maxit > 0) {
+        std::memset(alpha_beta_host, 0, (size_t)maxit * nrhs * 2 * sizeof(double));
+        if (it > 0)
+            NFFTGP_HIP_TRY(hipMemcpyAsync(alpha_beta_host, hist, (size_t)it * nrhs * 2 * sizeof(double),
+                                          hipMemcpyDeviceToHost, st));
+    }
+    NFFTGP_HIP_TRY(hipStreamSynchronize(st));
+    bool notpd = false, noconv = false;
+    for (int c = 0; c < nrhs; ++c) {
+        double rr = all[kRR * nrhs + c], rr0 = all[kRR0 * nrhs + c];
+        double rel = rr0 > 0.0 ? std::sqrt(rr / rr0) : 0.0;
+        if (iters_host) iters_host[c] = (int32_t)all[kIters * nrhs + c];
+        if (resid_host) resid_host[c] = rel;
+        if (all[kNotPD * nrhs + c] != 0.0) notpd = true;
+        else if (rel > tol) noconv = true;
+    }
+    if (notpd) return fail(NFFTGP_E_NOTPD, "CG met p^T Khat p <= 0 (operator not positive definite)");
+    if (noconv) return fail(NFFTGP_E_NOCONV, "CG did not reach tol within maxit");
+    return NFFTGP_OK;
+}
+
+nfftgp_status nfftgp_slq_logquad(const double *ab, const int32_t *iters, int32_t ncol, int32_t maxit,
+                                 const double *znorm2, double *out)
+{
+    set_error("");
+    if (!ab || !iters || !znorm2 || !out || ncol < 1 || maxit < 0)
+        return fail(NFFTGP_E_ARG, "bad slq arguments");
+    nfftgp_status status = NFFTGP_OK;
+    for (int c = 0; c < ncol; ++c) {
+        const int k = iters[c];
+        if (k < 0 || k > maxit) return fail(NFFTGP_E_ARG, "iters out of range");
+        if (k == 0) {
+            out[c] = 0.0;
+            continue;
+        }
+        // Lanczos tridiagonal from CG: T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+        // T_{j,j+1} = sqrt(beta_j)/alpha_j.
+        std::vector<double> dg(k), e(k, 0.0), z(k, 0.0);
+        for (int j = 0; j < k; ++j) {
+            const double a = ab[((size_t)j * ncol + c) * 2];
+            dg[j] = 1.0 / a;
+            if (j > 0) {
+                const double ap = ab[((size_t)(j - 1) * ncol + c) * 2];
+                const double bp = ab[((size_t)(j - 1) * ncol + c) * 2 + 1];
+                dg[j] += bp / ap;
+                e[j - 1] = std::sqrt(bp) / ap;
+            }
+        }
+        z[0] = 1.0;   // first row of the eigenvector matrix
+        // implicit QL iteration with Wilkinson-type shifts on the symmetric
+        // tridiagonal matrix (dg, e); rotations are applied to z.
+        for (int l = 0; l < k; ++l) {
+            int iter = 0, mm;
+            do {
+                for (mm = l; mm < k - 1; ++mm) {
+                    double dd = std::fabs(dg[mm]) + std::fabs(dg[mm + 1]);
+                    if (std::fabs(e[mm]) <= 1e-16 * dd) break;
+                }
+                if (mm != l) {
+                    if (++iter > 200) return fail(NFFTGP_E_NOCONV, "tridiagonal eigen-solver did not converge");
+                    double g = (dg[l + 1] - dg[l]) / (2.0 * e[l]);
+                    double r = std::hypot(g, 1.0);
+                    g = dg[mm] - dg[l] + e[l] / (g + (g >= 0 ? r : -r));
+                    double s = 1.0, cc = 1.0, pp = 0.0;
+                    int i;
+                    bool early = false;
+                    for (i = mm - 1; i >= l; --i) {
+                        double f = s * e[i], b = cc * e[i];
+                        r = std::hypot(f, g);
+                        e[i + 1] = r;
+                        if (r == 0.0) {
+                            dg[i + 1] -= pp;
+                            e[mm] = 0.0;
+                            early = true;
+                            break;
+                        }
+                        s = f / r;
+                        cc = g / r;
+                        g = dg[i + 1] - pp;
+                        r = (dg[i] - g) * s + 2.0 * cc * b;
+                        pp = s * r;
+                        dg[i + 1] = g + pp;
+                        g = cc * r - b;
+                        double zf = z[i + 1];
+                        z[i + 1] = s * z[i] + cc * zf;
+                        z[i] = cc * z[i] - s * zf;
+                    }
+                    if (early) continue;
+                    dg[l] -= pp;
+                    e[l] = g;
+                    e[mm] = 0.0;
+                }
+            } while (mm != l);
+        }
+        double acc = 0.0;
+        for (int j = 0; j < k; ++j) {
+            if (!(dg[j] > 0.0)) {
+                status = NFFTGP_E_NOTPD;
+                acc = NAN;
+                break;
+            }
+            acc += z[j] * z[j] * std::log(dg[j]);
+        }
+        out[c] = znorm2[c] * acc;
+    }
+    if (status != NFFTGP_OK) set_error("Lanczos matrix has a non-positive eigenvalue");
+    return status;
+}
+
+nfftgp_status nfftgp_get_window_info(nfftgp_plan plan, int32_t s, double *c0, double *c, int32_t *d,
+                                     int32_t *N, double *min_b, double *min_bder)
+{
+    set_error("");
+    if (!plan) return fail(NFFTGP_E_ARG, "plan is NULL");
+    if (s < 0 || s >= plan->P) return fail(NFFTGP_E_ARG, "window index out of range");
+    const Window &w = plan->win[s];
+    if (c0)
+        for (int q = 0; q < w.g.d; ++q) c0[q] = w.c0[q];
+    if (c) *c = w.c;
+    if (d) *d = w.g.d;
+    if (N) *N = w.g.N;
+    if (min_b) *min_b = w.min_b;
+    if (min_bder) *min_bder = w.min_bder;
+    return NFFTGP_OK;
+}
+
+nfftgp_status nfftgp_get_workspace_bytes(nfftgp_plan plan, size_t *bytes)
+{
+    set_error("");
+    if (!plan || !bytes) return fail(NFFTGP_E_ARG, "NULL argument");
+    *bytes = plan->bytes;
+    return NFFTGP_OK;
+}
+
+void nfftgp_plan_destroy(nfftgp_plan plan) { free_plan(plan); }
+
+}  // extern "C"

@@ -1,0 +1,178 @@
+// Internal declarations shared by the HIP translation units of libnfftgp.
+// Everything here is private to the library; the public surface is
+// include/nfftgp.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "nfftgp.h"
+
+namespace nfftgp {
+
+// Oversampling factor of the Kaiser-Bessel window (Appendix A): the FFT grid
+// has 2N points per dimension, i.e. sigma = 2, and the window shape parameter
+// is b = pi (2 - 1/sigma).
+constexpr double kSigma = 2.0;
+constexpr double kPi = 3.14159265358979323846264338327950288;
+inline double kb_beta() { return kPi * (2.0 - 1.0 / kSigma); }
+
+// Points handled by one spreading / interpolation work-group at most.
+constexpr int kMaxSubPoints = 1024;
+
+// Geometry of one window's oversampled grid and its tiling.
+struct WindowGeom {
+    int d = 0;       // window dimension (1..3)
+    int N = 0;       // bandwidth; index set I_N = [-N/2, N/2)^d
+    int ng = 0;      // FFT grid edge 2N
+    int tb = 0;      // tile (bin) edge in grid cells
+    int nb = 0;      // bins per dimension = ng / tb
+    int nbins = 0;   // nb^d
+    int pd = 0;      // padded tile edge tb + 2m
+    int pc = 0;      // padded tile cells pd^d
+    int64_t cells = 0;  // ng^d
+    int64_t dcells = 0; // (N+1)^d entries of the symmetrised diagonal
+};
+
+struct Window {
+    WindowGeom g;
+    int kernel = 0;
+    int feat[3] = {0, 0, 0};
+    double c0[3] = {0, 0, 0};
+    double c = 1.0;
+    double ell = 1.0;
+    double min_b = 0.0, min_bder = 0.0;
+    // device data (owned)
+    void *t_sorted = nullptr;   // d arrays of n grid coordinates, sorted by bin
+    int32_t *perm = nullptr;    // sorted position -> original point index
+    int32_t *sub_bin = nullptr, *sub_start = nullptr, *sub_count = nullptr;
+    int32_t *bin_sub_ptr = nullptr;  // CSR bins -> subproblems (nbins + 1)
+    int nsub = 0;
+    void *Dk = nullptr;     // symmetrised diagonal for K_s (dcells, plan precision)
+    void *Dder = nullptr;   // same for K_s^der
+};
+
+}  // namespace nfftgp
+
+struct nfftgp_plan_s {
+    int64_t n = 0;
+    int p = 0;
+    int P = 0;
+    int m = 0;
+    int prec = 0;
+    int max_nrhs = 0;
+    int scale_mode = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::vector<nfftgp::Window> win;
+    bool have_hyper = false;
+    double sigma_f = 0.0, sigma_eps = 0.0;
+    // workspaces (owned)
+    void *tilebuf = nullptr;     // spreading tiles
+    void *grid = nullptr;        // 2 x max_nrhs x max cells complex values
+    void *acc = nullptr, *comp = nullptr;  // n x max_nrhs compensated window sum
+    double *coef = nullptr;      // 4 x maxN^d complex doubles (set_hyper scratch)
+    double *bbar = nullptr;      // 2 x maxN^d doubles
+    double *minb = nullptr;      // 2 x P doubles
+    double *dot_part = nullptr;  // dot-product partials
+    double *cg_scal = nullptr;   // CG per-column scalars
+    double *cg_hist = nullptr;   // CG (alpha, beta) history
+    int cg_hist_cap = 0;
+    void *cg_r = nullptr, *cg_p = nullptr, *cg_ap = nullptr;  // n x max_nrhs
+    size_t bytes = 0;
+    std::vector<void *> allocs;
+};
+
+namespace nfftgp {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+#define NFFTGP_HIP_TRY(expr)                                                       \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            ::nfftgp::set_error(std::string(#expr) + ": " + hipGetErrorString(e_)); \
+            return NFFTGP_E_HIP;                                                   \
+        }                                                                          \
+    } while (0)
+
+// ---------------------------------------------------------------- plan-time kernels
+// Per-feature min / max over the n points of the given features (FP64 result,
+// 2*d doubles: lo[0..d), hi[0..d)) and a NaN flag.  `part` is scratch of
+// kPartBlocks * 2 * 3 doubles.
+constexpr int kPartBlocks = 256;
+hipError_t launch_minmax(int prec, const void *X, int64_t n, int64_t ldx, int d, const int *feat,
+                         double *part, double *out, int *nanflag, hipStream_t s);
+
+// Grid coordinates t = 2N c (x - c0) + N per window feature (SoA, d x n, plan
+// precision), bin keys, and a flag set when a scaled coordinate leaves
+// [-1/4, 1/4).
+hipError_t launch_coords(int prec, const void *X, int64_t n, int64_t ldx, int d, const int *feat,
+                         const double *c0, double c, const WindowGeom &g, void *t_out, int *keys,
+                         int *boxflag, hipStream_t s);
+
+// Stable counting sort of points by bin key.  hist: nbins * nblk ints;
+// scan_tmp: scan scratch; perm / t_sorted: outputs; bin_start: nbins + 1 ints.
+constexpr int kSortBlock = 4096;
+int64_t scan_scratch_ints(int64_t len);
+hipError_t launch_sort(int prec, int64_t n, int d, int nbins, const int *keys, const void *t_in,
+                       int *hist, int *scan_tmp, int *perm, void *t_sorted, int *bin_start,
+                       hipStream_t s);
+
+// ---------------------------------------------------------------- per-theta kernels
+// Coefficients b_k, b^der_k of one window (FP64) and the symmetrised diagonals.
+hipError_t launch_coefficients(int prec, const WindowGeom &g, int m, int kernel, double ell,
+                               double c, double *coef, double *bbar, void *Dk, void *Dder,
+                               double *minb_out, hipStream_t s);
+
+// ---------------------------------------------------------------- apply kernels
+hipError_t launch_fill(int prec, void *p, int64_t count, hipStream_t s);
+hipError_t launch_spread(int prec, const Window &w, int m, int64_t n, const void *V, int64_t ldv,
+                         int nrhs, void *tilebuf, hipStream_t s);
+hipError_t launch_fold(int prec, const Window &w, int m, int nrhs, const void *tilebuf, void *grid,
+                       hipStream_t s);
+hipError_t launch_fft(int prec, const WindowGeom &g, void *grid, int batch, bool inverse,
+                      hipStream_t s);
+hipError_t launch_diag(int prec, const Window &w, int nrhs, void *grid, bool with_der,
+                       hipStream_t s);
+hipError_t launch_interp(int prec, const Window &w, int m, int64_t n, int nrhs, const void *grid,
+                         bool with_der, void *acc, void *comp, void *dout, double dscale,
+                         hipStream_t s);
+hipError_t launch_assemble(int prec, int64_t n, int nrhs, const void *V, int64_t ldv,
+                           const void *acc, const void *comp, double sf, double se, void *KV,
+                           void *dsf, void *dse, hipStream_t s);
+
+// ---------------------------------------------------------------- CG / dots
+constexpr int kDotBlocks = 120;
+hipError_t launch_coldots(int prec, const void *A, int64_t lda, const void *B, int64_t ldb,
+                          int64_t n, int ncol, double *part, double *out, hipStream_t s);
+hipError_t launch_cg_init(int prec, int64_t n, int nrhs, const void *B, void *X, void *R, void *Pv,
+                          hipStream_t s);
+hipError_t launch_cg_start(int nrhs, double *scal, hipStream_t s);
+hipError_t launch_cg_alpha(int nrhs, double *scal, hipStream_t s);
+hipError_t launch_cg_xr(int prec, int64_t n, int nrhs, const double *scal, void *X, void *R,
+                        const void *Pv, const void *AP, hipStream_t s);
+hipError_t launch_cg_beta(int nrhs, double *scal, double tol, int it, double *hist,
+                          hipStream_t s);
+hipError_t launch_cg_p(int prec, int64_t n, int nrhs, const double *scal, const void *R, void *Pv,
+                       hipStream_t s);
+
+// Layout of the per-column CG scalar block (doubles, each an array of nrhs).
+enum CgSlot {
+    kRR = 0,      // current r^T r
+    kRR0 = 1,     // b^T b
+    kPAP = 2,     // p^T Khat p
+    kAlpha = 3,
+    kBeta = 4,
+    kActive = 5,  // 1 while the column iterates
+    kIters = 6,   // iterations done
+    kNotPD = 7,   // 1 if p^T Khat p <= 0 was met
+    kRRNew = 8,
+    kCgSlots = 9
+};
+
+}  // namespace nfftgp

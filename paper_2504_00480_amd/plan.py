@@ -1,0 +1,191 @@
+"""Python face of the C ABI (include/nfftgp.h): one class per plan.
+
+Device memory and streams come from PyTorch; every numerical step runs in
+libnfftgp's HIP kernels.  Names follow the paper: sigma_f, ell, sigma_eps,
+bandwidth N, window cutoff m, feature windows W_s.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+
+GAUSS = 0
+MATERN12 = 1
+SCALE_AUTO = 0
+SCALE_NONE = 1
+_KERNELS = {"gauss": GAUSS, "gaussian": GAUSS, "matern12": MATERN12, "matern": MATERN12}
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class AdditiveKernelPlan:
+    """Fast summation plan for fixed points X (n x p) and feature windows.
+
+    Parameters
+    ----------
+    X : torch.Tensor on a ROCm device, float32 or float64, n x p (row-major).
+    windows : list of feature-index lists (disjoint, 1..3 features each).
+    kernel : per-window kernel ("gauss" / "matern12" or 0 / 1), or one for all.
+    N : per-window bandwidth (power of two), or one for all.
+    m : window cutoff (2, 4, 6 or 8).
+    scale_mode : SCALE_AUTO (scale each window into [-1/4, 1/4)^d) or SCALE_NONE.
+    max_nrhs : largest number of vectors per apply / CG call (<= 64).
+    """
+
+    def __init__(self, X: torch.Tensor, windows: Sequence[Sequence[int]], kernel, N, m: int,
+                 scale_mode: int = SCALE_AUTO, max_nrhs: int = 1):
+        lib = _lib.load()
+        if not X.is_cuda:
+            raise ValueError("X must be a device tensor")
+        if X.dtype not in (torch.float32, torch.float64):
+            raise ValueError("X must be float32 or float64")
+        if X.dim() != 2 or X.stride(1) != 1:
+            raise ValueError("X must be a row-major n x p matrix")
+        self.dtype = X.dtype
+        self.device = X.device
+        self.prec = 0 if X.dtype == torch.float32 else 1
+        self.n, self.p = X.shape
+        self.windows = [list(map(int, w)) for w in windows]
+        P = len(self.windows)
+        self.P = P
+        ks = kernel if isinstance(kernel, (list, tuple)) else [kernel] * P
+        self.kernel = [(_KERNELS[k.lower()] if isinstance(k, str) else int(k)) for k in ks]
+        self.N = [int(x) for x in (N if isinstance(N, (list, tuple)) else [N] * P)]
+        self.m = int(m)
+        self.max_nrhs = int(max_nrhs)
+        ptr = np.zeros(P + 1, dtype=np.int32)
+        for s, w in enumerate(self.windows):
+            ptr[s + 1] = ptr[s] + len(w)
+        idx = np.array([f for w in self.windows for f in w] or [0], dtype=np.int32)
+        kt = np.array(self.kernel, dtype=np.int32)
+        Ns = np.array(self.N, dtype=np.int32)
+        self._stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.nfftgp_plan_create(ctypes.byref(h), _ptr(X), self.n, self.p, X.stride(0), P,
+                                        _np_ptr(ptr), _np_ptr(idx), _np_ptr(kt), _np_ptr(Ns), self.m,
+                                        self.prec, int(scale_mode), self.max_nrhs,
+                                        ctypes.c_void_p(self._stream.cuda_stream))
+        _lib.check(st, "nfftgp_plan_create")
+        self._h = h
+        self.sigma_f = None
+        self.ell = None
+        self.sigma_eps = None
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().nfftgp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def set_hyper(self, sigma_f: float, ell, sigma_eps: float):
+        """theta = (sigma_f, ell, sigma_eps); ell is one value or one per window."""
+        ells = np.array([float(e) for e in (ell if np.ndim(ell) else [ell] * self.P)], dtype=np.float64)
+        if ells.shape[0] != self.P:
+            raise ValueError("need one ell per window")
+        st = _lib.load().nfftgp_set_hyper(self._h, float(sigma_f), _np_ptr(ells), float(sigma_eps))
+        _lib.check(st, "nfftgp_set_hyper")
+        self.sigma_f, self.ell, self.sigma_eps = float(sigma_f), ells.copy(), float(sigma_eps)
+
+    def window_info(self, s: int) -> dict:
+        c0 = np.zeros(3)
+        c = ctypes.c_double()
+        d = ctypes.c_int32()
+        N = ctypes.c_int32()
+        mb = ctypes.c_double()
+        mbd = ctypes.c_double()
+        st = _lib.load().nfftgp_get_window_info(self._h, s, _np_ptr(c0), ctypes.byref(c), ctypes.byref(d),
+                                               ctypes.byref(N), ctypes.byref(mb), ctypes.byref(mbd))
+        _lib.check(st, "nfftgp_get_window_info")
+        return {"c0": c0[: d.value].copy(), "c": c.value, "d": d.value, "N": N.value,
+                "min_b": mb.value, "min_bder": mbd.value}
+
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _lib.check(_lib.load().nfftgp_get_workspace_bytes(self._h, ctypes.byref(b)), "workspace")
+        return int(b.value)
+
+    # ------------------------------------------------------------------
+    def _check_vec(self, V: torch.Tensor):
+        if V.dim() == 1:
+            V = V[:, None]
+        if V.dtype != self.dtype or V.device != self.device:
+            raise ValueError("vectors must match the plan's dtype and device")
+        if V.shape[0] != self.n:
+            raise ValueError("vectors must have n rows")
+        if V.stride(1) != 1:
+            V = V.contiguous()
+        return V
+
+    def apply(self, V: torch.Tensor, derivs: bool = False, out: torch.Tensor | None = None) -> dict:
+        """Khat V; with derivs also dKhat/d ell_s V (P blocks), dKhat/d sigma_f V, dKhat/d sigma_eps V."""
+        V = self._check_vec(V)
+        nrhs = V.shape[1]
+        KV = out if out is not None else torch.empty((self.n, nrhs), dtype=self.dtype, device=self.device)
+        dl = dsf = dse = None
+        if derivs:
+            dl = torch.empty((self.P, self.n, nrhs), dtype=self.dtype, device=self.device)
+            dsf = torch.empty((self.n, nrhs), dtype=self.dtype, device=self.device)
+            dse = torch.empty((self.n, nrhs), dtype=self.dtype, device=self.device)
+        st = _lib.load().nfftgp_apply(self._h, _ptr(V), V.stride(0), nrhs, _ptr(KV), _ptr(dl),
+                                      _ptr(dsf), _ptr(dse))
+        _lib.check(st, "nfftgp_apply")
+        res = {"KV": KV}
+        if derivs:
+            res.update({"dKV_dell": dl, "dKV_dsf": dsf, "dKV_dse": dse})
+        return res
+
+    def col_dots(self, A: torch.Tensor, B: torch.Tensor) -> np.ndarray:
+        """FP64 column dot products sum_i A[i, c] B[i, c] on the device."""
+        A = self._check_vec(A)
+        B = self._check_vec(B)
+        out = np.zeros(A.shape[1])
+        st = _lib.load().nfftgp_col_dots(self._h, _ptr(A), A.stride(0), _ptr(B), B.stride(0), A.shape[0],
+                                         A.shape[1], _np_ptr(out))
+        _lib.check(st, "nfftgp_col_dots")
+        return out
+
+    def cg(self, B: torch.Tensor, tol: float, maxit: int, check_every: int = 8, raise_on=("notpd",)):
+        """CG on Khat X = B from zero; returns (X, iters, (alpha, beta) history, rel. residuals, status)."""
+        B = self._check_vec(B).contiguous()
+        nrhs = B.shape[1]
+        X = torch.empty_like(B)
+        iters = np.zeros(nrhs, dtype=np.int32)
+        ab = np.zeros((max(maxit, 1), nrhs, 2))
+        res = np.zeros(nrhs)
+        st = _lib.load().nfftgp_cg(self._h, _ptr(B), nrhs, _ptr(X), float(tol), int(maxit), int(check_every),
+                                   _np_ptr(iters), _np_ptr(ab), _np_ptr(res))
+        if st not in (_lib.OK, _lib.E_NOCONV, _lib.E_NOTPD) or \
+                (st == _lib.E_NOTPD and "notpd" in raise_on) or (st == _lib.E_NOCONV and "noconv" in raise_on):
+            _lib.check(st, "nfftgp_cg")
+        return X, iters, ab, res, st
+
+
+def slq_logquad(ab: np.ndarray, iters: np.ndarray, znorm2: np.ndarray) -> np.ndarray:
+    """z^T logm(Khat) z for each column from its CG coefficients (stochastic Lanczos quadrature)."""
+    ab = np.ascontiguousarray(ab, dtype=np.float64)
+    maxit, ncol = ab.shape[0], ab.shape[1]
+    iters = np.ascontiguousarray(iters, dtype=np.int32)
+    zn = np.ascontiguousarray(znorm2, dtype=np.float64)
+    out = np.zeros(ncol)
+    st = _lib.load().nfftgp_slq_logquad(_np_ptr(ab), _np_ptr(iters), ncol, maxit, _np_ptr(zn), _np_ptr(out))
+    _lib.check(st, "nfftgp_slq_logquad")
+    return out
