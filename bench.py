@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Throughput of the additive-kernel fast summation on one MI355X.
+
+A step is one per-hyper-parameter pass of the hot path over one batch of
+vectors: the FP64 coefficient/diagonal setup for theta (set_hyper) followed by
+one additive apply that returns Khat V and every derivative product
+dKhat/d ell_s V, dKhat/d sigma_f V, dKhat/d sigma_eps V.  The value is
+n * nrhs / (seconds per step).  Inputs are resident in HBM before timing.
+
+Default workload: n = 100,000 points, p = 9 standard-normal features, three
+3-D Gaussian windows, ell = 0.5, sigma_f = 1, sigma_eps = 0.1, N = 32, m = 4,
+one vector, FP32.  Other workloads: --workload C1..C5.
+
+The JSON line also carries the roofline of the dominant kernel (timed with HIP
+events on the plan's stream inside the timed region), the oracle's CPU
+throughput on a bounded sample, and the parity of the timed result.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "kernel matvecs/sec (n×RHS/s) at ≤1e-4 rel err vs FP64; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"])
+    ap.add_argument("--prec", default=None, choices=[None, "f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-derivs", action="store_true", help="time the K-only apply as the step")
+    return ap.parse_args()
+
+
+def src_sha(*names):
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(ROOT, "paper_2504_00480_amd", "csrc", nm), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
+                                   "described in DESIGN.md but not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2504_00480_amd import AdditiveKernelPlan
+
+    w = workloads.CONFIGS[args.workload]()
+    prec = args.prec or ("f64" if args.workload == "C1" else "f32")
+    dt = torch.float32 if prec == "f32" else torch.float64
+    eb = 4 if prec == "f32" else 8
+    dev = torch.device("cuda:0")
+    X = torch.tensor(w.X, dtype=dt, device=dev)
+    V = torch.tensor(w.V, dtype=dt, device=dev)
+    n, nrhs, P = w.n, w.nrhs, len(w.windows)
+    derivs = not args.no_derivs
+    print(f"[bench] workload {w.name} prec {prec} steps {args.steps} warmup {args.warmup}",
+          file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = AdditiveKernelPlan(X, w.windows, w.ktype, w.N, w.m, scale_mode=w.scale_mode, max_nrhs=nrhs)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+
+    KV = torch.empty((n, nrhs), dtype=dt, device=dev)
+    dl = torch.empty((P, n, nrhs), dtype=dt, device=dev) if derivs else None
+    dsf = torch.empty((n, nrhs), dtype=dt, device=dev) if derivs else None
+    dse = torch.empty((n, nrhs), dtype=dt, device=dev) if derivs else None
+    from paper_2504_00480_amd import _lib
+    from paper_2504_00480_amd.plan import _ptr
+    lib = _lib.load()
+
+    def step():
+        plan.set_hyper(w.sigma_f, w.ell, w.sigma_eps)
+        st = lib.nfftgp_apply(plan._h, _ptr(V), V.stride(0), nrhs, _ptr(KV), _ptr(dl), _ptr(dsf), _ptr(dse))
+        if st != 0:
+            _lib.check(st, "nfftgp_apply")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
+    prof = plan.profile_read()
+    plan.profile(False)
+    ms_per_step = 1e3 * t_steps / args.steps
+    value = n * nrhs / (t_steps / args.steps)
+
+    # K-only apply (no set_hyper in the loop), for reference
+    def konly():
+        st = lib.nfftgp_apply(plan._h, _ptr(V), V.stride(0), nrhs, _ptr(KV), None, None, None)
+        if st != 0:
+            _lib.check(st, "nfftgp_apply")
+
+    for _ in range(3):
+        konly()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        konly()
+    torch.cuda.synchronize()
+    t_konly = (time.perf_counter() - t0) / args.steps
+    step()   # leave the derivative outputs of the timed configuration in place
+    torch.cuda.synchronize()
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.4f} ms/step", file=sys.stderr, flush=True)
+
+    # ---------------- roofline of the dominant kernel
+    geoms = []
+    for s, win in enumerate(w.windows):
+        d = len(win)
+        ng = 2 * w.N[s]
+        geoms.append((d, ng ** d))
+    taps = sum(n * nrhs * (2 * w.m) ** d for d, _ in geoms)          # per apply, all windows
+    cells = sum(c for _, c in geoms)
+    nout = 2 if derivs else 1
+    per_launch = {
+        # algorithmic work per launch, averaged over the windows of one apply
+        "spread": ("alu", 2.0 * taps / P, "TFLOP/s"),                 # one FMA per tap and vector
+        "interp": ("alu", 2.0 * taps * nout / P, "TFLOP/s"),          # one FMA per tap, vector, output
+        "fft_fwd": ("hbm", 2.0 * nrhs * cells * 2 * eb / P, "GB/s"),   # complex grid read + written once
+        "fft_inv": ("hbm", 2.0 * nout * nrhs * cells * 2 * eb / P, "GB/s"),
+        "fold": ("hbm", 1.0 * nrhs * cells * 2 * eb / P, "GB/s"),      # complex grid written once
+        "diag": ("hbm", (2.0 + 1.0 * nout) * nrhs * cells * 2 * eb / P, "GB/s"),
+        "assemble": ("hbm", (2 + 2 + 1 + (2 if derivs else 0)) * n * nrhs * eb, "GB/s"),
+        "coef": ("alu", 0.0, "TFLOP/s"),
+        "fill": ("hbm", n * nrhs * eb, "GB/s"),
+    }
+    kern = {k: {"total_ms": v[0], "launches": v[1], "avg_us": (1e3 * v[0] / v[1]) if v[1] else 0.0}
+            for k, v in prof.items() if v[1]}
+    dom = max((k for k in kern if k in per_launch and k != "coef"), key=lambda k: kern[k]["total_ms"])
+    bound, work, unit = per_launch[dom]
+    avg_s = kern[dom]["total_ms"] / 1e3 / kern[dom]["launches"]
+    if bound == "hbm":
+        achieved = work / avg_s / 1e9
+        peak = HBM_PEAK_GBS
+    else:
+        achieved = work / avg_s / 1e12
+        peak = FP32_PEAK_TFLOPS if prec == "f32" else FP64_PEAK_TFLOPS
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        try:
+            tj = json.load(open(tfile))
+            ent = tj.get(f"{args.workload}:{prec}:{dom}")
+            srcs = {"spread": ["k_grid.hip"], "interp": ["k_grid.hip"], "fold": ["k_grid.hip"],
+                    "fft_fwd": ["k_fft.hip"], "fft_inv": ["k_fft.hip"], "diag": ["k_fft.hip"],
+                    "assemble": ["k_grid.hip"], "fill": ["k_grid.hip"]}[dom]
+            if ent and ent.get("source_sha") == src_sha(*srcs):
+                traffic = ent["bytes_per_launch"]
+        except Exception:
+            traffic = None
+    roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": traffic,
+                "work_per_launch": work, "avg_launch_us": avg_s * 1e6}
+
+    # ---------------- parity of the timed result (O2 on sampled rows)
+    parity = None
+    cpu = None
+    need_oracle = not (args.no_parity and args.no_cpu_baseline)
+    if need_oracle:
+        import oracle
+        oracle.build(force=False)
+        Xo = X.double().cpu().numpy()
+        Vo = V.double().cpu().numpy()
+        pb = oracle.Problem(Xo, w.windows, w.ktype, w.ell, w.sigma_f, w.sigma_eps, w.N, w.scale_mode)
+    if not args.no_parity:
+        rows = np.linspace(0, n - 1, 200).astype(np.int64)
+        sparse_v = n * (2 ** 15) * P > 2e11    # NDFT over every point would take minutes
+        Vp = Vo
+        if sparse_v:
+            # linearity: test the same launch on a vector that is zero except on a sample
+            Vp = np.zeros_like(Vo)
+            Vp[rows] = Vo[rows]
+            Vp[:: max(1, n // 2000)] = Vo[:: max(1, n // 2000)]
+            Vt = torch.tensor(Vp, dtype=dt, device=dev)
+            out = plan.apply(Vt, derivs=derivs)
+            gk = out["KV"].double().cpu().numpy()[rows]
+            gd = out["dKV_dell"].double().cpu().numpy()[:, rows] if derivs else None
+        else:
+            gk = KV.double().cpu().numpy()[rows]
+            gd = dl.double().cpu().numpy()[:, rows] if derivs else None
+        t0 = time.perf_counter()
+        ref = oracle.rf_apply(pb, Vp, rows=rows, derivs=derivs)
+        t_par = time.perf_counter() - t0
+        ek = float(np.max(np.abs(gk - ref["KV"]).max(0) / np.abs(ref["KV"]).max(0)))
+        ed = None
+        if derivs:
+            ed = float(max(np.max(np.abs(gd[s] - ref["dKV_dell"][s]).max(0) /
+                                  np.abs(ref["dKV_dell"][s]).max(0)) for s in range(P)))
+        parity = {"reference": "O2 (trigonometric-kernel product, FP64 oracle)", "rows": int(len(rows)),
+                  "sparse_rhs": bool(sparse_v), "max_rel_err_KV": ek, "max_rel_err_dKV_dell": ed,
+                  "gate": 1e-4, "pass": bool(ek <= 1e-4 and (ed is None or ed <= 1e-4)),
+                  "oracle_seconds": t_par}
+        print(f"[bench] parity {parity}", file=sys.stderr, flush=True)
+
+    # ---------------- CPU baseline: exact dense product (O1) on sampled target rows
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(0)
+        nr = 1000
+        t_cpu = 0.0
+        while True:
+            rows = np.sort(rng.choice(n, size=min(nr, n), replace=False)).astype(np.int64)
+            t0 = time.perf_counter()
+            oracle.dense_apply(pb, Vo, rows=rows)
+            t_cpu = time.perf_counter() - t0
+            if t_cpu >= 8.0 or nr >= n:
+                break
+            nr = int(min(n, nr * max(2.0, 12.0 / max(t_cpu, 1e-3))))
+        cpu = {"value": len(rows) * nrhs / t_cpu, "unit": "n×RHS/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"exact dense additive product (O1, FP64, all derivative blocks) for {len(rows)} "
+                         f"random target rows x all {n} source points x {nrhs} vector(s); {t_cpu:.1f} s"}
+
+    res = {
+        "metric": METRIC, "value": value, "unit": "n×RHS/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "p": int(w.X.shape[1]),
+                   "windows": [len(x) for x in w.windows],
+                   "kernels": ["gauss" if k == 0 else "matern12" for k in w.ktype], "N": w.N, "m": w.m,
+                   "nrhs": nrhs, "ell": w.ell, "sigma_f": w.sigma_f, "sigma_eps": w.sigma_eps,
+                   "step": "set_hyper + apply with " + ("all derivative outputs" if derivs else "K only")},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity": parity,
+        "kernels": kern,
+        "k_only_apply": {"ms": t_konly * 1e3, "value": n * nrhs / t_konly},
+        "plan_seconds": t_plan,
+        "workspace_bytes": plan.workspace_bytes(),
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

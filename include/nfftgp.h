@@ -91,7 +91,7 @@ typedef struct nfftgp_plan_s *nfftgp_plan;
  *            The index set is I_N = {-N/2, ..., N/2-1}^d (eq. nfftkappa) and the
  *            oversampled FFT grid has (2N)^d points.
  *   m        window cutoff (Kaiser-Bessel support m/(2N) per dimension, Appendix A),
- *            2 <= m <= 8 and m < N/2.
+ *            m in {2, 4, 6, 8} and m < N/2 (E_DIM otherwise).
  *   max_nrhs largest nrhs that nfftgp_apply / nfftgp_cg will be given (1..64);
  *            workspaces are sized for it here.
  *   stream   hipStream_t to enqueue on (NULL = null stream).
@@ -168,6 +168,28 @@ nfftgp_status nfftgp_slq_logquad(const double *alpha_beta_host, const int32_t *i
  * set_hyper (min_b < 0 means K_{s,RF} can be indefinite).  Any output may be NULL. */
 nfftgp_status nfftgp_get_window_info(nfftgp_plan plan, int32_t s, double *c0, double *c,
                                      int32_t *d, int32_t *N, double *min_b, double *min_bder);
+
+/* Kernel timing with HIP events (a profiling aid).  While enabled, every
+ * kernel the plan enqueues is bracketed by two events on the plan's stream
+ * and tagged with one of the categories below; nfftgp_profile_read
+ * synchronises the stream and returns, per category, the summed duration in
+ * milliseconds and the number of launches since profiling was (re-)enabled.
+ * Enabling allocates events, so do not enable it while capturing a graph. */
+enum {
+    NFFTGP_PROF_FILL = 0,     /* clearing of the window-sum accumulators      */
+    NFFTGP_PROF_SPREAD = 1,   /* window spreading onto the tiles              */
+    NFFTGP_PROF_FOLD = 2,     /* sum of overlapping tiles into the grid       */
+    NFFTGP_PROF_FFT_FWD = 3,  /* forward FFT passes                           */
+    NFFTGP_PROF_DIAG = 4,     /* diagonal multiply                            */
+    NFFTGP_PROF_FFT_INV = 5,  /* inverse FFT passes                           */
+    NFFTGP_PROF_INTERP = 6,   /* window interpolation and window sum          */
+    NFFTGP_PROF_ASSEMBLE = 7, /* sigma scaling and derivative blocks          */
+    NFFTGP_PROF_COEF = 8,     /* per-theta coefficient kernels                */
+    NFFTGP_PROF_CG = 9,       /* CG dot products and vector updates           */
+    NFFTGP_PROF_COUNT = 10
+};
+nfftgp_status nfftgp_profile(nfftgp_plan plan, int32_t enable);
+nfftgp_status nfftgp_profile_read(nfftgp_plan plan, double *ms_host, int32_t *count_host);
 
 /* Device bytes the plan holds. */
 nfftgp_status nfftgp_get_workspace_bytes(nfftgp_plan plan, size_t *bytes);

@@ -333,16 +333,34 @@ def ndft_adjoint(pb: Problem, s: int, V):
 
 
 def rf_apply(pb: Problem, V, rows=None, method="ndft", derivs=True):
-    """O2 product on target rows, all windows (same keys as ``dense_apply``)."""
+    """O2 product on target rows, all windows (same keys as ``dense_apply``).
+
+    With the NDFT form the inner sums of a window serve both its kernel and
+    its derivative kernel (they do not depend on the coefficients)."""
     V = _as_rhs(V, pb.n)
     rows = _rows(rows, pb.n)
     nrhs = V.shape[1]
     KS = np.zeros((pb.P, rows.shape[0], nrhs))
     DL = np.zeros((pb.P, rows.shape[0], nrhs))
+    lib = _load()
     for s in range(pb.P):
-        KS[s] = rf_window(pb, s, V, rows, False, method)
-        if derivs:
-            DL[s] = pb.sigma_f ** 2 * rf_window(pb, s, V, rows, True, method)
+        if method == "pairwise":
+            KS[s] = rf_window(pb, s, V, rows, False, method)
+            if derivs:
+                DL[s] = pb.sigma_f ** 2 * rf_window(pb, s, V, rows, True, method)
+            continue
+        xs = pb.xs(s)
+        d = xs.shape[1]
+        N = pb.N[s]
+        A = np.zeros(N ** d * nrhs * 2)
+        lib.orc_ndft_adjoint(pb.n, d, _p(xs), N, _p(V), nrhs, _p(A))
+        for which, dst, scale in ((0, KS, 1.0), (1, DL, pb.sigma_f ** 2)):
+            if which == 1 and not derivs:
+                continue
+            b = np.ascontiguousarray(pb.coef(s)[which])
+            H = np.zeros((rows.shape[0], nrhs))
+            lib.orc_ndft_forward(d, _p(xs), N, _p(b), _p(A), nrhs, _p(rows), rows.shape[0], _p(H))
+            dst[s] = scale * H
     KV = pb.sigma_f ** 2 * KS.sum(axis=0) + pb.sigma_eps ** 2 * V[rows]
     return {"KV": KV, "dKV_dell": DL, "KsV": KS,
             "dKV_dsf": 2.0 * pb.sigma_f * KS.sum(axis=0),

@@ -46,10 +46,41 @@ nfftgp_status dalloc(nfftgp_plan p, void **ptr, size_t bytes)
 void free_plan(nfftgp_plan p)
 {
     if (!p) return;
-    if (p->stream || true) (void)hipStreamSynchronize(p->stream);
+    (void)hipStreamSynchronize(p->stream);
     for (void *a : p->allocs) (void)hipFree(a);
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     delete p;
 }
+
+// Event pair around one launch when profiling is on.
+int prof_begin(nfftgp_plan p)
+{
+    if (!p->prof) return -1;
+    while (p->ev_used + 2 > p->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        p->ev_pool.push_back(e);
+    }
+    int i = (int)p->ev_used;
+    p->ev_used += 2;
+    (void)hipEventRecord(p->ev_pool[i], p->stream);
+    return i;
+}
+
+void prof_end(nfftgp_plan p, int cat, int i)
+{
+    if (i < 0) return;
+    (void)hipEventRecord(p->ev_pool[i + 1], p->stream);
+    p->prof_cat.push_back(cat);
+    p->prof_ev.push_back(i);
+}
+
+#define PROF_LAUNCH(plan_, cat_, expr_)                   \
+    do {                                                   \
+        int pi_ = prof_begin(plan_);                       \
+        NFFTGP_HIP_TRY(expr_);                             \
+        prof_end(plan_, cat_, pi_);                        \
+    } while (0)
 
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
@@ -119,22 +150,26 @@ nfftgp_status apply_impl(nfftgp_plan p, const void *V, int64_t ldv, int nrhs, vo
     const bool with_der = dell != nullptr;
     const int64_t tot = p->n * nrhs;
     if (p->n == 0) return NFFTGP_OK;
-    NFFTGP_HIP_TRY(launch_fill(p->prec, p->acc, tot, s));
-    NFFTGP_HIP_TRY(launch_fill(p->prec, p->comp, tot, s));
+    PROF_LAUNCH(p, NFFTGP_PROF_FILL, launch_fill(p->prec, p->acc, tot, s));
+    PROF_LAUNCH(p, NFFTGP_PROF_FILL, launch_fill(p->prec, p->comp, tot, s));
     const size_t eb = prec_bytes(p->prec);
     for (int w = 0; w < p->P; ++w) {
         const Window &win = p->win[w];
-        NFFTGP_HIP_TRY(launch_spread(p->prec, win, p->m, p->n, V, ldv, nrhs, p->tilebuf, s));
-        NFFTGP_HIP_TRY(launch_fold(p->prec, win, p->m, nrhs, p->tilebuf, p->grid, s));
-        NFFTGP_HIP_TRY(launch_fft(p->prec, win.g, p->grid, nrhs, false, s));
-        NFFTGP_HIP_TRY(launch_diag(p->prec, win, nrhs, p->grid, with_der, s));
-        NFFTGP_HIP_TRY(launch_fft(p->prec, win.g, p->grid, nrhs * (with_der ? 2 : 1), true, s));
+        PROF_LAUNCH(p, NFFTGP_PROF_SPREAD,
+                    launch_spread(p->prec, win, p->m, p->n, V, ldv, nrhs, p->vsort, p->tilebuf, s));
+        PROF_LAUNCH(p, NFFTGP_PROF_FOLD, launch_fold(p->prec, win, p->m, nrhs, p->tilebuf, p->grid, s));
+        PROF_LAUNCH(p, NFFTGP_PROF_FFT_FWD, launch_fft(p->prec, win.g, p->grid, nrhs, false, s));
+        PROF_LAUNCH(p, NFFTGP_PROF_DIAG, launch_diag(p->prec, win, nrhs, p->grid, with_der, s));
+        PROF_LAUNCH(p, NFFTGP_PROF_FFT_INV,
+                    launch_fft(p->prec, win.g, p->grid, nrhs * (with_der ? 2 : 1), true, s));
         void *dout = with_der ? (void *)((char *)dell + (size_t)w * tot * eb) : nullptr;
-        NFFTGP_HIP_TRY(launch_interp(p->prec, win, p->m, p->n, nrhs, p->grid, with_der, p->acc,
-                                     p->comp, dout, p->sigma_f * p->sigma_f, s));
+        PROF_LAUNCH(p, NFFTGP_PROF_INTERP,
+                    launch_interp(p->prec, win, p->m, p->n, nrhs, p->grid, with_der, p->acc, p->comp,
+                                  dout, p->sigma_f * p->sigma_f, s));
     }
-    NFFTGP_HIP_TRY(launch_assemble(p->prec, p->n, nrhs, V, ldv, p->acc, p->comp, p->sigma_f,
-                                   p->sigma_eps, KV, dsf, dse, s));
+    PROF_LAUNCH(p, NFFTGP_PROF_ASSEMBLE,
+                launch_assemble(p->prec, p->n, nrhs, V, ldv, p->acc, p->comp, p->sigma_f,
+                                p->sigma_eps, KV, dsf, dse, s));
     return NFFTGP_OK;
 }
 
@@ -209,19 +244,33 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
     Scratch tmp;
     double *part = nullptr, *mm = nullptr;
     int *flags = nullptr, *keys = nullptr, *hist = nullptr, *scan_tmp = nullptr, *bin_start = nullptr;
-    void *t_uns = nullptr;
+    int *ids1 = nullptr;
+    void *t_uns = nullptr, *t1 = nullptr, *t2 = nullptr;
     int nblk = (int)std::max<int64_t>(1, (n + kSortBlock - 1) / kSortBlock);
-    int max_bins = 1;
-    for (int s = 0; s < P; ++s) max_bins = std::max(max_bins, make_geom(win_ptr[s + 1] - win_ptr[s], N[s], m).nbins);
-    int64_t hist_len = (int64_t)max_bins * nblk;
+    int max_keys = 1;
+    for (int s = 0; s < P; ++s) {
+        WindowGeom g = make_geom(win_ptr[s + 1] - win_ptr[s], N[s], m);
+        int local = 1;
+        for (int q = 0; q < g.d; ++q) local *= g.tb;
+        max_keys = std::max(max_keys, std::max(g.nbins, local));
+    }
+    int64_t hist_len = (int64_t)max_keys * nblk;
+    const int64_t n1 = std::max<int64_t>(n, 1);
     TRYH(tmp.get((void **)&part, kPartBlocks * 6 * sizeof(double)));
     TRYH(tmp.get((void **)&mm, 8 * sizeof(double)));
     TRYH(tmp.get((void **)&flags, 4 * sizeof(int)));
-    TRYH(tmp.get((void **)&keys, std::max<int64_t>(n, 1) * sizeof(int)));
+    TRYH(tmp.get((void **)&keys, n1 * sizeof(int)));
+    TRYH(tmp.get((void **)&ids1, n1 * sizeof(int)));
     TRYH(tmp.get((void **)&hist, (hist_len + 1) * sizeof(int)));
     TRYH(tmp.get((void **)&scan_tmp, scan_scratch_ints(hist_len) * sizeof(int)));
-    TRYH(tmp.get((void **)&bin_start, (max_bins + 1) * sizeof(int)));
-    TRYH(tmp.get(&t_uns, std::max<int64_t>(n, 1) * 3 * eb));
+    TRYH(tmp.get((void **)&bin_start, (max_keys + 1) * sizeof(int)));
+    TRYH(tmp.get(&t_uns, n1 * 3 * eb));
+    TRYH(tmp.get(&t1, n1 * 3 * eb));
+    TRYH(tmp.get(&t2, n1 * 3 * eb));
+    // points per spreading work-group: enough groups to fill the device for
+    // small n, fewer and longer runs (fewer partial tiles) for large n
+    int sub_sp = 256;
+    while (sub_sp < 4096 && (int64_t)sub_sp * 2048 < n) sub_sp *= 2;
 
     size_t tile_need = 0;
     int64_t max_cells = 1, maxK = 1;
@@ -264,12 +313,20 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
                 if (h > 0.0) w.c = 0.25 * (1.0 - std::ldexp(1.0, -20)) / h;
             }
         }
-        // --- grid coordinates, keys, sort
-        TRYS(dalloc(plan, &w.t_sorted, std::max<int64_t>(n, 1) * d * eb));
-        TRYS(dalloc(plan, (void **)&w.perm, std::max<int64_t>(n, 1) * sizeof(int)));
+        // --- grid coordinates; two stable counting-sort passes (cell inside the
+        // tile, then tile) leave the points grouped by tile and, inside a tile,
+        // by cell
+        int local = 1;
+        for (int q = 0; q < d; ++q) local *= w.g.tb;
+        TRYS(dalloc(plan, (void **)&w.perm, n1 * sizeof(int)));
+        TRYS(dalloc(plan, &w.rec, n1 * d * 2 * m * eb));
+        TRYS(dalloc(plan, (void **)&w.anchor, n1 * sizeof(int)));
         TRYH(launch_coords(prec, X_dev, n, ldx, d, w.feat, w.c0, w.c, w.g, t_uns, keys, flags + 1, st));
-        TRYH(launch_sort(prec, n, d, w.g.nbins, keys, t_uns, hist, scan_tmp, w.perm, w.t_sorted,
+        TRYH(launch_sort(prec, n, d, local, keys, nullptr, t_uns, hist, scan_tmp, ids1, t1, bin_start, st));
+        TRYH(launch_bin_keys(prec, t1, n, w.g, keys, st));
+        TRYH(launch_sort(prec, n, d, w.g.nbins, keys, ids1, t1, hist, scan_tmp, w.perm, t2,
                          bin_start, st));
+        TRYH(launch_weights(prec, t2, n, w.g, m, kb_knorm(m), w.rec, w.anchor, st));
         std::vector<int> bs(w.g.nbins + 1);
         TRYH(hipMemcpyAsync(bs.data(), bin_start, (w.g.nbins + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
         TRYH(hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -279,30 +336,46 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
             return fail(NFFTGP_E_BOX, "window " + std::to_string(s) +
                                           ": a scaled point lies outside [-1/4, 1/4)^d");
         }
-        // --- subproblems: runs of at most kMaxSubPoints points of one bin
-        std::vector<int> sb, ss, sc, bsp(w.g.nbins + 1, 0);
+        // --- subproblems: runs of points of one tile
+        std::vector<int> sb, ss, sc, bsp(w.g.nbins + 1, 0), ib, is, ic;
+        w.nbins_used = 0;
         for (int b = 0; b < w.g.nbins; ++b) {
             int cnt = bs[b + 1] - bs[b];
-            for (int off = 0; off < cnt; off += kMaxSubPoints) {
+            w.nbins_used += cnt > 0;
+            for (int off = 0; off < cnt; off += sub_sp) {
                 sb.push_back(b);
                 ss.push_back(bs[b] + off);
-                sc.push_back(std::min(kMaxSubPoints, cnt - off));
+                sc.push_back(std::min(sub_sp, cnt - off));
             }
             bsp[b + 1] = (int)sb.size();
+            for (int off = 0; off < cnt; off += kInterpSubPoints) {
+                ib.push_back(b);
+                is.push_back(bs[b] + off);
+                ic.push_back(std::min(kInterpSubPoints, cnt - off));
+            }
         }
         w.nsub = (int)sb.size();
+        w.nisub = (int)ib.size();
         TRYS(dalloc(plan, (void **)&w.sub_bin, std::max(1, w.nsub) * sizeof(int)));
         TRYS(dalloc(plan, (void **)&w.sub_start, std::max(1, w.nsub) * sizeof(int)));
         TRYS(dalloc(plan, (void **)&w.sub_count, std::max(1, w.nsub) * sizeof(int)));
         TRYS(dalloc(plan, (void **)&w.bin_sub_ptr, (w.g.nbins + 1) * sizeof(int)));
+        TRYS(dalloc(plan, (void **)&w.isub_bin, std::max(1, w.nisub) * sizeof(int)));
+        TRYS(dalloc(plan, (void **)&w.isub_start, std::max(1, w.nisub) * sizeof(int)));
+        TRYS(dalloc(plan, (void **)&w.isub_count, std::max(1, w.nisub) * sizeof(int)));
         if (w.nsub > 0) {
             TRYH(hipMemcpy(w.sub_bin, sb.data(), w.nsub * sizeof(int), hipMemcpyHostToDevice));
             TRYH(hipMemcpy(w.sub_start, ss.data(), w.nsub * sizeof(int), hipMemcpyHostToDevice));
             TRYH(hipMemcpy(w.sub_count, sc.data(), w.nsub * sizeof(int), hipMemcpyHostToDevice));
+            TRYH(hipMemcpy(w.isub_bin, ib.data(), w.nisub * sizeof(int), hipMemcpyHostToDevice));
+            TRYH(hipMemcpy(w.isub_start, is.data(), w.nisub * sizeof(int), hipMemcpyHostToDevice));
+            TRYH(hipMemcpy(w.isub_count, ic.data(), w.nisub * sizeof(int), hipMemcpyHostToDevice));
         }
         TRYH(hipMemcpy(w.bin_sub_ptr, bsp.data(), (w.g.nbins + 1) * sizeof(int), hipMemcpyHostToDevice));
         TRYS(dalloc(plan, &w.Dk, w.g.dcells * eb));
         TRYS(dalloc(plan, &w.Dder, w.g.dcells * eb));
+        TRYS(dalloc(plan, (void **)&w.cinv2, (N[s] + 1) * sizeof(double)));
+        TRYH(launch_window_coef(N[s], m, w.cinv2, st));
         tile_need = std::max(tile_need, (size_t)w.nsub * w.g.pc);
         max_cells = std::max(max_cells, w.g.cells);
         int64_t K = 1;
@@ -314,6 +387,7 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
     const size_t vec_bytes = std::max<int64_t>(n, 1) * max_nrhs * eb;
     TRYS(dalloc(plan, &plan->acc, vec_bytes));
     TRYS(dalloc(plan, &plan->comp, vec_bytes));
+    TRYS(dalloc(plan, &plan->vsort, vec_bytes));
     TRYS(dalloc(plan, (void **)&plan->coef, (size_t)8 * maxK * sizeof(double)));
     TRYS(dalloc(plan, (void **)&plan->bbar, (size_t)2 * maxK * sizeof(double)));
     TRYS(dalloc(plan, (void **)&plan->minb, (size_t)2 * P * sizeof(double)));
@@ -340,8 +414,9 @@ nfftgp_status nfftgp_set_hyper(nfftgp_plan plan, double sigma_f, const double *e
     const hipStream_t st = plan->stream;
     for (int s = 0; s < plan->P; ++s) {
         Window &w = plan->win[s];
-        NFFTGP_HIP_TRY(launch_coefficients(plan->prec, w.g, plan->m, w.kernel, ell[s], w.c, plan->coef,
-                                           plan->bbar, w.Dk, w.Dder, plan->minb + 2 * s, st));
+        PROF_LAUNCH(plan, NFFTGP_PROF_COEF,
+                    launch_coefficients(plan->prec, w.g, plan->m, w.kernel, ell[s], w.c, w.cinv2, plan->coef,
+                                        plan->bbar, w.Dk, w.Dder, plan->minb + 2 * s, st));
     }
     std::vector<double> mb(2 * plan->P);
     NFFTGP_HIP_TRY(hipMemcpyAsync(mb.data(), plan->minb, 2 * plan->P * sizeof(double),
@@ -409,23 +484,23 @@ nfftgp_status nfftgp_cg(nfftgp_plan plan, const void *B_dev, int32_t nrhs, void 
         plan->cg_hist_cap = maxit * nrhs;
     }
     double *hist = alpha_beta_host ? plan->cg_hist : nullptr;
-    NFFTGP_HIP_TRY(launch_cg_init(plan->prec, n, nrhs, B_dev, X_dev, plan->cg_r, plan->cg_p, st));
-    NFFTGP_HIP_TRY(launch_coldots(plan->prec, plan->cg_r, nrhs, plan->cg_r, nrhs, n, nrhs,
-                                  plan->dot_part, sc + kRR * nrhs, st));
-    NFFTGP_HIP_TRY(launch_cg_start(nrhs, sc, st));
+    PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_init(plan->prec, n, nrhs, B_dev, X_dev, plan->cg_r, plan->cg_p, st));
+    PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_coldots(plan->prec, plan->cg_r, nrhs, plan->cg_r, nrhs, n, nrhs,
+                                                         plan->dot_part, sc + kRR * nrhs, st));
+    PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_start(nrhs, sc, st));
     std::vector<double> act(nrhs);
     int it = 0;
     for (; it < maxit; ++it) {
         nfftgp_status e = apply_impl(plan, plan->cg_p, nrhs, nrhs, plan->cg_ap, nullptr, nullptr, nullptr);
         if (e != NFFTGP_OK) return e;
-        NFFTGP_HIP_TRY(launch_coldots(plan->prec, plan->cg_p, nrhs, plan->cg_ap, nrhs, n, nrhs,
-                                      plan->dot_part, sc + kPAP * nrhs, st));
-        NFFTGP_HIP_TRY(launch_cg_alpha(nrhs, sc, st));
-        NFFTGP_HIP_TRY(launch_cg_xr(plan->prec, n, nrhs, sc, X_dev, plan->cg_r, plan->cg_p, plan->cg_ap, st));
-        NFFTGP_HIP_TRY(launch_coldots(plan->prec, plan->cg_r, nrhs, plan->cg_r, nrhs, n, nrhs,
-                                      plan->dot_part, sc + kRRNew * nrhs, st));
-        NFFTGP_HIP_TRY(launch_cg_beta(nrhs, sc, tol, it, hist, st));
-        NFFTGP_HIP_TRY(launch_cg_p(plan->prec, n, nrhs, sc, plan->cg_r, plan->cg_p, st));
+        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_coldots(plan->prec, plan->cg_p, nrhs, plan->cg_ap, nrhs, n, nrhs,
+                                                         plan->dot_part, sc + kPAP * nrhs, st));
+        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_alpha(nrhs, sc, st));
+        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_xr(plan->prec, n, nrhs, sc, X_dev, plan->cg_r, plan->cg_p, plan->cg_ap, st));
+        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_coldots(plan->prec, plan->cg_r, nrhs, plan->cg_r, nrhs, n, nrhs,
+                                                         plan->dot_part, sc + kRRNew * nrhs, st));
+        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_beta(nrhs, sc, tol, it, hist, st));
+        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_p(plan->prec, n, nrhs, sc, plan->cg_r, plan->cg_p, st));
         if ((it + 1) % check_every == 0 || it + 1 == maxit) {
             NFFTGP_HIP_TRY(hipMemcpyAsync(act.data(), sc + kActive * nrhs, nrhs * sizeof(double),
                                           hipMemcpyDeviceToHost, st));
@@ -571,6 +646,36 @@ nfftgp_status nfftgp_get_workspace_bytes(nfftgp_plan plan, size_t *bytes)
     set_error("");
     if (!plan || !bytes) return fail(NFFTGP_E_ARG, "NULL argument");
     *bytes = plan->bytes;
+    return NFFTGP_OK;
+}
+
+nfftgp_status nfftgp_profile(nfftgp_plan plan, int32_t enable)
+{
+    set_error("");
+    if (!plan) return fail(NFFTGP_E_ARG, "plan is NULL");
+    plan->prof = enable != 0;
+    plan->ev_used = 0;
+    plan->prof_cat.clear();
+    plan->prof_ev.clear();
+    return NFFTGP_OK;
+}
+
+nfftgp_status nfftgp_profile_read(nfftgp_plan plan, double *ms_host, int32_t *count_host)
+{
+    set_error("");
+    if (!plan || !ms_host || !count_host) return fail(NFFTGP_E_ARG, "NULL argument");
+    NFFTGP_HIP_TRY(hipStreamSynchronize(plan->stream));
+    for (int c = 0; c < NFFTGP_PROF_COUNT; ++c) {
+        ms_host[c] = 0.0;
+        count_host[c] = 0;
+    }
+    for (size_t r = 0; r < plan->prof_cat.size(); ++r) {
+        float ms = 0.0f;
+        int i = plan->prof_ev[r];
+        NFFTGP_HIP_TRY(hipEventElapsedTime(&ms, plan->ev_pool[i], plan->ev_pool[i + 1]));
+        ms_host[plan->prof_cat[r]] += ms;
+        count_host[plan->prof_cat[r]] += 1;
+    }
     return NFFTGP_OK;
 }
 

@@ -86,9 +86,23 @@ __global__ void k_dft_axis(int d, int N, int axis, const double *__restrict__ in
     out[2 * (arr * K + e) + 1] = si;
 }
 
+// Normalised window coefficient per dimension, c(k) = I_0(m sqrt(beta^2 -
+// (2 pi k / 2N)^2)) / I_0(m beta) for k = -N/2..N/2 (index k + N/2), stored as
+// 1 / c(k)^2 -- the factor the diagonal applies once per transform.
+__global__ void k_window_coef(int N, int m, double beta, double *__restrict__ cinv2)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > N) return;
+    const int k = i - N / 2;
+    const double w = 2.0 * kPi * k / (2.0 * N);
+    const double c = bessel_i0(m * sqrt(beta * beta - w * w)) / bessel_i0(m * beta);
+    cinv2[i] = 1.0 / (c * c);
+}
+
 template <typename T>
-__global__ void k_make_diag(int d, int N, int m, double beta, const double *__restrict__ B,
-                            double *__restrict__ bbar, T *__restrict__ Dk, T *__restrict__ Dder)
+__global__ void k_make_diag(int d, int N, const double *__restrict__ cinv2,
+                            const double *__restrict__ B, double *__restrict__ bbar,
+                            T *__restrict__ Dk, T *__restrict__ Dder)
 {
     int64_t K = 1, KD = 1;
     for (int q = 0; q < d; ++q) {
@@ -110,15 +124,13 @@ __global__ void k_make_diag(int d, int N, int m, double beta, const double *__re
     }
     bool in_pos = true, in_neg = true;
     int64_t ip = 0, in_ = 0;
-    double C = 1.0;
-    const double ng = 2.0 * N, i0b = bessel_i0(m * beta);
+    double f = 1.0;
     for (int q = 0; q < d; ++q) {
         in_pos = in_pos && (kv[q] < N / 2);
         in_neg = in_neg && (-kv[q] < N / 2);
         ip = ip * N + (kv[q] + N / 2);
         in_ = in_ * N + (-kv[q] + N / 2);
-        double w = 2.0 * kPi * kv[q] / ng;
-        C *= bessel_i0(m * sqrt(beta * beta - w * w)) / i0b;
+        f *= cinv2[kv[q] + N / 2];
     }
     double bk = 0.0, bd = 0.0;
     if (in_pos) {
@@ -129,8 +141,8 @@ __global__ void k_make_diag(int d, int N, int m, double beta, const double *__re
         bk += B[2 * in_] * invK;
         bd += B[2 * (K + in_)] * invK;
     }
-    Dk[idx] = (T)(0.5 * bk / (C * C));
-    Dder[idx] = (T)(0.5 * bd / (C * C));
+    Dk[idx] = (T)(0.5 * bk * f);
+    Dder[idx] = (T)(0.5 * bd * f);
 }
 
 __global__ void __launch_bounds__(1024)
@@ -160,10 +172,17 @@ k_min2(const double *__restrict__ v, int64_t K, double *__restrict__ out)
 
 }  // namespace
 
-hipError_t launch_coefficients(int prec, const WindowGeom &g, int m, int kernel, double ell,
-                               double c, double *coef, double *bbar, void *Dk, void *Dder,
-                               double *minb_out, hipStream_t s)
+hipError_t launch_window_coef(int N, int m, double *cinv2, hipStream_t s)
 {
+    k_window_coef<<<1, 256, 0, s>>>(N, m, kb_beta(), cinv2);
+    return hipGetLastError();
+}
+
+hipError_t launch_coefficients(int prec, const WindowGeom &g, int m, int kernel, double ell,
+                               double c, const double *cinv2, double *coef, double *bbar, void *Dk,
+                               void *Dder, double *minb_out, hipStream_t s)
+{
+    (void)m;
     int64_t K = 1, KD = 1;
     for (int q = 0; q < g.d; ++q) {
         K *= g.N;
@@ -180,10 +199,10 @@ hipError_t launch_coefficients(int prec, const WindowGeom &g, int m, int kernel,
     int64_t nthr = KD > K ? KD : K;
     if (prec == NFFTGP_F32)
         k_make_diag<float><<<(unsigned)((nthr + 255) / 256), 256, 0, s>>>(
-            g.d, g.N, m, kb_beta(), a, bbar, (float *)Dk, (float *)Dder);
+            g.d, g.N, cinv2, a, bbar, (float *)Dk, (float *)Dder);
     else
         k_make_diag<double><<<(unsigned)((nthr + 255) / 256), 256, 0, s>>>(
-            g.d, g.N, m, kb_beta(), a, bbar, (double *)Dk, (double *)Dder);
+            g.d, g.N, cinv2, a, bbar, (double *)Dk, (double *)Dder);
     k_min2<<<1, 1024, 0, s>>>(bbar, K, minb_out);
     return hipGetLastError();
 }

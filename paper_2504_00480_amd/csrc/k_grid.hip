@@ -26,47 +26,6 @@ template <typename T> struct Cplx;
 template <> struct Cplx<float> { using type = float2; };
 template <> struct Cplx<double> { using type = double2; };
 
-template <typename T, int M>
-__device__ __forceinline__ T kb_psi(T t, T beta, T knorm)
-{
-    T s2 = T(M * M) - t * t;
-    s2 = s2 > T(0) ? s2 : T(0);
-    T s = sqrt(s2);
-    T z = beta * s;
-    T r;
-    if (z < T(1e-3)) {
-        r = beta * (T(1) + z * z * T(1.0 / 6.0));
-    } else {
-        r = T(0.5) * (expm1(z) - expm1(-z)) / s;
-    }
-    return r * knorm;
-}
-
-__device__ __forceinline__ float rdlane(float v, int l)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-__device__ __forceinline__ double rdlane(double v, int l)
-{
-    long long b = __double_as_longlong(v);
-    int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
-    int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
-
-__device__ __forceinline__ float bperm(float v, int l)
-{
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(l << 2, __float_as_int(v)));
-}
-__device__ __forceinline__ double bperm(double v, int l)
-{
-    long long b = __double_as_longlong(v);
-    int lo = __builtin_amdgcn_ds_bpermute(l << 2, (int)(b & 0xffffffffLL));
-    int hi = __builtin_amdgcn_ds_bpermute(l << 2, (int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 template <int D>
 __device__ __forceinline__ void bin_origin(int bin, int nb, int tb, int *org)
 {
@@ -78,100 +37,194 @@ __device__ __forceinline__ void bin_origin(int bin, int nb, int tb, int *org)
 }
 
 // ---------------------------------------------------------------- spreading
-template <typename T, int D, int M, int W>
-__global__ void __launch_bounds__(W * 64)
-k_spread(const T *__restrict__ ts, int64_t n, const int *__restrict__ perm,
-         const T *__restrict__ V, int64_t ldv, int nrhs, const int *__restrict__ sub_bin,
-         const int *__restrict__ sub_start, const int *__restrict__ sub_count, int tb, int nb,
-         T beta, T knorm, T *__restrict__ tilebuf)
+// One work-group of W waves per subproblem and chunk of R vectors.  Points
+// arrive sorted by cell inside their tile, so consecutive points often share
+// the cell floor(t) and therefore all (2m)^d target cells.  Contributions of
+// such a run are accumulated in registers: for d = 3, lane (b, c) of a wave
+// owns the tap column (b, c) and keeps values along the first dimension; for
+// d = 2 a lane owns tap (a, b), for d = 1 tap a.  The run is added to the
+// LDS tile once, after its last point.  The W waves of a group walk the same
+// points and share one tile: wave w handles the first-dimension taps whose
+// absolute cell index is w modulo W, so no two waves ever touch the same
+// cell.  Within a flush every lane touches a distinct cell and the flushes of
+// one wave are ordered, so the tile is updated with plain loads and stores
+// and the result does not depend on scheduling.
+template <typename T, int D, int M, int R, int W>
+__global__ void __launch_bounds__(64 * W)
+k_spread(const T *__restrict__ rec, const int *__restrict__ anchor, const T *__restrict__ vs,
+         int nrhs, const int *__restrict__ sub_bin, const int *__restrict__ sub_start,
+         const int *__restrict__ sub_count, int tb, int nb, int ng, T *__restrict__ tilebuf)
 {
     constexpr int TW = 2 * M;
-    constexpr int PW = 64 / TW;
+    constexpr int RS = D * TW;                                  // weights per point
+    constexpr int NITEM = D == 1 ? TW : TW * TW;                // lane work items
+    constexpr int NG = (NITEM + 63) / 64;
+    static_assert(D == 3 || W == 1, "tap splitting across waves is for d = 3");
+    static_assert(TW % W == 0, "waves must divide the taps");
+    constexpr int NA = D == 3 ? TW / W : 1;                     // registers per item
+    constexpr int CH = 64;                                      // points staged per chunk
+    // point data of one chunk, staged with coalesced loads so that the loop
+    // over points reads LDS instead of waiting on global memory per point
+    __shared__ T s_rec[CH * RS];
+    __shared__ T s_v[CH * R];
+    __shared__ int s_an[CH];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *tiles = reinterpret_cast<T *>(smem_raw);
     const int pd = tb + 2 * M;
     int pc = pd;
     for (int q = 1; q < D; ++q) pc *= pd;
-    const int sq = blockIdx.x, r = blockIdx.y;
+    const int sq = blockIdx.x, r0 = blockIdx.y * R;
     const int start = sub_start[sq], cnt = sub_count[sq];
+    const int end = start + cnt;
     int org[3] = {0, 0, 0};
     bin_origin<D>(sub_bin[sq], nb, tb, org);
-    for (int i = threadIdx.x; i < W * pc; i += blockDim.x) tiles[i] = T(0);
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    T *my = tiles + wave * pc;
-    const int pt = lane / TW, a = lane % TW;
-    for (int base = wave * PW; base < cnt; base += W * PW) {
-        const bool valid = (pt < PW) && (base + pt < cnt);
-        T w[D];
-        int anc[D];
-        T v = T(0);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < R * pc; i += 64 * W) tiles[i] = T(0);
+    int i0[NG], i1[NG];
+    bool act[NG];
 #pragma unroll
-        for (int q = 0; q < D; ++q) {
-            w[q] = T(0);
-            anc[q] = 0;
-        }
-        if (valid) {
-            const int64_t j = start + base + pt;
+    for (int g = 0; g < NG; ++g) {
+        const int it = lane + 64 * g;
+        act[g] = it < NITEM;
+        const int itc = act[g] ? it : 0;
+        i0[g] = D == 1 ? itc : itc / TW;
+        i1[g] = D == 1 ? 0 : itc % TW;
+    }
+    T acc[NG][NA][R];
 #pragma unroll
-            for (int q = 0; q < D; ++q) {
-                T t = ts[(int64_t)q * n + j];
-                T fl = floor(t);
-                anc[q] = (int)fl - org[q] + 1;   // local index of the first tap
-                w[q] = kb_psi<T, M>(t - (fl - T(M - 1) + T(a)), beta, knorm);
-            }
-            v = V[(int64_t)perm[j] * ldv + r];
-        }
-        if (D == 1) {
-            if (valid) atomicAdd(my + anc[0] + a, w[0] * v);
-            continue;
-        }
-        const int npts = min(PW, cnt - base);
-        for (int p = 0; p < npts; ++p) {
-            const int src = p * TW;
-            const int A0 = rdlane(anc[0], src);
-            const int A1 = rdlane(anc[D > 1 ? 1 : 0], src);
-            const int A2 = rdlane(anc[D > 2 ? 2 : 0], src);
-            const T vp = rdlane(v, src);
-            if (D == 2) {
+    for (int g = 0; g < NG; ++g)
 #pragma unroll
-                for (int it = 0; it < (TW * TW + 63) / 64; ++it) {
-                    const int tau = lane + 64 * it;
-                    const int ta = min(tau / TW, TW - 1), tbb = tau % TW;
-                    const T w0 = bperm(w[0], src + ta);
-                    const T w1 = bperm(w[D > 1 ? 1 : 0], src + tbb);
-                    if (tau < TW * TW) atomicAdd(my + (A0 + ta) * pd + (A1 + tbb), w0 * w1 * vp);
+        for (int k = 0; k < NA; ++k)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[g][k][r] = T(0);
+    const int nr = min(R, nrhs - r0);
+    // first owned tap of the current run along dimension 0 (d = 3)
+    int aoff = 0;
+    if (D == 3 && cnt > 0) {
+        const int c0 = (anchor[start] & 0x7fffffff) / (ng * ng);
+        aoff = ((wave - (c0 - M + 1)) % W + W) % W;
+    }
+    for (int cb = start; cb < end; cb += CH) {
+        const int nc = min(CH, end - cb);
+        __syncthreads();   // tiles cleared / previous chunk consumed
+        for (int i = tid; i < nc * RS; i += 64 * W) s_rec[i] = rec[(int64_t)cb * RS + i];
+        for (int i = tid; i < nc * R; i += 64 * W) {
+            const int u = i / R, r = i % R;
+            s_v[i] = r < nr ? vs[(int64_t)(cb + u) * nrhs + r0 + r] : T(0);
+        }
+        for (int i = tid; i < nc; i += 64 * W) s_an[i] = anchor[cb + i];
+        __syncthreads();
+        for (int u = 0; u < nc; ++u) {
+            const int an = s_an[u];
+            const T *rp = s_rec + u * RS;
+            T vr[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) vr[r] = s_v[u * R + r];
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                if (D == 3) {
+                    const T wbc = rp[TW + i0[g]] * rp[2 * TW + i1[g]];
+                    T z[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) z[r] = wbc * vr[r];
+#pragma unroll
+                    for (int k = 0; k < NA; ++k) {
+                        const T w0 = rp[aoff + k * W];
+#pragma unroll
+                        for (int r = 0; r < R; ++r) acc[g][k][r] += w0 * z[r];
+                    }
+                } else if (D == 2) {
+                    const T w = rp[i0[g]] * rp[TW + i1[g]];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[g][0][r] += w * vr[r];
+                } else {
+                    const T w = rp[i0[g]];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[g][0][r] += w * vr[r];
                 }
-            } else {
+            }
+            const int p = cb + u;
+            const bool last = p == end - 1;
+            if (an < 0 || last) {
+                // first-tap position of the run's cell inside the padded tile
+                int cell = an & 0x7fffffff, L[3] = {0, 0, 0};
+                for (int q = D - 1; q >= 0; --q) {
+                    L[q] = cell % ng - org[q] + 1;
+                    cell /= ng;
+                }
 #pragma unroll
-                for (int it = 0; it < (TW * TW + 63) / 64; ++it) {
-                    const int pi = lane + 64 * it;
-                    const int tbb = min(pi / TW, TW - 1), tc = pi % TW;
-                    const T w1 = bperm(w[D > 1 ? 1 : 0], src + tbb);
-                    const T w2 = bperm(w[D > 2 ? 2 : 0], src + tc);
-                    const T wbc = w1 * w2 * vp;
-                    if (pi < TW * TW) {
-                        T *col = my + (A1 + tbb) * pd + (A2 + tc) + A0 * pd * pd;
+                for (int g = 0; g < NG; ++g) {
+                    if (act[g]) {
 #pragma unroll
-                        for (int aa = 0; aa < TW; ++aa) {
-                            const T w0 = rdlane(w[0], src + aa);
-                            atomicAdd(col + aa * pd * pd, w0 * wbc);
+                        for (int k = 0; k < NA; ++k) {
+                            int idx;
+                            if (D == 3) idx = ((L[0] + aoff + k * W) * pd + L[1] + i0[g]) * pd + L[2] + i1[g];
+                            else if (D == 2) idx = (L[0] + i0[g]) * pd + L[1] + i1[g];
+                            else idx = L[0] + i0[g];
+#pragma unroll
+                            for (int r = 0; r < R; ++r) {
+                                tiles[r * pc + idx] += acc[g][k][r];
+                                acc[g][k][r] = T(0);
+                            }
                         }
                     }
                 }
+                if (D == 3 && !last) {
+                    const int na = u + 1 < nc ? s_an[u + 1] : anchor[p + 1];
+                    const int c0 = (na & 0x7fffffff) / (ng * ng);
+                    aoff = ((wave - (c0 - M + 1)) % W + W) % W;
+                }
             }
         }
     }
     __syncthreads();
-    T *out = tilebuf + ((int64_t)sq * nrhs + r) * pc;
-    for (int i = threadIdx.x; i < pc; i += blockDim.x) {
-        T s = tiles[i];
-        for (int c = 1; c < W; ++c) s += tiles[c * pc + i];
-        out[i] = s;
+    for (int r = 0; r < nr; ++r) {
+        T *out = tilebuf + ((int64_t)sq * nrhs + r0 + r) * pc;
+        for (int i = tid; i < pc; i += 64 * W) out[i] = tiles[r * pc + i];
     }
 }
 
+// Vectors in the window's sorted point order (vs[j][r] = V[perm[j]][r]).
+template <typename T>
+__global__ void k_gather(const T *__restrict__ V, int64_t ldv, const int *__restrict__ perm,
+                         int64_t n, int nrhs, T *__restrict__ vs)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * nrhs) return;
+    int64_t j = idx / nrhs;
+    int r = (int)(idx % nrhs);
+    vs[idx] = V[(int64_t)perm[j] * ldv + r];
+}
+
 // ---------------------------------------------------------------- fold
+// Phase 1: the subproblems of one tile are summed into the first one's slot
+// (in place, one thread per tile cell and vector, fixed order).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fold_bins(T *__restrict__ tilebuf, const int *__restrict__ bin_sub_ptr, int nrhs, int pc)
+{
+    // 64 cells per block and 4 slices of the subproblem list per cell; the
+    // slices are combined in a fixed order through LDS
+    __shared__ T part[4][64];
+    const int bin = blockIdx.y, r = blockIdx.z;
+    const int s0 = bin_sub_ptr[bin], s1 = bin_sub_ptr[bin + 1];
+    if (s1 - s0 < 2) return;
+    const int ci = threadIdx.x & 63, slice = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + ci;
+    T sum = T(0);
+    if (i < pc) {
+        for (int s = s0 + 1 + slice; s < s1; s += 4) sum += tilebuf[((int64_t)s * nrhs + r) * pc + i];
+    }
+    part[slice][ci] = sum;
+    __syncthreads();
+    if (slice == 0 && i < pc) {
+        T *dst = tilebuf + ((int64_t)s0 * nrhs + r) * pc;
+        dst[i] = dst[i] + ((part[0][ci] + part[1][ci]) + (part[2][ci] + part[3][ci]));
+    }
+}
+
+// Phase 2: every grid cell sums the (at most 3^d) tiles whose padded region
+// covers it.
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
 k_fold(const T *__restrict__ tilebuf, const int *__restrict__ bin_sub_ptr, int nrhs, int tb,
@@ -207,8 +260,8 @@ k_fold(const T *__restrict__ tilebuf, const int *__restrict__ bin_sub_ptr, int n
                     bin = bin * nb + b2;
                     li = li * pd + (l[2] - b2 * tb + m);
                 }
-                for (int s = bin_sub_ptr[bin]; s < bin_sub_ptr[bin + 1]; ++s)
-                    sum += tilebuf[((int64_t)s * nrhs + r) * pc + li];
+                const int s0 = bin_sub_ptr[bin];
+                if (bin_sub_ptr[bin + 1] > s0) sum += tilebuf[((int64_t)s0 * nrhs + r) * pc + li];
             }
     typename Cplx<T>::type o;
     o.x = sum;
@@ -217,68 +270,74 @@ k_fold(const T *__restrict__ tilebuf, const int *__restrict__ bin_sub_ptr, int n
 }
 
 // ---------------------------------------------------------------- interpolation
+// One thread per point (subproblems of at most 256 points of one tile).  The
+// padded tile of the grid (and of the derivative grid) is staged in LDS for
+// one vector at a time; the point's window weights are loaded once and reused
+// for every vector.  Results are added to the window sum with Kahan
+// compensation (deterministic: one thread owns each output entry).
 template <typename T, int D, int M, bool DER>
 __global__ void __launch_bounds__(256)
-k_interp(const T *__restrict__ ts, int64_t n, const int *__restrict__ perm,
+k_interp(const T *__restrict__ rec, const int *__restrict__ anchor, const int *__restrict__ perm,
          const int *__restrict__ sub_bin, const int *__restrict__ sub_start,
-         const int *__restrict__ sub_count, int tb, int nb, int ng, T beta, T knorm,
+         const int *__restrict__ sub_count, int tb, int nb, int ng,
          const typename Cplx<T>::type *__restrict__ gridK,
          const typename Cplx<T>::type *__restrict__ gridD, int64_t cells, int nrhs,
-         T *__restrict__ acc, T *__restrict__ comp, T *__restrict__ dout, T dscale)
+         T *__restrict__ acc, T *__restrict__ comp, T *__restrict__ dout, int64_t dstride, T dscale)
 {
     constexpr int TW = 2 * M;
+    constexpr int RS = D * TW;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *tK = reinterpret_cast<T *>(smem_raw);
     const int pd = tb + 2 * M;
     int pc = pd;
     for (int q = 1; q < D; ++q) pc *= pd;
     T *tD = tK + pc;
-    const int sq = blockIdx.x, r = blockIdx.y;
+    const int sq = blockIdx.x;
     const int start = sub_start[sq], cnt = sub_count[sq];
     int org[3] = {0, 0, 0};
     bin_origin<D>(sub_bin[sq], nb, tb, org);
-    const typename Cplx<T>::type *gK = gridK + (int64_t)r * cells;
-    const typename Cplx<T>::type *gD = DER ? gridD + (int64_t)r * cells : nullptr;
-    for (int i = threadIdx.x; i < pc; i += blockDim.x) {
-        int rem = i, loc[3] = {0, 0, 0};
+    const bool mine = (int)threadIdx.x < cnt;
+    const int64_t j = start + (mine ? (int)threadIdx.x : 0);
+    // weights and first-tap position of this thread's point; for d = 3 the
+    // first dimension's weights are re-read inside its (rolled) loop so that no
+    // register array is indexed by a loop variable
+    T w[D][TW];
+    const T *rp = rec + j * RS;
+#pragma unroll
+    for (int q = (D == 3 ? 1 : 0); q < D; ++q)
+#pragma unroll
+        for (int a = 0; a < TW; ++a) w[q][a] = rp[q * TW + a];
+    int A[3] = {0, 0, 0};
+    {
+        int cell = anchor[j] & 0x7fffffff;
         for (int q = D - 1; q >= 0; --q) {
-            loc[q] = rem % pd;
-            rem /= pd;
+            A[q] = cell % ng - org[q] + 1;
+            cell /= ng;
         }
-        bool in = true;
-        int64_t g = 0;
-        for (int q = 0; q < D; ++q) {
-            int l = org[q] - M + loc[q];
-            in = in && (l >= 0) && (l < ng);
-            g = g * ng + l;
-        }
-        tK[i] = in ? gK[g].x : T(0);
-        if (DER) tD[i] = in ? gD[g].x : T(0);
     }
-    __syncthreads();
-    for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
-        const int64_t j = start + p;
-        // per-dimension window weights; for d = 3 the first dimension's weights
-        // are evaluated inside its loop so that no register array is indexed
-        // by a loop variable
-        T w[D][TW];
-        T t0 = T(0), fl0 = T(0);
-        int A[3] = {0, 0, 0};
-#pragma unroll
-        for (int q = 0; q < D; ++q) {
-            T t = ts[(int64_t)q * n + j];
-            T fl = floor(t);
-            A[q] = (int)fl - org[q] + 1;
-            if (q == 0) {
-                t0 = t;
-                fl0 = fl;
+    const int64_t orow = (int64_t)perm[j] * nrhs;
+    for (int r = 0; r < nrhs; ++r) {
+        const typename Cplx<T>::type *gK = gridK + (int64_t)r * cells;
+        const typename Cplx<T>::type *gD = DER ? gridD + (int64_t)r * cells : nullptr;
+        if (r > 0) __syncthreads();
+        for (int i = threadIdx.x; i < pc; i += blockDim.x) {
+            int rem = i, loc[3] = {0, 0, 0};
+            for (int q = D - 1; q >= 0; --q) {
+                loc[q] = rem % pd;
+                rem /= pd;
             }
-            if (D < 3 || q > 0) {
-#pragma unroll
-                for (int aa = 0; aa < TW; ++aa)
-                    w[q][aa] = kb_psi<T, M>(t - (fl - T(M - 1) + T(aa)), beta, knorm);
+            bool in = true;
+            int64_t g = 0;
+            for (int q = 0; q < D; ++q) {
+                int l = org[q] - M + loc[q];
+                in = in && (l >= 0) && (l < ng);
+                g = g * ng + l;
             }
+            tK[i] = in ? gK[g].x : T(0);
+            if (DER) tD[i] = in ? gD[g].x : T(0);
         }
+        __syncthreads();
+        if (!mine) continue;
         T hK = T(0), hD = T(0);
         if (D == 1) {
 #pragma unroll
@@ -302,7 +361,7 @@ k_interp(const T *__restrict__ ts, int64_t n, const int *__restrict__ perm,
         } else {
 #pragma unroll 1
             for (int aa = 0; aa < TW; ++aa) {
-                const T w0 = kb_psi<T, M>(t0 - (fl0 - T(M - 1) + T(aa)), beta, knorm);
+                const T w0 = rp[aa];
                 T sK = T(0), sD = T(0);
 #pragma unroll
                 for (int bb = 0; bb < TW; ++bb) {
@@ -320,7 +379,7 @@ k_interp(const T *__restrict__ ts, int64_t n, const int *__restrict__ perm,
                 if (DER) hD += sD * w0;
             }
         }
-        const int64_t o = (int64_t)perm[j] * nrhs + r;
+        const int64_t o = orow + r;
         // compensated sum over windows (Kahan)
         T s0 = acc[o];
         T y = hK - comp[o];
@@ -329,6 +388,7 @@ k_interp(const T *__restrict__ ts, int64_t n, const int *__restrict__ perm,
         acc[o] = s1;
         if (DER) dout[o] = dscale * hD;
     }
+    (void)dstride;
 }
 
 template <typename T>
@@ -355,6 +415,8 @@ __global__ void k_assemble(int64_t n, int nrhs, const T *__restrict__ V, int64_t
     if (dse) dse[idx] = two_se * v;
 }
 
+}  // namespace
+
 // Normalisation 1 / (pi I_0(m b)) of psi, evaluated on the host in FP64.
 double kb_knorm(int m)
 {
@@ -367,6 +429,8 @@ double kb_knorm(int m)
     return 1.0 / (kPi * sum);
 }
 
+namespace {
+
 // Kernels that need more than 64 KiB of dynamic LDS must say so before launch.
 template <typename K>
 hipError_t allow_lds(K kernel, size_t bytes)
@@ -376,30 +440,31 @@ hipError_t allow_lds(K kernel, size_t bytes)
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <typename T, int D, int M>
-hipError_t spread_dm(const Window &w, int64_t n, const void *V, int64_t ldv, int nrhs,
-                     void *tilebuf, hipStream_t s)
+template <typename T, int D, int M, int R, int W>
+hipError_t spread_launch(const Window &w, const void *vs, int nrhs, void *tilebuf, hipStream_t s)
 {
     const WindowGeom &g = w.g;
-    size_t tile_bytes = (size_t)g.pc * sizeof(T);
-    dim3 grid((unsigned)w.nsub, (unsigned)nrhs);
-    T beta = (T)kb_beta(), knorm = (T)kb_knorm(M);
-    if (4 * tile_bytes <= 64 * 1024) {
-        k_spread<T, D, M, 4><<<grid, 256, 4 * tile_bytes, s>>>(
-            (const T *)w.t_sorted, n, w.perm, (const T *)V, ldv, nrhs, w.sub_bin, w.sub_start,
-            w.sub_count, g.tb, g.nb, beta, knorm, (T *)tilebuf);
-    } else if (2 * tile_bytes <= 64 * 1024) {
-        k_spread<T, D, M, 2><<<grid, 128, 2 * tile_bytes, s>>>(
-            (const T *)w.t_sorted, n, w.perm, (const T *)V, ldv, nrhs, w.sub_bin, w.sub_start,
-            w.sub_count, g.tb, g.nb, beta, knorm, (T *)tilebuf);
-    } else {
-        hipError_t e = allow_lds(k_spread<T, D, M, 1>, tile_bytes);
-        if (e != hipSuccess) return e;
-        k_spread<T, D, M, 1><<<grid, 64, tile_bytes, s>>>(
-            (const T *)w.t_sorted, n, w.perm, (const T *)V, ldv, nrhs, w.sub_bin, w.sub_start,
-            w.sub_count, g.tb, g.nb, beta, knorm, (T *)tilebuf);
-    }
+    const size_t shm = (size_t)g.pc * sizeof(T) * R;
+    hipError_t e = allow_lds(k_spread<T, D, M, R, W>, shm);
+    if (e != hipSuccess) return e;
+    dim3 grid((unsigned)w.nsub, (unsigned)((nrhs + R - 1) / R));
+    k_spread<T, D, M, R, W><<<grid, 64 * W, shm, s>>>(
+        (const T *)w.rec, w.anchor, (const T *)vs, nrhs, w.sub_bin, w.sub_start, w.sub_count, g.tb,
+        g.nb, g.ng, (T *)tilebuf);
     return hipGetLastError();
+}
+
+template <typename T, int D, int M>
+hipError_t spread_dm(const Window &w, int64_t n, const void *vs, int nrhs, void *tilebuf,
+                     hipStream_t s)
+{
+    (void)n;
+    // d = 3: 4 waves share a tile (2m taps split 4 ways: m = 2, 4, 6, 8 -> 1, 2, 3, 4
+    // each); two vectors per group when the two tiles stay within 40 KiB
+    constexpr int Wv = D == 3 ? 4 : 1;
+    if (nrhs >= 2 && 2 * (size_t)w.g.pc * sizeof(T) <= 40 * 1024)
+        return spread_launch<T, D, M, 2, Wv>(w, vs, nrhs, tilebuf, s);
+    return spread_launch<T, D, M, 1, Wv>(w, vs, nrhs, tilebuf, s);
 }
 
 template <typename T, int D, int M>
@@ -410,19 +475,18 @@ hipError_t interp_dm(const Window &w, int64_t n, int nrhs, const void *grid, boo
     using C = typename Cplx<T>::type;
     const C *gK = (const C *)grid;
     const C *gD = gK + (int64_t)nrhs * g.cells;
-    dim3 grd((unsigned)w.nsub, (unsigned)nrhs);
-    T beta = (T)kb_beta(), knorm = (T)kb_knorm(M);
     size_t shm = (size_t)g.pc * sizeof(T) * (with_der ? 2 : 1);
     hipError_t e = with_der ? allow_lds(k_interp<T, D, M, true>, shm) : allow_lds(k_interp<T, D, M, false>, shm);
     if (e != hipSuccess) return e;
     if (with_der)
-        k_interp<T, D, M, true><<<grd, 256, shm, s>>>(
-            (const T *)w.t_sorted, n, w.perm, w.sub_bin, w.sub_start, w.sub_count, g.tb, g.nb, g.ng,
-            beta, knorm, gK, gD, g.cells, nrhs, (T *)acc, (T *)comp, (T *)dout, (T)dscale);
+        k_interp<T, D, M, true><<<(unsigned)w.nisub, 256, shm, s>>>(
+            (const T *)w.rec, w.anchor, w.perm, w.isub_bin, w.isub_start, w.isub_count, g.tb, g.nb,
+            g.ng, gK, gD, g.cells, nrhs, (T *)acc, (T *)comp, (T *)dout, 0, (T)dscale);
     else
-        k_interp<T, D, M, false><<<grd, 256, shm, s>>>(
-            (const T *)w.t_sorted, n, w.perm, w.sub_bin, w.sub_start, w.sub_count, g.tb, g.nb, g.ng,
-            beta, knorm, gK, nullptr, g.cells, nrhs, (T *)acc, (T *)comp, nullptr, (T)dscale);
+        k_interp<T, D, M, false><<<(unsigned)w.nisub, 256, shm, s>>>(
+            (const T *)w.rec, w.anchor, w.perm, w.isub_bin, w.isub_start, w.isub_count, g.tb, g.nb,
+            g.ng, gK, nullptr, g.cells, nrhs, (T *)acc, (T *)comp, nullptr, 0, (T)dscale);
+    (void)n;
     return hipGetLastError();
 }
 
@@ -437,12 +501,14 @@ hipError_t interp_dm(const Window &w, int64_t n, int nrhs, const void *grid, boo
 
 template <typename T>
 hipError_t spread_t(const Window &w, int m, int64_t n, const void *V, int64_t ldv, int nrhs,
-                    void *tilebuf, hipStream_t s)
+                    void *vs, void *tilebuf, hipStream_t s)
 {
+    const int64_t tot = n * nrhs;
+    k_gather<T><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>((const T *)V, ldv, w.perm, n, nrhs, (T *)vs);
     switch (w.g.d) {
-    case 1: NFFTGP_DISPATCH_DM(spread_dm, T, 1, m, w, n, V, ldv, nrhs, tilebuf, s)
-    case 2: NFFTGP_DISPATCH_DM(spread_dm, T, 2, m, w, n, V, ldv, nrhs, tilebuf, s)
-    case 3: NFFTGP_DISPATCH_DM(spread_dm, T, 3, m, w, n, V, ldv, nrhs, tilebuf, s)
+    case 1: NFFTGP_DISPATCH_DM(spread_dm, T, 1, m, w, n, vs, nrhs, tilebuf, s)
+    case 2: NFFTGP_DISPATCH_DM(spread_dm, T, 2, m, w, n, vs, nrhs, tilebuf, s)
+    case 3: NFFTGP_DISPATCH_DM(spread_dm, T, 3, m, w, n, vs, nrhs, tilebuf, s)
     default: return hipErrorInvalidValue;
     }
 }
@@ -460,10 +526,13 @@ hipError_t interp_t(const Window &w, int m, int64_t n, int nrhs, const void *gri
 }
 
 template <typename T>
-hipError_t fold_t(const Window &w, int m, int nrhs, const void *tilebuf, void *grid, hipStream_t s)
+hipError_t fold_t(const Window &w, int m, int nrhs, void *tilebuf, void *grid, hipStream_t s)
 {
     const WindowGeom &g = w.g;
     using C = typename Cplx<T>::type;
+    if (w.nsub > w.nbins_used)
+        k_fold_bins<T><<<dim3((unsigned)((g.pc + 63) / 64), (unsigned)g.nbins, (unsigned)nrhs), 256, 0, s>>>(
+            (T *)tilebuf, w.bin_sub_ptr, nrhs, g.pc);
     int64_t tot = (int64_t)nrhs * g.cells;
     unsigned nblk = (unsigned)((tot + 255) / 256);
     switch (g.d) {
@@ -489,14 +558,14 @@ hipError_t launch_fill(int prec, void *p, int64_t count, hipStream_t s)
 }
 
 hipError_t launch_spread(int prec, const Window &w, int m, int64_t n, const void *V, int64_t ldv,
-                         int nrhs, void *tilebuf, hipStream_t s)
+                         int nrhs, void *vs, void *tilebuf, hipStream_t s)
 {
     if (w.nsub == 0) return hipSuccess;
-    return prec == NFFTGP_F32 ? spread_t<float>(w, m, n, V, ldv, nrhs, tilebuf, s)
-                              : spread_t<double>(w, m, n, V, ldv, nrhs, tilebuf, s);
+    return prec == NFFTGP_F32 ? spread_t<float>(w, m, n, V, ldv, nrhs, vs, tilebuf, s)
+                              : spread_t<double>(w, m, n, V, ldv, nrhs, vs, tilebuf, s);
 }
 
-hipError_t launch_fold(int prec, const Window &w, int m, int nrhs, const void *tilebuf, void *grid,
+hipError_t launch_fold(int prec, const Window &w, int m, int nrhs, void *tilebuf, void *grid,
                        hipStream_t s)
 {
     return prec == NFFTGP_F32 ? fold_t<float>(w, m, nrhs, tilebuf, grid, s)
@@ -507,7 +576,7 @@ hipError_t launch_interp(int prec, const Window &w, int m, int64_t n, int nrhs, 
                          bool with_der, void *acc, void *comp, void *dout, double dscale,
                          hipStream_t s)
 {
-    if (w.nsub == 0) return hipSuccess;
+    if (w.nisub == 0) return hipSuccess;
     return prec == NFFTGP_F32
                ? interp_t<float>(w, m, n, nrhs, grid, with_der, acc, comp, dout, dscale, s)
                : interp_t<double>(w, m, n, nrhs, grid, with_der, acc, comp, dout, dscale, s);

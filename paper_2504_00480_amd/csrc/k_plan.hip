@@ -79,10 +79,69 @@ k_coords(const T *__restrict__ X, int64_t n, int64_t ldx, int d, int f0, int f1,
         t_out[(int64_t)q * n + i] = t;
         int a = (int)floor((double)t);
         a = a < 0 ? 0 : (a > 2 * N - 1 ? 2 * N - 1 : a);
-        key = key * nb + a / tb;
+        key = key * tb + a % tb;   // cell inside its tile (first sort pass)
     }
     keys[i] = key;
     if (bad) atomicOr(boxflag, 1);
+    (void)nb;
+}
+
+// Tile ("bin") key of sorted coordinates (second sort pass).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_bin_keys(const T *__restrict__ t, int64_t n, int d, int ng, int tb, int nb, int *__restrict__ keys)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int key = 0;
+    for (int q = 0; q < d; ++q) {
+        int a = (int)floor((double)t[(int64_t)q * n + i]);
+        a = a < 0 ? 0 : (a > ng - 1 ? ng - 1 : a);
+        key = key * nb + a / tb;
+    }
+    keys[i] = key;
+}
+
+// Window weights of every sorted point, evaluated in FP64 from the stored
+// coordinate: record j holds psi(t_q - l) for the 2m taps l = floor(t_q)-m+1+a
+// of each dimension q (a = 0..2m-1), dimension-major.  anchor[j] packs the
+// cell floor(t) (row-major over the (2N)^d grid) and sets bit 31 when the
+// next point has another cell, so that spreading can flush per run of points.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_weights(const T *__restrict__ t, int64_t n, int d, int m, int ng, double beta, double knorm,
+          T *__restrict__ rec, int *__restrict__ anchor)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int tw = 2 * m;
+    int an = 0;
+    for (int q = 0; q < d; ++q) {
+        double tq = (double)t[(int64_t)q * n + i];
+        double fl = floor(tq);
+        an = an * ng + (int)fl;
+        for (int a = 0; a < tw; ++a) {
+            double u = tq - (fl - (m - 1) + a);
+            double s2 = (double)m * m - u * u;
+            s2 = s2 > 0.0 ? s2 : 0.0;
+            double sq = sqrt(s2), z = beta * sq;
+            double r = z < 1e-6 ? beta * (1.0 + z * z / 6.0) : sinh(z) / sq;
+            rec[(i * d + q) * tw + a] = (T)(r * knorm);
+        }
+    }
+    anchor[i] = an;
+}
+
+__global__ void __launch_bounds__(256)
+k_run_ends(int *__restrict__ anchor, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // each thread writes only its own entry; the neighbour may already carry
+    // its flag, so compare the cell bits only
+    const int a = anchor[i] & 0x7fffffff;
+    const bool last = (i == n - 1) || ((anchor[i + 1] & 0x7fffffff) != a);
+    if (last) anchor[i] = a | (int)0x80000000u;
 }
 
 // ---- stable counting sort ------------------------------------------------
@@ -169,8 +228,8 @@ k_scan_apply(int *__restrict__ data, int64_t len, const int *__restrict__ chunk_
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_scatter(const int *__restrict__ keys, int64_t n, int nbins, int nblk, int d,
-          const int *__restrict__ offs, const T *__restrict__ t_in, int *__restrict__ perm,
-          T *__restrict__ t_sorted)
+          const int *__restrict__ offs, const int *__restrict__ ids_in, const T *__restrict__ t_in,
+          int *__restrict__ perm, T *__restrict__ t_sorted)
 {
     extern __shared__ int sh[];
     int *cnt = sh;               // nbins
@@ -190,7 +249,7 @@ k_scatter(const int *__restrict__ keys, int64_t n, int nbins, int nblk, int d,
         __syncthreads();
         if (key >= 0) {
             atomicAdd(&cnt[key], 1);
-            perm[pos] = (int)i;
+            perm[pos] = ids_in ? ids_in[i] : (int)i;
             for (int q = 0; q < d; ++q) t_sorted[(int64_t)q * n + pos] = t_in[(int64_t)q * n + i];
         }
         __syncthreads();
@@ -242,9 +301,9 @@ hipError_t launch_coords(int prec, const void *X, int64_t n, int64_t ldx, int d,
 
 int64_t scan_scratch_ints(int64_t len) { return (len + 1023) / 1024 + 1; }
 
-hipError_t launch_sort(int prec, int64_t n, int d, int nbins, const int *keys, const void *t_in,
-                       int *hist, int *scan_tmp, int *perm, void *t_sorted, int *bin_start,
-                       hipStream_t s)
+hipError_t launch_sort(int prec, int64_t n, int d, int nbins, const int *keys, const int *ids_in,
+                       const void *t_in, int *hist, int *scan_tmp, int *perm, void *t_sorted,
+                       int *bin_start, hipStream_t s)
 {
     int nblk = (int)((n + kSortBlock - 1) / kSortBlock);
     if (nblk == 0) nblk = 1;
@@ -260,14 +319,41 @@ hipError_t launch_sort(int prec, int64_t n, int d, int nbins, const int *keys, c
     if (n > 0) {
         size_t shm = (nbins + 256) * sizeof(int);
         if (prec == NFFTGP_F32)
-            k_scatter<float><<<nblk, 256, shm, s>>>(keys, n, nbins, nblk, d, hist,
+            k_scatter<float><<<nblk, 256, shm, s>>>(keys, n, nbins, nblk, d, hist, ids_in,
                                                     (const float *)t_in, perm, (float *)t_sorted);
         else
-            k_scatter<double><<<nblk, 256, shm, s>>>(keys, n, nbins, nblk, d, hist,
+            k_scatter<double><<<nblk, 256, shm, s>>>(keys, n, nbins, nblk, d, hist, ids_in,
                                                      (const double *)t_in, perm,
                                                      (double *)t_sorted);
     }
     k_bin_start<<<(nbins + 1 + 255) / 256, 256, 0, s>>>(hist, nbins, nblk, n, bin_start);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_keys(int prec, const void *t, int64_t n, const WindowGeom &g, int *keys,
+                           hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    unsigned nblk = (unsigned)((n + 255) / 256);
+    if (prec == NFFTGP_F32)
+        k_bin_keys<float><<<nblk, 256, 0, s>>>((const float *)t, n, g.d, g.ng, g.tb, g.nb, keys);
+    else
+        k_bin_keys<double><<<nblk, 256, 0, s>>>((const double *)t, n, g.d, g.ng, g.tb, g.nb, keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_weights(int prec, const void *t, int64_t n, const WindowGeom &g, int m,
+                          double knorm, void *rec, int *anchor, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    unsigned nblk = (unsigned)((n + 255) / 256);
+    if (prec == NFFTGP_F32)
+        k_weights<float><<<nblk, 256, 0, s>>>((const float *)t, n, g.d, m, g.ng, kb_beta(), knorm,
+                                              (float *)rec, anchor);
+    else
+        k_weights<double><<<nblk, 256, 0, s>>>((const double *)t, n, g.d, m, g.ng, kb_beta(), knorm,
+                                               (double *)rec, anchor);
+    k_run_ends<<<nblk, 256, 0, s>>>(anchor, n);
     return hipGetLastError();
 }
 

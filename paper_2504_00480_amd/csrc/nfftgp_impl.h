@@ -21,8 +21,8 @@ constexpr double kSigma = 2.0;
 constexpr double kPi = 3.14159265358979323846264338327950288;
 inline double kb_beta() { return kPi * (2.0 - 1.0 / kSigma); }
 
-// Points handled by one spreading / interpolation work-group at most.
-constexpr int kMaxSubPoints = 1024;
+// Points handled by one interpolation work-group at most (one per thread).
+constexpr int kInterpSubPoints = 256;
 
 // Geometry of one window's oversampled grid and its tiling.
 struct WindowGeom {
@@ -47,13 +47,20 @@ struct Window {
     double ell = 1.0;
     double min_b = 0.0, min_bder = 0.0;
     // device data (owned)
-    void *t_sorted = nullptr;   // d arrays of n grid coordinates, sorted by bin
+    void *rec = nullptr;        // per sorted point: d x 2m window weights (plan precision)
+    int32_t *anchor = nullptr;  // per sorted point: packed cell floor(t); bit 31 = last of its run
     int32_t *perm = nullptr;    // sorted position -> original point index
+    // spreading subproblems (runs of points of one tile) and their CSR by tile
     int32_t *sub_bin = nullptr, *sub_start = nullptr, *sub_count = nullptr;
-    int32_t *bin_sub_ptr = nullptr;  // CSR bins -> subproblems (nbins + 1)
+    int32_t *bin_sub_ptr = nullptr;  // nbins + 1
     int nsub = 0;
+    int nbins_used = 0;              // tiles holding at least one point
+    // interpolation subproblems (at most kInterpSubPoints points of one tile)
+    int32_t *isub_bin = nullptr, *isub_start = nullptr, *isub_count = nullptr;
+    int nisub = 0;
     void *Dk = nullptr;     // symmetrised diagonal for K_s (dcells, plan precision)
     void *Dder = nullptr;   // same for K_s^der
+    double *cinv2 = nullptr;  // N+1 per-dimension factors 1 / c(k)^2 of the window
 };
 
 }  // namespace nfftgp
@@ -75,6 +82,7 @@ struct nfftgp_plan_s {
     void *tilebuf = nullptr;     // spreading tiles
     void *grid = nullptr;        // 2 x max_nrhs x max cells complex values
     void *acc = nullptr, *comp = nullptr;  // n x max_nrhs compensated window sum
+    void *vsort = nullptr;                 // n x max_nrhs vectors in a window's point order
     double *coef = nullptr;      // 4 x maxN^d complex doubles (set_hyper scratch)
     double *bbar = nullptr;      // 2 x maxN^d doubles
     double *minb = nullptr;      // 2 x P doubles
@@ -85,6 +93,12 @@ struct nfftgp_plan_s {
     void *cg_r = nullptr, *cg_p = nullptr, *cg_ap = nullptr;  // n x max_nrhs
     size_t bytes = 0;
     std::vector<void *> allocs;
+    // kernel timing (nfftgp_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<int> prof_cat;   // one entry per recorded launch: category
+    std::vector<int> prof_ev;    // index of its first event (second is +1)
 };
 
 namespace nfftgp {
@@ -119,21 +133,28 @@ hipError_t launch_coords(int prec, const void *X, int64_t n, int64_t ldx, int d,
 // scan_tmp: scan scratch; perm / t_sorted: outputs; bin_start: nbins + 1 ints.
 constexpr int kSortBlock = 4096;
 int64_t scan_scratch_ints(int64_t len);
-hipError_t launch_sort(int prec, int64_t n, int d, int nbins, const int *keys, const void *t_in,
-                       int *hist, int *scan_tmp, int *perm, void *t_sorted, int *bin_start,
-                       hipStream_t s);
+hipError_t launch_sort(int prec, int64_t n, int d, int nbins, const int *keys, const int *ids_in,
+                       const void *t_in, int *hist, int *scan_tmp, int *perm, void *t_sorted,
+                       int *bin_start, hipStream_t s);
+hipError_t launch_bin_keys(int prec, const void *t, int64_t n, const WindowGeom &g, int *keys,
+                           hipStream_t s);
+// Window weights and packed cells (with run-end flags) of the sorted points.
+double kb_knorm(int m);
+hipError_t launch_weights(int prec, const void *t, int64_t n, const WindowGeom &g, int m,
+                          double knorm, void *rec, int *anchor, hipStream_t s);
 
 // ---------------------------------------------------------------- per-theta kernels
 // Coefficients b_k, b^der_k of one window (FP64) and the symmetrised diagonals.
+hipError_t launch_window_coef(int N, int m, double *cinv2, hipStream_t s);
 hipError_t launch_coefficients(int prec, const WindowGeom &g, int m, int kernel, double ell,
-                               double c, double *coef, double *bbar, void *Dk, void *Dder,
-                               double *minb_out, hipStream_t s);
+                               double c, const double *cinv2, double *coef, double *bbar, void *Dk,
+                               void *Dder, double *minb_out, hipStream_t s);
 
 // ---------------------------------------------------------------- apply kernels
 hipError_t launch_fill(int prec, void *p, int64_t count, hipStream_t s);
 hipError_t launch_spread(int prec, const Window &w, int m, int64_t n, const void *V, int64_t ldv,
-                         int nrhs, void *tilebuf, hipStream_t s);
-hipError_t launch_fold(int prec, const Window &w, int m, int nrhs, const void *tilebuf, void *grid,
+                         int nrhs, void *vs, void *tilebuf, hipStream_t s);
+hipError_t launch_fold(int prec, const Window &w, int m, int nrhs, void *tilebuf, void *grid,
                        hipStream_t s);
 hipError_t launch_fft(int prec, const WindowGeom &g, void *grid, int batch, bool inverse,
                       hipStream_t s);

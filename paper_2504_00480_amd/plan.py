@@ -118,6 +118,17 @@ class AdditiveKernelPlan:
         return {"c0": c0[: d.value].copy(), "c": c.value, "d": d.value, "N": N.value,
                 "min_b": mb.value, "min_bder": mbd.value}
 
+    def profile(self, enable: bool = True):
+        """Start (or stop) per-category kernel timing with HIP events."""
+        _lib.check(_lib.load().nfftgp_profile(self._h, int(bool(enable))), "nfftgp_profile")
+
+    def profile_read(self) -> dict:
+        """{category: (total ms, launches)} since profiling was enabled."""
+        ms = np.zeros(len(_lib.PROF_NAMES))
+        cnt = np.zeros(len(_lib.PROF_NAMES), dtype=np.int32)
+        _lib.check(_lib.load().nfftgp_profile_read(self._h, _np_ptr(ms), _np_ptr(cnt)), "nfftgp_profile_read")
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(_lib.PROF_NAMES)}
+
     def workspace_bytes(self) -> int:
         b = ctypes.c_size_t()
         _lib.check(_lib.load().nfftgp_get_workspace_bytes(self._h, ctypes.byref(b)), "workspace")
