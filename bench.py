@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-derivs", action="store_true", help="time the K-only apply as the step")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 256 MiB device copy (counter calibration under a profiler)")
     return ap.parse_args()
 
 
@@ -131,6 +133,13 @@ def main():
     step()   # leave the derivative outputs of the timed configuration in place
     torch.cuda.synchronize()
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.4f} ms/step", file=sys.stderr, flush=True)
+    if args.calibrate_copy:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     # ---------------- roofline of the dominant kernel
     geoms = []
@@ -152,6 +161,7 @@ def main():
         "assemble": ("hbm", (2 + 2 + 1 + (2 if derivs else 0)) * n * nrhs * eb, "GB/s"),
         "coef": ("alu", 0.0, "TFLOP/s"),
         "fill": ("hbm", n * nrhs * eb, "GB/s"),
+        "gather": ("hbm", 2.0 * n * nrhs * eb + 4 * n, "GB/s"),
     }
     kern = {k: {"total_ms": v[0], "launches": v[1], "avg_us": (1e3 * v[0] / v[1]) if v[1] else 0.0}
             for k, v in prof.items() if v[1]}
@@ -172,7 +182,7 @@ def main():
             ent = tj.get(f"{args.workload}:{prec}:{dom}")
             srcs = {"spread": ["k_grid.hip"], "interp": ["k_grid.hip"], "fold": ["k_grid.hip"],
                     "fft_fwd": ["k_fft.hip"], "fft_inv": ["k_fft.hip"], "diag": ["k_fft.hip"],
-                    "assemble": ["k_grid.hip"], "fill": ["k_grid.hip"]}[dom]
+                    "assemble": ["k_grid.hip"], "fill": ["k_grid.hip"], "gather": ["k_grid.hip"]}[dom]
             if ent and ent.get("source_sha") == src_sha(*srcs):
                 traffic = ent["bytes_per_launch"]
         except Exception:

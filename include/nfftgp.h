@@ -186,7 +186,8 @@ enum {
     NFFTGP_PROF_ASSEMBLE = 7, /* sigma scaling and derivative blocks          */
     NFFTGP_PROF_COEF = 8,     /* per-theta coefficient kernels                */
     NFFTGP_PROF_CG = 9,       /* CG dot products and vector updates           */
-    NFFTGP_PROF_COUNT = 10
+    NFFTGP_PROF_GATHER = 10,  /* vectors gathered into a window's point order */
+    NFFTGP_PROF_COUNT = 11
 };
 nfftgp_status nfftgp_profile(nfftgp_plan plan, int32_t enable);
 nfftgp_status nfftgp_profile_read(nfftgp_plan plan, double *ms_host, int32_t *count_host);

@@ -25,7 +25,8 @@ E_NOCONV = -7
 SYMBOLS = ["nfftgp_plan_create", "nfftgp_set_hyper", "nfftgp_apply", "nfftgp_cg", "nfftgp_col_dots",
            "nfftgp_slq_logquad", "nfftgp_get_window_info", "nfftgp_get_workspace_bytes",
            "nfftgp_plan_destroy", "nfftgp_last_error", "nfftgp_profile", "nfftgp_profile_read"]
-PROF_NAMES = ["fill", "spread", "fold", "fft_fwd", "diag", "fft_inv", "interp", "assemble", "coef", "cg"]
+PROF_NAMES = ["fill", "spread", "fold", "fft_fwd", "diag", "fft_inv", "interp", "assemble", "coef", "cg",
+              "gather"]
 
 
 class NfftgpError(RuntimeError):

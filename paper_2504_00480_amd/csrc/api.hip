@@ -155,6 +155,7 @@ nfftgp_status apply_impl(nfftgp_plan p, const void *V, int64_t ldv, int nrhs, vo
     const size_t eb = prec_bytes(p->prec);
     for (int w = 0; w < p->P; ++w) {
         const Window &win = p->win[w];
+        PROF_LAUNCH(p, NFFTGP_PROF_GATHER, launch_gather(p->prec, win, p->n, V, ldv, nrhs, p->vsort, s));
         PROF_LAUNCH(p, NFFTGP_PROF_SPREAD,
                     launch_spread(p->prec, win, p->m, p->n, V, ldv, nrhs, p->vsort, p->tilebuf, s));
         PROF_LAUNCH(p, NFFTGP_PROF_FOLD, launch_fold(p->prec, win, p->m, nrhs, p->tilebuf, p->grid, s));

@@ -503,8 +503,8 @@ template <typename T>
 hipError_t spread_t(const Window &w, int m, int64_t n, const void *V, int64_t ldv, int nrhs,
                     void *vs, void *tilebuf, hipStream_t s)
 {
-    const int64_t tot = n * nrhs;
-    k_gather<T><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>((const T *)V, ldv, w.perm, n, nrhs, (T *)vs);
+    (void)V;
+    (void)ldv;
     switch (w.g.d) {
     case 1: NFFTGP_DISPATCH_DM(spread_dm, T, 1, m, w, n, vs, nrhs, tilebuf, s)
     case 2: NFFTGP_DISPATCH_DM(spread_dm, T, 2, m, w, n, vs, nrhs, tilebuf, s)
@@ -554,6 +554,20 @@ hipError_t launch_fill(int prec, void *p, int64_t count, hipStream_t s)
         k_fill<float><<<nblk, 256, 0, s>>>((float *)p, count);
     else
         k_fill<double><<<nblk, 256, 0, s>>>((double *)p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(int prec, const Window &w, int64_t n, const void *V, int64_t ldv, int nrhs,
+                         void *vs, hipStream_t s)
+{
+    const int64_t tot = n * nrhs;
+    if (tot == 0) return hipSuccess;
+    if (prec == NFFTGP_F32)
+        k_gather<float><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>((const float *)V, ldv, w.perm, n,
+                                                                        nrhs, (float *)vs);
+    else
+        k_gather<double><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>((const double *)V, ldv, w.perm, n,
+                                                                         nrhs, (double *)vs);
     return hipGetLastError();
 }
 

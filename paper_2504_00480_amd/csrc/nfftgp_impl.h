@@ -152,6 +152,8 @@ hipError_t launch_coefficients(int prec, const WindowGeom &g, int m, int kernel,
 
 // ---------------------------------------------------------------- apply kernels
 hipError_t launch_fill(int prec, void *p, int64_t count, hipStream_t s);
+hipError_t launch_gather(int prec, const Window &w, int64_t n, const void *V, int64_t ldv, int nrhs,
+                         void *vs, hipStream_t s);
 hipError_t launch_spread(int prec, const Window &w, int m, int64_t n, const void *V, int64_t ldv,
                          int nrhs, void *vs, void *tilebuf, hipStream_t s);
 hipError_t launch_fold(int prec, const Window &w, int m, int nrhs, void *tilebuf, void *grid,

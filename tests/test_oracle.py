@@ -132,7 +132,7 @@ def test_box_scaling_of_coefficients(orc, kt):
 @pytest.mark.parametrize("N", [16, 32])
 @pytest.mark.parametrize("ell", [0.05, 0.1, 0.2])
 def test_matern3d_error_within_theorems(orc, N, ell):
-    """Sec. 4.4 numerical check: with points uniform in [-1/4, 1/4)^3 the measured
+    """Sec. 4.3 numerical check: with points uniform in [-1/4, 1/4)^3 the measured
     sup |kappa - kappa_RF| (and for the derivative kernel) stays below the
     bounds of the two theorems of Sec. 4.2."""
     x = np.random.default_rng(5).uniform(-0.25, 0.25, size=(60, 3))
