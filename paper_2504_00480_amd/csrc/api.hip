@@ -148,29 +148,21 @@ nfftgp_status apply_impl(nfftgp_plan p, const void *V, int64_t ldv, int nrhs, vo
 {
     const hipStream_t s = p->stream;
     const bool with_der = dell != nullptr;
-    const int64_t tot = p->n * nrhs;
     if (p->n == 0) return NFFTGP_OK;
-    PROF_LAUNCH(p, NFFTGP_PROF_FILL, launch_fill(p->prec, p->acc, tot, s));
-    PROF_LAUNCH(p, NFFTGP_PROF_FILL, launch_fill(p->prec, p->comp, tot, s));
-    const size_t eb = prec_bytes(p->prec);
-    for (int w = 0; w < p->P; ++w) {
-        const Window &win = p->win[w];
-        PROF_LAUNCH(p, NFFTGP_PROF_GATHER, launch_gather(p->prec, win, p->n, V, ldv, nrhs, p->vsort, s));
-        PROF_LAUNCH(p, NFFTGP_PROF_SPREAD,
-                    launch_spread(p->prec, win, p->m, p->n, V, ldv, nrhs, p->vsort, p->tilebuf, s));
-        PROF_LAUNCH(p, NFFTGP_PROF_FOLD, launch_fold(p->prec, win, p->m, nrhs, p->tilebuf, p->grid, s));
-        PROF_LAUNCH(p, NFFTGP_PROF_FFT_FWD, launch_fft(p->prec, win.g, p->grid, nrhs, false, s));
-        PROF_LAUNCH(p, NFFTGP_PROF_DIAG, launch_diag(p->prec, win, nrhs, p->grid, with_der, s));
-        PROF_LAUNCH(p, NFFTGP_PROF_FFT_INV,
-                    launch_fft(p->prec, win.g, p->grid, nrhs * (with_der ? 2 : 1), true, s));
-        void *dout = with_der ? (void *)((char *)dell + (size_t)w * tot * eb) : nullptr;
+    for (const Group &G : p->groups) {
+        const int b = G.nwin * nrhs;
+        PROF_LAUNCH(p, NFFTGP_PROF_SPREAD, launch_spread(p->prec, G, p->m, V, ldv, nrhs, p->tilebuf, s));
+        PROF_LAUNCH(p, NFFTGP_PROF_FOLD, launch_fold(p->prec, G, p->m, nrhs, p->tilebuf, p->grid, s));
+        PROF_LAUNCH(p, NFFTGP_PROF_FFT_FWD, launch_fft(p->prec, G.g, p->grid, b, false, s));
+        PROF_LAUNCH(p, NFFTGP_PROF_DIAG, launch_diag(p->prec, G, nrhs, p->grid, with_der, s));
+        PROF_LAUNCH(p, NFFTGP_PROF_FFT_INV, launch_fft(p->prec, G.g, p->grid, b * (with_der ? 2 : 1), true, s));
         PROF_LAUNCH(p, NFFTGP_PROF_INTERP,
-                    launch_interp(p->prec, win, p->m, p->n, nrhs, p->grid, with_der, p->acc, p->comp,
-                                  dout, p->sigma_f * p->sigma_f, s));
+                    launch_interp(p->prec, G, p->m, p->n, nrhs, p->grid, with_der, p->hbuf, dell,
+                                  p->sigma_f * p->sigma_f, s));
     }
     PROF_LAUNCH(p, NFFTGP_PROF_ASSEMBLE,
-                launch_assemble(p->prec, p->n, nrhs, V, ldv, p->acc, p->comp, p->sigma_f,
-                                p->sigma_eps, KV, dsf, dse, s));
+                launch_assemble(p->prec, p->n, nrhs, p->P, V, ldv, p->hbuf, p->sigma_f, p->sigma_eps,
+                                KV, dsf, dse, s));
     return NFFTGP_OK;
 }
 
@@ -337,58 +329,80 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
             return fail(NFFTGP_E_BOX, "window " + std::to_string(s) +
                                           ": a scaled point lies outside [-1/4, 1/4)^d");
         }
-        // --- subproblems: runs of points of one tile
-        std::vector<int> sb, ss, sc, bsp(w.g.nbins + 1, 0), ib, is, ic;
-        w.nbins_used = 0;
-        for (int b = 0; b < w.g.nbins; ++b) {
-            int cnt = bs[b + 1] - bs[b];
-            w.nbins_used += cnt > 0;
-            for (int off = 0; off < cnt; off += sub_sp) {
-                sb.push_back(b);
-                ss.push_back(bs[b] + off);
-                sc.push_back(std::min(sub_sp, cnt - off));
-            }
-            bsp[b + 1] = (int)sb.size();
-            for (int off = 0; off < cnt; off += kInterpSubPoints) {
-                ib.push_back(b);
-                is.push_back(bs[b] + off);
-                ic.push_back(std::min(kInterpSubPoints, cnt - off));
-            }
-        }
-        w.nsub = (int)sb.size();
-        w.nisub = (int)ib.size();
-        TRYS(dalloc(plan, (void **)&w.sub_bin, std::max(1, w.nsub) * sizeof(int)));
-        TRYS(dalloc(plan, (void **)&w.sub_start, std::max(1, w.nsub) * sizeof(int)));
-        TRYS(dalloc(plan, (void **)&w.sub_count, std::max(1, w.nsub) * sizeof(int)));
-        TRYS(dalloc(plan, (void **)&w.bin_sub_ptr, (w.g.nbins + 1) * sizeof(int)));
-        TRYS(dalloc(plan, (void **)&w.isub_bin, std::max(1, w.nisub) * sizeof(int)));
-        TRYS(dalloc(plan, (void **)&w.isub_start, std::max(1, w.nisub) * sizeof(int)));
-        TRYS(dalloc(plan, (void **)&w.isub_count, std::max(1, w.nisub) * sizeof(int)));
-        if (w.nsub > 0) {
-            TRYH(hipMemcpy(w.sub_bin, sb.data(), w.nsub * sizeof(int), hipMemcpyHostToDevice));
-            TRYH(hipMemcpy(w.sub_start, ss.data(), w.nsub * sizeof(int), hipMemcpyHostToDevice));
-            TRYH(hipMemcpy(w.sub_count, sc.data(), w.nsub * sizeof(int), hipMemcpyHostToDevice));
-            TRYH(hipMemcpy(w.isub_bin, ib.data(), w.nisub * sizeof(int), hipMemcpyHostToDevice));
-            TRYH(hipMemcpy(w.isub_start, is.data(), w.nisub * sizeof(int), hipMemcpyHostToDevice));
-            TRYH(hipMemcpy(w.isub_count, ic.data(), w.nisub * sizeof(int), hipMemcpyHostToDevice));
-        }
-        TRYH(hipMemcpy(w.bin_sub_ptr, bsp.data(), (w.g.nbins + 1) * sizeof(int), hipMemcpyHostToDevice));
+        w.h_bin_start = bs;
         TRYS(dalloc(plan, &w.Dk, w.g.dcells * eb));
         TRYS(dalloc(plan, &w.Dder, w.g.dcells * eb));
         TRYS(dalloc(plan, (void **)&w.cinv2, (N[s] + 1) * sizeof(double)));
         TRYH(launch_window_coef(N[s], m, w.cinv2, st));
-        tile_need = std::max(tile_need, (size_t)w.nsub * w.g.pc);
-        max_cells = std::max(max_cells, w.g.cells);
         int64_t K = 1;
         for (int q = 0; q < d; ++q) K *= N[s];
         maxK = std::max(maxK, K);
     }
+    // --- window groups (equal dimension and bandwidth) and their work lists:
+    // spreading subproblems are runs of at most sub_sp points of one tile,
+    // interpolation subproblems runs of at most kInterpSubPoints
+    for (int s = 0; s < P; ++s) {
+        int gi = -1;
+        for (int k = 0; k < (int)plan->groups.size(); ++k)
+            if (plan->groups[k].g.d == plan->win[s].g.d && plan->groups[k].g.N == plan->win[s].g.N) gi = k;
+        if (gi < 0) {
+            plan->groups.emplace_back();
+            gi = (int)plan->groups.size() - 1;
+            plan->groups[gi].g = plan->win[s].g;
+        }
+        plan->groups[gi].wins.push_back(s);
+    }
+    size_t grid_need = 1;
+    for (Group &G : plan->groups) {
+        G.nwin = (int)G.wins.size();
+        std::vector<int> sw, sb, ss, sc, iw, ib, is, ic;
+        std::vector<WinDesc> hd(G.nwin);
+        for (int wl = 0; wl < G.nwin; ++wl) {
+            Window &w = plan->win[G.wins[wl]];
+            const std::vector<int> &bs = w.h_bin_start;
+            std::vector<int> bsp(w.g.nbins + 1, 0);
+            bsp[0] = (int)sb.size();
+            for (int b = 0; b < w.g.nbins; ++b) {
+                const int cnt = bs[b + 1] - bs[b];
+                G.nbins_used += cnt > 0;
+                for (int off = 0; off < cnt; off += sub_sp) {
+                    sw.push_back(wl);
+                    sb.push_back(b);
+                    ss.push_back(bs[b] + off);
+                    sc.push_back(std::min(sub_sp, cnt - off));
+                }
+                bsp[b + 1] = (int)sb.size();
+                for (int off = 0; off < cnt; off += kInterpSubPoints) {
+                    iw.push_back(wl);
+                    ib.push_back(b);
+                    is.push_back(bs[b] + off);
+                    ic.push_back(std::min(kInterpSubPoints, cnt - off));
+                }
+            }
+            TRYS(dalloc(plan, (void **)&w.bin_sub_ptr, (w.g.nbins + 1) * sizeof(int)));
+            TRYH(hipMemcpy(w.bin_sub_ptr, bsp.data(), (w.g.nbins + 1) * sizeof(int), hipMemcpyHostToDevice));
+            hd[wl] = WinDesc{w.rec, w.anchor, w.perm, w.bin_sub_ptr, w.Dk, w.Dder, G.wins[wl], 0};
+        }
+        G.nsub = (int)sb.size();
+        G.nisub = (int)ib.size();
+        int32_t **dst[8] = {&G.sub_win, &G.sub_bin, &G.sub_start, &G.sub_count,
+                            &G.isub_win, &G.isub_bin, &G.isub_start, &G.isub_count};
+        std::vector<int> *srcv[8] = {&sw, &sb, &ss, &sc, &iw, &ib, &is, &ic};
+        for (int k = 0; k < 8; ++k) {
+            TRYS(dalloc(plan, (void **)dst[k], std::max<size_t>(1, srcv[k]->size()) * sizeof(int)));
+            if (!srcv[k]->empty())
+                TRYH(hipMemcpy(*dst[k], srcv[k]->data(), srcv[k]->size() * sizeof(int), hipMemcpyHostToDevice));
+        }
+        TRYS(dalloc(plan, (void **)&G.desc, G.nwin * sizeof(WinDesc)));
+        TRYH(hipMemcpy(G.desc, hd.data(), G.nwin * sizeof(WinDesc), hipMemcpyHostToDevice));
+        tile_need = std::max(tile_need, (size_t)G.nsub * G.g.pc);
+        grid_need = std::max(grid_need, (size_t)2 * G.nwin * G.g.cells);
+    }
+    for (Window &w : plan->win) std::vector<int>().swap(w.h_bin_start);
     TRYS(dalloc(plan, &plan->tilebuf, std::max<size_t>(tile_need, 1) * max_nrhs * eb));
-    TRYS(dalloc(plan, &plan->grid, (size_t)max_cells * 2 * max_nrhs * 2 * eb));
+    TRYS(dalloc(plan, &plan->grid, grid_need * max_nrhs * 2 * eb));
     const size_t vec_bytes = std::max<int64_t>(n, 1) * max_nrhs * eb;
-    TRYS(dalloc(plan, &plan->acc, vec_bytes));
-    TRYS(dalloc(plan, &plan->comp, vec_bytes));
-    TRYS(dalloc(plan, &plan->vsort, vec_bytes));
+    TRYS(dalloc(plan, &plan->hbuf, vec_bytes * P));
     TRYS(dalloc(plan, (void **)&plan->coef, (size_t)8 * maxK * sizeof(double)));
     TRYS(dalloc(plan, (void **)&plan->bbar, (size_t)2 * maxK * sizeof(double)));
     TRYS(dalloc(plan, (void **)&plan->minb, (size_t)2 * P * sizeof(double)));

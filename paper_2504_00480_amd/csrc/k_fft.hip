@@ -108,16 +108,18 @@ k_fft_lines(typename Cplx<T>::type *__restrict__ data, int64_t S, int64_t nlines
 }
 
 // Multiply the spectrum by the symmetrised diagonal on [-N/2, N/2]^d and clear
-// every other frequency.  With DER the same input also gives the derivative
-// spectrum, written to out_der.
+// every other frequency.  The spectra of a group are stored [window][vector]
+// [cell]; with DER the same input also gives the derivative spectrum, written
+// one group-block further on.
 template <typename T, int D, bool DER>
 __global__ void __launch_bounds__(256)
-k_diag(typename Cplx<T>::type *__restrict__ spec, typename Cplx<T>::type *__restrict__ out_der,
-       const T *__restrict__ Dk, const T *__restrict__ Dder, int N, int64_t cells, int64_t total)
+k_diag(typename Cplx<T>::type *__restrict__ spec, const WinDesc *__restrict__ wd, int N,
+       int nrhs, int64_t cells, int64_t total)
 {
     using C = typename Cplx<T>::type;
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
+    const WinDesc &win = wd[idx / ((int64_t)nrhs * cells)];
     int64_t rem = idx % cells;
     const int ng = 2 * N;
     bool in = true;
@@ -133,11 +135,11 @@ k_diag(typename Cplx<T>::type *__restrict__ spec, typename Cplx<T>::type *__rest
     C v = spec[idx];
     C ok, od;
     if (in) {
-        T dk = Dk[di];
+        T dk = reinterpret_cast<const T *>(win.Dk)[di];
         ok.x = v.x * dk;
         ok.y = v.y * dk;
         if (DER) {
-            T dd = Dder[di];
+            T dd = reinterpret_cast<const T *>(win.Dder)[di];
             od.x = v.x * dd;
             od.y = v.y * dd;
         }
@@ -146,7 +148,7 @@ k_diag(typename Cplx<T>::type *__restrict__ spec, typename Cplx<T>::type *__rest
         od.x = od.y = T(0);
     }
     spec[idx] = ok;
-    if (DER) out_der[idx] = od;
+    if (DER) spec[total + idx] = od;
 }
 
 template <typename T, bool INV>
@@ -182,20 +184,18 @@ hipError_t fft_t(const WindowGeom &g, void *grid, int batch, hipStream_t s)
 }
 
 template <typename T>
-hipError_t diag_t(const Window &w, int nrhs, void *grid, bool with_der, hipStream_t s)
+hipError_t diag_t(const Group &G, int nrhs, void *grid, bool with_der, hipStream_t s)
 {
     using C = typename Cplx<T>::type;
-    const WindowGeom &g = w.g;
-    int64_t total = (int64_t)nrhs * g.cells;
+    const WindowGeom &g = G.g;
+    int64_t total = (int64_t)G.nwin * nrhs * g.cells;
     unsigned nblk = (unsigned)((total + 255) / 256);
     C *spec = (C *)grid;
-    C *der = spec + total;
-    const T *Dk = (const T *)w.Dk, *Dd = (const T *)w.Dder;
-#define NFFTGP_DIAG(DD)                                                                          \
-    if (with_der)                                                                                \
-        k_diag<T, DD, true><<<nblk, 256, 0, s>>>(spec, der, Dk, Dd, g.N, g.cells, total);        \
-    else                                                                                         \
-        k_diag<T, DD, false><<<nblk, 256, 0, s>>>(spec, nullptr, Dk, nullptr, g.N, g.cells, total);
+#define NFFTGP_DIAG(DD)                                                                        \
+    if (with_der)                                                                              \
+        k_diag<T, DD, true><<<nblk, 256, 0, s>>>(spec, G.desc, g.N, nrhs, g.cells, total);     \
+    else                                                                                       \
+        k_diag<T, DD, false><<<nblk, 256, 0, s>>>(spec, G.desc, g.N, nrhs, g.cells, total);
     switch (g.d) {
     case 1: NFFTGP_DIAG(1) break;
     case 2: NFFTGP_DIAG(2) break;
@@ -216,11 +216,11 @@ hipError_t launch_fft(int prec, const WindowGeom &g, void *grid, int batch, bool
     return inverse ? fft_t<double, true>(g, grid, batch, s) : fft_t<double, false>(g, grid, batch, s);
 }
 
-hipError_t launch_diag(int prec, const Window &w, int nrhs, void *grid, bool with_der,
+hipError_t launch_diag(int prec, const Group &G, int nrhs, void *grid, bool with_der,
                        hipStream_t s)
 {
-    return prec == NFFTGP_F32 ? diag_t<float>(w, nrhs, grid, with_der, s)
-                              : diag_t<double>(w, nrhs, grid, with_der, s);
+    return prec == NFFTGP_F32 ? diag_t<float>(G, nrhs, grid, with_der, s)
+                              : diag_t<double>(G, nrhs, grid, with_der, s);
 }
 
 }  // namespace nfftgp

@@ -7,16 +7,15 @@
 //
 // Coordinates t are in grid units (t = 2N x~ + N, x~ in [-1/4, 1/4)), so a
 // point touches the 2m cells floor(t)-m+1 .. floor(t)+m per dimension.  psi is
-// the Kaiser-Bessel window of Appendix A in grid units, normalised so that
-// its Fourier coefficient at frequency 0 is 1 / (2N):
-//   psi(t) = sinh(b sqrt(m^2 - t^2)) / (pi sqrt(m^2 - t^2) I_0(m b)),  |t| <= m.
+// the Kaiser-Bessel window of Appendix A in grid units, normalised so that its
+// Fourier coefficient at frequency 0 is 1 / (2N); the plan stores psi at the
+// 2m taps of every point (record `rec`, dimension-major).
 //
-// Points are sorted by tile ("bin", tb cells per dimension); a subproblem is a
-// run of at most kMaxSubPoints points of one bin.  Spreading accumulates one
-// subproblem into an LDS copy of its padded tile ((tb + 2m)^d cells) and writes
-// the tile out; no global atomics are used and the result does not depend on
-// scheduling: each wave owns one LDS copy and adds one point at a time, and
-// the copies and tiles are summed in a fixed order.
+// All windows of one group (same dimension and bandwidth) go through each
+// kernel in a single launch: work items (subproblems, tiles, grid cells) of the
+// group's windows are concatenated, and a per-window descriptor gives each
+// work item its window's point data.  A subproblem is a run of points of one
+// tile ("bin", tb cells per dimension) in the window's sorted order.
 #include "nfftgp_impl.h"
 
 namespace nfftgp {
@@ -48,12 +47,14 @@ __device__ __forceinline__ void bin_origin(int bin, int nb, int tb, int *org)
 // absolute cell index is w modulo W, so no two waves ever touch the same
 // cell.  Within a flush every lane touches a distinct cell and the flushes of
 // one wave are ordered, so the tile is updated with plain loads and stores
-// and the result does not depend on scheduling.
+// and the result does not depend on scheduling.  The points' weights, cells
+// and vector values are staged in LDS in chunks of 64 with coalesced loads.
 template <typename T, int D, int M, int R, int W>
 __global__ void __launch_bounds__(64 * W)
-k_spread(const T *__restrict__ rec, const int *__restrict__ anchor, const T *__restrict__ vs,
-         int nrhs, const int *__restrict__ sub_bin, const int *__restrict__ sub_start,
-         const int *__restrict__ sub_count, int tb, int nb, int ng, T *__restrict__ tilebuf)
+k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
+         const int *__restrict__ sub_bin, const int *__restrict__ sub_start,
+         const int *__restrict__ sub_count, const T *__restrict__ V, int64_t ldv, int nrhs, int tb,
+         int nb, int ng, T *__restrict__ tilebuf)
 {
     constexpr int TW = 2 * M;
     constexpr int RS = D * TW;                                  // weights per point
@@ -63,8 +64,6 @@ k_spread(const T *__restrict__ rec, const int *__restrict__ anchor, const T *__r
     static_assert(TW % W == 0, "waves must divide the taps");
     constexpr int NA = D == 3 ? TW / W : 1;                     // registers per item
     constexpr int CH = 64;                                      // points staged per chunk
-    // point data of one chunk, staged with coalesced loads so that the loop
-    // over points reads LDS instead of waiting on global memory per point
     __shared__ T s_rec[CH * RS];
     __shared__ T s_v[CH * R];
     __shared__ int s_an[CH];
@@ -74,6 +73,10 @@ k_spread(const T *__restrict__ rec, const int *__restrict__ anchor, const T *__r
     int pc = pd;
     for (int q = 1; q < D; ++q) pc *= pd;
     const int sq = blockIdx.x, r0 = blockIdx.y * R;
+    const WinDesc &win = wd[sub_win[sq]];
+    const T *rec = reinterpret_cast<const T *>(win.rec);
+    const int *anchor = win.anchor;
+    const int *perm = win.perm;
     const int start = sub_start[sq], cnt = sub_count[sq];
     const int end = start + cnt;
     int org[3] = {0, 0, 0};
@@ -110,7 +113,7 @@ k_spread(const T *__restrict__ rec, const int *__restrict__ anchor, const T *__r
         for (int i = tid; i < nc * RS; i += 64 * W) s_rec[i] = rec[(int64_t)cb * RS + i];
         for (int i = tid; i < nc * R; i += 64 * W) {
             const int u = i / R, r = i % R;
-            s_v[i] = r < nr ? vs[(int64_t)(cb + u) * nrhs + r0 + r] : T(0);
+            s_v[i] = r < nr ? V[(int64_t)perm[cb + u] * ldv + r0 + r] : T(0);
         }
         for (int i = tid; i < nc; i += 64 * W) s_an[i] = anchor[cb + i];
         __syncthreads();
@@ -184,30 +187,18 @@ k_spread(const T *__restrict__ rec, const int *__restrict__ anchor, const T *__r
     }
 }
 
-// Vectors in the window's sorted point order (vs[j][r] = V[perm[j]][r]).
-template <typename T>
-__global__ void k_gather(const T *__restrict__ V, int64_t ldv, const int *__restrict__ perm,
-                         int64_t n, int nrhs, T *__restrict__ vs)
-{
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * nrhs) return;
-    int64_t j = idx / nrhs;
-    int r = (int)(idx % nrhs);
-    vs[idx] = V[(int64_t)perm[j] * ldv + r];
-}
-
 // ---------------------------------------------------------------- fold
 // Phase 1: the subproblems of one tile are summed into the first one's slot
-// (in place, one thread per tile cell and vector, fixed order).
+// (in place, fixed order: 4 slices per cell combined through LDS).
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_fold_bins(T *__restrict__ tilebuf, const int *__restrict__ bin_sub_ptr, int nrhs, int pc)
+k_fold_bins(const WinDesc *__restrict__ wd, T *__restrict__ tilebuf, int nbins, int nrhs, int pc)
 {
-    // 64 cells per block and 4 slices of the subproblem list per cell; the
-    // slices are combined in a fixed order through LDS
     __shared__ T part[4][64];
-    const int bin = blockIdx.y, r = blockIdx.z;
-    const int s0 = bin_sub_ptr[bin], s1 = bin_sub_ptr[bin + 1];
+    const int wb = blockIdx.y, r = blockIdx.z;
+    const int *bsp = wd[wb / nbins].bin_sub_ptr;
+    const int bin = wb % nbins;
+    const int s0 = bsp[bin], s1 = bsp[bin + 1];
     if (s1 - s0 < 2) return;
     const int ci = threadIdx.x & 63, slice = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + ci;
@@ -224,17 +215,19 @@ k_fold_bins(T *__restrict__ tilebuf, const int *__restrict__ bin_sub_ptr, int nr
 }
 
 // Phase 2: every grid cell sums the (at most 3^d) tiles whose padded region
-// covers it.
+// covers it.  Output layout [window][vector][cell].
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
-k_fold(const T *__restrict__ tilebuf, const int *__restrict__ bin_sub_ptr, int nrhs, int tb,
-       int nb, int ng, int m, int pd, int pc, int64_t cells,
+k_fold(const WinDesc *__restrict__ wd, const T *__restrict__ tilebuf, int nrhs, int tb, int nb,
+       int ng, int m, int pd, int pc, int64_t cells, int64_t total,
        typename Cplx<T>::type *__restrict__ grid)
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)nrhs * cells) return;
-    const int r = (int)(idx / cells);
+    if (idx >= total) return;
+    const int64_t wr = idx / cells;
+    const int w = (int)(wr / nrhs), r = (int)(wr % nrhs);
     const int64_t cell = idx % cells;
+    const int *bsp = wd[w].bin_sub_ptr;
     int l[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     int64_t rem = cell;
     for (int q = D - 1; q >= 0; --q) {
@@ -260,8 +253,8 @@ k_fold(const T *__restrict__ tilebuf, const int *__restrict__ bin_sub_ptr, int n
                     bin = bin * nb + b2;
                     li = li * pd + (l[2] - b2 * tb + m);
                 }
-                const int s0 = bin_sub_ptr[bin];
-                if (bin_sub_ptr[bin + 1] > s0) sum += tilebuf[((int64_t)s0 * nrhs + r) * pc + li];
+                const int s0 = bsp[bin];
+                if (bsp[bin + 1] > s0) sum += tilebuf[((int64_t)s0 * nrhs + r) * pc + li];
             }
     typename Cplx<T>::type o;
     o.x = sum;
@@ -273,16 +266,15 @@ k_fold(const T *__restrict__ tilebuf, const int *__restrict__ bin_sub_ptr, int n
 // One thread per point (subproblems of at most 256 points of one tile).  The
 // padded tile of the grid (and of the derivative grid) is staged in LDS for
 // one vector at a time; the point's window weights are loaded once and reused
-// for every vector.  Results are added to the window sum with Kahan
-// compensation (deterministic: one thread owns each output entry).
+// for every vector.  Each window writes its own block of the per-window
+// output buffer (one owner thread per entry).
 template <typename T, int D, int M, bool DER>
 __global__ void __launch_bounds__(256)
-k_interp(const T *__restrict__ rec, const int *__restrict__ anchor, const int *__restrict__ perm,
+k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
          const int *__restrict__ sub_bin, const int *__restrict__ sub_start,
-         const int *__restrict__ sub_count, int tb, int nb, int ng,
-         const typename Cplx<T>::type *__restrict__ gridK,
-         const typename Cplx<T>::type *__restrict__ gridD, int64_t cells, int nrhs,
-         T *__restrict__ acc, T *__restrict__ comp, T *__restrict__ dout, int64_t dstride, T dscale)
+         const int *__restrict__ sub_count, int tb, int nb, int ng, int nwin,
+         const typename Cplx<T>::type *__restrict__ grid, int64_t cells, int nrhs, int64_t n,
+         T *__restrict__ hbuf, T *__restrict__ dout, T dscale)
 {
     constexpr int TW = 2 * M;
     constexpr int RS = D * TW;
@@ -293,6 +285,9 @@ k_interp(const T *__restrict__ rec, const int *__restrict__ anchor, const int *_
     for (int q = 1; q < D; ++q) pc *= pd;
     T *tD = tK + pc;
     const int sq = blockIdx.x;
+    const int wi = sub_win[sq];
+    const WinDesc &win = wd[wi];
+    const T *rec = reinterpret_cast<const T *>(win.rec);
     const int start = sub_start[sq], cnt = sub_count[sq];
     int org[3] = {0, 0, 0};
     bin_origin<D>(sub_bin[sq], nb, tb, org);
@@ -309,16 +304,19 @@ k_interp(const T *__restrict__ rec, const int *__restrict__ anchor, const int *_
         for (int a = 0; a < TW; ++a) w[q][a] = rp[q * TW + a];
     int A[3] = {0, 0, 0};
     {
-        int cell = anchor[j] & 0x7fffffff;
+        int cell = win.anchor[j] & 0x7fffffff;
         for (int q = D - 1; q >= 0; --q) {
             A[q] = cell % ng - org[q] + 1;
             cell /= ng;
         }
     }
-    const int64_t orow = (int64_t)perm[j] * nrhs;
+    const int64_t orow = (int64_t)win.perm[j] * nrhs;
+    T *hout = hbuf + (int64_t)win.s_global * n * nrhs;
+    T *dblk = DER ? dout + (int64_t)win.s_global * n * nrhs : nullptr;
     for (int r = 0; r < nrhs; ++r) {
-        const typename Cplx<T>::type *gK = gridK + (int64_t)r * cells;
-        const typename Cplx<T>::type *gD = DER ? gridD + (int64_t)r * cells : nullptr;
+        const typename Cplx<T>::type *gK = grid + ((int64_t)wi * nrhs + r) * cells;
+        const typename Cplx<T>::type *gD =
+            DER ? grid + ((int64_t)(nwin + wi) * nrhs + r) * cells : nullptr;
         if (r > 0) __syncthreads();
         for (int i = threadIdx.x; i < pc; i += blockDim.x) {
             int rem = i, loc[3] = {0, 0, 0};
@@ -379,40 +377,142 @@ k_interp(const T *__restrict__ rec, const int *__restrict__ anchor, const int *_
                 if (DER) hD += sD * w0;
             }
         }
-        const int64_t o = orow + r;
-        // compensated sum over windows (Kahan)
-        T s0 = acc[o];
-        T y = hK - comp[o];
-        T s1 = s0 + y;
-        comp[o] = (s1 - s0) - y;
-        acc[o] = s1;
-        if (DER) dout[o] = dscale * hD;
+        hout[orow + r] = hK;
+        if (DER) dblk[orow + r] = dscale * hD;
     }
-    (void)dstride;
 }
 
+// sigma_f^2 sum_s h^(s) + sigma_eps^2 v, summed over windows in order with
+// Kahan compensation; derivative blocks for sigma_f and sigma_eps.
 template <typename T>
-__global__ void k_fill(T *__restrict__ p, int64_t count)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = T(0);
-}
-
-template <typename T>
-__global__ void k_assemble(int64_t n, int nrhs, const T *__restrict__ V, int64_t ldv,
-                           const T *__restrict__ acc, const T *__restrict__ comp, T sf2, T se2,
-                           T two_sf, T two_se, T *__restrict__ KV, T *__restrict__ dsf,
-                           T *__restrict__ dse)
+__global__ void k_assemble(int64_t n, int nrhs, int P, const T *__restrict__ V, int64_t ldv,
+                           const T *__restrict__ hbuf, T sf2, T se2, T two_sf, T two_se,
+                           T *__restrict__ KV, T *__restrict__ dsf, T *__restrict__ dse)
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * nrhs) return;
+    const int64_t tot = n * nrhs;
+    if (idx >= tot) return;
     int64_t i = idx / nrhs;
     int r = (int)(idx % nrhs);
-    T s = acc[idx] - comp[idx];
+    T s = T(0), c = T(0);
+    for (int w = 0; w < P; ++w) {
+        const T y = hbuf[(int64_t)w * tot + idx] - c;
+        const T t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
     T v = V[i * ldv + r];
     KV[idx] = sf2 * s + se2 * v;
     if (dsf) dsf[idx] = two_sf * s;
     if (dse) dse[idx] = two_se * v;
+}
+
+// Kernels that need more than 64 KiB of dynamic LDS must say so before launch.
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes)
+{
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename T, int D, int M, int R, int W>
+hipError_t spread_launch(const Group &G, const void *V, int64_t ldv, int nrhs, void *tilebuf,
+                         hipStream_t s)
+{
+    const WindowGeom &g = G.g;
+    const size_t shm = (size_t)g.pc * sizeof(T) * R;
+    hipError_t e = allow_lds(k_spread<T, D, M, R, W>, shm);
+    if (e != hipSuccess) return e;
+    dim3 grid((unsigned)G.nsub, (unsigned)((nrhs + R - 1) / R));
+    k_spread<T, D, M, R, W><<<grid, 64 * W, shm, s>>>(G.desc, G.sub_win, G.sub_bin, G.sub_start,
+                                                        G.sub_count, (const T *)V, ldv, nrhs, g.tb,
+                                                        g.nb, g.ng, (T *)tilebuf);
+    return hipGetLastError();
+}
+
+template <typename T, int D, int M>
+hipError_t spread_dm(const Group &G, const void *V, int64_t ldv, int nrhs, void *tilebuf,
+                     hipStream_t s)
+{
+    // d = 3: 4 waves share a tile (2m taps split 4 ways: m = 2, 4, 6, 8 -> 1, 2, 3, 4
+    // each); two vectors per group when the two tiles stay within 40 KiB
+    constexpr int Wv = D == 3 ? 4 : 1;
+    if (nrhs >= 2 && 2 * (size_t)G.g.pc * sizeof(T) <= 40 * 1024)
+        return spread_launch<T, D, M, 2, Wv>(G, V, ldv, nrhs, tilebuf, s);
+    return spread_launch<T, D, M, 1, Wv>(G, V, ldv, nrhs, tilebuf, s);
+}
+
+template <typename T, int D, int M>
+hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool with_der,
+                     void *hbuf, void *dout, double dscale, hipStream_t s)
+{
+    const WindowGeom &g = G.g;
+    using C = typename Cplx<T>::type;
+    size_t shm = (size_t)g.pc * sizeof(T) * (with_der ? 2 : 1);
+    hipError_t e = with_der ? allow_lds(k_interp<T, D, M, true>, shm) : allow_lds(k_interp<T, D, M, false>, shm);
+    if (e != hipSuccess) return e;
+    if (with_der)
+        k_interp<T, D, M, true><<<(unsigned)G.nisub, 256, shm, s>>>(
+            G.desc, G.isub_win, G.isub_bin, G.isub_start, G.isub_count, g.tb, g.nb, g.ng, G.nwin,
+            (const C *)grid, g.cells, nrhs, n, (T *)hbuf, (T *)dout, (T)dscale);
+    else
+        k_interp<T, D, M, false><<<(unsigned)G.nisub, 256, shm, s>>>(
+            G.desc, G.isub_win, G.isub_bin, G.isub_start, G.isub_count, g.tb, g.nb, g.ng, G.nwin,
+            (const C *)grid, g.cells, nrhs, n, (T *)hbuf, nullptr, (T)dscale);
+    return hipGetLastError();
+}
+
+#define NFFTGP_DISPATCH_DM(FN, T, D, M, ...)                         \
+    switch (M) {                                                     \
+    case 2: return FN<T, D, 2>(__VA_ARGS__);                         \
+    case 4: return FN<T, D, 4>(__VA_ARGS__);                         \
+    case 6: return FN<T, D, 6>(__VA_ARGS__);                         \
+    case 8: return FN<T, D, 8>(__VA_ARGS__);                         \
+    default: return hipErrorInvalidValue;                            \
+    }
+
+template <typename T>
+hipError_t spread_t(const Group &G, int m, const void *V, int64_t ldv, int nrhs, void *tilebuf,
+                    hipStream_t s)
+{
+    switch (G.g.d) {
+    case 1: NFFTGP_DISPATCH_DM(spread_dm, T, 1, m, G, V, ldv, nrhs, tilebuf, s)
+    case 2: NFFTGP_DISPATCH_DM(spread_dm, T, 2, m, G, V, ldv, nrhs, tilebuf, s)
+    case 3: NFFTGP_DISPATCH_DM(spread_dm, T, 3, m, G, V, ldv, nrhs, tilebuf, s)
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t interp_t(const Group &G, int m, int64_t n, int nrhs, const void *grid, bool with_der,
+                    void *hbuf, void *dout, double dscale, hipStream_t s)
+{
+    switch (G.g.d) {
+    case 1: NFFTGP_DISPATCH_DM(interp_dm, T, 1, m, G, n, nrhs, grid, with_der, hbuf, dout, dscale, s)
+    case 2: NFFTGP_DISPATCH_DM(interp_dm, T, 2, m, G, n, nrhs, grid, with_der, hbuf, dout, dscale, s)
+    case 3: NFFTGP_DISPATCH_DM(interp_dm, T, 3, m, G, n, nrhs, grid, with_der, hbuf, dout, dscale, s)
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t fold_t(const Group &G, int m, int nrhs, void *tilebuf, void *grid, hipStream_t s)
+{
+    const WindowGeom &g = G.g;
+    using C = typename Cplx<T>::type;
+    if (G.nsub > G.nbins_used)
+        k_fold_bins<T><<<dim3((unsigned)((g.pc + 63) / 64), (unsigned)(G.nwin * g.nbins), (unsigned)nrhs), 256, 0, s>>>(
+            G.desc, (T *)tilebuf, g.nbins, nrhs, g.pc);
+    const int64_t tot = (int64_t)G.nwin * nrhs * g.cells;
+    unsigned nblk = (unsigned)((tot + 255) / 256);
+    switch (g.d) {
+    case 1: k_fold<T, 1><<<nblk, 256, 0, s>>>(G.desc, (const T *)tilebuf, nrhs, g.tb, g.nb, g.ng, m, g.pd, g.pc, g.cells, tot, (C *)grid); break;
+    case 2: k_fold<T, 2><<<nblk, 256, 0, s>>>(G.desc, (const T *)tilebuf, nrhs, g.tb, g.nb, g.ng, m, g.pd, g.pc, g.cells, tot, (C *)grid); break;
+    case 3: k_fold<T, 3><<<nblk, 256, 0, s>>>(G.desc, (const T *)tilebuf, nrhs, g.tb, g.nb, g.ng, m, g.pd, g.pc, g.cells, tot, (C *)grid); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -429,190 +529,46 @@ double kb_knorm(int m)
     return 1.0 / (kPi * sum);
 }
 
-namespace {
-
-// Kernels that need more than 64 KiB of dynamic LDS must say so before launch.
-template <typename K>
-hipError_t allow_lds(K kernel, size_t bytes)
+hipError_t launch_spread(int prec, const Group &G, int m, const void *V, int64_t ldv, int nrhs,
+                         void *tilebuf, hipStream_t s)
 {
-    if (bytes <= 64 * 1024) return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (G.nsub == 0) return hipSuccess;
+    return prec == NFFTGP_F32 ? spread_t<float>(G, m, V, ldv, nrhs, tilebuf, s)
+                              : spread_t<double>(G, m, V, ldv, nrhs, tilebuf, s);
 }
 
-template <typename T, int D, int M, int R, int W>
-hipError_t spread_launch(const Window &w, const void *vs, int nrhs, void *tilebuf, hipStream_t s)
-{
-    const WindowGeom &g = w.g;
-    const size_t shm = (size_t)g.pc * sizeof(T) * R;
-    hipError_t e = allow_lds(k_spread<T, D, M, R, W>, shm);
-    if (e != hipSuccess) return e;
-    dim3 grid((unsigned)w.nsub, (unsigned)((nrhs + R - 1) / R));
-    k_spread<T, D, M, R, W><<<grid, 64 * W, shm, s>>>(
-        (const T *)w.rec, w.anchor, (const T *)vs, nrhs, w.sub_bin, w.sub_start, w.sub_count, g.tb,
-        g.nb, g.ng, (T *)tilebuf);
-    return hipGetLastError();
-}
-
-template <typename T, int D, int M>
-hipError_t spread_dm(const Window &w, int64_t n, const void *vs, int nrhs, void *tilebuf,
-                     hipStream_t s)
-{
-    (void)n;
-    // d = 3: 4 waves share a tile (2m taps split 4 ways: m = 2, 4, 6, 8 -> 1, 2, 3, 4
-    // each); two vectors per group when the two tiles stay within 40 KiB
-    constexpr int Wv = D == 3 ? 4 : 1;
-    if (nrhs >= 2 && 2 * (size_t)w.g.pc * sizeof(T) <= 40 * 1024)
-        return spread_launch<T, D, M, 2, Wv>(w, vs, nrhs, tilebuf, s);
-    return spread_launch<T, D, M, 1, Wv>(w, vs, nrhs, tilebuf, s);
-}
-
-template <typename T, int D, int M>
-hipError_t interp_dm(const Window &w, int64_t n, int nrhs, const void *grid, bool with_der,
-                     void *acc, void *comp, void *dout, double dscale, hipStream_t s)
-{
-    const WindowGeom &g = w.g;
-    using C = typename Cplx<T>::type;
-    const C *gK = (const C *)grid;
-    const C *gD = gK + (int64_t)nrhs * g.cells;
-    size_t shm = (size_t)g.pc * sizeof(T) * (with_der ? 2 : 1);
-    hipError_t e = with_der ? allow_lds(k_interp<T, D, M, true>, shm) : allow_lds(k_interp<T, D, M, false>, shm);
-    if (e != hipSuccess) return e;
-    if (with_der)
-        k_interp<T, D, M, true><<<(unsigned)w.nisub, 256, shm, s>>>(
-            (const T *)w.rec, w.anchor, w.perm, w.isub_bin, w.isub_start, w.isub_count, g.tb, g.nb,
-            g.ng, gK, gD, g.cells, nrhs, (T *)acc, (T *)comp, (T *)dout, 0, (T)dscale);
-    else
-        k_interp<T, D, M, false><<<(unsigned)w.nisub, 256, shm, s>>>(
-            (const T *)w.rec, w.anchor, w.perm, w.isub_bin, w.isub_start, w.isub_count, g.tb, g.nb,
-            g.ng, gK, nullptr, g.cells, nrhs, (T *)acc, (T *)comp, nullptr, 0, (T)dscale);
-    (void)n;
-    return hipGetLastError();
-}
-
-#define NFFTGP_DISPATCH_DM(FN, T, D, M, ...)                         \
-    switch (M) {                                                     \
-    case 2: return FN<T, D, 2>(__VA_ARGS__);                         \
-    case 4: return FN<T, D, 4>(__VA_ARGS__);                         \
-    case 6: return FN<T, D, 6>(__VA_ARGS__);                         \
-    case 8: return FN<T, D, 8>(__VA_ARGS__);                         \
-    default: return hipErrorInvalidValue;                            \
-    }
-
-template <typename T>
-hipError_t spread_t(const Window &w, int m, int64_t n, const void *V, int64_t ldv, int nrhs,
-                    void *vs, void *tilebuf, hipStream_t s)
-{
-    (void)V;
-    (void)ldv;
-    switch (w.g.d) {
-    case 1: NFFTGP_DISPATCH_DM(spread_dm, T, 1, m, w, n, vs, nrhs, tilebuf, s)
-    case 2: NFFTGP_DISPATCH_DM(spread_dm, T, 2, m, w, n, vs, nrhs, tilebuf, s)
-    case 3: NFFTGP_DISPATCH_DM(spread_dm, T, 3, m, w, n, vs, nrhs, tilebuf, s)
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename T>
-hipError_t interp_t(const Window &w, int m, int64_t n, int nrhs, const void *grid, bool with_der,
-                    void *acc, void *comp, void *dout, double dscale, hipStream_t s)
-{
-    switch (w.g.d) {
-    case 1: NFFTGP_DISPATCH_DM(interp_dm, T, 1, m, w, n, nrhs, grid, with_der, acc, comp, dout, dscale, s)
-    case 2: NFFTGP_DISPATCH_DM(interp_dm, T, 2, m, w, n, nrhs, grid, with_der, acc, comp, dout, dscale, s)
-    case 3: NFFTGP_DISPATCH_DM(interp_dm, T, 3, m, w, n, nrhs, grid, with_der, acc, comp, dout, dscale, s)
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename T>
-hipError_t fold_t(const Window &w, int m, int nrhs, void *tilebuf, void *grid, hipStream_t s)
-{
-    const WindowGeom &g = w.g;
-    using C = typename Cplx<T>::type;
-    if (w.nsub > w.nbins_used)
-        k_fold_bins<T><<<dim3((unsigned)((g.pc + 63) / 64), (unsigned)g.nbins, (unsigned)nrhs), 256, 0, s>>>(
-            (T *)tilebuf, w.bin_sub_ptr, nrhs, g.pc);
-    int64_t tot = (int64_t)nrhs * g.cells;
-    unsigned nblk = (unsigned)((tot + 255) / 256);
-    switch (g.d) {
-    case 1: k_fold<T, 1><<<nblk, 256, 0, s>>>((const T *)tilebuf, w.bin_sub_ptr, nrhs, g.tb, g.nb, g.ng, m, g.pd, g.pc, g.cells, (C *)grid); break;
-    case 2: k_fold<T, 2><<<nblk, 256, 0, s>>>((const T *)tilebuf, w.bin_sub_ptr, nrhs, g.tb, g.nb, g.ng, m, g.pd, g.pc, g.cells, (C *)grid); break;
-    case 3: k_fold<T, 3><<<nblk, 256, 0, s>>>((const T *)tilebuf, w.bin_sub_ptr, nrhs, g.tb, g.nb, g.ng, m, g.pd, g.pc, g.cells, (C *)grid); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-}  // namespace
-
-hipError_t launch_fill(int prec, void *p, int64_t count, hipStream_t s)
-{
-    if (count <= 0) return hipSuccess;
-    unsigned nblk = (unsigned)((count + 255) / 256);
-    if (prec == NFFTGP_F32)
-        k_fill<float><<<nblk, 256, 0, s>>>((float *)p, count);
-    else
-        k_fill<double><<<nblk, 256, 0, s>>>((double *)p, count);
-    return hipGetLastError();
-}
-
-hipError_t launch_gather(int prec, const Window &w, int64_t n, const void *V, int64_t ldv, int nrhs,
-                         void *vs, hipStream_t s)
-{
-    const int64_t tot = n * nrhs;
-    if (tot == 0) return hipSuccess;
-    if (prec == NFFTGP_F32)
-        k_gather<float><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>((const float *)V, ldv, w.perm, n,
-                                                                        nrhs, (float *)vs);
-    else
-        k_gather<double><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>((const double *)V, ldv, w.perm, n,
-                                                                         nrhs, (double *)vs);
-    return hipGetLastError();
-}
-
-hipError_t launch_spread(int prec, const Window &w, int m, int64_t n, const void *V, int64_t ldv,
-                         int nrhs, void *vs, void *tilebuf, hipStream_t s)
-{
-    if (w.nsub == 0) return hipSuccess;
-    return prec == NFFTGP_F32 ? spread_t<float>(w, m, n, V, ldv, nrhs, vs, tilebuf, s)
-                              : spread_t<double>(w, m, n, V, ldv, nrhs, vs, tilebuf, s);
-}
-
-hipError_t launch_fold(int prec, const Window &w, int m, int nrhs, void *tilebuf, void *grid,
+hipError_t launch_fold(int prec, const Group &G, int m, int nrhs, void *tilebuf, void *grid,
                        hipStream_t s)
 {
-    return prec == NFFTGP_F32 ? fold_t<float>(w, m, nrhs, tilebuf, grid, s)
-                              : fold_t<double>(w, m, nrhs, tilebuf, grid, s);
+    return prec == NFFTGP_F32 ? fold_t<float>(G, m, nrhs, tilebuf, grid, s)
+                              : fold_t<double>(G, m, nrhs, tilebuf, grid, s);
 }
 
-hipError_t launch_interp(int prec, const Window &w, int m, int64_t n, int nrhs, const void *grid,
-                         bool with_der, void *acc, void *comp, void *dout, double dscale,
-                         hipStream_t s)
+hipError_t launch_interp(int prec, const Group &G, int m, int64_t n, int nrhs, const void *grid,
+                         bool with_der, void *hbuf, void *dout, double dscale, hipStream_t s)
 {
-    if (w.nisub == 0) return hipSuccess;
+    if (G.nisub == 0) return hipSuccess;
     return prec == NFFTGP_F32
-               ? interp_t<float>(w, m, n, nrhs, grid, with_der, acc, comp, dout, dscale, s)
-               : interp_t<double>(w, m, n, nrhs, grid, with_der, acc, comp, dout, dscale, s);
+               ? interp_t<float>(G, m, n, nrhs, grid, with_der, hbuf, dout, dscale, s)
+               : interp_t<double>(G, m, n, nrhs, grid, with_der, hbuf, dout, dscale, s);
 }
 
-hipError_t launch_assemble(int prec, int64_t n, int nrhs, const void *V, int64_t ldv,
-                           const void *acc, const void *comp, double sf, double se, void *KV,
-                           void *dsf, void *dse, hipStream_t s)
+hipError_t launch_assemble(int prec, int64_t n, int nrhs, int P, const void *V, int64_t ldv,
+                           const void *hbuf, double sf, double se, void *KV, void *dsf, void *dse,
+                           hipStream_t s)
 {
     int64_t tot = n * nrhs;
     if (tot == 0) return hipSuccess;
     unsigned nblk = (unsigned)((tot + 255) / 256);
     if (prec == NFFTGP_F32)
-        k_assemble<float><<<nblk, 256, 0, s>>>(n, nrhs, (const float *)V, ldv, (const float *)acc,
-                                               (const float *)comp, (float)(sf * sf),
-                                               (float)(se * se), (float)(2 * sf), (float)(2 * se),
-                                               (float *)KV, (float *)dsf, (float *)dse);
+        k_assemble<float><<<nblk, 256, 0, s>>>(n, nrhs, P, (const float *)V, ldv, (const float *)hbuf,
+                                               (float)(sf * sf), (float)(se * se), (float)(2 * sf),
+                                               (float)(2 * se), (float *)KV, (float *)dsf,
+                                               (float *)dse);
     else
-        k_assemble<double><<<nblk, 256, 0, s>>>(n, nrhs, (const double *)V, ldv,
-                                                (const double *)acc, (const double *)comp, sf * sf,
-                                                se * se, 2 * sf, 2 * se, (double *)KV,
-                                                (double *)dsf, (double *)dse);
+        k_assemble<double><<<nblk, 256, 0, s>>>(n, nrhs, P, (const double *)V, ldv,
+                                                (const double *)hbuf, sf * sf, se * se, 2 * sf,
+                                                2 * se, (double *)KV, (double *)dsf, (double *)dse);
     return hipGetLastError();
 }
 

@@ -50,17 +50,38 @@ struct Window {
     void *rec = nullptr;        // per sorted point: d x 2m window weights (plan precision)
     int32_t *anchor = nullptr;  // per sorted point: packed cell floor(t); bit 31 = last of its run
     int32_t *perm = nullptr;    // sorted position -> original point index
-    // spreading subproblems (runs of points of one tile) and their CSR by tile
-    int32_t *sub_bin = nullptr, *sub_start = nullptr, *sub_count = nullptr;
-    int32_t *bin_sub_ptr = nullptr;  // nbins + 1
-    int nsub = 0;
-    int nbins_used = 0;              // tiles holding at least one point
-    // interpolation subproblems (at most kInterpSubPoints points of one tile)
-    int32_t *isub_bin = nullptr, *isub_start = nullptr, *isub_count = nullptr;
-    int nisub = 0;
+    int32_t *bin_sub_ptr = nullptr;  // tile -> spreading subproblems of its group (nbins + 1)
     void *Dk = nullptr;     // symmetrised diagonal for K_s (dcells, plan precision)
     void *Dder = nullptr;   // same for K_s^der
     double *cinv2 = nullptr;  // N+1 per-dimension factors 1 / c(k)^2 of the window
+    // host copies used while the plan is built
+    std::vector<int> h_bin_start;
+};
+
+// Per-window data a kernel needs, in device memory (one array per group).
+struct WinDesc {
+    const void *rec;
+    const int32_t *anchor;
+    const int32_t *perm;
+    const int32_t *bin_sub_ptr;
+    const void *Dk;
+    const void *Dder;
+    int32_t s_global;   // window index in the plan
+    int32_t pad_;
+};
+
+// Windows of equal dimension and bandwidth go through every apply kernel in
+// one launch; their work lists are concatenated.
+struct Group {
+    WindowGeom g;
+    int nwin = 0;
+    std::vector<int> wins;       // plan window indices
+    WinDesc *desc = nullptr;     // device, nwin entries
+    int32_t *sub_win = nullptr, *sub_bin = nullptr, *sub_start = nullptr, *sub_count = nullptr;
+    int nsub = 0;                // spreading subproblems (tile slots)
+    int32_t *isub_win = nullptr, *isub_bin = nullptr, *isub_start = nullptr, *isub_count = nullptr;
+    int nisub = 0;               // interpolation subproblems
+    int nbins_used = 0;          // tiles holding at least one point
 };
 
 }  // namespace nfftgp
@@ -76,13 +97,13 @@ struct nfftgp_plan_s {
     hipStream_t stream = nullptr;
     int device = 0;
     std::vector<nfftgp::Window> win;
+    std::vector<nfftgp::Group> groups;
     bool have_hyper = false;
     double sigma_f = 0.0, sigma_eps = 0.0;
     // workspaces (owned)
     void *tilebuf = nullptr;     // spreading tiles
-    void *grid = nullptr;        // 2 x max_nrhs x max cells complex values
-    void *acc = nullptr, *comp = nullptr;  // n x max_nrhs compensated window sum
-    void *vsort = nullptr;                 // n x max_nrhs vectors in a window's point order
+    void *grid = nullptr;        // 2 x (windows of a group) x max_nrhs x cells complex values
+    void *hbuf = nullptr;        // P x n x max_nrhs per-window products
     double *coef = nullptr;      // 4 x maxN^d complex doubles (set_hyper scratch)
     double *bbar = nullptr;      // 2 x maxN^d doubles
     double *minb = nullptr;      // 2 x P doubles
@@ -151,23 +172,19 @@ hipError_t launch_coefficients(int prec, const WindowGeom &g, int m, int kernel,
                                void *Dder, double *minb_out, hipStream_t s);
 
 // ---------------------------------------------------------------- apply kernels
-hipError_t launch_fill(int prec, void *p, int64_t count, hipStream_t s);
-hipError_t launch_gather(int prec, const Window &w, int64_t n, const void *V, int64_t ldv, int nrhs,
-                         void *vs, hipStream_t s);
-hipError_t launch_spread(int prec, const Window &w, int m, int64_t n, const void *V, int64_t ldv,
-                         int nrhs, void *vs, void *tilebuf, hipStream_t s);
-hipError_t launch_fold(int prec, const Window &w, int m, int nrhs, void *tilebuf, void *grid,
+hipError_t launch_spread(int prec, const Group &G, int m, const void *V, int64_t ldv, int nrhs,
+                         void *tilebuf, hipStream_t s);
+hipError_t launch_fold(int prec, const Group &G, int m, int nrhs, void *tilebuf, void *grid,
                        hipStream_t s);
 hipError_t launch_fft(int prec, const WindowGeom &g, void *grid, int batch, bool inverse,
                       hipStream_t s);
-hipError_t launch_diag(int prec, const Window &w, int nrhs, void *grid, bool with_der,
+hipError_t launch_diag(int prec, const Group &G, int nrhs, void *grid, bool with_der,
                        hipStream_t s);
-hipError_t launch_interp(int prec, const Window &w, int m, int64_t n, int nrhs, const void *grid,
-                         bool with_der, void *acc, void *comp, void *dout, double dscale,
-                         hipStream_t s);
-hipError_t launch_assemble(int prec, int64_t n, int nrhs, const void *V, int64_t ldv,
-                           const void *acc, const void *comp, double sf, double se, void *KV,
-                           void *dsf, void *dse, hipStream_t s);
+hipError_t launch_interp(int prec, const Group &G, int m, int64_t n, int nrhs, const void *grid,
+                         bool with_der, void *hbuf, void *dout, double dscale, hipStream_t s);
+hipError_t launch_assemble(int prec, int64_t n, int nrhs, int P, const void *V, int64_t ldv,
+                           const void *hbuf, double sf, double se, void *KV, void *dsf, void *dse,
+                           hipStream_t s);
 
 // ---------------------------------------------------------------- CG / dots
 constexpr int kDotBlocks = 120;
