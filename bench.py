@@ -150,14 +150,15 @@ def main():
     taps = sum(n * nrhs * (2 * w.m) ** d for d, _ in geoms)          # per apply, all windows
     cells = sum(c for _, c in geoms)
     nout = 2 if derivs else 1
-    per_launch = {
-        # algorithmic work per launch, averaged over the windows of one apply
-        "spread": ("alu", 2.0 * taps / P, "TFLOP/s"),                 # one FMA per tap and vector
-        "interp": ("alu", 2.0 * taps * nout / P, "TFLOP/s"),          # one FMA per tap, vector, output
-        "fft_fwd": ("hbm", 2.0 * nrhs * cells * 2 * eb / P, "GB/s"),   # complex grid read + written once
-        "fft_inv": ("hbm", 2.0 * nout * nrhs * cells * 2 * eb / P, "GB/s"),
-        "fold": ("hbm", 1.0 * nrhs * cells * 2 * eb / P, "GB/s"),      # complex grid written once
-        "diag": ("hbm", (2.0 + 1.0 * nout) * nrhs * cells * 2 * eb / P, "GB/s"),
+    # algorithmic work per apply (all windows); a launch of a window group does
+    # the share of its windows, so per launch = per apply / launches per apply
+    per_apply = {
+        "spread": ("alu", 2.0 * taps, "TFLOP/s"),                     # one FMA per tap and vector
+        "interp": ("alu", 2.0 * taps * nout, "TFLOP/s"),              # one FMA per tap, vector, output
+        "fft_fwd": ("hbm", 2.0 * nrhs * cells * 2 * eb, "GB/s"),       # complex grid read + written once
+        "fft_inv": ("hbm", 2.0 * nout * nrhs * cells * 2 * eb, "GB/s"),
+        "fold": ("hbm", 1.0 * nrhs * cells * 2 * eb, "GB/s"),          # complex grid written once
+        "diag": ("hbm", (2.0 + 1.0 * nout) * nrhs * cells * 2 * eb, "GB/s"),
         "assemble": ("hbm", (2 + 2 + 1 + (2 if derivs else 0)) * n * nrhs * eb, "GB/s"),
         "coef": ("alu", 0.0, "TFLOP/s"),
         "fill": ("hbm", n * nrhs * eb, "GB/s"),
@@ -165,8 +166,9 @@ def main():
     }
     kern = {k: {"total_ms": v[0], "launches": v[1], "avg_us": (1e3 * v[0] / v[1]) if v[1] else 0.0}
             for k, v in prof.items() if v[1]}
-    dom = max((k for k in kern if k in per_launch and k != "coef"), key=lambda k: kern[k]["total_ms"])
-    bound, work, unit = per_launch[dom]
+    dom = max((k for k in kern if k in per_apply and k != "coef"), key=lambda k: kern[k]["total_ms"])
+    bound, work, unit = per_apply[dom]
+    work = work * args.steps / kern[dom]["launches"]
     avg_s = kern[dom]["total_ms"] / 1e3 / kern[dom]["launches"]
     if bound == "hbm":
         achieved = work / avg_s / 1e9

@@ -3,6 +3,7 @@
 // quadrature.  See include/nfftgp.h for the contract of every entry point.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -49,6 +50,7 @@ void free_plan(nfftgp_plan p)
     (void)hipStreamSynchronize(p->stream);
     for (void *a : p->allocs) (void)hipFree(a);
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+    if (p->minb_host) (void)hipHostFree(p->minb_host);
     delete p;
 }
 
@@ -260,10 +262,11 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
     TRYH(tmp.get(&t_uns, n1 * 3 * eb));
     TRYH(tmp.get(&t1, n1 * 3 * eb));
     TRYH(tmp.get(&t2, n1 * 3 * eb));
-    // points per spreading work-group: enough groups to fill the device for
-    // small n, fewer and longer runs (fewer partial tiles) for large n
+    // points per spreading work-group: short runs for small n (enough groups to
+    // fill the device), longer runs for large n (fewer partial tiles to fold)
     int sub_sp = 256;
-    while (sub_sp < 4096 && (int64_t)sub_sp * 2048 < n) sub_sp *= 2;
+    if (n > 131072)
+        while (sub_sp < 4096 && (int64_t)sub_sp * 512 < n) sub_sp *= 2;
 
     size_t tile_need = 0;
     int64_t max_cells = 1, maxK = 1;
@@ -276,7 +279,7 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         for (int q = 0; q < d; ++q) w.feat[q] = win_idx[win_ptr[s] + q];
         // --- scaling into [-1/4, 1/4)^d
         double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-        int hflags[2] = {0, 0};
+        int hflags[3] = {0, 0, 0};
         TRYH(hipMemsetAsync(flags, 0, 4 * sizeof(int), st));
         if (n > 0) {
             TRYH(launch_minmax(prec, X_dev, n, ldx, d, w.feat, part, mm, flags, st));
@@ -319,10 +322,10 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         TRYH(launch_bin_keys(prec, t1, n, w.g, keys, st));
         TRYH(launch_sort(prec, n, d, w.g.nbins, keys, ids1, t1, hist, scan_tmp, w.perm, t2,
                          bin_start, st));
-        TRYH(launch_weights(prec, t2, n, w.g, m, kb_knorm(m), w.rec, w.anchor, st));
+        TRYH(launch_weights(prec, t2, n, w.g, m, kb_knorm(m), w.rec, w.anchor, flags + 2, st));
         std::vector<int> bs(w.g.nbins + 1);
         TRYH(hipMemcpyAsync(bs.data(), bin_start, (w.g.nbins + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
-        TRYH(hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        TRYH(hipMemcpyAsync(hflags, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
         TRYH(hipStreamSynchronize(st));
         if (hflags[1]) {
             free_plan(plan);
@@ -330,10 +333,9 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
                                           ": a scaled point lies outside [-1/4, 1/4)^d");
         }
         w.h_bin_start = bs;
+        w.h_cells_used = hflags[2];
         TRYS(dalloc(plan, &w.Dk, w.g.dcells * eb));
         TRYS(dalloc(plan, &w.Dder, w.g.dcells * eb));
-        TRYS(dalloc(plan, (void **)&w.cinv2, (N[s] + 1) * sizeof(double)));
-        TRYH(launch_window_coef(N[s], m, w.cinv2, st));
         int64_t K = 1;
         for (int q = 0; q < d; ++q) K *= N[s];
         maxK = std::max(maxK, K);
@@ -352,7 +354,7 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         }
         plan->groups[gi].wins.push_back(s);
     }
-    size_t grid_need = 1;
+    size_t grid_need = 1, coef_need = 8;
     for (Group &G : plan->groups) {
         G.nwin = (int)G.wins.size();
         std::vector<int> sw, sb, ss, sc, iw, ib, is, ic;
@@ -385,6 +387,43 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         }
         G.nsub = (int)sb.size();
         G.nisub = (int)ib.size();
+        // interpolation variant: register-held runs for 3-D windows whose
+        // points per occupied cell are many; in 1-D and 2-D a run's footprint
+        // covers few lanes and the per-point variant is faster
+        // (NFFTGP_INTERP=run or =tile overrides the choice)
+        {
+            int64_t pts = 0, cells_used = 0;
+            for (int wl = 0; wl < G.nwin; ++wl) {
+                pts += n;
+                cells_used += plan->win[G.wins[wl]].h_cells_used;
+            }
+            const char *ov = std::getenv("NFFTGP_INTERP");
+            if (ov && std::strcmp(ov, "run") == 0) G.use_run_interp = n > 0;
+            else if (ov && std::strcmp(ov, "tile") == 0) G.use_run_interp = false;
+            else G.use_run_interp = G.g.d == 3 && cells_used > 0 &&
+                                    pts >= (int64_t)kRunInterpMinRun * cells_used;
+        }
+        if (G.use_run_interp) {
+            // points per wave: up to kRunSubPoints, fewer while that leaves
+            // under 8192 waves for the group
+            int rsp = kRunSubPoints;
+            while (rsp > 64 && (int64_t)G.nwin * n < (int64_t)rsp * 8192) rsp /= 2;
+            std::vector<int> rw, rs, rc;
+            for (int wl = 0; wl < G.nwin; ++wl)
+                for (int64_t off = 0; off < n; off += rsp) {
+                    rw.push_back(wl);
+                    rs.push_back((int)off);
+                    rc.push_back((int)std::min<int64_t>(rsp, n - off));
+                }
+            G.nrsub = (int)rw.size();
+            int32_t **rdst[3] = {&G.rsub_win, &G.rsub_start, &G.rsub_count};
+            std::vector<int> *rsrc[3] = {&rw, &rs, &rc};
+            for (int k = 0; k < 3; ++k) {
+                TRYS(dalloc(plan, (void **)rdst[k], std::max<size_t>(1, rsrc[k]->size()) * sizeof(int)));
+                if (!rsrc[k]->empty())
+                    TRYH(hipMemcpy(*rdst[k], rsrc[k]->data(), rsrc[k]->size() * sizeof(int), hipMemcpyHostToDevice));
+            }
+        }
         int32_t **dst[8] = {&G.sub_win, &G.sub_bin, &G.sub_start, &G.sub_count,
                             &G.isub_win, &G.isub_bin, &G.isub_start, &G.isub_count};
         std::vector<int> *srcv[8] = {&sw, &sb, &ss, &sc, &iw, &ib, &is, &ic};
@@ -392,6 +431,15 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
             TRYS(dalloc(plan, (void **)dst[k], std::max<size_t>(1, srcv[k]->size()) * sizeof(int)));
             if (!srcv[k]->empty())
                 TRYH(hipMemcpy(*dst[k], srcv[k]->data(), srcv[k]->size() * sizeof(int), hipMemcpyHostToDevice));
+        }
+        TRYS(dalloc(plan, (void **)&G.cinv2, (G.g.N + 1) * sizeof(double)));
+        TRYH(launch_window_coef(G.g.N, m, G.cinv2, st));
+        TRYS(dalloc(plan, (void **)&G.tw, G.g.N * sizeof(double2)));
+        TRYH(launch_twiddles(G.g.N, G.tw, st));
+        {
+            int64_t Kg = 1;
+            for (int q = 0; q < G.g.d; ++q) Kg *= G.g.N;
+            coef_need = std::max(coef_need, (size_t)8 * G.nwin * Kg);
         }
         TRYS(dalloc(plan, (void **)&G.desc, G.nwin * sizeof(WinDesc)));
         TRYH(hipMemcpy(G.desc, hd.data(), G.nwin * sizeof(WinDesc), hipMemcpyHostToDevice));
@@ -403,8 +451,13 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
     TRYS(dalloc(plan, &plan->grid, grid_need * max_nrhs * 2 * eb));
     const size_t vec_bytes = std::max<int64_t>(n, 1) * max_nrhs * eb;
     TRYS(dalloc(plan, &plan->hbuf, vec_bytes * P));
-    TRYS(dalloc(plan, (void **)&plan->coef, (size_t)8 * maxK * sizeof(double)));
-    TRYS(dalloc(plan, (void **)&plan->bbar, (size_t)2 * maxK * sizeof(double)));
+    TRYS(dalloc(plan, (void **)&plan->coef, coef_need * sizeof(double)));
+    TRYS(dalloc(plan, (void **)&plan->bbar, coef_need / 4 * sizeof(double)));
+    {
+        void *h = nullptr;
+        TRYH(hipHostMalloc(&h, 2 * P * sizeof(double), hipHostMallocDefault));
+        plan->minb_host = (double *)h;
+    }
     TRYS(dalloc(plan, (void **)&plan->minb, (size_t)2 * P * sizeof(double)));
     TRYS(dalloc(plan, (void **)&plan->dot_part, (size_t)kDotBlocks * 64 * sizeof(double) + 64 * sizeof(double)));
     TRYS(dalloc(plan, (void **)&plan->cg_scal, (size_t)kCgSlots * 64 * sizeof(double)));
@@ -427,21 +480,26 @@ nfftgp_status nfftgp_set_hyper(nfftgp_plan plan, double sigma_f, const double *e
     for (int s = 0; s < plan->P; ++s)
         if (!(ell[s] > 0.0) || !std::isfinite(ell[s])) return fail(NFFTGP_E_ARG, "ell must be finite and > 0");
     const hipStream_t st = plan->stream;
-    for (int s = 0; s < plan->P; ++s) {
-        Window &w = plan->win[s];
+    for (const Group &G : plan->groups) {
+        CoefParams prm;
+        std::memset(&prm, 0, sizeof(prm));
+        prm.nwin = G.nwin;
+        for (int wl = 0; wl < G.nwin; ++wl) {
+            const int s = G.wins[wl];
+            prm.ell[wl] = ell[s];
+            prm.c[wl] = plan->win[s].c;
+            prm.kernel[wl] = plan->win[s].kernel;
+        }
         PROF_LAUNCH(plan, NFFTGP_PROF_COEF,
-                    launch_coefficients(plan->prec, w.g, plan->m, w.kernel, ell[s], w.c, w.cinv2, plan->coef,
-                                        plan->bbar, w.Dk, w.Dder, plan->minb + 2 * s, st));
+                    launch_coefficients(plan->prec, G, prm, G.cinv2, G.tw, plan->coef, plan->bbar,
+                                        plan->minb, st));
     }
-    std::vector<double> mb(2 * plan->P);
-    NFFTGP_HIP_TRY(hipMemcpyAsync(mb.data(), plan->minb, 2 * plan->P * sizeof(double),
+    // min_k b_k is read back lazily (nfftgp_get_window_info), so set_hyper does
+    // not synchronise
+    NFFTGP_HIP_TRY(hipMemcpyAsync(plan->minb_host, plan->minb, 2 * plan->P * sizeof(double),
                                   hipMemcpyDeviceToHost, st));
-    NFFTGP_HIP_TRY(hipStreamSynchronize(st));
-    for (int s = 0; s < plan->P; ++s) {
-        plan->win[s].ell = ell[s];
-        plan->win[s].min_b = mb[2 * s];
-        plan->win[s].min_bder = mb[2 * s + 1];
-    }
+    plan->minb_pending = true;
+    for (int s = 0; s < plan->P; ++s) plan->win[s].ell = ell[s];
     plan->sigma_f = sigma_f;
     plan->sigma_eps = sigma_eps;
     plan->have_hyper = true;
@@ -645,6 +703,14 @@ nfftgp_status nfftgp_get_window_info(nfftgp_plan plan, int32_t s, double *c0, do
     set_error("");
     if (!plan) return fail(NFFTGP_E_ARG, "plan is NULL");
     if (s < 0 || s >= plan->P) return fail(NFFTGP_E_ARG, "window index out of range");
+    if (plan->minb_pending) {
+        NFFTGP_HIP_TRY(hipStreamSynchronize(plan->stream));
+        for (int k = 0; k < plan->P; ++k) {
+            plan->win[k].min_b = plan->minb_host[2 * k];
+            plan->win[k].min_bder = plan->minb_host[2 * k + 1];
+        }
+        plan->minb_pending = false;
+    }
     const Window &w = plan->win[s];
     if (c0)
         for (int q = 0; q < w.g.d; ++q) c0[q] = w.c0[q];

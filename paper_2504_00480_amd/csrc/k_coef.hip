@@ -28,13 +28,17 @@ __device__ double bessel_i0(double z)
     return sum;
 }
 
-__global__ void k_sample(int d, int N, int kernel, double ell, double c, double *__restrict__ coef)
+// Samples of every window of a group: arrays [window][2][K] of complex values
+// (kernel, then ell-derivative), K = N^d, index l + N/2 per axis.
+__global__ void k_sample(int d, int N, CoefParams prm, double *__restrict__ coef)
 {
     int64_t K = 1;
     for (int q = 0; q < d; ++q) K *= N;
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= K) return;
-    int64_t rem = idx;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= K * prm.nwin) return;
+    const int w = (int)(idx / K);
+    const int64_t e = idx % K;
+    int64_t rem = e;
     double r2 = 0.0;
     for (int q = 0; q < d; ++q) {
         int l = (int)(rem % N) - N / 2;
@@ -42,30 +46,33 @@ __global__ void k_sample(int d, int N, int kernel, double ell, double c, double 
         double x = (double)l / (double)N;
         r2 += x * x;
     }
-    double r = sqrt(r2) / c;   // distance in caller units
+    const double ell = prm.ell[w];
+    const double r = sqrt(r2) / prm.c[w];   // distance in caller units
     double v, dv;
-    if (kernel == NFFTGP_GAUSS) {
+    if (prm.kernel[w] == NFFTGP_GAUSS) {
         v = exp(-(r * r) / (2.0 * ell * ell));
         dv = (r * r) / (ell * ell * ell) * v;
     } else {
         v = exp(-r / ell);
         dv = r / (ell * ell) * v;
     }
-    coef[2 * idx] = v;
-    coef[2 * idx + 1] = 0.0;
-    coef[2 * (K + idx)] = dv;
-    coef[2 * (K + idx) + 1] = 0.0;
+    double *base = coef + (int64_t)w * 4 * K;
+    base[2 * e] = v;
+    base[2 * e + 1] = 0.0;
+    base[2 * (K + e)] = dv;
+    base[2 * (K + e) + 1] = 0.0;
 }
 
-// One axis of the d-dimensional DFT, applied to two stacked arrays:
-// out[.., k, ..] = sum_l in[.., l, ..] exp(-2 pi i l k / N), l, k in [-N/2, N/2).
-__global__ void k_dft_axis(int d, int N, int axis, const double *__restrict__ in,
-                           double *__restrict__ out)
+// One axis of the d-dimensional DFT, applied to all 2 x nwin stacked arrays:
+// out[.., k, ..] = sum_l in[.., l, ..] exp(-2 pi i l k / N), l, k in [-N/2, N/2);
+// tw[j] = exp(-2 pi i j / N).
+__global__ void k_dft_axis(int d, int N, int axis, int narr, const double2 *__restrict__ tw,
+                           const double *__restrict__ in, double *__restrict__ out)
 {
     int64_t K = 1;
     for (int q = 0; q < d; ++q) K *= N;
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= 2 * K) return;
+    if (idx >= (int64_t)narr * K) return;
     int64_t arr = idx / K, e = idx % K;
     int64_t stride = 1;
     for (int q = d - 1; q > axis; --q) stride *= N;
@@ -75,15 +82,22 @@ __global__ void k_dft_axis(int d, int N, int axis, const double *__restrict__ in
     double sr = 0.0, si = 0.0;
     for (int ll = 0; ll < N; ++ll) {
         int l = ll - N / 2;
-        int ph = ((l * k) % N + N) % N;               // exp(-2 pi i ph / N)
-        double sn, cs;
-        sincospi(-2.0 * (double)ph / (double)N, &sn, &cs);
+        const double2 t = tw[((l * k) % N + N) % N];
         double ar = in[2 * (base + (int64_t)ll * stride)], ai = in[2 * (base + (int64_t)ll * stride) + 1];
-        sr += ar * cs - ai * sn;
-        si += ar * sn + ai * cs;
+        sr += ar * t.x - ai * t.y;
+        si += ar * t.y + ai * t.x;
     }
     out[2 * (arr * K + e)] = sr;
     out[2 * (arr * K + e) + 1] = si;
+}
+
+__global__ void k_twiddles(int N, double2 *__restrict__ tw)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    double sn, cs;
+    sincospi(-2.0 * (double)j / (double)N, &sn, &cs);
+    tw[j] = make_double2(cs, sn);
 }
 
 // Normalised window coefficient per dimension, c(k) = I_0(m sqrt(beta^2 -
@@ -100,20 +114,25 @@ __global__ void k_window_coef(int N, int m, double beta, double *__restrict__ ci
 }
 
 template <typename T>
-__global__ void k_make_diag(int d, int N, const double *__restrict__ cinv2,
-                            const double *__restrict__ B, double *__restrict__ bbar,
-                            T *__restrict__ Dk, T *__restrict__ Dder)
+__global__ void k_make_diag(int d, int N, int nwin, const double *__restrict__ cinv2,
+                            const double *__restrict__ coef, double *__restrict__ bbar,
+                            const WinDesc *__restrict__ wd)
 {
     int64_t K = 1, KD = 1;
     for (int q = 0; q < d; ++q) {
         K *= N;
         KD *= (N + 1);
     }
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t span = KD > K ? KD : K;
+    int64_t gidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gidx >= span * nwin) return;
+    const int w = (int)(gidx / span);
+    const int64_t idx = gidx % span;
+    const double *B = coef + (int64_t)w * 4 * K;
     const double invK = 1.0 / (double)K;
     if (idx < K) {   // plain coefficients on I_N (for the definiteness report)
-        bbar[idx] = B[2 * idx] * invK;
-        bbar[K + idx] = B[2 * (K + idx)] * invK;
+        bbar[(int64_t)w * 2 * K + idx] = B[2 * idx] * invK;
+        bbar[(int64_t)w * 2 * K + K + idx] = B[2 * (K + idx)] * invK;
     }
     if (idx >= KD) return;
     int kv[3] = {0, 0, 0};
@@ -141,14 +160,19 @@ __global__ void k_make_diag(int d, int N, const double *__restrict__ cinv2,
         bk += B[2 * in_] * invK;
         bd += B[2 * (K + in_)] * invK;
     }
-    Dk[idx] = (T)(0.5 * bk * f);
-    Dder[idx] = (T)(0.5 * bd * f);
+    reinterpret_cast<T *>(const_cast<void *>(wd[w].Dk))[idx] = (T)(0.5 * bk * f);
+    reinterpret_cast<T *>(const_cast<void *>(wd[w].Dder))[idx] = (T)(0.5 * bd * f);
 }
 
+// Smallest b_k and b^der_k of every window of the group (one block per window),
+// written to minb[2 * s_global + {0, 1}].
 __global__ void __launch_bounds__(1024)
-k_min2(const double *__restrict__ v, int64_t K, double *__restrict__ out)
+k_min2(const double *__restrict__ bbar, int64_t K, const WinDesc *__restrict__ wd,
+       double *__restrict__ minb)
 {
     __shared__ double s0[1024], s1[1024];
+    const int w = blockIdx.x;
+    const double *v = bbar + (int64_t)w * 2 * K;
     double a = INFINITY, b = INFINITY;
     for (int64_t i = threadIdx.x; i < K; i += 1024) {
         a = fmin(a, v[i]);
@@ -165,8 +189,8 @@ k_min2(const double *__restrict__ v, int64_t K, double *__restrict__ out)
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        out[0] = s0[0];
-        out[1] = s1[0];
+        minb[2 * wd[w].s_global] = s0[0];
+        minb[2 * wd[w].s_global + 1] = s1[0];
     }
 }
 
@@ -178,32 +202,37 @@ hipError_t launch_window_coef(int N, int m, double *cinv2, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_coefficients(int prec, const WindowGeom &g, int m, int kernel, double ell,
-                               double c, const double *cinv2, double *coef, double *bbar, void *Dk,
-                               void *Dder, double *minb_out, hipStream_t s)
+hipError_t launch_twiddles(int N, double2 *tw, hipStream_t s)
 {
-    (void)m;
+    k_twiddles<<<(N + 255) / 256, 256, 0, s>>>(N, tw);
+    return hipGetLastError();
+}
+
+hipError_t launch_coefficients(int prec, const Group &G, const CoefParams &prm, const double *cinv2,
+                               const double2 *tw, double *coef, double *bbar, double *minb,
+                               hipStream_t s)
+{
+    const WindowGeom &g = G.g;
     int64_t K = 1, KD = 1;
     for (int q = 0; q < g.d; ++q) {
         K *= g.N;
         KD *= (g.N + 1);
     }
-    double *a = coef, *b = coef + 4 * K;   // two ping-pong buffers of 2 x K complex
-    k_sample<<<(unsigned)((K + 255) / 256), 256, 0, s>>>(g.d, g.N, kernel, ell, c, a);
+    const int nw = G.nwin;
+    double *a = coef, *b = coef + (int64_t)nw * 4 * K;   // ping-pong: [window][2][K] complex each
+    k_sample<<<(unsigned)((nw * K + 255) / 256), 256, 0, s>>>(g.d, g.N, prm, a);
     for (int q = 0; q < g.d; ++q) {
-        k_dft_axis<<<(unsigned)((2 * K + 255) / 256), 256, 0, s>>>(g.d, g.N, q, a, b);
+        k_dft_axis<<<(unsigned)((2 * nw * K + 255) / 256), 256, 0, s>>>(g.d, g.N, q, 2 * nw, tw, a, b);
         double *t = a;
         a = b;
         b = t;
     }
-    int64_t nthr = KD > K ? KD : K;
+    const int64_t span = (KD > K ? KD : K) * nw;
     if (prec == NFFTGP_F32)
-        k_make_diag<float><<<(unsigned)((nthr + 255) / 256), 256, 0, s>>>(
-            g.d, g.N, cinv2, a, bbar, (float *)Dk, (float *)Dder);
+        k_make_diag<float><<<(unsigned)((span + 255) / 256), 256, 0, s>>>(g.d, g.N, nw, cinv2, a, bbar, G.desc);
     else
-        k_make_diag<double><<<(unsigned)((nthr + 255) / 256), 256, 0, s>>>(
-            g.d, g.N, cinv2, a, bbar, (double *)Dk, (double *)Dder);
-    k_min2<<<1, 1024, 0, s>>>(bbar, K, minb_out);
+        k_make_diag<double><<<(unsigned)((span + 255) / 256), 256, 0, s>>>(g.d, g.N, nw, cinv2, a, bbar, G.desc);
+    k_min2<<<nw, 1024, 0, s>>>(bbar, K, G.desc, minb);
     return hipGetLastError();
 }
 

@@ -382,6 +382,153 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     }
 }
 
+// Sum over the 64 lanes of a wave, returned in every lane.  FP32: DPP moves
+// inside rows of 16 lanes (swap neighbours, swap pairs, rotate by 4 and by 8),
+// then the four row sums are read with readlane; FP64 uses shuffles.
+__device__ __forceinline__ float dpp_f(float v, int ctrl_sel)
+{
+    int x = __float_as_int(v), r;
+    switch (ctrl_sel) {
+    case 0: r = __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false); break;    // quad_perm [1,0,3,2]
+    case 1: r = __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false); break;    // quad_perm [2,3,0,1]
+    case 2: r = __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false); break;   // row_ror:4
+    default: r = __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false); break;  // row_ror:8
+    }
+    return __int_as_float(r);
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+    v += dpp_f(v, 0);
+    v += dpp_f(v, 1);
+    v += dpp_f(v, 2);
+    v += dpp_f(v, 3);
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (a + b) + (c + d);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Interpolation for windows whose points come in long runs of equal cells.
+// One wave per subproblem; lane (b, c) holds the (b, c) tap column of the
+// run's grid footprint in registers (loaded once per run and vector), so each
+// point costs 2m FMAs per column plus one cross-lane sum, instead of (2m)^d
+// LDS reads per thread.  Point data are staged in LDS in chunks of 64.
+template <typename T, int D, int M, bool DER>
+__global__ void __launch_bounds__(64)
+k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
+             const int *__restrict__ sub_start, const int *__restrict__ sub_count, int ng, int nwin,
+             const typename Cplx<T>::type *__restrict__ grid, int64_t cells, int nrhs, int64_t n,
+             T *__restrict__ hbuf, T *__restrict__ dout, T dscale)
+{
+    constexpr int TW = 2 * M;
+    constexpr int RS = D * TW;
+    constexpr int NITEM = D == 1 ? TW : TW * TW;
+    constexpr int NG = (NITEM + 63) / 64;
+    constexpr int NA = D == 3 ? TW : 1;
+    constexpr int CH = 64;
+    __shared__ T s_rec[CH * RS];
+    __shared__ int s_an[CH];
+    __shared__ int s_perm[CH];
+    const int lane = threadIdx.x;
+    const int wi = sub_win[blockIdx.x];
+    const WinDesc &win = wd[wi];
+    const T *rec = reinterpret_cast<const T *>(win.rec);
+    const int start = sub_start[blockIdx.x], cnt = sub_count[blockIdx.x];
+    const int end = start + cnt;
+    int i0[NG], i1[NG];
+    T actv[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const int it = lane + 64 * g;
+        const bool a = it < NITEM;
+        actv[g] = a ? T(1) : T(0);
+        const int itc = a ? it : 0;
+        i0[g] = D == 1 ? itc : itc / TW;
+        i1[g] = D == 1 ? 0 : itc % TW;
+    }
+    T *hout = hbuf + (int64_t)win.s_global * n * nrhs;
+    T *dblk = DER ? dout + (int64_t)win.s_global * n * nrhs : nullptr;
+    for (int cb = start; cb < end; cb += CH) {
+        const int nc = min(CH, end - cb);
+        __syncthreads();
+        for (int i = lane; i < nc * RS; i += 64) s_rec[i] = rec[(int64_t)cb * RS + i];
+        if (lane < nc) {
+            s_an[lane] = win.anchor[cb + lane] & 0x7fffffff;
+            s_perm[lane] = win.perm[cb + lane];
+        }
+        __syncthreads();
+        for (int r = 0; r < nrhs; ++r) {
+            const typename Cplx<T>::type *gK = grid + ((int64_t)wi * nrhs + r) * cells;
+            const typename Cplx<T>::type *gD =
+                DER ? grid + ((int64_t)(nwin + wi) * nrhs + r) * cells : gK;
+            T G[NG][NA], GD[NG][NA];
+            int cur = -1;
+            for (int u = 0; u < nc; ++u) {
+                const int an = s_an[u];
+                if (an != cur) {
+                    cur = an;
+                    int c[3] = {0, 0, 0}, cell = an;
+                    for (int q = D - 1; q >= 0; --q) {
+                        c[q] = cell % ng - M + 1;
+                        cell /= ng;
+                    }
+#pragma unroll
+                    for (int g = 0; g < NG; ++g)
+#pragma unroll
+                        for (int a = 0; a < NA; ++a) {
+                            int64_t gi;
+                            if (D == 3) gi = ((int64_t)(c[0] + a) * ng + c[1] + i0[g]) * ng + c[2] + i1[g];
+                            else if (D == 2) gi = (int64_t)(c[0] + i0[g]) * ng + c[1] + i1[g];
+                            else gi = c[0] + i0[g];
+                            G[g][a] = gK[gi].x;
+                            if (DER) GD[g][a] = gD[gi].x;
+                        }
+                }
+                const T *rp = s_rec + u * RS;
+                T t = T(0), td = T(0);
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    if (D == 3) {
+                        T sk = T(0), sd = T(0);
+#pragma unroll
+                        for (int a = 0; a < NA; ++a) {
+                            const T w0 = rp[a];
+                            sk += w0 * G[g][a];
+                            if (DER) sd += w0 * GD[g][a];
+                        }
+                        const T wbc = actv[g] * rp[TW + i0[g]] * rp[2 * TW + i1[g]];
+                        t += sk * wbc;
+                        if (DER) td += sd * wbc;
+                    } else if (D == 2) {
+                        const T wab = actv[g] * rp[i0[g]] * rp[TW + i1[g]];
+                        t += G[g][0] * wab;
+                        if (DER) td += GD[g][0] * wab;
+                    } else {
+                        const T wa = actv[g] * rp[i0[g]];
+                        t += G[g][0] * wa;
+                        if (DER) td += GD[g][0] * wa;
+                    }
+                }
+                const T h = wave_sum(t);
+                const T hd = DER ? wave_sum(td) : T(0);
+                if (lane == 0) {
+                    const int64_t o = (int64_t)s_perm[u] * nrhs + r;
+                    hout[o] = h;
+                    if (DER) dblk[o] = dscale * hd;
+                }
+            }
+        }
+    }
+}
+
 // sigma_f^2 sum_s h^(s) + sigma_eps^2 v, summed over windows in order with
 // Kahan compensation; derivative blocks for sigma_f and sigma_eps.
 template <typename T>
@@ -449,6 +596,17 @@ hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool
 {
     const WindowGeom &g = G.g;
     using C = typename Cplx<T>::type;
+    if (G.use_run_interp) {
+        if (with_der)
+            k_interp_run<T, D, M, true><<<(unsigned)G.nrsub, 64, 0, s>>>(
+                G.desc, G.rsub_win, G.rsub_start, G.rsub_count, g.ng, G.nwin, (const C *)grid, g.cells,
+                nrhs, n, (T *)hbuf, (T *)dout, (T)dscale);
+        else
+            k_interp_run<T, D, M, false><<<(unsigned)G.nrsub, 64, 0, s>>>(
+                G.desc, G.rsub_win, G.rsub_start, G.rsub_count, g.ng, G.nwin, (const C *)grid, g.cells,
+                nrhs, n, (T *)hbuf, nullptr, (T)dscale);
+        return hipGetLastError();
+    }
     size_t shm = (size_t)g.pc * sizeof(T) * (with_der ? 2 : 1);
     hipError_t e = with_der ? allow_lds(k_interp<T, D, M, true>, shm) : allow_lds(k_interp<T, D, M, false>, shm);
     if (e != hipSuccess) return e;
@@ -547,7 +705,7 @@ hipError_t launch_fold(int prec, const Group &G, int m, int nrhs, void *tilebuf,
 hipError_t launch_interp(int prec, const Group &G, int m, int64_t n, int nrhs, const void *grid,
                          bool with_der, void *hbuf, void *dout, double dscale, hipStream_t s)
 {
-    if (G.nisub == 0) return hipSuccess;
+    if (G.nisub == 0 && G.nrsub == 0) return hipSuccess;
     return prec == NFFTGP_F32
                ? interp_t<float>(G, m, n, nrhs, grid, with_der, hbuf, dout, dscale, s)
                : interp_t<double>(G, m, n, nrhs, grid, with_der, hbuf, dout, dscale, s);

@@ -23,6 +23,10 @@ inline double kb_beta() { return kPi * (2.0 - 1.0 / kSigma); }
 
 // Points handled by one interpolation work-group at most (one per thread).
 constexpr int kInterpSubPoints = 256;
+// Points per wave in run-based interpolation, and the average run length
+// (points per occupied cell) from which it is used for 3-D windows.
+constexpr int kRunSubPoints = 512;
+constexpr int kRunInterpMinRun = 24;
 
 // Geometry of one window's oversampled grid and its tiling.
 struct WindowGeom {
@@ -53,9 +57,9 @@ struct Window {
     int32_t *bin_sub_ptr = nullptr;  // tile -> spreading subproblems of its group (nbins + 1)
     void *Dk = nullptr;     // symmetrised diagonal for K_s (dcells, plan precision)
     void *Dder = nullptr;   // same for K_s^der
-    double *cinv2 = nullptr;  // N+1 per-dimension factors 1 / c(k)^2 of the window
     // host copies used while the plan is built
     std::vector<int> h_bin_start;
+    int64_t h_cells_used = 0;   // occupied grid cells (runs of equal cells)
 };
 
 // Per-window data a kernel needs, in device memory (one array per group).
@@ -82,6 +86,13 @@ struct Group {
     int32_t *isub_win = nullptr, *isub_bin = nullptr, *isub_start = nullptr, *isub_count = nullptr;
     int nisub = 0;               // interpolation subproblems
     int nbins_used = 0;          // tiles holding at least one point
+    // interpolation by register-held runs (chosen when runs of equal cells are long):
+    // contiguous ranges of at most kRunSubPoints sorted points
+    bool use_run_interp = false;
+    int32_t *rsub_win = nullptr, *rsub_start = nullptr, *rsub_count = nullptr;
+    int nrsub = 0;
+    double *cinv2 = nullptr;     // N+1 window factors 1 / c(k)^2 (same for the whole group)
+    double2 *tw = nullptr;       // N twiddles exp(-2 pi i j / N) for the coefficient DFT
 };
 
 }  // namespace nfftgp
@@ -106,7 +117,9 @@ struct nfftgp_plan_s {
     void *hbuf = nullptr;        // P x n x max_nrhs per-window products
     double *coef = nullptr;      // 4 x maxN^d complex doubles (set_hyper scratch)
     double *bbar = nullptr;      // 2 x maxN^d doubles
-    double *minb = nullptr;      // 2 x P doubles
+    double *minb = nullptr;      // 2 x P doubles (device)
+    double *minb_host = nullptr; // 2 x P doubles (pinned host copy, read lazily)
+    bool minb_pending = false;
     double *dot_part = nullptr;  // dot-product partials
     double *cg_scal = nullptr;   // CG per-column scalars
     double *cg_hist = nullptr;   // CG (alpha, beta) history
@@ -159,19 +172,28 @@ hipError_t launch_sort(int prec, int64_t n, int d, int nbins, const int *keys, c
                        int *bin_start, hipStream_t s);
 hipError_t launch_bin_keys(int prec, const void *t, int64_t n, const WindowGeom &g, int *keys,
                            hipStream_t s);
-// Window weights and packed cells (with run-end flags) of the sorted points.
+// Window weights and packed cells (with run-end flags) of the sorted points;
+// *runs (zeroed by the caller) is increased by the number of runs of equal cells.
 double kb_knorm(int m);
 hipError_t launch_weights(int prec, const void *t, int64_t n, const WindowGeom &g, int m,
-                          double knorm, void *rec, int *anchor, hipStream_t s);
+                          double knorm, void *rec, int *anchor, int *runs, hipStream_t s);
 
 // ---------------------------------------------------------------- per-theta kernels
 // Coefficients b_k, b^der_k of one window (FP64) and the symmetrised diagonals.
+// Per-window parameters of one group's coefficient kernels (passed by value).
+struct CoefParams {
+    double ell[NFFTGP_MAX_WINDOWS];
+    double c[NFFTGP_MAX_WINDOWS];
+    int32_t kernel[NFFTGP_MAX_WINDOWS];
+    int32_t nwin;
+};
 hipError_t launch_window_coef(int N, int m, double *cinv2, hipStream_t s);
-hipError_t launch_coefficients(int prec, const WindowGeom &g, int m, int kernel, double ell,
-                               double c, const double *cinv2, double *coef, double *bbar, void *Dk,
-                               void *Dder, double *minb_out, hipStream_t s);
+hipError_t launch_twiddles(int N, double2 *tw, hipStream_t s);
 
 // ---------------------------------------------------------------- apply kernels
+hipError_t launch_coefficients(int prec, const Group &G, const CoefParams &prm, const double *cinv2,
+                               const double2 *tw, double *coef, double *bbar, double *minb,
+                               hipStream_t s);
 hipError_t launch_spread(int prec, const Group &G, int m, const void *V, int64_t ldv, int nrhs,
                          void *tilebuf, hipStream_t s);
 hipError_t launch_fold(int prec, const Group &G, int m, int nrhs, void *tilebuf, void *grid,
