@@ -180,9 +180,9 @@ enum {
     NFFTGP_PROF_FILL = 0,     /* clearing of the window-sum accumulators      */
     NFFTGP_PROF_SPREAD = 1,   /* window spreading onto the tiles              */
     NFFTGP_PROF_FOLD = 2,     /* sum of overlapping tiles into the grid       */
-    NFFTGP_PROF_FFT_FWD = 3,  /* forward FFT passes                           */
-    NFFTGP_PROF_DIAG = 4,     /* diagonal multiply                            */
-    NFFTGP_PROF_FFT_INV = 5,  /* inverse FFT passes                           */
+    NFFTGP_PROF_FFT_FWD = 3,  /* forward FFT passes of axes d-1..1            */
+    NFFTGP_PROF_DIAG = 4,     /* axis 0: forward FFT, diagonal, inverse FFT   */
+    NFFTGP_PROF_FFT_INV = 5,  /* inverse FFT passes of axes 1..d-1            */
     NFFTGP_PROF_INTERP = 6,   /* window interpolation and window sum          */
     NFFTGP_PROF_ASSEMBLE = 7, /* sigma scaling and derivative blocks          */
     NFFTGP_PROF_COEF = 8,     /* per-theta coefficient kernels                */

@@ -152,12 +152,13 @@ nfftgp_status apply_impl(nfftgp_plan p, const void *V, int64_t ldv, int nrhs, vo
     const bool with_der = dell != nullptr;
     if (p->n == 0) return NFFTGP_OK;
     for (const Group &G : p->groups) {
-        const int b = G.nwin * nrhs;
         PROF_LAUNCH(p, NFFTGP_PROF_SPREAD, launch_spread(p->prec, G, p->m, V, ldv, nrhs, p->tilebuf, s));
         PROF_LAUNCH(p, NFFTGP_PROF_FOLD, launch_fold(p->prec, G, p->m, nrhs, p->tilebuf, p->grid, s));
-        PROF_LAUNCH(p, NFFTGP_PROF_FFT_FWD, launch_fft(p->prec, G.g, p->grid, b, false, s));
-        PROF_LAUNCH(p, NFFTGP_PROF_DIAG, launch_diag(p->prec, G, nrhs, p->grid, with_der, s));
-        PROF_LAUNCH(p, NFFTGP_PROF_FFT_INV, launch_fft(p->prec, G.g, p->grid, b * (with_der ? 2 : 1), true, s));
+        if (G.g.d > 1)
+            PROF_LAUNCH(p, NFFTGP_PROF_FFT_FWD, launch_fft_fwd(p->prec, G, p->m, p->grid, nrhs, s));
+        PROF_LAUNCH(p, NFFTGP_PROF_DIAG, launch_fft_diag(p->prec, G, p->m, p->grid, nrhs, with_der, s));
+        if (G.g.d > 1)
+            PROF_LAUNCH(p, NFFTGP_PROF_FFT_INV, launch_fft_inv(p->prec, G, p->m, p->grid, nrhs, with_der, s));
         PROF_LAUNCH(p, NFFTGP_PROF_INTERP,
                     launch_interp(p->prec, G, p->m, p->n, nrhs, p->grid, with_der, p->hbuf, dell,
                                   p->sigma_f * p->sigma_f, s));
@@ -317,12 +318,13 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         TRYS(dalloc(plan, (void **)&w.perm, n1 * sizeof(int)));
         TRYS(dalloc(plan, &w.rec, n1 * d * 2 * m * eb));
         TRYS(dalloc(plan, (void **)&w.anchor, n1 * sizeof(int)));
+        TRYS(dalloc(plan, (void **)&w.lpos, n1 * sizeof(int)));
         TRYH(launch_coords(prec, X_dev, n, ldx, d, w.feat, w.c0, w.c, w.g, t_uns, keys, flags + 1, st));
         TRYH(launch_sort(prec, n, d, local, keys, nullptr, t_uns, hist, scan_tmp, ids1, t1, bin_start, st));
         TRYH(launch_bin_keys(prec, t1, n, w.g, keys, st));
         TRYH(launch_sort(prec, n, d, w.g.nbins, keys, ids1, t1, hist, scan_tmp, w.perm, t2,
                          bin_start, st));
-        TRYH(launch_weights(prec, t2, n, w.g, m, kb_knorm(m), w.rec, w.anchor, flags + 2, st));
+        TRYH(launch_weights(prec, t2, n, w.g, m, kb_knorm(m), w.rec, w.anchor, w.lpos, flags + 2, st));
         std::vector<int> bs(w.g.nbins + 1);
         TRYH(hipMemcpyAsync(bs.data(), bin_start, (w.g.nbins + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
         TRYH(hipMemcpyAsync(hflags, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -357,7 +359,7 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
     size_t grid_need = 1, coef_need = 8;
     for (Group &G : plan->groups) {
         G.nwin = (int)G.wins.size();
-        std::vector<int> sw, sb, ss, sc, iw, ib, is, ic;
+        std::vector<int> sw, sb, ss, sc, iw, ib, is, ic, fbl;
         std::vector<WinDesc> hd(G.nwin);
         for (int wl = 0; wl < G.nwin; ++wl) {
             Window &w = plan->win[G.wins[wl]];
@@ -374,6 +376,7 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
                     sc.push_back(std::min(sub_sp, cnt - off));
                 }
                 bsp[b + 1] = (int)sb.size();
+                if (bsp[b + 1] - bsp[b] >= 2) fbl.push_back(wl * w.g.nbins + b);
                 for (int off = 0; off < cnt; off += kInterpSubPoints) {
                     iw.push_back(wl);
                     ib.push_back(b);
@@ -383,7 +386,7 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
             }
             TRYS(dalloc(plan, (void **)&w.bin_sub_ptr, (w.g.nbins + 1) * sizeof(int)));
             TRYH(hipMemcpy(w.bin_sub_ptr, bsp.data(), (w.g.nbins + 1) * sizeof(int), hipMemcpyHostToDevice));
-            hd[wl] = WinDesc{w.rec, w.anchor, w.perm, w.bin_sub_ptr, w.Dk, w.Dder, G.wins[wl], 0};
+            hd[wl] = WinDesc{w.rec, w.anchor, w.lpos, w.perm, w.bin_sub_ptr, w.Dk, w.Dder, G.wins[wl], 0};
         }
         G.nsub = (int)sb.size();
         G.nisub = (int)ib.size();
@@ -424,10 +427,11 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
                     TRYH(hipMemcpy(*rdst[k], rsrc[k]->data(), rsrc[k]->size() * sizeof(int), hipMemcpyHostToDevice));
             }
         }
-        int32_t **dst[8] = {&G.sub_win, &G.sub_bin, &G.sub_start, &G.sub_count,
-                            &G.isub_win, &G.isub_bin, &G.isub_start, &G.isub_count};
-        std::vector<int> *srcv[8] = {&sw, &sb, &ss, &sc, &iw, &ib, &is, &ic};
-        for (int k = 0; k < 8; ++k) {
+        G.nfb = (int)fbl.size();
+        int32_t **dst[9] = {&G.sub_win, &G.sub_bin, &G.sub_start, &G.sub_count,
+                            &G.isub_win, &G.isub_bin, &G.isub_start, &G.isub_count, &G.fb};
+        std::vector<int> *srcv[9] = {&sw, &sb, &ss, &sc, &iw, &ib, &is, &ic, &fbl};
+        for (int k = 0; k < 9; ++k) {
             TRYS(dalloc(plan, (void **)dst[k], std::max<size_t>(1, srcv[k]->size()) * sizeof(int)));
             if (!srcv[k]->empty())
                 TRYH(hipMemcpy(*dst[k], srcv[k]->data(), srcv[k]->size() * sizeof(int), hipMemcpyHostToDevice));

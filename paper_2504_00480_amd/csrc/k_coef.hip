@@ -28,27 +28,13 @@ __device__ double bessel_i0(double z)
     return sum;
 }
 
-// Samples of every window of a group: arrays [window][2][K] of complex values
-// (kernel, then ell-derivative), K = N^d, index l + N/2 per axis.
-__global__ void k_sample(int d, int N, CoefParams prm, double *__restrict__ coef)
+// Kernel and ell-derivative samples at grid offset l (index set [-N/2, N/2)^d,
+// spacing 1/N in scaled units); r is the distance in caller units.
+__device__ __forceinline__ void sample_pair(const CoefParams &prm, int w, double r2, double &v,
+                                            double &dv)
 {
-    int64_t K = 1;
-    for (int q = 0; q < d; ++q) K *= N;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= K * prm.nwin) return;
-    const int w = (int)(idx / K);
-    const int64_t e = idx % K;
-    int64_t rem = e;
-    double r2 = 0.0;
-    for (int q = 0; q < d; ++q) {
-        int l = (int)(rem % N) - N / 2;
-        rem /= N;
-        double x = (double)l / (double)N;
-        r2 += x * x;
-    }
     const double ell = prm.ell[w];
-    const double r = sqrt(r2) / prm.c[w];   // distance in caller units
-    double v, dv;
+    const double r = sqrt(r2) / prm.c[w];
     if (prm.kernel[w] == NFFTGP_GAUSS) {
         v = exp(-(r * r) / (2.0 * ell * ell));
         dv = (r * r) / (ell * ell * ell) * v;
@@ -56,16 +42,52 @@ __global__ void k_sample(int d, int N, CoefParams prm, double *__restrict__ coef
         v = exp(-r / ell);
         dv = r / (ell * ell) * v;
     }
-    double *base = coef + (int64_t)w * 4 * K;
-    base[2 * e] = v;
-    base[2 * e + 1] = 0.0;
-    base[2 * (K + e)] = dv;
-    base[2 * (K + e) + 1] = 0.0;
 }
 
-// One axis of the d-dimensional DFT, applied to all 2 x nwin stacked arrays:
-// out[.., k, ..] = sum_l in[.., l, ..] exp(-2 pi i l k / N), l, k in [-N/2, N/2);
-// tw[j] = exp(-2 pi i j / N).
+// First DFT axis (axis 0) of the samples of every window of a group, with the
+// samples evaluated on the fly.  Output arrays [window][2][K] of complex values
+// (kernel, then ell-derivative), K = N^d, index l + N/2 per axis:
+// out[k, rest] = sum_l f(l, rest) exp(-2 pi i l k / N); tw[j] = exp(-2 pi i j / N).
+__global__ void k_dft_first(int d, int N, CoefParams prm, const double2 *__restrict__ tw,
+                            double *__restrict__ out)
+{
+    int64_t K = 1;
+    for (int q = 0; q < d; ++q) K *= N;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= K * prm.nwin) return;
+    const int w = (int)(idx / K);
+    const int64_t e = idx % K;
+    const int64_t stride = K / N;                  // axis 0 is the slowest index
+    const int k = (int)(e / stride) - N / 2;
+    int64_t rem = e % stride;
+    double rest2 = 0.0;
+    for (int q = 1; q < d; ++q) {
+        const int l = (int)(rem % N) - N / 2;      // last axis fastest
+        rem /= N;
+        const double x = (double)l / (double)N;
+        rest2 += x * x;
+    }
+    double sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
+    for (int ll = 0; ll < N; ++ll) {
+        const int l = ll - N / 2;
+        const double x = (double)l / (double)N;
+        double v, dv;
+        sample_pair(prm, w, rest2 + x * x, v, dv);
+        const double2 t = tw[(l * k) & (N - 1)];   // N is a power of two
+        sr += v * t.x;
+        si += v * t.y;
+        dr += dv * t.x;
+        di += dv * t.y;
+    }
+    double *base = out + (int64_t)w * 4 * K;
+    base[2 * e] = sr;
+    base[2 * e + 1] = si;
+    base[2 * (K + e)] = dr;
+    base[2 * (K + e) + 1] = di;
+}
+
+// One further axis of the d-dimensional DFT, applied to all 2 x nwin stacked
+// arrays: out[.., k, ..] = sum_l in[.., l, ..] exp(-2 pi i l k / N).
 __global__ void k_dft_axis(int d, int N, int axis, int narr, const double2 *__restrict__ tw,
                            const double *__restrict__ in, double *__restrict__ out)
 {
@@ -82,7 +104,7 @@ __global__ void k_dft_axis(int d, int N, int axis, int narr, const double2 *__re
     double sr = 0.0, si = 0.0;
     for (int ll = 0; ll < N; ++ll) {
         int l = ll - N / 2;
-        const double2 t = tw[((l * k) % N + N) % N];
+        const double2 t = tw[(l * k) & (N - 1)];
         double ar = in[2 * (base + (int64_t)ll * stride)], ai = in[2 * (base + (int64_t)ll * stride) + 1];
         sr += ar * t.x - ai * t.y;
         si += ar * t.y + ai * t.x;
@@ -113,75 +135,93 @@ __global__ void k_window_coef(int N, int m, double beta, double *__restrict__ ci
     cinv2[i] = 1.0 / (c * c);
 }
 
+// Grid (ceil(span / 256), nwin): block x of window y.  Besides the diagonal,
+// every block writes the minima of the plain coefficients b_k, b^der_k it
+// visited to part[(y * gridDim.x + x) * 2 + {0, 1}].
 template <typename T>
-__global__ void k_make_diag(int d, int N, int nwin, const double *__restrict__ cinv2,
-                            const double *__restrict__ coef, double *__restrict__ bbar,
-                            const WinDesc *__restrict__ wd)
+__global__ void __launch_bounds__(256)
+k_make_diag(int d, int N, const double *__restrict__ cinv2, const double *__restrict__ coef,
+            const WinDesc *__restrict__ wd, double *__restrict__ part)
 {
+    __shared__ double s0[256], s1[256];
     int64_t K = 1, KD = 1;
     for (int q = 0; q < d; ++q) {
         K *= N;
         KD *= (N + 1);
     }
-    const int64_t span = KD > K ? KD : K;
-    int64_t gidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gidx >= span * nwin) return;
-    const int w = (int)(gidx / span);
-    const int64_t idx = gidx % span;
+    const int w = blockIdx.y;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const double *B = coef + (int64_t)w * 4 * K;
     const double invK = 1.0 / (double)K;
+    double mk = INFINITY, md = INFINITY;
     if (idx < K) {   // plain coefficients on I_N (for the definiteness report)
-        bbar[(int64_t)w * 2 * K + idx] = B[2 * idx] * invK;
-        bbar[(int64_t)w * 2 * K + K + idx] = B[2 * (K + idx)] * invK;
+        mk = B[2 * idx] * invK;
+        md = B[2 * (K + idx)] * invK;
     }
-    if (idx >= KD) return;
-    int kv[3] = {0, 0, 0};
-    int64_t rem = idx;
-    for (int q = d - 1; q >= 0; --q) {
-        kv[q] = (int)(rem % (N + 1)) - N / 2;
-        rem /= (N + 1);
+    if (idx < KD) {
+        int kv[3] = {0, 0, 0};
+        int64_t rem = idx;
+        for (int q = d - 1; q >= 0; --q) {
+            kv[q] = (int)(rem % (N + 1)) - N / 2;
+            rem /= (N + 1);
+        }
+        bool in_pos = true, in_neg = true;
+        int64_t ip = 0, in_ = 0;
+        double f = 1.0;
+        for (int q = 0; q < d; ++q) {
+            in_pos = in_pos && (kv[q] < N / 2);
+            in_neg = in_neg && (-kv[q] < N / 2);
+            ip = ip * N + (kv[q] + N / 2);
+            in_ = in_ * N + (-kv[q] + N / 2);
+            f *= cinv2[kv[q] + N / 2];
+        }
+        double bk = 0.0, bd = 0.0;
+        if (in_pos) {
+            bk += B[2 * ip] * invK;
+            bd += B[2 * (K + ip)] * invK;
+        }
+        if (in_neg) {
+            bk += B[2 * in_] * invK;
+            bd += B[2 * (K + in_)] * invK;
+        }
+        reinterpret_cast<T *>(const_cast<void *>(wd[w].Dk))[idx] = (T)(0.5 * bk * f);
+        reinterpret_cast<T *>(const_cast<void *>(wd[w].Dder))[idx] = (T)(0.5 * bd * f);
     }
-    bool in_pos = true, in_neg = true;
-    int64_t ip = 0, in_ = 0;
-    double f = 1.0;
-    for (int q = 0; q < d; ++q) {
-        in_pos = in_pos && (kv[q] < N / 2);
-        in_neg = in_neg && (-kv[q] < N / 2);
-        ip = ip * N + (kv[q] + N / 2);
-        in_ = in_ * N + (-kv[q] + N / 2);
-        f *= cinv2[kv[q] + N / 2];
+    s0[threadIdx.x] = mk;
+    s1[threadIdx.x] = md;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            s0[threadIdx.x] = fmin(s0[threadIdx.x], s0[threadIdx.x + off]);
+            s1[threadIdx.x] = fmin(s1[threadIdx.x], s1[threadIdx.x + off]);
+        }
+        __syncthreads();
     }
-    double bk = 0.0, bd = 0.0;
-    if (in_pos) {
-        bk += B[2 * ip] * invK;
-        bd += B[2 * (K + ip)] * invK;
+    if (threadIdx.x == 0) {
+        const int64_t o = ((int64_t)w * gridDim.x + blockIdx.x) * 2;
+        part[o] = s0[0];
+        part[o + 1] = s1[0];
     }
-    if (in_neg) {
-        bk += B[2 * in_] * invK;
-        bd += B[2 * (K + in_)] * invK;
-    }
-    reinterpret_cast<T *>(const_cast<void *>(wd[w].Dk))[idx] = (T)(0.5 * bk * f);
-    reinterpret_cast<T *>(const_cast<void *>(wd[w].Dder))[idx] = (T)(0.5 * bd * f);
 }
 
-// Smallest b_k and b^der_k of every window of the group (one block per window),
-// written to minb[2 * s_global + {0, 1}].
-__global__ void __launch_bounds__(1024)
-k_min2(const double *__restrict__ bbar, int64_t K, const WinDesc *__restrict__ wd,
+// Smallest b_k and b^der_k of every window of the group (one block per window)
+// from the block minima, written to minb[2 * s_global + {0, 1}].
+__global__ void __launch_bounds__(256)
+k_min2(const double *__restrict__ part, int nper, const WinDesc *__restrict__ wd,
        double *__restrict__ minb)
 {
-    __shared__ double s0[1024], s1[1024];
+    __shared__ double s0[256], s1[256];
     const int w = blockIdx.x;
-    const double *v = bbar + (int64_t)w * 2 * K;
+    const double *v = part + (int64_t)w * nper * 2;
     double a = INFINITY, b = INFINITY;
-    for (int64_t i = threadIdx.x; i < K; i += 1024) {
-        a = fmin(a, v[i]);
-        b = fmin(b, v[K + i]);
+    for (int i = threadIdx.x; i < nper; i += 256) {
+        a = fmin(a, v[2 * i]);
+        b = fmin(b, v[2 * i + 1]);
     }
     s0[threadIdx.x] = a;
     s1[threadIdx.x] = b;
     __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
+    for (int off = 128; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) {
             s0[threadIdx.x] = fmin(s0[threadIdx.x], s0[threadIdx.x + off]);
             s1[threadIdx.x] = fmin(s1[threadIdx.x], s1[threadIdx.x + off]);
@@ -220,19 +260,20 @@ hipError_t launch_coefficients(int prec, const Group &G, const CoefParams &prm, 
     }
     const int nw = G.nwin;
     double *a = coef, *b = coef + (int64_t)nw * 4 * K;   // ping-pong: [window][2][K] complex each
-    k_sample<<<(unsigned)((nw * K + 255) / 256), 256, 0, s>>>(g.d, g.N, prm, a);
-    for (int q = 0; q < g.d; ++q) {
+    k_dft_first<<<(unsigned)((nw * K + 255) / 256), 256, 0, s>>>(g.d, g.N, prm, tw, a);
+    for (int q = 1; q < g.d; ++q) {
         k_dft_axis<<<(unsigned)((2 * nw * K + 255) / 256), 256, 0, s>>>(g.d, g.N, q, 2 * nw, tw, a, b);
         double *t = a;
         a = b;
         b = t;
     }
-    const int64_t span = (KD > K ? KD : K) * nw;
+    const unsigned nper = (unsigned)(((KD > K ? KD : K) + 255) / 256);
+    const dim3 grid(nper, (unsigned)nw);
     if (prec == NFFTGP_F32)
-        k_make_diag<float><<<(unsigned)((span + 255) / 256), 256, 0, s>>>(g.d, g.N, nw, cinv2, a, bbar, G.desc);
+        k_make_diag<float><<<grid, 256, 0, s>>>(g.d, g.N, cinv2, a, G.desc, bbar);
     else
-        k_make_diag<double><<<(unsigned)((span + 255) / 256), 256, 0, s>>>(g.d, g.N, nw, cinv2, a, bbar, G.desc);
-    k_min2<<<nw, 1024, 0, s>>>(bbar, K, G.desc, minb);
+        k_make_diag<double><<<grid, 256, 0, s>>>(g.d, g.N, cinv2, a, G.desc, bbar);
+    k_min2<<<nw, 256, 0, s>>>(bbar, (int)nper, G.desc, minb);
     return hipGetLastError();
 }
 

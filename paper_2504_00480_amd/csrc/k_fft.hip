@@ -2,15 +2,28 @@
 // forward and inverse transforms (Appendix A steps 1-2 and their adjoint).
 //
 // The grid is stored [batch][l_0][l_1]...[l_{d-1}] (last index fastest) as
-// interleaved complex values.  A work-group transforms 16 lines along one axis
-// in LDS (iterative radix-2 after a bit-reversed load); for strided axes the
-// 16 lines are adjacent in the fastest index, so every global access is a
-// contiguous run of 16 complex values.  The forward transform uses
+// interleaved complex values.  The forward transform uses
 // exp(-2 pi i k l / n_g), the inverse exp(+2 pi i k l / n_g) without scaling.
-//
 // Grid index l corresponds to the spatial offset l - N; the sign factor
 // (-1)^k this introduces in both transforms cancels in the product, so the
 // diagonal is applied at the plain signed frequency k.
+//
+// Pruning.  Every point has t in [N/2, 3N/2], so spreading only reaches the
+// cells Omega = [N/2 - m + 1, 3N/2 + m] of each axis and interpolation only
+// reads them; the diagonal is zero outside the frequencies
+// F = [-N/2, N/2] (indices 0..N/2 and 2N - N/2..2N-1).  Axis by axis, the
+// forward transform of axis q reads Omega and keeps F, the inverse reads F and
+// writes Omega, and a line of axis q only exists for the positions its other
+// axes hold at that stage: Omega for the axes before q, F for those after
+// (the axes are transformed from the last to the first and back).  Cells and
+// frequencies outside these ranges are never read, so they need not be
+// cleared.  The first axis is transformed forward, multiplied by the diagonal
+// (and by the derivative diagonal) and transformed back in one pass.
+//
+// A work-group transforms LPB lines of one axis in LDS (iterative radix-2
+// after a bit-reversed load).  Lines are numbered with the fastest other axis
+// varying fastest, so for strided axes consecutive lines of a group read
+// consecutive addresses.
 #include "nfftgp_impl.h"
 
 namespace nfftgp {
@@ -20,57 +33,30 @@ template <typename T> struct Cplx;
 template <> struct Cplx<float> { using type = float2; };
 template <> struct Cplx<double> { using type = double2; };
 
-constexpr int kLines = 16;
+// Position j of a cyclic range (start, len) on a grid of edge ng (power of 2).
+__device__ __forceinline__ int cyc_pos(int start, int j, int ng) { return (start + j) & (ng - 1); }
+__device__ __forceinline__ bool cyc_has(int start, int len, int k, int ng)
+{
+    return ((k - start) & (ng - 1)) < len;
+}
 
-template <typename T, int LOGN, bool INV>
-__global__ void __launch_bounds__(256)
-k_fft_lines(typename Cplx<T>::type *__restrict__ data, int64_t S, int64_t nlines)
+struct PruneGeom {
+    int d, ng, N;
+    int olo, on;   // Omega: cells olo .. olo + on - 1
+    int flo, fn;   // F: indices flo .. flo + fn - 1 modulo ng
+    int64_t cells;
+};
+
+template <typename T, int LOGN>
+__device__ __forceinline__ void fft_stages(typename Cplx<T>::type (*buf)[(1 << LOGN) + 1],
+                                           const typename Cplx<T>::type *tw, int lpb)
 {
     using C = typename Cplx<T>::type;
     constexpr int NG = 1 << LOGN;
-    __shared__ C buf[kLines][NG + 1];
-    __shared__ C tw[NG / 2];
-    for (int t = threadIdx.x; t < NG / 2; t += blockDim.x) {
-        double sn, cs;
-        sincospi((INV ? 2.0 : -2.0) * (double)t / (double)NG, &sn, &cs);
-        tw[t].x = (T)cs;
-        tw[t].y = (T)sn;
-    }
-    const int64_t b = blockIdx.x;
-    int64_t outer0 = 0, outer = 0, inner0 = 0;
-    if (S == 1) {
-        outer0 = b * kLines;
-    } else {
-        const int64_t nib = S / kLines;
-        outer = b / nib;
-        inner0 = (b % nib) * kLines;
-    }
-    for (int idx = threadIdx.x; idx < kLines * NG; idx += blockDim.x) {
-        int li, k;
-        int64_t addr;
-        bool ok = true;
-        if (S == 1) {
-            li = idx / NG;
-            k = idx % NG;
-            ok = outer0 + li < nlines;
-            addr = (outer0 + li) * NG + k;
-        } else {
-            k = idx / kLines;
-            li = idx % kLines;
-            addr = outer * NG * S + (int64_t)k * S + inner0 + li;
-        }
-        const int rk = (int)(__brev((unsigned)k) >> (32 - LOGN));
-        C v;
-        v.x = T(0);
-        v.y = T(0);
-        if (ok) v = data[addr];
-        buf[li][rk] = v;
-    }
-    __syncthreads();
 #pragma unroll
     for (int s = 1; s <= LOGN; ++s) {
         const int len = 1 << s, half = len >> 1;
-        for (int bfi = threadIdx.x; bfi < kLines * NG / 2; bfi += blockDim.x) {
+        for (int bfi = threadIdx.x; bfi < lpb * NG / 2; bfi += blockDim.x) {
             const int li = bfi / (NG / 2), rest = bfi % (NG / 2);
             const int grp = rest / half, j = rest % half;
             const int i0 = grp * len + j, i1 = i0 + half;
@@ -89,138 +75,248 @@ k_fft_lines(typename Cplx<T>::type *__restrict__ data, int64_t S, int64_t nlines
         }
         __syncthreads();
     }
-    for (int idx = threadIdx.x; idx < kLines * NG; idx += blockDim.x) {
+}
+
+// MODE 0: forward transform of axis ax (reads Omega, writes F);
+// MODE 1: inverse transform of axis ax (reads F, writes Omega);
+// MODE 2: axis 0 forward, diagonal, inverse (reads Omega, writes Omega of the
+//         K block and, with DER, of the derivative block der_off batches on).
+template <typename T, int LOGN, int LPB, int MODE, bool DER>
+__global__ void __launch_bounds__(256)
+k_fft_pruned(typename Cplx<T>::type *__restrict__ data, PruneGeom pg, int ax, int64_t nlines,
+             int64_t lines_per_batch, const WinDesc *__restrict__ wd, int nrhs, int64_t der_off)
+{
+    using C = typename Cplx<T>::type;
+    constexpr int NG = 1 << LOGN;
+    __shared__ C buf[LPB][NG + 1];
+    __shared__ C buf2[MODE == 2 ? LPB : 1][MODE == 2 ? NG + 1 : 1];
+    __shared__ C twf[NG / 2];
+    __shared__ C twi[MODE == 2 ? NG / 2 : 1];
+    __shared__ int64_t s_base[LPB];
+    __shared__ int s_ok[LPB];
+    __shared__ int s_di[LPB];
+    __shared__ int s_win[LPB];
+    for (int t = threadIdx.x; t < NG / 2; t += blockDim.x) {
+        double sn, cs;
+        sincospi((MODE == 1 ? 2.0 : -2.0) * (double)t / (double)NG, &sn, &cs);
+        twf[t].x = (T)cs;
+        twf[t].y = (T)sn;
+        if (MODE == 2) {
+            twi[t].x = (T)cs;
+            twi[t].y = (T)(-sn);
+        }
+    }
+    const int ng = NG;
+    int64_t S = 1;
+    for (int q = ax + 1; q < pg.d; ++q) S *= ng;
+    // line bases: other axes before ax hold Omega, after ax hold F
+    if ((int)threadIdx.x < LPB) {
+        const int li = threadIdx.x;
+        const int64_t L = (int64_t)blockIdx.x * LPB + li;
+        const bool ok = L < nlines;
+        const int64_t Lc = ok ? L : 0;
+        const int64_t b = Lc / lines_per_batch;
+        int64_t rem = Lc % lines_per_batch;
+        int64_t base = b * pg.cells;
+        int di = 0, dstride = 1;   // offset in the (N+1)^d diagonal of the F axes
+        int64_t stride = 1;
+        for (int q = pg.d - 1; q >= 0; --q) {
+            if (q != ax) {
+                const bool om = q < ax;
+                const int len = om ? pg.on : pg.fn;
+                const int j = (int)(rem % len);
+                rem /= len;
+                const int pos = cyc_pos(om ? pg.olo : pg.flo, j, ng);
+                base += (int64_t)pos * stride;
+                if (!om) {
+                    const int f = pos < pg.N ? pos : pos - ng;
+                    di += (f + pg.N / 2) * dstride;
+                }
+            }
+            dstride *= pg.N + 1;
+            stride *= ng;
+        }
+        s_base[li] = base;
+        s_ok[li] = ok;
+        s_di[li] = di;
+        s_win[li] = (int)(b / nrhs);
+    }
+    __syncthreads();
+    const bool in_om = MODE != 1;                    // input set: Omega or F
+    const int ilo = in_om ? pg.olo : pg.flo, ilen = in_om ? pg.on : pg.fn;
+    for (int idx = threadIdx.x; idx < LPB * NG; idx += blockDim.x) {
         int li, k;
-        int64_t addr;
-        bool ok = true;
         if (S == 1) {
             li = idx / NG;
             k = idx % NG;
-            ok = outer0 + li < nlines;
-            addr = (outer0 + li) * NG + k;
         } else {
-            k = idx / kLines;
-            li = idx % kLines;
-            addr = outer * NG * S + (int64_t)k * S + inner0 + li;
+            k = idx / LPB;
+            li = idx % LPB;
         }
-        if (ok) data[addr] = buf[li][k];
+        C v;
+        v.x = T(0);
+        v.y = T(0);
+        if (s_ok[li] && cyc_has(ilo, ilen, k, ng)) v = data[s_base[li] + (int64_t)k * S];
+        buf[li][__brev((unsigned)k) >> (32 - LOGN)] = v;
     }
-}
-
-// Multiply the spectrum by the symmetrised diagonal on [-N/2, N/2]^d and clear
-// every other frequency.  The spectra of a group are stored [window][vector]
-// [cell]; with DER the same input also gives the derivative spectrum, written
-// one group-block further on.
-template <typename T, int D, bool DER>
-__global__ void __launch_bounds__(256)
-k_diag(typename Cplx<T>::type *__restrict__ spec, const WinDesc *__restrict__ wd, int N,
-       int nrhs, int64_t cells, int64_t total)
-{
-    using C = typename Cplx<T>::type;
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const WinDesc &win = wd[idx / ((int64_t)nrhs * cells)];
-    int64_t rem = idx % cells;
-    const int ng = 2 * N;
-    bool in = true;
-    int64_t di = 0, stride = 1;
-    for (int q = D - 1; q >= 0; --q) {
-        int K = (int)(rem % ng);
-        rem /= ng;
-        int f = K < N ? K : K - ng;
-        in = in && (f >= -N / 2) && (f <= N / 2);
-        di += (int64_t)(f + N / 2) * stride;
-        stride *= (N + 1);
-    }
-    C v = spec[idx];
-    C ok, od;
-    if (in) {
-        T dk = reinterpret_cast<const T *>(win.Dk)[di];
-        ok.x = v.x * dk;
-        ok.y = v.y * dk;
-        if (DER) {
-            T dd = reinterpret_cast<const T *>(win.Dder)[di];
-            od.x = v.x * dd;
-            od.y = v.y * dd;
+    __syncthreads();
+    fft_stages<T, LOGN>(buf, twf, LPB);
+    if constexpr (MODE != 2) {
+        const int olo2 = MODE == 0 ? pg.flo : pg.olo, olen = MODE == 0 ? pg.fn : pg.on;
+        for (int idx = threadIdx.x; idx < LPB * NG; idx += blockDim.x) {
+            int li, k;
+            if (S == 1) {
+                li = idx / NG;
+                k = idx % NG;
+            } else {
+                k = idx / LPB;
+                li = idx % LPB;
+            }
+            if (s_ok[li] && cyc_has(olo2, olen, k, ng)) data[s_base[li] + (int64_t)k * S] = buf[li][k];
         }
     } else {
-        ok.x = ok.y = T(0);
-        od.x = od.y = T(0);
+    // MODE 2 (ax == 0, stride S): diagonal of axis 0 frequency k times the
+    // line's offset in the (N+1)^d diagonal, then the inverse transform
+    int64_t dstr0 = 1;
+    for (int q = 1; q < pg.d; ++q) dstr0 *= (pg.N + 1);
+#pragma unroll 1
+    for (int pass = 0; pass < (DER ? 2 : 1); ++pass) {
+        for (int idx = threadIdx.x; idx < LPB * NG; idx += blockDim.x) {
+            const int k = S == 1 ? idx % NG : idx / LPB, li = S == 1 ? idx / NG : idx % LPB;
+            const int f = k < pg.N ? k : k - ng;
+            T dv = T(0);
+            if (s_ok[li] && f >= -pg.N / 2 && f <= pg.N / 2) {
+                const WinDesc &w = wd[s_win[li]];
+                const T *D = reinterpret_cast<const T *>(pass == 0 ? w.Dk : w.Dder);
+                dv = D[(int64_t)(f + pg.N / 2) * dstr0 + s_di[li]];
+            }
+            C v = buf[li][k];
+            v.x *= dv;
+            v.y *= dv;
+            buf2[li][__brev((unsigned)k) >> (32 - LOGN)] = v;
+        }
+        __syncthreads();
+        fft_stages<T, LOGN>(buf2, twi, LPB);
+        const int64_t off = pass == 0 ? 0 : der_off * pg.cells;
+        for (int idx = threadIdx.x; idx < LPB * NG; idx += blockDim.x) {
+            const int k = S == 1 ? idx % NG : idx / LPB, li = S == 1 ? idx / NG : idx % LPB;
+            if (s_ok[li] && cyc_has(pg.olo, pg.on, k, ng)) data[off + s_base[li] + (int64_t)k * S] = buf2[li][k];
+        }
+        __syncthreads();
     }
-    spec[idx] = ok;
-    if (DER) spec[total + idx] = od;
+    }
 }
 
-template <typename T, bool INV>
-hipError_t fft_t(const WindowGeom &g, void *grid, int batch, hipStream_t s)
+PruneGeom prune_geom(const WindowGeom &g, int m)
 {
-    using C = typename Cplx<T>::type;
-    int logn = 0;
-    while ((1 << logn) < g.ng) ++logn;
-    for (int ax = 0; ax < g.d; ++ax) {
-        int64_t S = 1;
-        for (int q = ax + 1; q < g.d; ++q) S *= g.ng;
-        int64_t nouter = batch;
-        for (int q = 0; q < ax; ++q) nouter *= g.ng;
-        int64_t nblk, nlines;
-        if (S == 1) {
-            nlines = nouter;
-            nblk = (nlines + kLines - 1) / kLines;
-        } else {
-            nlines = nouter * S;
-            nblk = nouter * (S / kLines);
-        }
-        C *p = (C *)grid;
-        switch (logn) {
-        case 4: k_fft_lines<T, 4, INV><<<(unsigned)nblk, 256, 0, s>>>(p, S, nlines); break;
-        case 5: k_fft_lines<T, 5, INV><<<(unsigned)nblk, 256, 0, s>>>(p, S, nlines); break;
-        case 6: k_fft_lines<T, 6, INV><<<(unsigned)nblk, 256, 0, s>>>(p, S, nlines); break;
-        case 7: k_fft_lines<T, 7, INV><<<(unsigned)nblk, 256, 0, s>>>(p, S, nlines); break;
-        case 8: k_fft_lines<T, 8, INV><<<(unsigned)nblk, 256, 0, s>>>(p, S, nlines); break;
-        default: return hipErrorInvalidValue;
-        }
-    }
+    PruneGeom pg;
+    pg.d = g.d;
+    pg.ng = g.ng;
+    pg.N = g.N;
+    pg.olo = g.N / 2 - m + 1;
+    pg.on = g.N + 2 * m;
+    pg.flo = g.ng - g.N / 2;
+    pg.fn = g.N + 1;
+    pg.cells = g.cells;
+    return pg;
+}
+
+int64_t lines_of(const PruneGeom &pg, int ax)
+{
+    int64_t l = 1;
+    for (int q = 0; q < pg.d; ++q)
+        if (q != ax) l *= q < ax ? pg.on : pg.fn;
+    return l;
+}
+
+template <typename T, int LOGN, int MODE, bool DER>
+hipError_t fft_launch(void *grid, const PruneGeom &pg, int ax, int64_t batch, const WinDesc *wd,
+                      int nrhs, int64_t der_off, hipStream_t s)
+{
+    constexpr int LPB = (1 << LOGN) >= 256 ? 4 : ((1 << LOGN) >= 128 ? 8 : 16);
+    const int64_t lpb = lines_of(pg, ax);
+    const int64_t nlines = batch * lpb;
+    const unsigned nblk = (unsigned)((nlines + LPB - 1) / LPB);
+    if (nblk == 0) return hipSuccess;
+    k_fft_pruned<T, LOGN, LPB, MODE, DER><<<nblk, 256, 0, s>>>(
+        (typename Cplx<T>::type *)grid, pg, ax, nlines, lpb, wd, nrhs, der_off);
     return hipGetLastError();
+}
+
+template <typename T, int MODE, bool DER>
+hipError_t fft_dispatch(int logn, void *grid, const PruneGeom &pg, int ax, int64_t batch,
+                        const WinDesc *wd, int nrhs, int64_t der_off, hipStream_t s)
+{
+    switch (logn) {
+    case 4: return fft_launch<T, 4, MODE, DER>(grid, pg, ax, batch, wd, nrhs, der_off, s);
+    case 5: return fft_launch<T, 5, MODE, DER>(grid, pg, ax, batch, wd, nrhs, der_off, s);
+    case 6: return fft_launch<T, 6, MODE, DER>(grid, pg, ax, batch, wd, nrhs, der_off, s);
+    case 7: return fft_launch<T, 7, MODE, DER>(grid, pg, ax, batch, wd, nrhs, der_off, s);
+    case 8: return fft_launch<T, 8, MODE, DER>(grid, pg, ax, batch, wd, nrhs, der_off, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int log2i(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
 }
 
 template <typename T>
-hipError_t diag_t(const Group &G, int nrhs, void *grid, bool with_der, hipStream_t s)
+hipError_t fwd_t(const Group &G, int m, void *grid, int nrhs, hipStream_t s)
 {
-    using C = typename Cplx<T>::type;
-    const WindowGeom &g = G.g;
-    int64_t total = (int64_t)G.nwin * nrhs * g.cells;
-    unsigned nblk = (unsigned)((total + 255) / 256);
-    C *spec = (C *)grid;
-#define NFFTGP_DIAG(DD)                                                                        \
-    if (with_der)                                                                              \
-        k_diag<T, DD, true><<<nblk, 256, 0, s>>>(spec, G.desc, g.N, nrhs, g.cells, total);     \
-    else                                                                                       \
-        k_diag<T, DD, false><<<nblk, 256, 0, s>>>(spec, G.desc, g.N, nrhs, g.cells, total);
-    switch (g.d) {
-    case 1: NFFTGP_DIAG(1) break;
-    case 2: NFFTGP_DIAG(2) break;
-    case 3: NFFTGP_DIAG(3) break;
-    default: return hipErrorInvalidValue;
+    const PruneGeom pg = prune_geom(G.g, m);
+    const int64_t batch = (int64_t)G.nwin * nrhs;
+    for (int ax = G.g.d - 1; ax >= 1; --ax) {
+        hipError_t e = fft_dispatch<T, 0, false>(log2i(G.g.ng), grid, pg, ax, batch, G.desc, nrhs, 0, s);
+        if (e != hipSuccess) return e;
     }
-#undef NFFTGP_DIAG
-    return hipGetLastError();
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t inv_t(const Group &G, int m, void *grid, int nrhs, bool with_der, hipStream_t s)
+{
+    const PruneGeom pg = prune_geom(G.g, m);
+    const int64_t batch = (int64_t)G.nwin * nrhs * (with_der ? 2 : 1);
+    for (int ax = 1; ax < G.g.d; ++ax) {
+        hipError_t e = fft_dispatch<T, 1, false>(log2i(G.g.ng), grid, pg, ax, batch, G.desc, nrhs, 0, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t fused_t(const Group &G, int m, void *grid, int nrhs, bool with_der, hipStream_t s)
+{
+    const PruneGeom pg = prune_geom(G.g, m);
+    const int64_t batch = (int64_t)G.nwin * nrhs;
+    if (with_der)
+        return fft_dispatch<T, 2, true>(log2i(G.g.ng), grid, pg, 0, batch, G.desc, nrhs, batch, s);
+    return fft_dispatch<T, 2, false>(log2i(G.g.ng), grid, pg, 0, batch, G.desc, nrhs, batch, s);
 }
 
 }  // namespace
 
-hipError_t launch_fft(int prec, const WindowGeom &g, void *grid, int batch, bool inverse,
-                      hipStream_t s)
+hipError_t launch_fft_fwd(int prec, const Group &G, int m, void *grid, int nrhs, hipStream_t s)
 {
-    if (prec == NFFTGP_F32)
-        return inverse ? fft_t<float, true>(g, grid, batch, s) : fft_t<float, false>(g, grid, batch, s);
-    return inverse ? fft_t<double, true>(g, grid, batch, s) : fft_t<double, false>(g, grid, batch, s);
+    return prec == NFFTGP_F32 ? fwd_t<float>(G, m, grid, nrhs, s) : fwd_t<double>(G, m, grid, nrhs, s);
 }
 
-hipError_t launch_diag(int prec, const Group &G, int nrhs, void *grid, bool with_der,
-                       hipStream_t s)
+hipError_t launch_fft_diag(int prec, const Group &G, int m, void *grid, int nrhs, bool with_der,
+                           hipStream_t s)
 {
-    return prec == NFFTGP_F32 ? diag_t<float>(G, nrhs, grid, with_der, s)
-                              : diag_t<double>(G, nrhs, grid, with_der, s);
+    return prec == NFFTGP_F32 ? fused_t<float>(G, m, grid, nrhs, with_der, s)
+                              : fused_t<double>(G, m, grid, nrhs, with_der, s);
+}
+
+hipError_t launch_fft_inv(int prec, const Group &G, int m, void *grid, int nrhs, bool with_der,
+                          hipStream_t s)
+{
+    return prec == NFFTGP_F32 ? inv_t<float>(G, m, grid, nrhs, with_der, s)
+                              : inv_t<double>(G, m, grid, nrhs, with_der, s);
 }
 
 }  // namespace nfftgp

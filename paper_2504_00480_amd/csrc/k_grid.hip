@@ -18,12 +18,24 @@
 // tile ("bin", tb cells per dimension) in the window's sorted order.
 #include "nfftgp_impl.h"
 
+#include <cstdlib>
+
 namespace nfftgp {
 namespace {
 
 template <typename T> struct Cplx;
 template <> struct Cplx<float> { using type = float2; };
 template <> struct Cplx<double> { using type = double2; };
+
+// i / d for 0 <= i < 2^22 and 0 < d <= 1024 by a float reciprocal and one
+// correction step (exact in that range).
+__device__ __forceinline__ int fdiv_small(int i, int d, float inv_d)
+{
+    int q = (int)((float)i * inv_d);
+    const int r = i - q * d;
+    q += (r >= d) - (r < 0);
+    return q;
+}
 
 template <int D>
 __device__ __forceinline__ void bin_origin(int bin, int nb, int tb, int *org)
@@ -44,17 +56,18 @@ __device__ __forceinline__ void bin_origin(int bin, int nb, int tb, int *org)
 // d = 2 a lane owns tap (a, b), for d = 1 tap a.  The run is added to the
 // LDS tile once, after its last point.  The W waves of a group walk the same
 // points and share one tile: wave w handles the first-dimension taps whose
-// absolute cell index is w modulo W, so no two waves ever touch the same
-// cell.  Within a flush every lane touches a distinct cell and the flushes of
-// one wave are ordered, so the tile is updated with plain loads and stores
-// and the result does not depend on scheduling.  The points' weights, cells
-// and vector values are staged in LDS in chunks of 64 with coalesced loads.
+// position in the padded tile is w modulo W, so no two waves ever touch the
+// same cell.  Within a flush every lane touches a distinct cell and the
+// flushes of one wave are ordered, so the tile is updated with plain loads and
+// stores and the result does not depend on scheduling.  The points' weights,
+// tile positions and vector values are staged in LDS in chunks of 64 with
+// coalesced loads; the run boundaries of a chunk come from one ballot over its
+// run-end flags, so the per-point loop has no branches.
 template <typename T, int D, int M, int R, int W>
 __global__ void __launch_bounds__(64 * W)
 k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
-         const int *__restrict__ sub_bin, const int *__restrict__ sub_start,
-         const int *__restrict__ sub_count, const T *__restrict__ V, int64_t ldv, int nrhs, int tb,
-         int nb, int ng, T *__restrict__ tilebuf)
+         const int *__restrict__ sub_start, const int *__restrict__ sub_count,
+         const T *__restrict__ V, int64_t ldv, int nrhs, int pd, T *__restrict__ tilebuf)
 {
     constexpr int TW = 2 * M;
     constexpr int RS = D * TW;                                  // weights per point
@@ -66,24 +79,22 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     constexpr int CH = 64;                                      // points staged per chunk
     __shared__ T s_rec[CH * RS];
     __shared__ T s_v[CH * R];
-    __shared__ int s_an[CH];
+    __shared__ int s_lp[CH];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *tiles = reinterpret_cast<T *>(smem_raw);
-    const int pd = tb + 2 * M;
     int pc = pd;
     for (int q = 1; q < D; ++q) pc *= pd;
     const int sq = blockIdx.x, r0 = blockIdx.y * R;
     const WinDesc &win = wd[sub_win[sq]];
     const T *rec = reinterpret_cast<const T *>(win.rec);
-    const int *anchor = win.anchor;
+    const int *lpos = win.lpos;
     const int *perm = win.perm;
     const int start = sub_start[sq], cnt = sub_count[sq];
     const int end = start + cnt;
-    int org[3] = {0, 0, 0};
-    bin_origin<D>(sub_bin[sq], nb, tb, org);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int i = tid; i < R * pc; i += 64 * W) tiles[i] = T(0);
-    int i0[NG], i1[NG];
+    // per lane: item indices and the item's offset inside the padded tile
+    int i0[NG], i1[NG], off[NG];
     bool act[NG];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
@@ -92,7 +103,9 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
         const int itc = act[g] ? it : 0;
         i0[g] = D == 1 ? itc : itc / TW;
         i1[g] = D == 1 ? 0 : itc % TW;
+        off[g] = D == 3 ? i0[g] * pd + i1[g] : (D == 2 ? i0[g] * pd + i1[g] : i0[g]);
     }
+    const int pd2 = D == 3 ? pd * pd : 0;
     T acc[NG][NA][R];
 #pragma unroll
     for (int g = 0; g < NG; ++g)
@@ -101,12 +114,6 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[g][k][r] = T(0);
     const int nr = min(R, nrhs - r0);
-    // first owned tap of the current run along dimension 0 (d = 3)
-    int aoff = 0;
-    if (D == 3 && cnt > 0) {
-        const int c0 = (anchor[start] & 0x7fffffff) / (ng * ng);
-        aoff = ((wave - (c0 - M + 1)) % W + W) % W;
-    }
     for (int cb = start; cb < end; cb += CH) {
         const int nc = min(CH, end - cb);
         __syncthreads();   // tiles cleared / previous chunk consumed
@@ -115,55 +122,59 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             const int u = i / R, r = i % R;
             s_v[i] = r < nr ? V[(int64_t)perm[cb + u] * ldv + r0 + r] : T(0);
         }
-        for (int i = tid; i < nc; i += 64 * W) s_an[i] = anchor[cb + i];
+        for (int i = tid; i < nc; i += 64 * W) s_lp[i] = lpos[cb + i];
         __syncthreads();
-        for (int u = 0; u < nc; ++u) {
-            const int an = s_an[u];
-            const T *rp = s_rec + u * RS;
-            T vr[R];
+        // run ends inside this chunk (the subproblem's last point ends a run)
+        const bool isend = lane < nc && (s_lp[lane] < 0 || cb + lane == end - 1);
+        const unsigned long long ends = __ballot(isend);
+        int u0 = 0;
+        while (u0 < nc) {
+            const unsigned long long rest = ends >> u0;
+            const bool flush = rest != 0ull;
+            const int u1 = flush ? u0 + (int)__builtin_ctzll(rest) : nc - 1;
+            const int lp = __builtin_amdgcn_readfirstlane(s_lp[u0] & 0x7fffffff);
+            // first owned tap along dimension 0 (tile position = wave mod W)
+            const int aoff = D == 3 ? ((wave - (lp >> 20)) % W + W) % W : 0;
+            for (int u = u0; u <= u1; ++u) {
+                const T *rp = s_rec + u * RS;
+                T vr[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) vr[r] = s_v[u * R + r];
-#pragma unroll
-            for (int g = 0; g < NG; ++g) {
+                for (int r = 0; r < R; ++r) vr[r] = s_v[u * R + r];
+                T w0[NA];
                 if (D == 3) {
-                    const T wbc = rp[TW + i0[g]] * rp[2 * TW + i1[g]];
-                    T z[R];
 #pragma unroll
-                    for (int r = 0; r < R; ++r) z[r] = wbc * vr[r];
+                    for (int k = 0; k < NA; ++k) w0[k] = rp[aoff + k * W];
+                }
 #pragma unroll
-                    for (int k = 0; k < NA; ++k) {
-                        const T w0 = rp[aoff + k * W];
+                for (int g = 0; g < NG; ++g) {
+                    if (D == 3) {
+                        const T wbc = rp[TW + i0[g]] * rp[2 * TW + i1[g]];
+                        T z[R];
 #pragma unroll
-                        for (int r = 0; r < R; ++r) acc[g][k][r] += w0 * z[r];
+                        for (int r = 0; r < R; ++r) z[r] = wbc * vr[r];
+#pragma unroll
+                        for (int k = 0; k < NA; ++k)
+#pragma unroll
+                            for (int r = 0; r < R; ++r) acc[g][k][r] += w0[k] * z[r];
+                    } else if (D == 2) {
+                        const T w = rp[i0[g]] * rp[TW + i1[g]];
+#pragma unroll
+                        for (int r = 0; r < R; ++r) acc[g][0][r] += w * vr[r];
+                    } else {
+                        const T w = rp[i0[g]];
+#pragma unroll
+                        for (int r = 0; r < R; ++r) acc[g][0][r] += w * vr[r];
                     }
-                } else if (D == 2) {
-                    const T w = rp[i0[g]] * rp[TW + i1[g]];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) acc[g][0][r] += w * vr[r];
-                } else {
-                    const T w = rp[i0[g]];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) acc[g][0][r] += w * vr[r];
                 }
             }
-            const int p = cb + u;
-            const bool last = p == end - 1;
-            if (an < 0 || last) {
-                // first-tap position of the run's cell inside the padded tile
-                int cell = an & 0x7fffffff, L[3] = {0, 0, 0};
-                for (int q = D - 1; q >= 0; --q) {
-                    L[q] = cell % ng - org[q] + 1;
-                    cell /= ng;
-                }
+            if (flush) {
+                const int base = (lp & 0xfffff) + (D == 3 ? aoff * pd2 : 0);
 #pragma unroll
                 for (int g = 0; g < NG; ++g) {
                     if (act[g]) {
 #pragma unroll
                         for (int k = 0; k < NA; ++k) {
-                            int idx;
-                            if (D == 3) idx = ((L[0] + aoff + k * W) * pd + L[1] + i0[g]) * pd + L[2] + i1[g];
-                            else if (D == 2) idx = (L[0] + i0[g]) * pd + L[1] + i1[g];
-                            else idx = L[0] + i0[g];
+                            const int idx = base + (D == 3 ? k * W * pd2 : 0) + off[g];
 #pragma unroll
                             for (int r = 0; r < R; ++r) {
                                 tiles[r * pc + idx] += acc[g][k][r];
@@ -172,12 +183,8 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                         }
                     }
                 }
-                if (D == 3 && !last) {
-                    const int na = u + 1 < nc ? s_an[u + 1] : anchor[p + 1];
-                    const int c0 = (na & 0x7fffffff) / (ng * ng);
-                    aoff = ((wave - (c0 - M + 1)) % W + W) % W;
-                }
             }
+            u0 = u1 + 1;
         }
     }
     __syncthreads();
@@ -190,12 +197,14 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
 // ---------------------------------------------------------------- fold
 // Phase 1: the subproblems of one tile are summed into the first one's slot
 // (in place, fixed order: 4 slices per cell combined through LDS).
+// Only tiles with two or more subproblems are listed (fb: window * nbins + tile).
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_fold_bins(const WinDesc *__restrict__ wd, T *__restrict__ tilebuf, int nbins, int nrhs, int pc)
+k_fold_bins(const WinDesc *__restrict__ wd, const int *__restrict__ fb, T *__restrict__ tilebuf,
+            int nbins, int nrhs, int pc)
 {
     __shared__ T part[4][64];
-    const int wb = blockIdx.y, r = blockIdx.z;
+    const int wb = fb[blockIdx.y], r = blockIdx.z;
     const int *bsp = wd[wb / nbins].bin_sub_ptr;
     const int bin = wb % nbins;
     const int s0 = bsp[bin], s1 = bsp[bin + 1];
@@ -214,25 +223,28 @@ k_fold_bins(const WinDesc *__restrict__ wd, T *__restrict__ tilebuf, int nbins, 
     }
 }
 
-// Phase 2: every grid cell sums the (at most 3^d) tiles whose padded region
-// covers it.  Output layout [window][vector][cell].
+// Phase 2: every grid cell of the occupied range (cells olo .. olo + on - 1 of
+// each axis; the FFT reads no other cell) sums the (at most 3^d) tiles whose
+// padded region covers it.  Output layout [window][vector][cell].
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
 k_fold(const WinDesc *__restrict__ wd, const T *__restrict__ tilebuf, int nrhs, int tb, int nb,
-       int ng, int m, int pd, int pc, int64_t cells, int64_t total,
+       int ng, int m, int pd, int pc, int64_t cells, int olo, int on, int64_t ocells, int64_t total,
        typename Cplx<T>::type *__restrict__ grid)
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    const int64_t wr = idx / cells;
+    const int64_t wr = idx / ocells;
     const int w = (int)(wr / nrhs), r = (int)(wr % nrhs);
-    const int64_t cell = idx % cells;
+    int64_t rem = idx % ocells;
     const int *bsp = wd[w].bin_sub_ptr;
     int l[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    int64_t rem = cell;
+    int64_t cell = 0, cstride = 1;
     for (int q = D - 1; q >= 0; --q) {
-        l[q] = (int)(rem % ng);
-        rem /= ng;
+        l[q] = olo + (int)(rem % on);
+        rem /= on;
+        cell += (int64_t)l[q] * cstride;
+        cstride *= ng;
         // bins b with b*tb - m <= l <= b*tb - m + pd - 1
         int num = l[q] + m - pd + 1;
         int blo = num >= 0 ? (num + tb - 1) / tb : -((-num) / tb);
@@ -259,7 +271,7 @@ k_fold(const WinDesc *__restrict__ wd, const T *__restrict__ tilebuf, int nrhs, 
     typename Cplx<T>::type o;
     o.x = sum;
     o.y = T(0);
-    grid[idx] = o;
+    grid[wr * cells + cell] = o;
 }
 
 // ---------------------------------------------------------------- interpolation
@@ -284,6 +296,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     int pc = pd;
     for (int q = 1; q < D; ++q) pc *= pd;
     T *tD = tK + pc;
+    const float inv_pd = 1.0f / (float)pd;
     const int sq = blockIdx.x;
     const int wi = sub_win[sq];
     const WinDesc &win = wd[wi];
@@ -302,14 +315,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     for (int q = (D == 3 ? 1 : 0); q < D; ++q)
 #pragma unroll
         for (int a = 0; a < TW; ++a) w[q][a] = rp[q * TW + a];
-    int A[3] = {0, 0, 0};
-    {
-        int cell = win.anchor[j] & 0x7fffffff;
-        for (int q = D - 1; q >= 0; --q) {
-            A[q] = cell % ng - org[q] + 1;
-            cell /= ng;
-        }
-    }
+    const int lin = win.lpos[j] & 0xfffff;   // first tap inside the padded tile
     const int64_t orow = (int64_t)win.perm[j] * nrhs;
     T *hout = hbuf + (int64_t)win.s_global * n * nrhs;
     T *dblk = DER ? dout + (int64_t)win.s_global * n * nrhs : nullptr;
@@ -321,8 +327,9 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
         for (int i = threadIdx.x; i < pc; i += blockDim.x) {
             int rem = i, loc[3] = {0, 0, 0};
             for (int q = D - 1; q >= 0; --q) {
-                loc[q] = rem % pd;
-                rem /= pd;
+                const int qt = fdiv_small(rem, pd, inv_pd);
+                loc[q] = rem - qt * pd;
+                rem = qt;
             }
             bool in = true;
             int64_t g = 0;
@@ -340,14 +347,14 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
         if (D == 1) {
 #pragma unroll
             for (int aa = 0; aa < TW; ++aa) {
-                hK += tK[A[0] + aa] * w[0][aa];
-                if (DER) hD += tD[A[0] + aa] * w[0][aa];
+                hK += tK[lin + aa] * w[0][aa];
+                if (DER) hD += tD[lin + aa] * w[0][aa];
             }
         } else if (D == 2) {
 #pragma unroll
             for (int aa = 0; aa < TW; ++aa) {
                 T sK = T(0), sD = T(0);
-                const int row = (A[0] + aa) * pd + A[1];
+                const int row = lin + aa * pd;
 #pragma unroll
                 for (int bb = 0; bb < TW; ++bb) {
                     sK += tK[row + bb] * w[D > 1 ? 1 : 0][bb];
@@ -363,7 +370,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                 T sK = T(0), sD = T(0);
 #pragma unroll
                 for (int bb = 0; bb < TW; ++bb) {
-                    const int row = ((A[0] + aa) * pd + (A[1] + bb)) * pd + A[2];
+                    const int row = lin + (aa * pd + bb) * pd;
                     T cK = T(0), cD = T(0);
 #pragma unroll
                     for (int cc = 0; cc < TW; ++cc) {
@@ -572,22 +579,32 @@ hipError_t spread_launch(const Group &G, const void *V, int64_t ldv, int nrhs, v
     hipError_t e = allow_lds(k_spread<T, D, M, R, W>, shm);
     if (e != hipSuccess) return e;
     dim3 grid((unsigned)G.nsub, (unsigned)((nrhs + R - 1) / R));
-    k_spread<T, D, M, R, W><<<grid, 64 * W, shm, s>>>(G.desc, G.sub_win, G.sub_bin, G.sub_start,
-                                                        G.sub_count, (const T *)V, ldv, nrhs, g.tb,
-                                                        g.nb, g.ng, (T *)tilebuf);
+    k_spread<T, D, M, R, W><<<grid, 64 * W, shm, s>>>(G.desc, G.sub_win, G.sub_start, G.sub_count,
+                                                        (const T *)V, ldv, nrhs, g.pd, (T *)tilebuf);
     return hipGetLastError();
+}
+
+int spread_waves_override()
+{
+    const char *e = std::getenv("NFFTGP_SPREAD_W");
+    return e ? std::atoi(e) : 0;
 }
 
 template <typename T, int D, int M>
 hipError_t spread_dm(const Group &G, const void *V, int64_t ldv, int nrhs, void *tilebuf,
                      hipStream_t s)
 {
-    // d = 3: 4 waves share a tile (2m taps split 4 ways: m = 2, 4, 6, 8 -> 1, 2, 3, 4
-    // each); two vectors per group when the two tiles stay within 40 KiB
-    constexpr int Wv = D == 3 ? 4 : 1;
-    if (nrhs >= 2 && 2 * (size_t)G.g.pc * sizeof(T) <= 40 * 1024)
-        return spread_launch<T, D, M, 2, Wv>(G, V, ldv, nrhs, tilebuf, s);
-    return spread_launch<T, D, M, 1, Wv>(G, V, ldv, nrhs, tilebuf, s);
+    // d = 3: W waves share a tile (2m taps split W ways); two vectors per
+    // group when the two tiles stay within 40 KiB
+    const bool two = nrhs >= 2 && 2 * (size_t)G.g.pc * sizeof(T) <= 40 * 1024;
+    constexpr int W2 = D == 3 ? 2 : 1, W4 = D == 3 ? 4 : 1;
+    const int wv = D == 3 ? spread_waves_override() : 1;
+    if (wv == 1) return two ? spread_launch<T, D, M, 2, 1>(G, V, ldv, nrhs, tilebuf, s)
+                            : spread_launch<T, D, M, 1, 1>(G, V, ldv, nrhs, tilebuf, s);
+    if (wv == 2) return two ? spread_launch<T, D, M, 2, W2>(G, V, ldv, nrhs, tilebuf, s)
+                            : spread_launch<T, D, M, 1, W2>(G, V, ldv, nrhs, tilebuf, s);
+    return two ? spread_launch<T, D, M, 2, W4>(G, V, ldv, nrhs, tilebuf, s)
+               : spread_launch<T, D, M, 1, W4>(G, V, ldv, nrhs, tilebuf, s);
 }
 
 template <typename T, int D, int M>
@@ -659,17 +676,25 @@ hipError_t fold_t(const Group &G, int m, int nrhs, void *tilebuf, void *grid, hi
 {
     const WindowGeom &g = G.g;
     using C = typename Cplx<T>::type;
-    if (G.nsub > G.nbins_used)
-        k_fold_bins<T><<<dim3((unsigned)((g.pc + 63) / 64), (unsigned)(G.nwin * g.nbins), (unsigned)nrhs), 256, 0, s>>>(
-            G.desc, (T *)tilebuf, g.nbins, nrhs, g.pc);
-    const int64_t tot = (int64_t)G.nwin * nrhs * g.cells;
+    if (G.nfb > 0)
+        k_fold_bins<T><<<dim3((unsigned)((g.pc + 63) / 64), (unsigned)G.nfb, (unsigned)nrhs), 256, 0, s>>>(
+            G.desc, G.fb, (T *)tilebuf, g.nbins, nrhs, g.pc);
+    // occupied cells per axis: N/2 - m + 1 .. 3N/2 + m (every t lies in [N/2, 3N/2])
+    const int olo = g.N / 2 - m + 1, on = g.N + 2 * m;
+    int64_t ocells = 1;
+    for (int q = 0; q < g.d; ++q) ocells *= on;
+    const int64_t tot = (int64_t)G.nwin * nrhs * ocells;
     unsigned nblk = (unsigned)((tot + 255) / 256);
+#define NFFTGP_FOLD(DD)                                                                            \
+    k_fold<T, DD><<<nblk, 256, 0, s>>>(G.desc, (const T *)tilebuf, nrhs, g.tb, g.nb, g.ng, m, g.pd, \
+                                       g.pc, g.cells, olo, on, ocells, tot, (C *)grid);
     switch (g.d) {
-    case 1: k_fold<T, 1><<<nblk, 256, 0, s>>>(G.desc, (const T *)tilebuf, nrhs, g.tb, g.nb, g.ng, m, g.pd, g.pc, g.cells, tot, (C *)grid); break;
-    case 2: k_fold<T, 2><<<nblk, 256, 0, s>>>(G.desc, (const T *)tilebuf, nrhs, g.tb, g.nb, g.ng, m, g.pd, g.pc, g.cells, tot, (C *)grid); break;
-    case 3: k_fold<T, 3><<<nblk, 256, 0, s>>>(G.desc, (const T *)tilebuf, nrhs, g.tb, g.nb, g.ng, m, g.pd, g.pc, g.cells, tot, (C *)grid); break;
+    case 1: NFFTGP_FOLD(1) break;
+    case 2: NFFTGP_FOLD(2) break;
+    case 3: NFFTGP_FOLD(3) break;
     default: return hipErrorInvalidValue;
     }
+#undef NFFTGP_FOLD
     return hipGetLastError();
 }
 

@@ -105,21 +105,28 @@ k_bin_keys(const T *__restrict__ t, int64_t n, int d, int ng, int tb, int nb, in
 // Window weights of every sorted point, evaluated in FP64 from the stored
 // coordinate: record j holds psi(t_q - l) for the 2m taps l = floor(t_q)-m+1+a
 // of each dimension q (a = 0..2m-1), dimension-major.  anchor[j] packs the
-// cell floor(t) (row-major over the (2N)^d grid) and sets bit 31 when the
-// next point has another cell, so that spreading can flush per run of points.
+// cell floor(t) (row-major over the (2N)^d grid); lpos[j] packs the position
+// of the first tap inside the point's padded tile (edge pd = tb + 2m, origin
+// one tile edge tb * bin - m): bits 0-19 the row-major offset, bits 20-26 the
+// first coordinate.  Both get bit 31 when the next point has another cell, so
+// that spreading can flush per run of points.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_weights(const T *__restrict__ t, int64_t n, int d, int m, int ng, double beta, double knorm,
-          T *__restrict__ rec, int *__restrict__ anchor)
+k_weights(const T *__restrict__ t, int64_t n, int d, int m, int ng, int tb, int pd, double beta,
+          double knorm, T *__restrict__ rec, int *__restrict__ anchor, int *__restrict__ lpos)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int tw = 2 * m;
-    int an = 0;
+    int an = 0, lin = 0, l0 = 0;
     for (int q = 0; q < d; ++q) {
         double tq = (double)t[(int64_t)q * n + i];
         double fl = floor(tq);
-        an = an * ng + (int)fl;
+        const int c = (int)fl;
+        an = an * ng + c;
+        const int L = c % tb + 1;   // first tap - padded tile origin = c - tb * bin + 1
+        lin = lin * pd + L;
+        if (q == 0) l0 = L;
         for (int a = 0; a < tw; ++a) {
             double u = tq - (fl - (m - 1) + a);
             double s2 = (double)m * m - u * u;
@@ -130,10 +137,11 @@ k_weights(const T *__restrict__ t, int64_t n, int d, int m, int ng, double beta,
         }
     }
     anchor[i] = an;
+    lpos[i] = lin | (l0 << 20);
 }
 
 __global__ void __launch_bounds__(256)
-k_run_ends(int *__restrict__ anchor, int64_t n, int *__restrict__ runs)
+k_run_ends(int *__restrict__ anchor, int *__restrict__ lpos, int64_t n, int *__restrict__ runs)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool last = false;
@@ -142,7 +150,10 @@ k_run_ends(int *__restrict__ anchor, int64_t n, int *__restrict__ runs)
         // carry its flag, so compare the cell bits only
         const int a = anchor[i] & 0x7fffffff;
         last = (i == n - 1) || ((anchor[i + 1] & 0x7fffffff) != a);
-        if (last) anchor[i] = a | (int)0x80000000u;
+        if (last) {
+            anchor[i] = a | (int)0x80000000u;
+            lpos[i] = lpos[i] | (int)0x80000000u;
+        }
     }
     // number of runs (= occupied cells): one atomic per wave
     const unsigned long long bal = __ballot(last);
@@ -348,17 +359,17 @@ hipError_t launch_bin_keys(int prec, const void *t, int64_t n, const WindowGeom 
 }
 
 hipError_t launch_weights(int prec, const void *t, int64_t n, const WindowGeom &g, int m,
-                          double knorm, void *rec, int *anchor, int *runs, hipStream_t s)
+                          double knorm, void *rec, int *anchor, int *lpos, int *runs, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     unsigned nblk = (unsigned)((n + 255) / 256);
     if (prec == NFFTGP_F32)
-        k_weights<float><<<nblk, 256, 0, s>>>((const float *)t, n, g.d, m, g.ng, kb_beta(), knorm,
-                                              (float *)rec, anchor);
+        k_weights<float><<<nblk, 256, 0, s>>>((const float *)t, n, g.d, m, g.ng, g.tb, g.pd, kb_beta(),
+                                              knorm, (float *)rec, anchor, lpos);
     else
-        k_weights<double><<<nblk, 256, 0, s>>>((const double *)t, n, g.d, m, g.ng, kb_beta(), knorm,
-                                               (double *)rec, anchor);
-    k_run_ends<<<nblk, 256, 0, s>>>(anchor, n, runs);
+        k_weights<double><<<nblk, 256, 0, s>>>((const double *)t, n, g.d, m, g.ng, g.tb, g.pd,
+                                               kb_beta(), knorm, (double *)rec, anchor, lpos);
+    k_run_ends<<<nblk, 256, 0, s>>>(anchor, lpos, n, runs);
     return hipGetLastError();
 }
 

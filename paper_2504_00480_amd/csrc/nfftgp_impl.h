@@ -53,6 +53,8 @@ struct Window {
     // device data (owned)
     void *rec = nullptr;        // per sorted point: d x 2m window weights (plan precision)
     int32_t *anchor = nullptr;  // per sorted point: packed cell floor(t); bit 31 = last of its run
+    int32_t *lpos = nullptr;    // per sorted point: first-tap position in its padded tile
+                                // (bits 0-19 offset, 20-26 first coordinate; bit 31 as anchor)
     int32_t *perm = nullptr;    // sorted position -> original point index
     int32_t *bin_sub_ptr = nullptr;  // tile -> spreading subproblems of its group (nbins + 1)
     void *Dk = nullptr;     // symmetrised diagonal for K_s (dcells, plan precision)
@@ -66,6 +68,7 @@ struct Window {
 struct WinDesc {
     const void *rec;
     const int32_t *anchor;
+    const int32_t *lpos;
     const int32_t *perm;
     const int32_t *bin_sub_ptr;
     const void *Dk;
@@ -86,6 +89,8 @@ struct Group {
     int32_t *isub_win = nullptr, *isub_bin = nullptr, *isub_start = nullptr, *isub_count = nullptr;
     int nisub = 0;               // interpolation subproblems
     int nbins_used = 0;          // tiles holding at least one point
+    int32_t *fb = nullptr;       // tiles split into several subproblems (window * nbins + tile)
+    int nfb = 0;
     // interpolation by register-held runs (chosen when runs of equal cells are long):
     // contiguous ranges of at most kRunSubPoints sorted points
     bool use_run_interp = false;
@@ -116,7 +121,7 @@ struct nfftgp_plan_s {
     void *grid = nullptr;        // 2 x (windows of a group) x max_nrhs x cells complex values
     void *hbuf = nullptr;        // P x n x max_nrhs per-window products
     double *coef = nullptr;      // 4 x maxN^d complex doubles (set_hyper scratch)
-    double *bbar = nullptr;      // 2 x maxN^d doubles
+    double *bbar = nullptr;      // block minima of the coefficients (set_hyper scratch)
     double *minb = nullptr;      // 2 x P doubles (device)
     double *minb_host = nullptr; // 2 x P doubles (pinned host copy, read lazily)
     bool minb_pending = false;
@@ -172,11 +177,12 @@ hipError_t launch_sort(int prec, int64_t n, int d, int nbins, const int *keys, c
                        int *bin_start, hipStream_t s);
 hipError_t launch_bin_keys(int prec, const void *t, int64_t n, const WindowGeom &g, int *keys,
                            hipStream_t s);
-// Window weights and packed cells (with run-end flags) of the sorted points;
-// *runs (zeroed by the caller) is increased by the number of runs of equal cells.
+// Window weights, packed cells and tile positions (with run-end flags) of the
+// sorted points; *runs (zeroed by the caller) is increased by the number of
+// runs of equal cells.
 double kb_knorm(int m);
 hipError_t launch_weights(int prec, const void *t, int64_t n, const WindowGeom &g, int m,
-                          double knorm, void *rec, int *anchor, int *runs, hipStream_t s);
+                          double knorm, void *rec, int *anchor, int *lpos, int *runs, hipStream_t s);
 
 // ---------------------------------------------------------------- per-theta kernels
 // Coefficients b_k, b^der_k of one window (FP64) and the symmetrised diagonals.
@@ -198,10 +204,14 @@ hipError_t launch_spread(int prec, const Group &G, int m, const void *V, int64_t
                          void *tilebuf, hipStream_t s);
 hipError_t launch_fold(int prec, const Group &G, int m, int nrhs, void *tilebuf, void *grid,
                        hipStream_t s);
-hipError_t launch_fft(int prec, const WindowGeom &g, void *grid, int batch, bool inverse,
-                      hipStream_t s);
-hipError_t launch_diag(int prec, const Group &G, int nrhs, void *grid, bool with_der,
-                       hipStream_t s);
+// Pruned FFT pipeline of one group: forward transforms of axes d-1..1, then
+// axis 0 forward + diagonal (and derivative diagonal) + axis 0 inverse, then
+// inverse transforms of axes 1..d-1 over the K (and derivative) blocks.
+hipError_t launch_fft_fwd(int prec, const Group &G, int m, void *grid, int nrhs, hipStream_t s);
+hipError_t launch_fft_diag(int prec, const Group &G, int m, void *grid, int nrhs, bool with_der,
+                           hipStream_t s);
+hipError_t launch_fft_inv(int prec, const Group &G, int m, void *grid, int nrhs, bool with_der,
+                          hipStream_t s);
 hipError_t launch_interp(int prec, const Group &G, int m, int64_t n, int nrhs, const void *grid,
                          bool with_der, void *hbuf, void *dout, double dscale, hipStream_t s);
 hipError_t launch_assemble(int prec, int64_t n, int nrhs, int P, const void *V, int64_t ldv,
