@@ -401,12 +401,14 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
                 cells_used += plan->win[G.wins[wl]].h_cells_used;
             }
             const char *ov = std::getenv("NFFTGP_INTERP");
+            const bool mfma_ok = prec == NFFTGP_F32 && G.g.d == 3 && m <= 6 && n > 0;
             if (ov && std::strcmp(ov, "run") == 0) G.use_run_interp = n > 0;
             else if (ov && std::strcmp(ov, "tile") == 0) G.use_run_interp = false;
+            else if (ov && std::strcmp(ov, "mfma") == 0) G.use_mfma_interp = mfma_ok;
             else G.use_run_interp = G.g.d == 3 && cells_used > 0 &&
                                     pts >= (int64_t)kRunInterpMinRun * cells_used;
         }
-        if (G.use_run_interp) {
+        if (G.use_run_interp || G.use_mfma_interp) {
             // points per wave: up to kRunSubPoints, fewer while that leaves
             // under 8192 waves for the group
             int rsp = kRunSubPoints;
@@ -438,13 +440,7 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         }
         TRYS(dalloc(plan, (void **)&G.cinv2, (G.g.N + 1) * sizeof(double)));
         TRYH(launch_window_coef(G.g.N, m, G.cinv2, st));
-        TRYS(dalloc(plan, (void **)&G.tw, G.g.N * sizeof(double2)));
-        TRYH(launch_twiddles(G.g.N, G.tw, st));
-        {
-            int64_t Kg = 1;
-            for (int q = 0; q < G.g.d; ++q) Kg *= G.g.N;
-            coef_need = std::max(coef_need, (size_t)8 * G.nwin * Kg);
-        }
+        coef_need = std::max(coef_need, (size_t)coef_scratch_doubles(G.g, G.nwin));
         TRYS(dalloc(plan, (void **)&G.desc, G.nwin * sizeof(WinDesc)));
         TRYH(hipMemcpy(G.desc, hd.data(), G.nwin * sizeof(WinDesc), hipMemcpyHostToDevice));
         tile_need = std::max(tile_need, (size_t)G.nsub * G.g.pc);
@@ -456,13 +452,11 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
     const size_t vec_bytes = std::max<int64_t>(n, 1) * max_nrhs * eb;
     TRYS(dalloc(plan, &plan->hbuf, vec_bytes * P));
     TRYS(dalloc(plan, (void **)&plan->coef, coef_need * sizeof(double)));
-    TRYS(dalloc(plan, (void **)&plan->bbar, coef_need / 4 * sizeof(double)));
     {
         void *h = nullptr;
         TRYH(hipHostMalloc(&h, 2 * P * sizeof(double), hipHostMallocDefault));
         plan->minb_host = (double *)h;
     }
-    TRYS(dalloc(plan, (void **)&plan->minb, (size_t)2 * P * sizeof(double)));
     TRYS(dalloc(plan, (void **)&plan->dot_part, (size_t)kDotBlocks * 64 * sizeof(double) + 64 * sizeof(double)));
     TRYS(dalloc(plan, (void **)&plan->cg_scal, (size_t)kCgSlots * 64 * sizeof(double)));
     TRYS(dalloc(plan, &plan->cg_r, vec_bytes));
@@ -495,13 +489,10 @@ nfftgp_status nfftgp_set_hyper(nfftgp_plan plan, double sigma_f, const double *e
             prm.kernel[wl] = plan->win[s].kernel;
         }
         PROF_LAUNCH(plan, NFFTGP_PROF_COEF,
-                    launch_coefficients(plan->prec, G, prm, G.cinv2, G.tw, plan->coef, plan->bbar,
-                                        plan->minb, st));
+                    launch_coefficients(plan->prec, G, prm, G.cinv2, plan->coef, plan->minb_host, st));
     }
-    // min_k b_k is read back lazily (nfftgp_get_window_info), so set_hyper does
-    // not synchronise
-    NFFTGP_HIP_TRY(hipMemcpyAsync(plan->minb_host, plan->minb, 2 * plan->P * sizeof(double),
-                                  hipMemcpyDeviceToHost, st));
+    // the kernels write min_k b_k into pinned host memory; it is read after a
+    // stream synchronisation (nfftgp_get_window_info), so set_hyper does not wait
     plan->minb_pending = true;
     for (int s = 0; s < plan->P; ++s) plan->win[s].ell = ell[s];
     plan->sigma_f = sigma_f;

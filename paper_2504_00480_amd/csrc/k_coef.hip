@@ -12,6 +12,7 @@
 // symmetrisation makes the product the real part of the trigonometric sum,
 // which is the symmetric matrix sum_k b_k cos(2 pi k.(x_i - x_j)).
 #include "nfftgp_impl.h"
+#include "nfftgp_dev.h"
 
 namespace nfftgp {
 namespace {
@@ -28,8 +29,8 @@ __device__ double bessel_i0(double z)
     return sum;
 }
 
-// Kernel and ell-derivative samples at grid offset l (index set [-N/2, N/2)^d,
-// spacing 1/N in scaled units); r is the distance in caller units.
+// Kernel and ell-derivative at distance sqrt(r2) in scaled units (converted to
+// caller units by the window's scale c).
 __device__ __forceinline__ void sample_pair(const CoefParams &prm, int w, double r2, double &v,
                                             double &dv)
 {
@@ -44,82 +45,137 @@ __device__ __forceinline__ void sample_pair(const CoefParams &prm, int w, double
     }
 }
 
-// First DFT axis (axis 0) of the samples of every window of a group, with the
-// samples evaluated on the fly.  Output arrays [window][2][K] of complex values
-// (kernel, then ell-derivative), K = N^d, index l + N/2 per axis:
-// out[k, rest] = sum_l f(l, rest) exp(-2 pi i l k / N); tw[j] = exp(-2 pi i j / N).
-__global__ void k_dft_first(int d, int N, CoefParams prm, const double2 *__restrict__ tw,
-                            double *__restrict__ out)
+constexpr int kMaxH = 65;   // N/2 + 1 for N <= 128
+
+// All per-hyper-parameter work of one window and one array (kernel or
+// ell-derivative) in one work-group.  The samples f(l) = kappa(|l| / N),
+// l in [-N/2, N/2)^d, are real and even in every coordinate (l = -N/2 has no
+// partner and enters once), so their DFT is real and even; per axis
+//
+//   sum_l g(l) exp(-2 pi i l k / N) = g(0) + 2 sum_{0<l<N/2} g(l) cos(2 pi l k / N)
+//                                     + g(N/2) (-1)^k,
+//
+// a real transform on the H = N/2 + 1 magnitudes l, k = 0..N/2, applied axis
+// by axis (scratch: two arrays of H^d doubles per window and array).  Then
+// b(k) = N^-d B(|k_1|, .., |k_d|) on I_N, the smallest b_k is the smallest of
+// these values, and in D(k) the term b(k) counts when no k_q = N/2, the term
+// b(-k) when no k_q = -N/2.  Grid (2, nwin): x = array (0: K, 1: derivative),
+// y = window of the group; the smallest coefficient goes to
+// minb[2 * s_global + x] (host-visible memory) and the transformed array to
+// the start of the block's scratch, where k_coef_diag reads it.
+// With INLDS the two H^d arrays live in LDS (dynamic shared memory, used when
+// they fit); otherwise in the global scratch.
+template <bool INLDS>
+__global__ void __launch_bounds__(1024)
+k_coef_all(int d, int N, CoefParams prm, double *__restrict__ scratch, const WinDesc *__restrict__ wd,
+           double *__restrict__ minb)
 {
-    int64_t K = 1;
-    for (int q = 0; q < d; ++q) K *= N;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= K * prm.nwin) return;
-    const int w = (int)(idx / K);
-    const int64_t e = idx % K;
-    const int64_t stride = K / N;                  // axis 0 is the slowest index
-    const int k = (int)(e / stride) - N / 2;
-    int64_t rem = e % stride;
-    double rest2 = 0.0;
-    for (int q = 1; q < d; ++q) {
-        const int l = (int)(rem % N) - N / 2;      // last axis fastest
-        rem /= N;
-        const double x = (double)l / (double)N;
-        rest2 += x * x;
+    __shared__ double cw[kMaxH * kMaxH];
+    __shared__ double red[1024];
+    extern __shared__ double dyn[];
+    const int arr = blockIdx.x, w = blockIdx.y;
+    const int H = N / 2 + 1;
+    const float invH = 1.0f / (float)H;
+    int KH = 1, K = 1;   // at most 65^3
+    for (int q = 0; q < d; ++q) {
+        KH *= H;
+        K *= N;
     }
-    double sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
-    for (int ll = 0; ll < N; ++ll) {
-        const int l = ll - N / 2;
-        const double x = (double)l / (double)N;
+    double *A = INLDS ? dyn : scratch + ((int64_t)w * 2 + arr) * 2 * KH;
+    double *B = A + KH;
+    for (int i = threadIdx.x; i < H * H; i += blockDim.x) {
+        const int l = i / H, k = i % H;
+        double c;
+        if (l == 0) c = 1.0;
+        else if (l == N / 2) c = (k & 1) ? -1.0 : 1.0;
+        else c = 2.0 * cospi(2.0 * (double)((l * k) & (N - 1)) / (double)N);
+        cw[i] = c;
+    }
+    // samples at magnitudes l_q = 0..N/2 (l_q = N/2 stands for the offset -N/2)
+    for (int i = threadIdx.x; i < KH; i += blockDim.x) {
+        int rem = i;
+        double r2 = 0.0;
+        for (int q = 0; q < d; ++q) {
+            const int qt = fdiv_small(rem, H, invH);
+            const double x = (double)(rem - qt * H) / (double)N;
+            rem = qt;
+            r2 += x * x;
+        }
         double v, dv;
-        sample_pair(prm, w, rest2 + x * x, v, dv);
-        const double2 t = tw[(l * k) & (N - 1)];   // N is a power of two
-        sr += v * t.x;
-        si += v * t.y;
-        dr += dv * t.x;
-        di += dv * t.y;
+        sample_pair(prm, w, r2, v, dv);
+        A[i] = arr == 0 ? v : dv;
     }
-    double *base = out + (int64_t)w * 4 * K;
-    base[2 * e] = sr;
-    base[2 * e + 1] = si;
-    base[2 * (K + e)] = dr;
-    base[2 * (K + e) + 1] = di;
+    __syncthreads();
+    // axis passes (axis q has stride H^(d-1-q))
+    int stride = KH / H;
+    for (int q = 0; q < d; ++q) {
+        const float inv_st = 1.0f / (float)stride;
+        for (int i = threadIdx.x; i < KH; i += blockDim.x) {
+            const int hi = fdiv_small(i, stride, inv_st);   // i / stride
+            const int k = hi - fdiv_small(hi, H, invH) * H;
+            const int base = i - k * stride;
+            double acc = 0.0;
+            for (int l = 0; l < H; ++l) acc += cw[l * H + k] * A[base + l * stride];
+            B[i] = acc;
+        }
+        __syncthreads();
+        double *t = A;
+        A = B;
+        B = t;
+        stride /= H;
+    }
+    const double invK = 1.0 / (double)K;
+    double mn = INFINITY;
+    for (int i = threadIdx.x; i < KH; i += blockDim.x) mn = fmin(mn, A[i] * invK);
+    red[threadIdx.x] = mn;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) minb[2 * wd[w].s_global + arr] = red[0];
+    // transformed array for the diagonal kernel
+    double *out = scratch + ((int64_t)w * 2 + arr) * 2 * KH;
+    if (INLDS || out != A)
+        for (int i = threadIdx.x; i < KH; i += blockDim.x) out[i] = A[i];
 }
 
-// One further axis of the d-dimensional DFT, applied to all 2 x nwin stacked
-// arrays: out[.., k, ..] = sum_l in[.., l, ..] exp(-2 pi i l k / N).
-__global__ void k_dft_axis(int d, int N, int axis, int narr, const double2 *__restrict__ tw,
-                           const double *__restrict__ in, double *__restrict__ out)
+// Diagonal D(k) on [-N/2, N/2]^d of every window and array of the group from
+// the transformed arrays (scratch layout of k_coef_all).  Grid
+// (ceil((N+1)^d / 256), 2, nwin).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_coef_diag(int d, int N, const double *__restrict__ cinv2, const double *__restrict__ scratch,
+            const WinDesc *__restrict__ wd)
 {
-    int64_t K = 1;
-    for (int q = 0; q < d; ++q) K *= N;
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)narr * K) return;
-    int64_t arr = idx / K, e = idx % K;
-    int64_t stride = 1;
-    for (int q = d - 1; q > axis; --q) stride *= N;
-    int kk = (int)((e / stride) % N);
-    int64_t base = arr * K + e - (int64_t)kk * stride;
-    int k = kk - N / 2;
-    double sr = 0.0, si = 0.0;
-    for (int ll = 0; ll < N; ++ll) {
-        int l = ll - N / 2;
-        const double2 t = tw[(l * k) & (N - 1)];
-        double ar = in[2 * (base + (int64_t)ll * stride)], ai = in[2 * (base + (int64_t)ll * stride) + 1];
-        sr += ar * t.x - ai * t.y;
-        si += ar * t.y + ai * t.x;
+    const int arr = blockIdx.y, w = blockIdx.z;
+    const int H = N / 2 + 1;
+    const float invN1 = 1.0f / (float)(N + 1);
+    int KH = 1, KD = 1, K = 1;
+    for (int q = 0; q < d; ++q) {
+        KH *= H;
+        KD *= N + 1;
+        K *= N;
     }
-    out[2 * (arr * K + e)] = sr;
-    out[2 * (arr * K + e) + 1] = si;
-}
-
-__global__ void k_twiddles(int N, double2 *__restrict__ tw)
-{
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    double sn, cs;
-    sincospi(-2.0 * (double)j / (double)N, &sn, &cs);
-    tw[j] = make_double2(cs, sn);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= KD) return;
+    const double *A = scratch + ((int64_t)w * 2 + arr) * 2 * KH;
+    int rem = i, ai = 0, astr = 1;
+    bool in_pos = true, in_neg = true;
+    double f = 1.0;
+    for (int q = d - 1; q >= 0; --q) {
+        const int qt = fdiv_small(rem, N + 1, invN1);
+        const int k = rem - qt * (N + 1) - N / 2;
+        rem = qt;
+        in_pos = in_pos && k < N / 2;
+        in_neg = in_neg && k > -N / 2;
+        ai += (k < 0 ? -k : k) * astr;
+        astr *= H;
+        f *= cinv2[k + N / 2];
+    }
+    const double cnt = (in_pos ? 1.0 : 0.0) + (in_neg ? 1.0 : 0.0);
+    T *Dout = reinterpret_cast<T *>(const_cast<void *>(arr == 0 ? wd[w].Dk : wd[w].Dder));
+    Dout[i] = (T)(0.5 * cnt * A[ai] / (double)K * f);
 }
 
 // Normalised window coefficient per dimension, c(k) = I_0(m sqrt(beta^2 -
@@ -135,105 +191,6 @@ __global__ void k_window_coef(int N, int m, double beta, double *__restrict__ ci
     cinv2[i] = 1.0 / (c * c);
 }
 
-// Grid (ceil(span / 256), nwin): block x of window y.  Besides the diagonal,
-// every block writes the minima of the plain coefficients b_k, b^der_k it
-// visited to part[(y * gridDim.x + x) * 2 + {0, 1}].
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_make_diag(int d, int N, const double *__restrict__ cinv2, const double *__restrict__ coef,
-            const WinDesc *__restrict__ wd, double *__restrict__ part)
-{
-    __shared__ double s0[256], s1[256];
-    int64_t K = 1, KD = 1;
-    for (int q = 0; q < d; ++q) {
-        K *= N;
-        KD *= (N + 1);
-    }
-    const int w = blockIdx.y;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const double *B = coef + (int64_t)w * 4 * K;
-    const double invK = 1.0 / (double)K;
-    double mk = INFINITY, md = INFINITY;
-    if (idx < K) {   // plain coefficients on I_N (for the definiteness report)
-        mk = B[2 * idx] * invK;
-        md = B[2 * (K + idx)] * invK;
-    }
-    if (idx < KD) {
-        int kv[3] = {0, 0, 0};
-        int64_t rem = idx;
-        for (int q = d - 1; q >= 0; --q) {
-            kv[q] = (int)(rem % (N + 1)) - N / 2;
-            rem /= (N + 1);
-        }
-        bool in_pos = true, in_neg = true;
-        int64_t ip = 0, in_ = 0;
-        double f = 1.0;
-        for (int q = 0; q < d; ++q) {
-            in_pos = in_pos && (kv[q] < N / 2);
-            in_neg = in_neg && (-kv[q] < N / 2);
-            ip = ip * N + (kv[q] + N / 2);
-            in_ = in_ * N + (-kv[q] + N / 2);
-            f *= cinv2[kv[q] + N / 2];
-        }
-        double bk = 0.0, bd = 0.0;
-        if (in_pos) {
-            bk += B[2 * ip] * invK;
-            bd += B[2 * (K + ip)] * invK;
-        }
-        if (in_neg) {
-            bk += B[2 * in_] * invK;
-            bd += B[2 * (K + in_)] * invK;
-        }
-        reinterpret_cast<T *>(const_cast<void *>(wd[w].Dk))[idx] = (T)(0.5 * bk * f);
-        reinterpret_cast<T *>(const_cast<void *>(wd[w].Dder))[idx] = (T)(0.5 * bd * f);
-    }
-    s0[threadIdx.x] = mk;
-    s1[threadIdx.x] = md;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            s0[threadIdx.x] = fmin(s0[threadIdx.x], s0[threadIdx.x + off]);
-            s1[threadIdx.x] = fmin(s1[threadIdx.x], s1[threadIdx.x + off]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const int64_t o = ((int64_t)w * gridDim.x + blockIdx.x) * 2;
-        part[o] = s0[0];
-        part[o + 1] = s1[0];
-    }
-}
-
-// Smallest b_k and b^der_k of every window of the group (one block per window)
-// from the block minima, written to minb[2 * s_global + {0, 1}].
-__global__ void __launch_bounds__(256)
-k_min2(const double *__restrict__ part, int nper, const WinDesc *__restrict__ wd,
-       double *__restrict__ minb)
-{
-    __shared__ double s0[256], s1[256];
-    const int w = blockIdx.x;
-    const double *v = part + (int64_t)w * nper * 2;
-    double a = INFINITY, b = INFINITY;
-    for (int i = threadIdx.x; i < nper; i += 256) {
-        a = fmin(a, v[2 * i]);
-        b = fmin(b, v[2 * i + 1]);
-    }
-    s0[threadIdx.x] = a;
-    s1[threadIdx.x] = b;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            s0[threadIdx.x] = fmin(s0[threadIdx.x], s0[threadIdx.x + off]);
-            s1[threadIdx.x] = fmin(s1[threadIdx.x], s1[threadIdx.x + off]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        minb[2 * wd[w].s_global] = s0[0];
-        minb[2 * wd[w].s_global + 1] = s1[0];
-    }
-}
-
 }  // namespace
 
 hipError_t launch_window_coef(int N, int m, double *cinv2, hipStream_t s)
@@ -242,38 +199,36 @@ hipError_t launch_window_coef(int N, int m, double *cinv2, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_twiddles(int N, double2 *tw, hipStream_t s)
+int64_t coef_scratch_doubles(const WindowGeom &g, int nwin)
 {
-    k_twiddles<<<(N + 255) / 256, 256, 0, s>>>(N, tw);
-    return hipGetLastError();
+    int64_t KH = 1;
+    for (int q = 0; q < g.d; ++q) KH *= g.N / 2 + 1;
+    return 4 * KH * nwin;
 }
 
 hipError_t launch_coefficients(int prec, const Group &G, const CoefParams &prm, const double *cinv2,
-                               const double2 *tw, double *coef, double *bbar, double *minb,
-                               hipStream_t s)
+                               double *scratch, double *minb, hipStream_t s)
 {
-    const WindowGeom &g = G.g;
-    int64_t K = 1, KD = 1;
-    for (int q = 0; q < g.d; ++q) {
-        K *= g.N;
-        KD *= (g.N + 1);
+    const dim3 grid(2, (unsigned)G.nwin);
+    int64_t KH = 1, KD = 1;
+    for (int q = 0; q < G.g.d; ++q) {
+        KH *= G.g.N / 2 + 1;
+        KD *= G.g.N + 1;
     }
-    const int nw = G.nwin;
-    double *a = coef, *b = coef + (int64_t)nw * 4 * K;   // ping-pong: [window][2][K] complex each
-    k_dft_first<<<(unsigned)((nw * K + 255) / 256), 256, 0, s>>>(g.d, g.N, prm, tw, a);
-    for (int q = 1; q < g.d; ++q) {
-        k_dft_axis<<<(unsigned)((2 * nw * K + 255) / 256), 256, 0, s>>>(g.d, g.N, q, 2 * nw, tw, a, b);
-        double *t = a;
-        a = b;
-        b = t;
+    const size_t lds = (size_t)2 * KH * sizeof(double);
+    if (lds <= 96 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_coef_all<true>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        k_coef_all<true><<<grid, 1024, lds, s>>>(G.g.d, G.g.N, prm, scratch, G.desc, minb);
+    } else {
+        k_coef_all<false><<<grid, 1024, 0, s>>>(G.g.d, G.g.N, prm, scratch, G.desc, minb);
     }
-    const unsigned nper = (unsigned)(((KD > K ? KD : K) + 255) / 256);
-    const dim3 grid(nper, (unsigned)nw);
+    const dim3 dgrid((unsigned)((KD + 255) / 256), 2, (unsigned)G.nwin);
     if (prec == NFFTGP_F32)
-        k_make_diag<float><<<grid, 256, 0, s>>>(g.d, g.N, cinv2, a, G.desc, bbar);
+        k_coef_diag<float><<<dgrid, 256, 0, s>>>(G.g.d, G.g.N, cinv2, scratch, G.desc);
     else
-        k_make_diag<double><<<grid, 256, 0, s>>>(g.d, g.N, cinv2, a, G.desc, bbar);
-    k_min2<<<nw, 256, 0, s>>>(bbar, (int)nper, G.desc, minb);
+        k_coef_diag<double><<<dgrid, 256, 0, s>>>(G.g.d, G.g.N, cinv2, scratch, G.desc);
     return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@
 // varying fastest, so for strided axes consecutive lines of a group read
 // consecutive addresses.
 #include "nfftgp_impl.h"
+#include "nfftgp_dev.h"
 
 namespace nfftgp {
 namespace {
@@ -115,8 +116,9 @@ k_fft_pruned(typename Cplx<T>::type *__restrict__ data, PruneGeom pg, int ax, in
         const int64_t L = (int64_t)blockIdx.x * LPB + li;
         const bool ok = L < nlines;
         const int64_t Lc = ok ? L : 0;
+        // lines of one batch entry: at most 257^2, so 32-bit index math below
         const int64_t b = Lc / lines_per_batch;
-        int64_t rem = Lc % lines_per_batch;
+        int rem = (int)(Lc - b * lines_per_batch);
         int64_t base = b * pg.cells;
         int di = 0, dstride = 1;   // offset in the (N+1)^d diagonal of the F axes
         int64_t stride = 1;
@@ -124,8 +126,9 @@ k_fft_pruned(typename Cplx<T>::type *__restrict__ data, PruneGeom pg, int ax, in
             if (q != ax) {
                 const bool om = q < ax;
                 const int len = om ? pg.on : pg.fn;
-                const int j = (int)(rem % len);
-                rem /= len;
+                const int qt = fdiv_small(rem, len, 1.0f / (float)len);
+                const int j = rem - qt * len;
+                rem = qt;
                 const int pos = cyc_pos(om ? pg.olo : pg.flo, j, ng);
                 base += (int64_t)pos * stride;
                 if (!om) {

@@ -17,8 +17,10 @@
 // work item its window's point data.  A subproblem is a run of points of one
 // tile ("bin", tb cells per dimension) in the window's sorted order.
 #include "nfftgp_impl.h"
+#include "nfftgp_dev.h"
 
 #include <cstdlib>
+#include <type_traits>
 
 namespace nfftgp {
 namespace {
@@ -26,16 +28,6 @@ namespace {
 template <typename T> struct Cplx;
 template <> struct Cplx<float> { using type = float2; };
 template <> struct Cplx<double> { using type = double2; };
-
-// i / d for 0 <= i < 2^22 and 0 < d <= 1024 by a float reciprocal and one
-// correction step (exact in that range).
-__device__ __forceinline__ int fdiv_small(int i, int d, float inv_d)
-{
-    int q = (int)((float)i * inv_d);
-    const int r = i - q * d;
-    q += (r >= d) - (r < 0);
-    return q;
-}
 
 template <int D>
 __device__ __forceinline__ void bin_origin(int bin, int nb, int tb, int *org)
@@ -114,16 +106,44 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[g][k][r] = T(0);
     const int nr = min(R, nrhs - r0);
+    // the next chunk's global data is loaded into registers while the current
+    // chunk is processed
+    constexpr int NT = 64 * W;
+    constexpr int NREC = (CH * RS + NT - 1) / NT, NV = (CH * R + NT - 1) / NT;
+    T g_rec[NREC], g_v[NV];
+    int g_lp = 0;
+    auto fetch = [&](int cb) {
+        const int nc = min(CH, end - cb);
+#pragma unroll
+        for (int k = 0; k < NREC; ++k) {
+            const int i = tid + k * NT;
+            g_rec[k] = i < nc * RS ? rec[(int64_t)cb * RS + i] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const int i = tid + k * NT;
+            const int u = i / R, r = i % R;
+            g_v[k] = (i < nc * R && r < nr) ? V[(int64_t)perm[cb + u] * ldv + r0 + r] : T(0);
+        }
+        g_lp = tid < nc ? lpos[cb + tid] : 0;
+    };
+    if (cnt > 0) fetch(start);
     for (int cb = start; cb < end; cb += CH) {
         const int nc = min(CH, end - cb);
         __syncthreads();   // tiles cleared / previous chunk consumed
-        for (int i = tid; i < nc * RS; i += 64 * W) s_rec[i] = rec[(int64_t)cb * RS + i];
-        for (int i = tid; i < nc * R; i += 64 * W) {
-            const int u = i / R, r = i % R;
-            s_v[i] = r < nr ? V[(int64_t)perm[cb + u] * ldv + r0 + r] : T(0);
+#pragma unroll
+        for (int k = 0; k < NREC; ++k) {
+            const int i = tid + k * NT;
+            if (i < CH * RS) s_rec[i] = g_rec[k];
         }
-        for (int i = tid; i < nc; i += 64 * W) s_lp[i] = lpos[cb + i];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const int i = tid + k * NT;
+            if (i < CH * R) s_v[i] = g_v[k];
+        }
+        if (tid < CH) s_lp[tid] = g_lp;
         __syncthreads();
+        if (cb + CH < end) fetch(cb + CH);
         // run ends inside this chunk (the subproblem's last point ends a run)
         const bool isend = lane < nc && (s_lp[lane] < 0 || cb + lane == end - 1);
         const unsigned long long ends = __ballot(isend);
@@ -135,36 +155,52 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             const int lp = __builtin_amdgcn_readfirstlane(s_lp[u0] & 0x7fffffff);
             // first owned tap along dimension 0 (tile position = wave mod W)
             const int aoff = D == 3 ? ((wave - (lp >> 20)) % W + W) % W : 0;
-            for (int u = u0; u <= u1; ++u) {
+            // per-point operands; the next point's are read from LDS while the
+            // current point is accumulated
+            T cv[R], cw0[NA], cw1[NG], cw2[NG];
+            auto load = [&](int u, T *v, T *w0, T *w1, T *w2) {
                 const T *rp = s_rec + u * RS;
-                T vr[R];
 #pragma unroll
-                for (int r = 0; r < R; ++r) vr[r] = s_v[u * R + r];
-                T w0[NA];
-                if (D == 3) {
+                for (int r = 0; r < R; ++r) v[r] = s_v[u * R + r];
 #pragma unroll
-                    for (int k = 0; k < NA; ++k) w0[k] = rp[aoff + k * W];
-                }
+                for (int k = 0; k < NA; ++k) w0[k] = D == 3 ? rp[aoff + k * W] : T(1);
 #pragma unroll
                 for (int g = 0; g < NG; ++g) {
                     if (D == 3) {
-                        const T wbc = rp[TW + i0[g]] * rp[2 * TW + i1[g]];
-                        T z[R];
-#pragma unroll
-                        for (int r = 0; r < R; ++r) z[r] = wbc * vr[r];
-#pragma unroll
-                        for (int k = 0; k < NA; ++k)
-#pragma unroll
-                            for (int r = 0; r < R; ++r) acc[g][k][r] += w0[k] * z[r];
+                        w1[g] = rp[TW + i0[g]];
+                        w2[g] = rp[2 * TW + i1[g]];
                     } else if (D == 2) {
-                        const T w = rp[i0[g]] * rp[TW + i1[g]];
-#pragma unroll
-                        for (int r = 0; r < R; ++r) acc[g][0][r] += w * vr[r];
+                        w1[g] = rp[i0[g]];
+                        w2[g] = rp[TW + i1[g]];
                     } else {
-                        const T w = rp[i0[g]];
-#pragma unroll
-                        for (int r = 0; r < R; ++r) acc[g][0][r] += w * vr[r];
+                        w1[g] = rp[i0[g]];
+                        w2[g] = T(1);
                     }
+                }
+            };
+            load(u0, cv, cw0, cw1, cw2);
+            for (int u = u0; u <= u1; ++u) {
+                T nv[R], nw0[NA], nw1[NG], nw2[NG];
+                load(u < u1 ? u + 1 : u, nv, nw0, nw1, nw2);
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    const T wbc = cw1[g] * cw2[g];
+                    T z[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) z[r] = wbc * cv[r];
+#pragma unroll
+                    for (int k = 0; k < NA; ++k)
+#pragma unroll
+                        for (int r = 0; r < R; ++r) acc[g][k][r] += cw0[k] * z[r];
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) cv[r] = nv[r];
+#pragma unroll
+                for (int k = 0; k < NA; ++k) cw0[k] = nw0[k];
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    cw1[g] = nw1[g];
+                    cw2[g] = nw2[g];
                 }
             }
             if (flush) {
@@ -229,26 +265,31 @@ k_fold_bins(const WinDesc *__restrict__ wd, const int *__restrict__ fb, T *__res
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
 k_fold(const WinDesc *__restrict__ wd, const T *__restrict__ tilebuf, int nrhs, int tb, int nb,
-       int ng, int m, int pd, int pc, int64_t cells, int olo, int on, int64_t ocells, int64_t total,
+       int ng, int m, int pd, int pc, int64_t cells, int olo, int on, int ocells,
        typename Cplx<T>::type *__restrict__ grid)
 {
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const int64_t wr = idx / ocells;
-    const int w = (int)(wr / nrhs), r = (int)(wr % nrhs);
-    int64_t rem = idx % ocells;
+    // one thread per occupied cell; blockIdx.y = window * nrhs + vector
+    const int ci = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ci >= ocells) return;
+    const int wr = blockIdx.y;
+    const int w = wr / nrhs, r = wr % nrhs;
+    int rem = ci;
+    const float inv_on = 1.0f / (float)on;
     const int *bsp = wd[w].bin_sub_ptr;
     int l[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     int64_t cell = 0, cstride = 1;
     for (int q = D - 1; q >= 0; --q) {
-        l[q] = olo + (int)(rem % on);
-        rem /= on;
+        const int qt = fdiv_small(rem, on, inv_on);
+        l[q] = olo + (rem - qt * on);
+        rem = qt;
         cell += (int64_t)l[q] * cstride;
         cstride *= ng;
         // bins b with b*tb - m <= l <= b*tb - m + pd - 1
         int num = l[q] + m - pd + 1;
-        int blo = num >= 0 ? (num + tb - 1) / tb : -((-num) / tb);
-        int bhi = (l[q] + m) / tb;
+        // tb is a power of two: floor / ceil division by shifts
+        const int sh = __ffs(tb) - 1;
+        int blo = -((-num) >> sh);   // ceil(num / tb)
+        int bhi = (l[q] + m) >> sh;
         lo[q] = blo < 0 ? 0 : blo;
         hi[q] = bhi > nb - 1 ? nb - 1 : bhi;
     }
@@ -271,7 +312,7 @@ k_fold(const WinDesc *__restrict__ wd, const T *__restrict__ tilebuf, int nrhs, 
     typename Cplx<T>::type o;
     o.x = sum;
     o.y = T(0);
-    grid[wr * cells + cell] = o;
+    grid[(int64_t)wr * cells + cell] = o;
 }
 
 // ---------------------------------------------------------------- interpolation
@@ -536,6 +577,134 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     }
 }
 
+// Interpolation of 3-D windows on the matrix cores (FP32).  Points of one cell
+// share the (2m)^3 grid values F[a][b][c] they read, so for a tile of up to 16
+// points u of one cell
+//
+//   T[(a,b)][u] = sum_c F[(a,b)][c] psi_2,u[c]        (16 x 4 MFMA tiles, K = c)
+//   h_u         = sum_(a,b) psi_0,u[a] psi_1,u[b] T[(a,b)][u]
+//
+// The rows (a, b) are packed 16 per MFMA tile: RA rows per a (2m, or 16 for
+// 2m > 8 with rows b >= 2m left zero), AP = 16 / RA values of a per tile.  With
+// v_mfma_f32_16x16x4f32, lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// and receives D[4 (l / 16) + r][l % 16], r = 0..3; so lane l finishes the
+// second sum over its rows for point l % 16 and four lanes are added with two
+// shuffles.  One wave per subproblem (a contiguous range of sorted points of
+// one window); point data are staged in LDS in chunks of 64; F (and the
+// derivative grid's F) is loaded from the grid once per run and vector.
+template <int M, bool DER>
+__global__ void __launch_bounds__(64)
+k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
+              const int *__restrict__ sub_start, const int *__restrict__ sub_count, int ng, int nwin,
+              const float2 *__restrict__ grid, int64_t cells, int nrhs, int64_t n,
+              float *__restrict__ hbuf, float *__restrict__ dout, float dscale)
+{
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    constexpr int TW = 2 * M;
+    constexpr int RS = 3 * TW;
+    constexpr int RA = TW <= 8 ? TW : 16;     // rows per value of a
+    constexpr int AP = 16 / RA;               // values of a per MFMA tile
+    constexpr int MT = TW / AP;               // MFMA tiles along (a, b)
+    constexpr int KS = TW / 4;                // K steps along c
+    constexpr int CH = 64;
+    static_assert(TW % 4 == 0 && 16 % RA == 0, "tap count");
+    __shared__ float s_rec[CH * RS];
+    __shared__ int s_an[CH];
+    __shared__ int s_perm[CH];
+    const int lane = threadIdx.x;
+    const int li = lane & 15, g = lane >> 4;
+    const int wi = sub_win[blockIdx.x];
+    const WinDesc &win = wd[wi];
+    const float *rec = reinterpret_cast<const float *>(win.rec);
+    const int start = sub_start[blockIdx.x], end = start + sub_count[blockIdx.x];
+    // A operand position of this lane: row i = li of each tile, column c = 4 s + g
+    const int a_in = li / RA, b_in = li % RA;
+    const bool row_ok = b_in < TW;
+    // D rows of this lane: a = t AP + aoff, b = boff + r
+    const int aoff = (4 * g) / RA, boff = (4 * g) % RA;
+    float *hout = hbuf + (int64_t)win.s_global * n * nrhs;
+    float *dblk = DER ? dout + (int64_t)win.s_global * n * nrhs : nullptr;
+    for (int cb = start; cb < end; cb += CH) {
+        const int nc = min(CH, end - cb);
+        __syncthreads();
+        for (int i = lane; i < nc * RS; i += 64) s_rec[i] = rec[(int64_t)cb * RS + i];
+        if (lane < nc) {
+            s_an[lane] = win.anchor[cb + lane] & 0x7fffffff;
+            s_perm[lane] = win.perm[cb + lane];
+        }
+        __syncthreads();
+        for (int r = 0; r < nrhs; ++r) {
+            const float2 *gK = grid + ((int64_t)wi * nrhs + r) * cells;
+            const float2 *gD = DER ? grid + ((int64_t)(nwin + wi) * nrhs + r) * cells : gK;
+            float AK[MT][KS], AD[MT][KS];
+            int cur = -1;
+            int u = 0;
+            while (u < nc) {
+                const int cell = __builtin_amdgcn_readfirstlane(s_an[u]);
+                if (cell != cur) {
+                    cur = cell;
+                    const int c2 = cell % ng, c1 = (cell / ng) % ng, c0 = cell / (ng * ng);
+                    const int64_t base = ((int64_t)(c0 - M + 1 + a_in) * ng + (c1 - M + 1 + b_in)) * ng +
+                                         (c2 - M + 1 + g);
+#pragma unroll
+                    for (int t = 0; t < MT; ++t)
+#pragma unroll
+                        for (int s = 0; s < KS; ++s) {
+                            const int64_t o = base + (int64_t)t * AP * ng * ng + 4 * s;
+                            AK[t][s] = row_ok ? gK[o].x : 0.f;
+                            if (DER) AD[t][s] = row_ok ? gD[o].x : 0.f;
+                        }
+                }
+                // points u .. u + tl - 1 share the cell (tl <= 16)
+                const bool same = lane < 16 && u + lane < nc && s_an[u + lane] == cell;
+                const unsigned long long msk = __ballot(same);
+                const int tl = (int)__builtin_ctzll(~msk);
+                const bool pv = li < tl;
+                const float *rp = s_rec + (u + (pv ? li : 0)) * RS;
+                float bw[KS];
+#pragma unroll
+                for (int s = 0; s < KS; ++s) bw[s] = pv ? rp[2 * TW + 4 * s + g] : 0.f;
+                float w1[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) w1[q] = (boff + q < TW) ? rp[TW + boff + q] : 0.f;
+                // per MFMA tile: the K-chain over c, then the second contraction
+                // over this lane's rows (point li)
+                float hK = 0.f, hD = 0.f;
+#pragma unroll
+                for (int t = 0; t < MT; ++t) {
+                    v4f aK = v4f{0.f, 0.f, 0.f, 0.f}, aD = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int s = 0; s < KS; ++s) {
+                        aK = __builtin_amdgcn_mfma_f32_16x16x4f32(AK[t][s], bw[s], aK, 0, 0, 0);
+                        if (DER) aD = __builtin_amdgcn_mfma_f32_16x16x4f32(AD[t][s], bw[s], aD, 0, 0, 0);
+                    }
+                    const float w0 = rp[t * AP + aoff];
+                    float sK = 0.f, sD = 0.f;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        sK += w1[q] * aK[q];
+                        if (DER) sD += w1[q] * aD[q];
+                    }
+                    hK += w0 * sK;
+                    if (DER) hD += w0 * sD;
+                }
+                hK += __shfl_xor(hK, 16, 64);
+                hK += __shfl_xor(hK, 32, 64);
+                if (DER) {
+                    hD += __shfl_xor(hD, 16, 64);
+                    hD += __shfl_xor(hD, 32, 64);
+                }
+                if (g == 0 && pv) {
+                    const int64_t o = (int64_t)s_perm[u + li] * nrhs + r;
+                    hout[o] = hK;
+                    if (DER) dblk[o] = dscale * hD;
+                }
+                u += tl;
+            }
+        }
+    }
+}
+
 // sigma_f^2 sum_s h^(s) + sigma_eps^2 v, summed over windows in order with
 // Kahan compensation; derivative blocks for sigma_f and sigma_eps.
 template <typename T>
@@ -613,6 +782,19 @@ hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool
 {
     const WindowGeom &g = G.g;
     using C = typename Cplx<T>::type;
+    if constexpr (std::is_same<T, float>::value && D == 3 && M <= 6) {
+        if (G.use_mfma_interp) {
+            if (with_der)
+                k_interp_mfma<M, true><<<(unsigned)G.nrsub, 64, 0, s>>>(
+                    G.desc, G.rsub_win, G.rsub_start, G.rsub_count, g.ng, G.nwin, (const float2 *)grid,
+                    g.cells, nrhs, n, (float *)hbuf, (float *)dout, (float)dscale);
+            else
+                k_interp_mfma<M, false><<<(unsigned)G.nrsub, 64, 0, s>>>(
+                    G.desc, G.rsub_win, G.rsub_start, G.rsub_count, g.ng, G.nwin, (const float2 *)grid,
+                    g.cells, nrhs, n, (float *)hbuf, nullptr, (float)dscale);
+            return hipGetLastError();
+        }
+    }
     if (G.use_run_interp) {
         if (with_der)
             k_interp_run<T, D, M, true><<<(unsigned)G.nrsub, 64, 0, s>>>(
@@ -683,11 +865,10 @@ hipError_t fold_t(const Group &G, int m, int nrhs, void *tilebuf, void *grid, hi
     const int olo = g.N / 2 - m + 1, on = g.N + 2 * m;
     int64_t ocells = 1;
     for (int q = 0; q < g.d; ++q) ocells *= on;
-    const int64_t tot = (int64_t)G.nwin * nrhs * ocells;
-    unsigned nblk = (unsigned)((tot + 255) / 256);
-#define NFFTGP_FOLD(DD)                                                                            \
-    k_fold<T, DD><<<nblk, 256, 0, s>>>(G.desc, (const T *)tilebuf, nrhs, g.tb, g.nb, g.ng, m, g.pd, \
-                                       g.pc, g.cells, olo, on, ocells, tot, (C *)grid);
+    const dim3 fgrid((unsigned)((ocells + 255) / 256), (unsigned)(G.nwin * nrhs));
+#define NFFTGP_FOLD(DD)                                                                              \
+    k_fold<T, DD><<<fgrid, 256, 0, s>>>(G.desc, (const T *)tilebuf, nrhs, g.tb, g.nb, g.ng, m, g.pd, \
+                                        g.pc, g.cells, olo, on, (int)ocells, (C *)grid);
     switch (g.d) {
     case 1: NFFTGP_FOLD(1) break;
     case 2: NFFTGP_FOLD(2) break;

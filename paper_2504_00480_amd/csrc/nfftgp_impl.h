@@ -94,10 +94,11 @@ struct Group {
     // interpolation by register-held runs (chosen when runs of equal cells are long):
     // contiguous ranges of at most kRunSubPoints sorted points
     bool use_run_interp = false;
+    bool use_mfma_interp = false;   // FP32 3-D windows, m <= 6: matrix-core interpolation
+                                    // over the same point ranges
     int32_t *rsub_win = nullptr, *rsub_start = nullptr, *rsub_count = nullptr;
     int nrsub = 0;
     double *cinv2 = nullptr;     // N+1 window factors 1 / c(k)^2 (same for the whole group)
-    double2 *tw = nullptr;       // N twiddles exp(-2 pi i j / N) for the coefficient DFT
 };
 
 }  // namespace nfftgp
@@ -120,10 +121,9 @@ struct nfftgp_plan_s {
     void *tilebuf = nullptr;     // spreading tiles
     void *grid = nullptr;        // 2 x (windows of a group) x max_nrhs x cells complex values
     void *hbuf = nullptr;        // P x n x max_nrhs per-window products
-    double *coef = nullptr;      // 4 x maxN^d complex doubles (set_hyper scratch)
-    double *bbar = nullptr;      // block minima of the coefficients (set_hyper scratch)
-    double *minb = nullptr;      // 2 x P doubles (device)
-    double *minb_host = nullptr; // 2 x P doubles (pinned host copy, read lazily)
+    double *coef = nullptr;      // set_hyper scratch (real coefficient transforms)
+    double *minb_host = nullptr; // 2 x P smallest coefficients (pinned, written by the
+                                 // coefficient kernel, read lazily)
     bool minb_pending = false;
     double *dot_part = nullptr;  // dot-product partials
     double *cg_scal = nullptr;   // CG per-column scalars
@@ -194,12 +194,14 @@ struct CoefParams {
     int32_t nwin;
 };
 hipError_t launch_window_coef(int N, int m, double *cinv2, hipStream_t s);
-hipError_t launch_twiddles(int N, double2 *tw, hipStream_t s);
+// Scratch (doubles) the coefficient kernel of a group needs.
+int64_t coef_scratch_doubles(const WindowGeom &g, int nwin);
 
 // ---------------------------------------------------------------- apply kernels
+// Coefficients and diagonals of every window of a group (one launch); the
+// smallest b_k, b^der_k of window s go to minb[2 s], minb[2 s + 1].
 hipError_t launch_coefficients(int prec, const Group &G, const CoefParams &prm, const double *cinv2,
-                               const double2 *tw, double *coef, double *bbar, double *minb,
-                               hipStream_t s);
+                               double *scratch, double *minb, hipStream_t s);
 hipError_t launch_spread(int prec, const Group &G, int m, const void *V, int64_t ldv, int nrhs,
                          void *tilebuf, hipStream_t s);
 hipError_t launch_fold(int prec, const Group &G, int m, int nrhs, void *tilebuf, void *grid,
