@@ -155,54 +155,50 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             const int lp = __builtin_amdgcn_readfirstlane(s_lp[u0] & 0x7fffffff);
             // first owned tap along dimension 0 (tile position = wave mod W)
             const int aoff = D == 3 ? ((wave - (lp >> 20)) % W + W) % W : 0;
-            // per-point operands; the next point's are read from LDS while the
-            // current point is accumulated
-            T cv[R], cw0[NA], cw1[NG], cw2[NG];
-            auto load = [&](int u, T *v, T *w0, T *w1, T *w2) {
-                const T *rp = s_rec + u * RS;
+            // points are accumulated in groups of 4 while the run has that many
+            // left, then one by one: the LDS reads of a group are issued
+            // together, so one wait covers the group
+            auto accumulate = [&](auto pu_tag, int u) {
+                constexpr int PU = decltype(pu_tag)::value;
+                T v[PU][R], w0[PU][NA], w1[PU][NG], w2[PU][NG];
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[r] = s_v[u * R + r];
+                for (int p = 0; p < PU; ++p) {
+                    const T *rp = s_rec + (u + p) * RS;
 #pragma unroll
-                for (int k = 0; k < NA; ++k) w0[k] = D == 3 ? rp[aoff + k * W] : T(1);
+                    for (int r = 0; r < R; ++r) v[p][r] = s_v[(u + p) * R + r];
 #pragma unroll
-                for (int g = 0; g < NG; ++g) {
-                    if (D == 3) {
-                        w1[g] = rp[TW + i0[g]];
-                        w2[g] = rp[2 * TW + i1[g]];
-                    } else if (D == 2) {
-                        w1[g] = rp[i0[g]];
-                        w2[g] = rp[TW + i1[g]];
-                    } else {
-                        w1[g] = rp[i0[g]];
-                        w2[g] = T(1);
+                    for (int k = 0; k < NA; ++k) w0[p][k] = D == 3 ? rp[aoff + k * W] : T(1);
+#pragma unroll
+                    for (int g = 0; g < NG; ++g) {
+                        if (D == 3) {
+                            w1[p][g] = rp[TW + i0[g]];
+                            w2[p][g] = rp[2 * TW + i1[g]];
+                        } else if (D == 2) {
+                            w1[p][g] = rp[i0[g]];
+                            w2[p][g] = rp[TW + i1[g]];
+                        } else {
+                            w1[p][g] = rp[i0[g]];
+                            w2[p][g] = T(1);
+                        }
                     }
                 }
+#pragma unroll
+                for (int p = 0; p < PU; ++p)
+#pragma unroll
+                    for (int g = 0; g < NG; ++g) {
+                        const T wbc = w1[p][g] * w2[p][g];
+                        T z[R];
+#pragma unroll
+                        for (int r = 0; r < R; ++r) z[r] = wbc * v[p][r];
+#pragma unroll
+                        for (int k = 0; k < NA; ++k)
+#pragma unroll
+                            for (int r = 0; r < R; ++r) acc[g][k][r] += w0[p][k] * z[r];
+                    }
             };
-            load(u0, cv, cw0, cw1, cw2);
-            for (int u = u0; u <= u1; ++u) {
-                T nv[R], nw0[NA], nw1[NG], nw2[NG];
-                load(u < u1 ? u + 1 : u, nv, nw0, nw1, nw2);
-#pragma unroll
-                for (int g = 0; g < NG; ++g) {
-                    const T wbc = cw1[g] * cw2[g];
-                    T z[R];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) z[r] = wbc * cv[r];
-#pragma unroll
-                    for (int k = 0; k < NA; ++k)
-#pragma unroll
-                        for (int r = 0; r < R; ++r) acc[g][k][r] += cw0[k] * z[r];
-                }
-#pragma unroll
-                for (int r = 0; r < R; ++r) cv[r] = nv[r];
-#pragma unroll
-                for (int k = 0; k < NA; ++k) cw0[k] = nw0[k];
-#pragma unroll
-                for (int g = 0; g < NG; ++g) {
-                    cw1[g] = nw1[g];
-                    cw2[g] = nw2[g];
-                }
-            }
+            int u = u0;
+            for (; u + 3 <= u1; u += 4) accumulate(std::integral_constant<int, 4>(), u);
+            for (; u <= u1; ++u) accumulate(std::integral_constant<int, 1>(), u);
             if (flush) {
                 const int base = (lp & 0xfffff) + (D == 3 ? aoff * pd2 : 0);
 #pragma unroll
