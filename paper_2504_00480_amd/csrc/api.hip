@@ -401,14 +401,12 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
                 cells_used += plan->win[G.wins[wl]].h_cells_used;
             }
             const char *ov = std::getenv("NFFTGP_INTERP");
-            const bool mfma_ok = prec == NFFTGP_F32 && G.g.d == 3 && m <= 6 && n > 0;
             if (ov && std::strcmp(ov, "run") == 0) G.use_run_interp = n > 0;
             else if (ov && std::strcmp(ov, "tile") == 0) G.use_run_interp = false;
-            else if (ov && std::strcmp(ov, "mfma") == 0) G.use_mfma_interp = mfma_ok;
             else G.use_run_interp = G.g.d == 3 && cells_used > 0 &&
                                     pts >= (int64_t)kRunInterpMinRun * cells_used;
         }
-        if (G.use_run_interp || G.use_mfma_interp) {
+        if (G.use_run_interp) {
             // points per wave: up to kRunSubPoints, fewer while that leaves
             // under 8192 waves for the group
             int rsp = kRunSubPoints;

@@ -48,16 +48,16 @@ struct PruneGeom {
     int64_t cells;
 };
 
-template <typename T, int LOGN>
+template <typename T, int LOGN, int LPB>
 __device__ __forceinline__ void fft_stages(typename Cplx<T>::type (*buf)[(1 << LOGN) + 1],
-                                           const typename Cplx<T>::type *tw, int lpb)
+                                           const typename Cplx<T>::type *tw)
 {
     using C = typename Cplx<T>::type;
     constexpr int NG = 1 << LOGN;
 #pragma unroll
     for (int s = 1; s <= LOGN; ++s) {
         const int len = 1 << s, half = len >> 1;
-        for (int bfi = threadIdx.x; bfi < lpb * NG / 2; bfi += blockDim.x) {
+        for (int bfi = threadIdx.x; bfi < LPB * NG / 2; bfi += 256) {
             const int li = bfi / (NG / 2), rest = bfi % (NG / 2);
             const int grp = rest / half, j = rest % half;
             const int i0 = grp * len + j, i1 = i0 + half;
@@ -147,7 +147,7 @@ k_fft_pruned(typename Cplx<T>::type *__restrict__ data, PruneGeom pg, int ax, in
     __syncthreads();
     const bool in_om = MODE != 1;                    // input set: Omega or F
     const int ilo = in_om ? pg.olo : pg.flo, ilen = in_om ? pg.on : pg.fn;
-    for (int idx = threadIdx.x; idx < LPB * NG; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < LPB * NG; idx += 256) {
         int li, k;
         if (S == 1) {
             li = idx / NG;
@@ -163,10 +163,10 @@ k_fft_pruned(typename Cplx<T>::type *__restrict__ data, PruneGeom pg, int ax, in
         buf[li][__brev((unsigned)k) >> (32 - LOGN)] = v;
     }
     __syncthreads();
-    fft_stages<T, LOGN>(buf, twf, LPB);
+    fft_stages<T, LOGN, LPB>(buf, twf);
     if constexpr (MODE != 2) {
         const int olo2 = MODE == 0 ? pg.flo : pg.olo, olen = MODE == 0 ? pg.fn : pg.on;
-        for (int idx = threadIdx.x; idx < LPB * NG; idx += blockDim.x) {
+        for (int idx = threadIdx.x; idx < LPB * NG; idx += 256) {
             int li, k;
             if (S == 1) {
                 li = idx / NG;
@@ -184,7 +184,7 @@ k_fft_pruned(typename Cplx<T>::type *__restrict__ data, PruneGeom pg, int ax, in
     for (int q = 1; q < pg.d; ++q) dstr0 *= (pg.N + 1);
 #pragma unroll 1
     for (int pass = 0; pass < (DER ? 2 : 1); ++pass) {
-        for (int idx = threadIdx.x; idx < LPB * NG; idx += blockDim.x) {
+        for (int idx = threadIdx.x; idx < LPB * NG; idx += 256) {
             const int k = S == 1 ? idx % NG : idx / LPB, li = S == 1 ? idx / NG : idx % LPB;
             const int f = k < pg.N ? k : k - ng;
             T dv = T(0);
@@ -199,9 +199,9 @@ k_fft_pruned(typename Cplx<T>::type *__restrict__ data, PruneGeom pg, int ax, in
             buf2[li][__brev((unsigned)k) >> (32 - LOGN)] = v;
         }
         __syncthreads();
-        fft_stages<T, LOGN>(buf2, twi, LPB);
+        fft_stages<T, LOGN, LPB>(buf2, twi);
         const int64_t off = pass == 0 ? 0 : der_off * pg.cells;
-        for (int idx = threadIdx.x; idx < LPB * NG; idx += blockDim.x) {
+        for (int idx = threadIdx.x; idx < LPB * NG; idx += 256) {
             const int k = S == 1 ? idx % NG : idx / LPB, li = S == 1 ? idx / NG : idx % LPB;
             if (s_ok[li] && cyc_has(pg.olo, pg.on, k, ng)) data[off + s_base[li] + (int64_t)k * S] = buf2[li][k];
         }

@@ -20,7 +20,6 @@
 #include "nfftgp_dev.h"
 
 #include <cstdlib>
-#include <type_traits>
 
 namespace nfftgp {
 namespace {
@@ -325,14 +324,17 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
          const typename Cplx<T>::type *__restrict__ grid, int64_t cells, int nrhs, int64_t n,
          T *__restrict__ hbuf, T *__restrict__ dout, T dscale)
 {
+    using C = typename Cplx<T>::type;
     constexpr int TW = 2 * M;
     constexpr int RS = D * TW;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    // the tile of the grid, interleaved with the derivative grid's tile when
+    // DER (one LDS read gives both values of a tap)
     T *tK = reinterpret_cast<T *>(smem_raw);
+    C *tKD = reinterpret_cast<C *>(smem_raw);
     const int pd = tb + 2 * M;
     int pc = pd;
     for (int q = 1; q < D; ++q) pc *= pd;
-    T *tD = tK + pc;
     const float inv_pd = 1.0f / (float)pd;
     const int sq = blockIdx.x;
     const int wi = sub_win[sq];
@@ -356,47 +358,72 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     const int64_t orow = (int64_t)win.perm[j] * nrhs;
     T *hout = hbuf + (int64_t)win.s_global * n * nrhs;
     T *dblk = DER ? dout + (int64_t)win.s_global * n * nrhs : nullptr;
+    // one tap: value times weight into the K (and derivative) sums
+    auto tap = [&](int idx, T wt, T &sK, T &sD) {
+        if constexpr (DER) {
+            const C v = tKD[idx];
+            sK += v.x * wt;
+            sD += v.y * wt;
+        } else {
+            sK += tK[idx] * wt;
+        }
+    };
     for (int r = 0; r < nrhs; ++r) {
-        const typename Cplx<T>::type *gK = grid + ((int64_t)wi * nrhs + r) * cells;
-        const typename Cplx<T>::type *gD =
-            DER ? grid + ((int64_t)(nwin + wi) * nrhs + r) * cells : nullptr;
+        const C *gK = grid + ((int64_t)wi * nrhs + r) * cells;
+        const C *gD = DER ? grid + ((int64_t)(nwin + wi) * nrhs + r) * cells : nullptr;
         if (r > 0) __syncthreads();
-        for (int i = threadIdx.x; i < pc; i += blockDim.x) {
-            int rem = i, loc[3] = {0, 0, 0};
-            for (int q = D - 1; q >= 0; --q) {
-                const int qt = fdiv_small(rem, pd, inv_pd);
-                loc[q] = rem - qt * pd;
-                rem = qt;
+        // staged in batches of SB cells per thread: the loads of a batch are
+        // all in flight before the first LDS store
+        constexpr int SB = 8;
+        for (int i0 = 0; i0 < pc; i0 += SB * 256) {
+            T vK[SB], vD[SB];
+#pragma unroll
+            for (int b = 0; b < SB; ++b) {
+                const int i = i0 + b * 256 + (int)threadIdx.x;
+                int rem = i, loc[3] = {0, 0, 0};
+                for (int q = D - 1; q >= 0; --q) {
+                    const int qt = fdiv_small(rem, pd, inv_pd);
+                    loc[q] = rem - qt * pd;
+                    rem = qt;
+                }
+                bool in = i < pc;
+                int64_t g = 0;
+                for (int q = 0; q < D; ++q) {
+                    int l = org[q] - M + loc[q];
+                    in = in && (l >= 0) && (l < ng);
+                    g = g * ng + l;
+                }
+                vK[b] = in ? gK[g].x : T(0);
+                vD[b] = (DER && in) ? gD[g].x : T(0);
             }
-            bool in = true;
-            int64_t g = 0;
-            for (int q = 0; q < D; ++q) {
-                int l = org[q] - M + loc[q];
-                in = in && (l >= 0) && (l < ng);
-                g = g * ng + l;
+#pragma unroll
+            for (int b = 0; b < SB; ++b) {
+                const int i = i0 + b * 256 + (int)threadIdx.x;
+                if (i < pc) {
+                    if constexpr (DER) {
+                        C v;
+                        v.x = vK[b];
+                        v.y = vD[b];
+                        tKD[i] = v;
+                    } else {
+                        tK[i] = vK[b];
+                    }
+                }
             }
-            tK[i] = in ? gK[g].x : T(0);
-            if (DER) tD[i] = in ? gD[g].x : T(0);
         }
         __syncthreads();
         if (!mine) continue;
         T hK = T(0), hD = T(0);
         if (D == 1) {
 #pragma unroll
-            for (int aa = 0; aa < TW; ++aa) {
-                hK += tK[lin + aa] * w[0][aa];
-                if (DER) hD += tD[lin + aa] * w[0][aa];
-            }
+            for (int aa = 0; aa < TW; ++aa) tap(lin + aa, w[0][aa], hK, hD);
         } else if (D == 2) {
 #pragma unroll
             for (int aa = 0; aa < TW; ++aa) {
                 T sK = T(0), sD = T(0);
                 const int row = lin + aa * pd;
 #pragma unroll
-                for (int bb = 0; bb < TW; ++bb) {
-                    sK += tK[row + bb] * w[D > 1 ? 1 : 0][bb];
-                    if (DER) sD += tD[row + bb] * w[D > 1 ? 1 : 0][bb];
-                }
+                for (int bb = 0; bb < TW; ++bb) tap(row + bb, w[D > 1 ? 1 : 0][bb], sK, sD);
                 hK += sK * w[0][aa];
                 if (DER) hD += sD * w[0][aa];
             }
@@ -410,10 +437,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                     const int row = lin + (aa * pd + bb) * pd;
                     T cK = T(0), cD = T(0);
 #pragma unroll
-                    for (int cc = 0; cc < TW; ++cc) {
-                        cK += tK[row + cc] * w[D > 2 ? 2 : 0][cc];
-                        if (DER) cD += tD[row + cc] * w[D > 2 ? 2 : 0][cc];
-                    }
+                    for (int cc = 0; cc < TW; ++cc) tap(row + cc, w[D > 2 ? 2 : 0][cc], cK, cD);
                     sK += cK * w[D > 1 ? 1 : 0][bb];
                     if (DER) sD += cD * w[D > 1 ? 1 : 0][bb];
                 }
@@ -503,10 +527,20 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     for (int cb = start; cb < end; cb += CH) {
         const int nc = min(CH, end - cb);
         __syncthreads();
-        for (int i = lane; i < nc * RS; i += 64) s_rec[i] = rec[(int64_t)cb * RS + i];
-        if (lane < nc) {
-            s_an[lane] = win.anchor[cb + lane] & 0x7fffffff;
-            s_perm[lane] = win.perm[cb + lane];
+        {
+            // all loads of the chunk in flight before the LDS stores
+            T v[RS];
+#pragma unroll
+            for (int k = 0; k < RS; ++k) {
+                const int i = lane + 64 * k;
+                v[k] = i < nc * RS ? rec[(int64_t)cb * RS + i] : T(0);
+            }
+            const int an = lane < nc ? win.anchor[cb + lane] & 0x7fffffff : 0;
+            const int pm = lane < nc ? win.perm[cb + lane] : 0;
+#pragma unroll
+            for (int k = 0; k < RS; ++k) s_rec[lane + 64 * k] = v[k];
+            s_an[lane] = an;
+            s_perm[lane] = pm;
         }
         __syncthreads();
         for (int r = 0; r < nrhs; ++r) {
@@ -568,134 +602,6 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                     hout[o] = h;
                     if (DER) dblk[o] = dscale * hd;
                 }
-            }
-        }
-    }
-}
-
-// Interpolation of 3-D windows on the matrix cores (FP32).  Points of one cell
-// share the (2m)^3 grid values F[a][b][c] they read, so for a tile of up to 16
-// points u of one cell
-//
-//   T[(a,b)][u] = sum_c F[(a,b)][c] psi_2,u[c]        (16 x 4 MFMA tiles, K = c)
-//   h_u         = sum_(a,b) psi_0,u[a] psi_1,u[b] T[(a,b)][u]
-//
-// The rows (a, b) are packed 16 per MFMA tile: RA rows per a (2m, or 16 for
-// 2m > 8 with rows b >= 2m left zero), AP = 16 / RA values of a per tile.  With
-// v_mfma_f32_16x16x4f32, lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
-// and receives D[4 (l / 16) + r][l % 16], r = 0..3; so lane l finishes the
-// second sum over its rows for point l % 16 and four lanes are added with two
-// shuffles.  One wave per subproblem (a contiguous range of sorted points of
-// one window); point data are staged in LDS in chunks of 64; F (and the
-// derivative grid's F) is loaded from the grid once per run and vector.
-template <int M, bool DER>
-__global__ void __launch_bounds__(64)
-k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
-              const int *__restrict__ sub_start, const int *__restrict__ sub_count, int ng, int nwin,
-              const float2 *__restrict__ grid, int64_t cells, int nrhs, int64_t n,
-              float *__restrict__ hbuf, float *__restrict__ dout, float dscale)
-{
-    typedef float v4f __attribute__((ext_vector_type(4)));
-    constexpr int TW = 2 * M;
-    constexpr int RS = 3 * TW;
-    constexpr int RA = TW <= 8 ? TW : 16;     // rows per value of a
-    constexpr int AP = 16 / RA;               // values of a per MFMA tile
-    constexpr int MT = TW / AP;               // MFMA tiles along (a, b)
-    constexpr int KS = TW / 4;                // K steps along c
-    constexpr int CH = 64;
-    static_assert(TW % 4 == 0 && 16 % RA == 0, "tap count");
-    __shared__ float s_rec[CH * RS];
-    __shared__ int s_an[CH];
-    __shared__ int s_perm[CH];
-    const int lane = threadIdx.x;
-    const int li = lane & 15, g = lane >> 4;
-    const int wi = sub_win[blockIdx.x];
-    const WinDesc &win = wd[wi];
-    const float *rec = reinterpret_cast<const float *>(win.rec);
-    const int start = sub_start[blockIdx.x], end = start + sub_count[blockIdx.x];
-    // A operand position of this lane: row i = li of each tile, column c = 4 s + g
-    const int a_in = li / RA, b_in = li % RA;
-    const bool row_ok = b_in < TW;
-    // D rows of this lane: a = t AP + aoff, b = boff + r
-    const int aoff = (4 * g) / RA, boff = (4 * g) % RA;
-    float *hout = hbuf + (int64_t)win.s_global * n * nrhs;
-    float *dblk = DER ? dout + (int64_t)win.s_global * n * nrhs : nullptr;
-    for (int cb = start; cb < end; cb += CH) {
-        const int nc = min(CH, end - cb);
-        __syncthreads();
-        for (int i = lane; i < nc * RS; i += 64) s_rec[i] = rec[(int64_t)cb * RS + i];
-        if (lane < nc) {
-            s_an[lane] = win.anchor[cb + lane] & 0x7fffffff;
-            s_perm[lane] = win.perm[cb + lane];
-        }
-        __syncthreads();
-        for (int r = 0; r < nrhs; ++r) {
-            const float2 *gK = grid + ((int64_t)wi * nrhs + r) * cells;
-            const float2 *gD = DER ? grid + ((int64_t)(nwin + wi) * nrhs + r) * cells : gK;
-            float AK[MT][KS], AD[MT][KS];
-            int cur = -1;
-            int u = 0;
-            while (u < nc) {
-                const int cell = __builtin_amdgcn_readfirstlane(s_an[u]);
-                if (cell != cur) {
-                    cur = cell;
-                    const int c2 = cell % ng, c1 = (cell / ng) % ng, c0 = cell / (ng * ng);
-                    const int64_t base = ((int64_t)(c0 - M + 1 + a_in) * ng + (c1 - M + 1 + b_in)) * ng +
-                                         (c2 - M + 1 + g);
-#pragma unroll
-                    for (int t = 0; t < MT; ++t)
-#pragma unroll
-                        for (int s = 0; s < KS; ++s) {
-                            const int64_t o = base + (int64_t)t * AP * ng * ng + 4 * s;
-                            AK[t][s] = row_ok ? gK[o].x : 0.f;
-                            if (DER) AD[t][s] = row_ok ? gD[o].x : 0.f;
-                        }
-                }
-                // points u .. u + tl - 1 share the cell (tl <= 16)
-                const bool same = lane < 16 && u + lane < nc && s_an[u + lane] == cell;
-                const unsigned long long msk = __ballot(same);
-                const int tl = (int)__builtin_ctzll(~msk);
-                const bool pv = li < tl;
-                const float *rp = s_rec + (u + (pv ? li : 0)) * RS;
-                float bw[KS];
-#pragma unroll
-                for (int s = 0; s < KS; ++s) bw[s] = pv ? rp[2 * TW + 4 * s + g] : 0.f;
-                float w1[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) w1[q] = (boff + q < TW) ? rp[TW + boff + q] : 0.f;
-                // per MFMA tile: the K-chain over c, then the second contraction
-                // over this lane's rows (point li)
-                float hK = 0.f, hD = 0.f;
-#pragma unroll
-                for (int t = 0; t < MT; ++t) {
-                    v4f aK = v4f{0.f, 0.f, 0.f, 0.f}, aD = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int s = 0; s < KS; ++s) {
-                        aK = __builtin_amdgcn_mfma_f32_16x16x4f32(AK[t][s], bw[s], aK, 0, 0, 0);
-                        if (DER) aD = __builtin_amdgcn_mfma_f32_16x16x4f32(AD[t][s], bw[s], aD, 0, 0, 0);
-                    }
-                    const float w0 = rp[t * AP + aoff];
-                    float sK = 0.f, sD = 0.f;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        sK += w1[q] * aK[q];
-                        if (DER) sD += w1[q] * aD[q];
-                    }
-                    hK += w0 * sK;
-                    if (DER) hD += w0 * sD;
-                }
-                hK += __shfl_xor(hK, 16, 64);
-                hK += __shfl_xor(hK, 32, 64);
-                if (DER) {
-                    hD += __shfl_xor(hD, 16, 64);
-                    hD += __shfl_xor(hD, 32, 64);
-                }
-                if (g == 0 && pv) {
-                    const int64_t o = (int64_t)s_perm[u + li] * nrhs + r;
-                    hout[o] = hK;
-                    if (DER) dblk[o] = dscale * hD;
-                }
-                u += tl;
             }
         }
     }
@@ -778,19 +684,6 @@ hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool
 {
     const WindowGeom &g = G.g;
     using C = typename Cplx<T>::type;
-    if constexpr (std::is_same<T, float>::value && D == 3 && M <= 6) {
-        if (G.use_mfma_interp) {
-            if (with_der)
-                k_interp_mfma<M, true><<<(unsigned)G.nrsub, 64, 0, s>>>(
-                    G.desc, G.rsub_win, G.rsub_start, G.rsub_count, g.ng, G.nwin, (const float2 *)grid,
-                    g.cells, nrhs, n, (float *)hbuf, (float *)dout, (float)dscale);
-            else
-                k_interp_mfma<M, false><<<(unsigned)G.nrsub, 64, 0, s>>>(
-                    G.desc, G.rsub_win, G.rsub_start, G.rsub_count, g.ng, G.nwin, (const float2 *)grid,
-                    g.cells, nrhs, n, (float *)hbuf, nullptr, (float)dscale);
-            return hipGetLastError();
-        }
-    }
     if (G.use_run_interp) {
         if (with_der)
             k_interp_run<T, D, M, true><<<(unsigned)G.nrsub, 64, 0, s>>>(

@@ -94,8 +94,6 @@ struct Group {
     // interpolation by register-held runs (chosen when runs of equal cells are long):
     // contiguous ranges of at most kRunSubPoints sorted points
     bool use_run_interp = false;
-    bool use_mfma_interp = false;   // FP32 3-D windows, m <= 6: matrix-core interpolation
-                                    // over the same point ranges
     int32_t *rsub_win = nullptr, *rsub_start = nullptr, *rsub_count = nullptr;
     int nrsub = 0;
     double *cinv2 = nullptr;     // N+1 window factors 1 / c(k)^2 (same for the whole group)

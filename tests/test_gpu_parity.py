@@ -68,15 +68,12 @@ SMALL = [
 ]
 
 
-@pytest.mark.parametrize("interp", ["tile", "run", "mfma"])
+@pytest.mark.parametrize("interp", ["tile", "run"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("case", SMALL, ids=[f"case{c[0]}" for c in SMALL])
 def test_small_parity(orc, case, prec, interp, monkeypatch):
-    """Every interpolation variant (per-point tile reads; register-held runs of
-    equal cells; matrix-core tiles of equal cells, FP32 3-D windows with
-    m <= 6), forced through NFFTGP_INTERP at plan creation."""
-    if interp == "mfma" and prec == "f64":
-        pytest.skip("the matrix-core variant is FP32 only")
+    """Both interpolation variants (per-point tile reads; register-held runs of
+    equal cells), forced through NFFTGP_INTERP at plan creation."""
     monkeypatch.setenv("NFFTGP_INTERP", interp)
     seed, n, dims, kt, ell, N, m, nrhs, dist = case
     w = workloads.small(seed, n, dims, kt, ell, N, m, nrhs, dist=dist, scale_mode=1 if dist == "box" else 0)
@@ -143,15 +140,14 @@ def test_derivative_matches_finite_difference(orc):
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_interp_variants_agree(prec, monkeypatch):
     """The interpolation variants evaluate the same sums in different orders:
-    FP64 results agree to rounding, FP32 to a few ulps of the scale (the
-    matrix-core variant runs for FP32 only; for FP64 it falls back)."""
+    FP64 results agree to rounding, FP32 to a few ulps of the scale."""
     from paper_2504_00480_amd import AdditiveKernelPlan
     w = workloads.small(13, 20000, [3, 2, 1], [0, 1, 0], [0.4, 0.6, 0.3], [32, 32, 64], 6, 2, dist="cluster")
     dt = torch.float64 if prec == "f64" else torch.float32
     X = torch.tensor(w.X, dtype=dt, device="cuda:0")
     V = torch.tensor(w.V, dtype=dt, device="cuda:0")
     outs = []
-    for mode in ("tile", "run", "mfma"):
+    for mode in ("tile", "run"):
         monkeypatch.setenv("NFFTGP_INTERP", mode)
         plan = AdditiveKernelPlan(X, w.windows, w.ktype, w.N, w.m, max_nrhs=2)
         plan.set_hyper(1.3, w.ell, 0.2)
