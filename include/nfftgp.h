@@ -177,17 +177,17 @@ nfftgp_status nfftgp_get_window_info(nfftgp_plan plan, int32_t s, double *c0, do
  * milliseconds and the number of launches since profiling was (re-)enabled.
  * Enabling allocates events, so do not enable it while capturing a graph. */
 enum {
-    NFFTGP_PROF_FILL = 0,     /* clearing of the window-sum accumulators      */
+    NFFTGP_PROF_FILL = 0,     /* reserved (no kernel in this version)         */
     NFFTGP_PROF_SPREAD = 1,   /* window spreading onto the tiles              */
     NFFTGP_PROF_FOLD = 2,     /* sum of overlapping tiles into the grid       */
     NFFTGP_PROF_FFT_FWD = 3,  /* forward FFT passes of axes d-1..1            */
     NFFTGP_PROF_DIAG = 4,     /* axis 0: forward FFT, diagonal, inverse FFT   */
     NFFTGP_PROF_FFT_INV = 5,  /* inverse FFT passes of axes 1..d-1            */
-    NFFTGP_PROF_INTERP = 6,   /* window interpolation and window sum          */
-    NFFTGP_PROF_ASSEMBLE = 7, /* sigma scaling and derivative blocks          */
+    NFFTGP_PROF_INTERP = 6,   /* window interpolation into per-window outputs */
+    NFFTGP_PROF_ASSEMBLE = 7, /* window sum, sigma scaling, derivative blocks */
     NFFTGP_PROF_COEF = 8,     /* per-theta coefficient kernels                */
     NFFTGP_PROF_CG = 9,       /* CG dot products and vector updates           */
-    NFFTGP_PROF_GATHER = 10,  /* vectors gathered into a window's point order */
+    NFFTGP_PROF_GATHER = 10,  /* reserved (no kernel in this version)         */
     NFFTGP_PROF_COUNT = 11
 };
 nfftgp_status nfftgp_profile(nfftgp_plan plan, int32_t enable);

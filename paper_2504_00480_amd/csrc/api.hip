@@ -264,10 +264,13 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
     TRYH(tmp.get(&t1, n1 * 3 * eb));
     TRYH(tmp.get(&t2, n1 * 3 * eb));
     // points per spreading work-group: short runs for small n (enough groups to
-    // fill the device), longer runs for large n (fewer partial tiles to fold)
-    int sub_sp = 256;
-    if (n > 131072)
-        while (sub_sp < 4096 && (int64_t)sub_sp * 512 < n) sub_sp *= 2;
+    // fill the device), longer runs for large n (fewer partial tiles to fold);
+    // measured on 1e5..2e6 points: 128 at 1e5, 1024 at 2e5, 2048 at 5e5, 4096 at 2e6
+    int sub_sp = 128;
+    if (n > 131072) {
+        sub_sp = 256;
+        while (sub_sp < 4096 && (int64_t)sub_sp * 256 < n) sub_sp *= 2;
+    }
 
     size_t tile_need = 0;
     int64_t max_cells = 1, maxK = 1;
@@ -437,7 +440,8 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
                 TRYH(hipMemcpy(*dst[k], srcv[k]->data(), srcv[k]->size() * sizeof(int), hipMemcpyHostToDevice));
         }
         TRYS(dalloc(plan, (void **)&G.cinv2, (G.g.N + 1) * sizeof(double)));
-        TRYH(launch_window_coef(G.g.N, m, G.cinv2, st));
+        TRYS(dalloc(plan, (void **)&G.cw, (size_t)(G.g.N / 2 + 1) * (G.g.N / 2 + 1) * sizeof(double)));
+        TRYH(launch_window_coef(G.g.N, m, G.cinv2, G.cw, st));
         coef_need = std::max(coef_need, (size_t)coef_scratch_doubles(G.g, G.nwin));
         TRYS(dalloc(plan, (void **)&G.desc, G.nwin * sizeof(WinDesc)));
         TRYH(hipMemcpy(G.desc, hd.data(), G.nwin * sizeof(WinDesc), hipMemcpyHostToDevice));

@@ -47,55 +47,46 @@ __device__ __forceinline__ void sample_pair(const CoefParams &prm, int w, double
 
 constexpr int kMaxH = 65;   // N/2 + 1 for N <= 128
 
-// All per-hyper-parameter work of one window and one array (kernel or
-// ell-derivative) in one work-group.  The samples f(l) = kappa(|l| / N),
-// l in [-N/2, N/2)^d, are real and even in every coordinate (l = -N/2 has no
-// partner and enters once), so their DFT is real and even; per axis
+// The samples f(l) = kappa(|l| / N), l in [-N/2, N/2)^d, are real and even in
+// every coordinate (l = -N/2 has no partner and enters once), so their DFT is
+// real and even; per axis
 //
 //   sum_l g(l) exp(-2 pi i l k / N) = g(0) + 2 sum_{0<l<N/2} g(l) cos(2 pi l k / N)
 //                                     + g(N/2) (-1)^k,
 //
 // a real transform on the H = N/2 + 1 magnitudes l, k = 0..N/2, applied axis
-// by axis (scratch: two arrays of H^d doubles per window and array).  Then
-// b(k) = N^-d B(|k_1|, .., |k_d|) on I_N, the smallest b_k is the smallest of
-// these values, and in D(k) the term b(k) counts when no k_q = N/2, the term
-// b(-k) when no k_q = -N/2.  Grid (2, nwin): x = array (0: K, 1: derivative),
-// y = window of the group; the smallest coefficient goes to
-// minb[2 * s_global + x] (host-visible memory) and the transformed array to
-// the start of the block's scratch, where k_coef_diag reads it.
-// With INLDS the two H^d arrays live in LDS (dynamic shared memory, used when
-// they fit); otherwise in the global scratch.
-template <bool INLDS>
-__global__ void __launch_bounds__(1024)
-k_coef_all(int d, int N, CoefParams prm, double *__restrict__ scratch, const WinDesc *__restrict__ wd,
-           double *__restrict__ minb)
+// by axis.  Then b(k) = N^-d B(|k_1|, .., |k_d|) on I_N, the smallest b_k is
+// the smallest of these values, and in D(k) the term b(k) counts when no
+// k_q = N/2, the term b(-k) when no k_q = -N/2.
+__device__ __forceinline__ double cos_weight(int l, int k, int N)
+{
+    if (l == 0) return 1.0;
+    if (l == N / 2) return (k & 1) ? -1.0 : 1.0;
+    return 2.0 * cospi(2.0 * (double)((l * k) & (N - 1)) / (double)N);
+}
+
+// Stage 1: samples and the transforms of axes 0..d-2 of one slab (last-axis
+// magnitude l = blockIdx.x) of one window (blockIdx.z) and array (blockIdx.y:
+// 0 kernel, 1 derivative), in LDS.  Output S[w][arr][k_0..k_{d-2}][l] in the
+// scratch (H^d doubles per window and array).
+__global__ void __launch_bounds__(256)
+k_coef_slab(int d, int N, CoefParams prm, const double *__restrict__ cwg, double *__restrict__ scratch)
 {
     __shared__ double cw[kMaxH * kMaxH];
-    __shared__ double red[1024];
-    extern __shared__ double dyn[];
-    const int arr = blockIdx.x, w = blockIdx.y;
+    // a slab holds H^(d-1) values: at most 33^2 (d = 3 needs N <= 64), 65 for d = 2
+    __shared__ double A[33 * 33], B[33 * 33];
+    const int l_last = blockIdx.x, arr = blockIdx.y, w = blockIdx.z;
     const int H = N / 2 + 1;
     const float invH = 1.0f / (float)H;
-    int KH = 1, K = 1;   // at most 65^3
-    for (int q = 0; q < d; ++q) {
-        KH *= H;
-        K *= N;
-    }
-    double *A = INLDS ? dyn : scratch + ((int64_t)w * 2 + arr) * 2 * KH;
-    double *B = A + KH;
-    for (int i = threadIdx.x; i < H * H; i += blockDim.x) {
-        const int l = i / H, k = i % H;
-        double c;
-        if (l == 0) c = 1.0;
-        else if (l == N / 2) c = (k & 1) ? -1.0 : 1.0;
-        else c = 2.0 * cospi(2.0 * (double)((l * k) & (N - 1)) / (double)N);
-        cw[i] = c;
-    }
-    // samples at magnitudes l_q = 0..N/2 (l_q = N/2 stands for the offset -N/2)
-    for (int i = threadIdx.x; i < KH; i += blockDim.x) {
+    int KS = 1;   // slab size H^(d-1)
+    for (int q = 0; q + 1 < d; ++q) KS *= H;
+    int KH = KS * H;
+    for (int i = threadIdx.x; i < H * H && d > 1; i += 256) cw[i] = cwg[i];
+    const double xl = (double)l_last / (double)N;
+    for (int i = threadIdx.x; i < KS; i += 256) {
         int rem = i;
-        double r2 = 0.0;
-        for (int q = 0; q < d; ++q) {
+        double r2 = xl * xl;
+        for (int q = 0; q + 1 < d; ++q) {
             const int qt = fdiv_small(rem, H, invH);
             const double x = (double)(rem - qt * H) / (double)N;
             rem = qt;
@@ -106,76 +97,114 @@ k_coef_all(int d, int N, CoefParams prm, double *__restrict__ scratch, const Win
         A[i] = arr == 0 ? v : dv;
     }
     __syncthreads();
-    // axis passes (axis q has stride H^(d-1-q))
-    int stride = KH / H;
-    for (int q = 0; q < d; ++q) {
+    double *src = A, *dst = B;
+    int stride = KS / H;   // axis q of the slab has stride H^(d-2-q)
+    for (int q = 0; q + 1 < d; ++q) {
         const float inv_st = 1.0f / (float)stride;
-        for (int i = threadIdx.x; i < KH; i += blockDim.x) {
-            const int hi = fdiv_small(i, stride, inv_st);   // i / stride
+        for (int i = threadIdx.x; i < KS; i += 256) {
+            const int hi = fdiv_small(i, stride, inv_st);
             const int k = hi - fdiv_small(hi, H, invH) * H;
             const int base = i - k * stride;
             double acc = 0.0;
-            for (int l = 0; l < H; ++l) acc += cw[l * H + k] * A[base + l * stride];
-            B[i] = acc;
+            for (int l = 0; l < H; ++l) acc += cw[l * H + k] * src[base + l * stride];
+            dst[i] = acc;
         }
         __syncthreads();
-        double *t = A;
-        A = B;
-        B = t;
-        stride /= H;
+        double *t = src;
+        src = dst;
+        dst = t;
+        stride = stride > 1 ? stride / H : 1;
     }
-    const double invK = 1.0 / (double)K;
-    double mn = INFINITY;
-    for (int i = threadIdx.x; i < KH; i += blockDim.x) mn = fmin(mn, A[i] * invK);
-    red[threadIdx.x] = mn;
-    __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) minb[2 * wd[w].s_global + arr] = red[0];
-    // transformed array for the diagonal kernel
-    double *out = scratch + ((int64_t)w * 2 + arr) * 2 * KH;
-    if (INLDS || out != A)
-        for (int i = threadIdx.x; i < KH; i += blockDim.x) out[i] = A[i];
+    double *S = scratch + ((int64_t)w * 2 + arr) * KH;
+    for (int i = threadIdx.x; i < KS; i += 256) S[(int64_t)i * H + l_last] = src[i];
 }
 
-// Diagonal D(k) on [-N/2, N/2]^d of every window and array of the group from
-// the transformed arrays (scratch layout of k_coef_all).  Grid
-// (ceil((N+1)^d / 256), 2, nwin).
+// Stage 2: transform of the last axis on the fly and the diagonal
+// D(k) on [-N/2, N/2]^d; the smallest b over the block goes to
+// part[(w * 2 + arr) * gridDim.x + blockIdx.x].  Grid (ceil((N+1)^d / 256), 2, nwin).
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_coef_diag(int d, int N, const double *__restrict__ cinv2, const double *__restrict__ scratch,
-            const WinDesc *__restrict__ wd)
+k_coef_diag(int d, int N, const double *__restrict__ cinv2, const double *__restrict__ cwg,
+            const double *__restrict__ scratch, const WinDesc *__restrict__ wd, double *__restrict__ part)
 {
+    __shared__ double cw[kMaxH * kMaxH];
+    __shared__ double red[256];
     const int arr = blockIdx.y, w = blockIdx.z;
     const int H = N / 2 + 1;
     const float invN1 = 1.0f / (float)(N + 1);
+    for (int j = threadIdx.x; j < H * H; j += 256) cw[j] = cwg[j];
+    __syncthreads();
     int KH = 1, KD = 1, K = 1;
     for (int q = 0; q < d; ++q) {
         KH *= H;
         KD *= N + 1;
         K *= N;
     }
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= KD) return;
-    const double *A = scratch + ((int64_t)w * 2 + arr) * 2 * KH;
-    int rem = i, ai = 0, astr = 1;
-    bool in_pos = true, in_neg = true;
-    double f = 1.0;
-    for (int q = d - 1; q >= 0; --q) {
-        const int qt = fdiv_small(rem, N + 1, invN1);
-        const int k = rem - qt * (N + 1) - N / 2;
-        rem = qt;
-        in_pos = in_pos && k < N / 2;
-        in_neg = in_neg && k > -N / 2;
-        ai += (k < 0 ? -k : k) * astr;
-        astr *= H;
-        f *= cinv2[k + N / 2];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const double *S = scratch + ((int64_t)w * 2 + arr) * KH;
+    double b = INFINITY;
+    if (i < KD) {
+        int rem = i, ai = 0, astr = H, kl = 0;
+        bool in_pos = true, in_neg = true;
+        double f = 1.0;
+        for (int q = d - 1; q >= 0; --q) {
+            const int qt = fdiv_small(rem, N + 1, invN1);
+            const int k = rem - qt * (N + 1) - N / 2;
+            rem = qt;
+            in_pos = in_pos && k < N / 2;
+            in_neg = in_neg && k > -N / 2;
+            const int ka = k < 0 ? -k : k;
+            if (q == d - 1) kl = ka;
+            else {
+                ai += ka * astr;
+                astr *= H;
+            }
+            f *= cinv2[k + N / 2];
+        }
+        // S is stored [slab index][last-axis l]; ai = H * slab index
+        double acc = 0.0;
+        for (int l = 0; l < H; ++l) acc += cw[l * H + kl] * S[ai + l];
+        b = acc / (double)K;
+        const double c = (in_pos ? 1.0 : 0.0) + (in_neg ? 1.0 : 0.0);
+        T *Dout = reinterpret_cast<T *>(const_cast<void *>(arr == 0 ? wd[w].Dk : wd[w].Dder));
+        Dout[i] = (T)(0.5 * c * b * f);
     }
-    const double cnt = (in_pos ? 1.0 : 0.0) + (in_neg ? 1.0 : 0.0);
-    T *Dout = reinterpret_cast<T *>(const_cast<void *>(arr == 0 ? wd[w].Dk : wd[w].Dder));
-    Dout[i] = (T)(0.5 * cnt * A[ai] / (double)K * f);
+    red[threadIdx.x] = b;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[((int64_t)w * 2 + arr) * gridDim.x + blockIdx.x] = red[0];
+}
+
+// Stage 3: smallest coefficient of every window (blockIdx.y) and array
+// (blockIdx.x) from the block minima, written to minb[2 * s_global + arr]
+// (host-visible memory).
+__global__ void __launch_bounds__(256)
+k_coef_min(const double *__restrict__ part, int nper, const WinDesc *__restrict__ wd,
+           double *__restrict__ minb)
+{
+    __shared__ double red[256];
+    const int arr = blockIdx.x, w = blockIdx.y;
+    const double *p = part + ((int64_t)w * 2 + arr) * nper;
+    double m = INFINITY;
+    for (int j = threadIdx.x; j < nper; j += 256) m = fmin(m, p[j]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) minb[2 * wd[w].s_global + arr] = red[0];
+}
+
+// Weights cw[l * H + k] of the real transform on the H = N/2 + 1 magnitudes.
+__global__ void k_cos_table(int N, double *__restrict__ cw)
+{
+    const int H = N / 2 + 1;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < H * H) cw[i] = cos_weight(i / H, i % H, N);
 }
 
 // Normalised window coefficient per dimension, c(k) = I_0(m sqrt(beta^2 -
@@ -193,42 +222,43 @@ __global__ void k_window_coef(int N, int m, double beta, double *__restrict__ ci
 
 }  // namespace
 
-hipError_t launch_window_coef(int N, int m, double *cinv2, hipStream_t s)
+hipError_t launch_window_coef(int N, int m, double *cinv2, double *cw, hipStream_t s)
 {
     k_window_coef<<<1, 256, 0, s>>>(N, m, kb_beta(), cinv2);
+    const int H = N / 2 + 1;
+    k_cos_table<<<(H * H + 255) / 256, 256, 0, s>>>(N, cw);
     return hipGetLastError();
 }
 
 int64_t coef_scratch_doubles(const WindowGeom &g, int nwin)
 {
-    int64_t KH = 1;
-    for (int q = 0; q < g.d; ++q) KH *= g.N / 2 + 1;
-    return 4 * KH * nwin;
+    int64_t KH = 1, KD = 1;
+    for (int q = 0; q < g.d; ++q) {
+        KH *= g.N / 2 + 1;
+        KD *= g.N + 1;
+    }
+    // slabs, then the per-block minima
+    return 2 * KH * nwin + 2 * ((KD + 255) / 256) * nwin;
 }
 
 hipError_t launch_coefficients(int prec, const Group &G, const CoefParams &prm, const double *cinv2,
                                double *scratch, double *minb, hipStream_t s)
 {
-    const dim3 grid(2, (unsigned)G.nwin);
+    const int d = G.g.d, N = G.g.N, H = N / 2 + 1;
     int64_t KH = 1, KD = 1;
-    for (int q = 0; q < G.g.d; ++q) {
-        KH *= G.g.N / 2 + 1;
-        KD *= G.g.N + 1;
+    for (int q = 0; q < d; ++q) {
+        KH *= H;
+        KD *= N + 1;
     }
-    const size_t lds = (size_t)2 * KH * sizeof(double);
-    if (lds <= 96 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_coef_all<true>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        k_coef_all<true><<<grid, 1024, lds, s>>>(G.g.d, G.g.N, prm, scratch, G.desc, minb);
-    } else {
-        k_coef_all<false><<<grid, 1024, 0, s>>>(G.g.d, G.g.N, prm, scratch, G.desc, minb);
-    }
-    const dim3 dgrid((unsigned)((KD + 255) / 256), 2, (unsigned)G.nwin);
+    k_coef_slab<<<dim3((unsigned)H, 2, (unsigned)G.nwin), 256, 0, s>>>(d, N, prm, G.cw, scratch);
+    double *part = scratch + 2 * KH * G.nwin;
+    const unsigned nper = (unsigned)((KD + 255) / 256);
+    const dim3 dgrid(nper, 2, (unsigned)G.nwin);
     if (prec == NFFTGP_F32)
-        k_coef_diag<float><<<dgrid, 256, 0, s>>>(G.g.d, G.g.N, cinv2, scratch, G.desc);
+        k_coef_diag<float><<<dgrid, 256, 0, s>>>(d, N, cinv2, G.cw, scratch, G.desc, part);
     else
-        k_coef_diag<double><<<dgrid, 256, 0, s>>>(G.g.d, G.g.N, cinv2, scratch, G.desc);
+        k_coef_diag<double><<<dgrid, 256, 0, s>>>(d, N, cinv2, G.cw, scratch, G.desc, part);
+    k_coef_min<<<dim3(2, (unsigned)G.nwin), 256, 0, s>>>(part, (int)nper, G.desc, minb);
     return hipGetLastError();
 }
 

@@ -78,6 +78,122 @@ __device__ __forceinline__ void fft_stages(typename Cplx<T>::type (*buf)[(1 << L
     }
 }
 
+// Radix-2 stages over `nl` lines of a buffer with row pitch NG + 1.
+template <typename T, int LOGN>
+__device__ __forceinline__ void fft_stages_n(typename Cplx<T>::type *buf, int nl,
+                                             const typename Cplx<T>::type *tw)
+{
+    using C = typename Cplx<T>::type;
+    constexpr int NG = 1 << LOGN;
+#pragma unroll
+    for (int s = 1; s <= LOGN; ++s) {
+        const int len = 1 << s, half = len >> 1;
+        for (int bfi = threadIdx.x; bfi < nl * NG / 2; bfi += 256) {
+            const int li = bfi / (NG / 2), rest = bfi % (NG / 2);
+            const int grp = rest / half, j = rest % half;
+            const int i0 = grp * len + j, i1 = i0 + half;
+            C *row = buf + li * (NG + 1);
+            const C w = tw[j * (NG / len)];
+            const C u = row[i0], x = row[i1];
+            C v;
+            v.x = x.x * w.x - x.y * w.y;
+            v.y = x.x * w.y + x.y * w.x;
+            C o0, o1;
+            o0.x = u.x + v.x;
+            o0.y = u.y + v.y;
+            o1.x = u.x - v.x;
+            o1.y = u.y - v.y;
+            row[i0] = o0;
+            row[i1] = o1;
+        }
+        __syncthreads();
+    }
+}
+
+// 3-D grids with 2N <= 64: axes 2 and 1 of one slab (batch b, first index l0)
+// in one work-group.  Forward (INV false): rows l1 in Omega are transformed
+// along axis 2 (input Omega, kept F), then columns K2 in F along axis 1
+// (input Omega, written F).  Inverse: columns K2 in F along axis 1 (input F,
+// kept Omega), then rows l1 in Omega along axis 2 (input F, written Omega).
+// Grid (on, batch); LDS rows[on][NG + 1] and cols[fn][NG + 1].
+template <typename T, int LOGN, bool INV>
+__global__ void __launch_bounds__(256)
+k_fft_slab(typename Cplx<T>::type *__restrict__ data, PruneGeom pg)
+{
+    using C = typename Cplx<T>::type;
+    constexpr int NG = 1 << LOGN;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *rows = reinterpret_cast<C *>(smem_raw);            // [on][NG + 1]
+    C *cols = rows + pg.on * (NG + 1);                     // [fn][NG + 1]
+    __shared__ C tw[NG / 2];
+    for (int t = threadIdx.x; t < NG / 2; t += 256) {
+        double sn, cs;
+        sincospi((INV ? 2.0 : -2.0) * (double)t / (double)NG, &sn, &cs);
+        tw[t].x = (T)cs;
+        tw[t].y = (T)sn;
+    }
+    const int l0 = pg.olo + blockIdx.x;
+    C *slab = data + (int64_t)blockIdx.y * pg.cells + (int64_t)l0 * NG * NG;
+    const int on = pg.on, fn = pg.fn;
+    C zero;
+    zero.x = T(0);
+    zero.y = T(0);
+    if (!INV) {
+        // rows: l1 = olo + j, input along axis 2 at Omega
+        for (int idx = threadIdx.x; idx < on * NG; idx += 256) {
+            const int j = idx / NG, k = idx % NG;
+            C v = zero;
+            if (cyc_has(pg.olo, on, k, NG)) v = slab[(pg.olo + j) * NG + k];
+            rows[j * (NG + 1) + (__brev((unsigned)k) >> (32 - LOGN))] = v;
+        }
+        __syncthreads();
+        fft_stages_n<T, LOGN>(rows, on, tw);
+        // columns K2 in F: bit-reversed along l1 (rows outside Omega are zero)
+        for (int idx = threadIdx.x; idx < fn * NG; idx += 256) {
+            const int c = idx / NG, l1 = idx % NG;
+            const int k2 = cyc_pos(pg.flo, c, NG);
+            C v = zero;
+            if (cyc_has(pg.olo, on, l1, NG)) v = rows[(l1 - pg.olo) * (NG + 1) + k2];
+            cols[c * (NG + 1) + (__brev((unsigned)l1) >> (32 - LOGN))] = v;
+        }
+        __syncthreads();
+        fft_stages_n<T, LOGN>(cols, fn, tw);
+        // write (K1 in F, K2 in F)
+        for (int idx = threadIdx.x; idx < fn * fn; idx += 256) {
+            const int a = idx / fn, c = idx % fn;
+            const int k1 = cyc_pos(pg.flo, a, NG), k2 = cyc_pos(pg.flo, c, NG);
+            slab[k1 * NG + k2] = cols[c * (NG + 1) + k1];
+        }
+    } else {
+        // columns K2 in F along axis 1: input K1 in F
+        for (int idx = threadIdx.x; idx < fn * NG; idx += 256) {
+            const int c = idx / NG, k1 = idx % NG;
+            const int k2 = cyc_pos(pg.flo, c, NG);
+            C v = zero;
+            if (cyc_has(pg.flo, fn, k1, NG)) v = slab[k1 * NG + k2];
+            cols[c * (NG + 1) + (__brev((unsigned)k1) >> (32 - LOGN))] = v;
+        }
+        __syncthreads();
+        fft_stages_n<T, LOGN>(cols, fn, tw);
+        // rows l1 in Omega along axis 2: input K2 in F (others zero)
+        for (int idx = threadIdx.x; idx < on * NG; idx += 256) {
+            const int j = idx / NG, k2 = idx % NG;
+            C v = zero;
+            if (cyc_has(pg.flo, fn, k2, NG)) {
+                const int c = (k2 - pg.flo) & (NG - 1);
+                v = cols[c * (NG + 1) + pg.olo + j];
+            }
+            rows[j * (NG + 1) + (__brev((unsigned)k2) >> (32 - LOGN))] = v;
+        }
+        __syncthreads();
+        fft_stages_n<T, LOGN>(rows, on, tw);
+        for (int idx = threadIdx.x; idx < on * on; idx += 256) {
+            const int j = idx / on, c = idx % on;
+            slab[(pg.olo + j) * NG + pg.olo + c] = rows[j * (NG + 1) + pg.olo + c];
+        }
+    }
+}
+
 // MODE 0: forward transform of axis ax (reads Omega, writes F);
 // MODE 1: inverse transform of axis ax (reads F, writes Omega);
 // MODE 2: axis 0 forward, diagonal, inverse (reads Omega, writes Omega of the
@@ -267,11 +383,43 @@ int log2i(int v)
     return l;
 }
 
+// Slab pass of a 3-D group (2N <= 64): one launch for axes 2 and 1.
+template <typename T, bool INV>
+hipError_t slab_t(const Group &G, const PruneGeom &pg, void *grid, int64_t batch, hipStream_t s)
+{
+    using C = typename Cplx<T>::type;
+    const size_t shm = (size_t)(pg.on + pg.fn) * (G.g.ng + 1) * sizeof(C);
+    const dim3 grd((unsigned)pg.on, (unsigned)batch);
+    hipError_t e;
+    switch (G.g.ng) {
+    case 16:
+        e = hipFuncSetAttribute((const void *)k_fft_slab<T, 4, INV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+        k_fft_slab<T, 4, INV><<<grd, 256, shm, s>>>((C *)grid, pg);
+        break;
+    case 32:
+        e = hipFuncSetAttribute((const void *)k_fft_slab<T, 5, INV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+        k_fft_slab<T, 5, INV><<<grd, 256, shm, s>>>((C *)grid, pg);
+        break;
+    case 64:
+        e = hipFuncSetAttribute((const void *)k_fft_slab<T, 6, INV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+        k_fft_slab<T, 6, INV><<<grd, 256, shm, s>>>((C *)grid, pg);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+bool use_slab(const Group &G) { return G.g.d == 3 && G.g.ng <= 64; }
+
 template <typename T>
 hipError_t fwd_t(const Group &G, int m, void *grid, int nrhs, hipStream_t s)
 {
     const PruneGeom pg = prune_geom(G.g, m);
     const int64_t batch = (int64_t)G.nwin * nrhs;
+    if (use_slab(G)) return slab_t<T, false>(G, pg, grid, batch, s);
     for (int ax = G.g.d - 1; ax >= 1; --ax) {
         hipError_t e = fft_dispatch<T, 0, false>(log2i(G.g.ng), grid, pg, ax, batch, G.desc, nrhs, 0, s);
         if (e != hipSuccess) return e;
@@ -284,6 +432,7 @@ hipError_t inv_t(const Group &G, int m, void *grid, int nrhs, bool with_der, hip
 {
     const PruneGeom pg = prune_geom(G.g, m);
     const int64_t batch = (int64_t)G.nwin * nrhs * (with_der ? 2 : 1);
+    if (use_slab(G)) return slab_t<T, true>(G, pg, grid, batch, s);
     for (int ax = 1; ax < G.g.d; ++ax) {
         hipError_t e = fft_dispatch<T, 1, false>(log2i(G.g.ng), grid, pg, ax, batch, G.desc, nrhs, 0, s);
         if (e != hipSuccess) return e;

@@ -484,6 +484,22 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Sum over each row of 16 lanes, returned in every lane of the row.
+__device__ __forceinline__ float row_sum(float v)
+{
+    v += dpp_f(v, 0);
+    v += dpp_f(v, 1);
+    v += dpp_f(v, 2);
+    v += dpp_f(v, 3);
+    return v;
+}
+
+__device__ __forceinline__ double row_sum(double v)
+{
+    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 // Interpolation for windows whose points come in long runs of equal cells.
 // One wave per subproblem; lane (b, c) holds the (b, c) tap column of the
 // run's grid footprint in registers (loaded once per run and vector), so each
@@ -505,6 +521,7 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     __shared__ T s_rec[CH * RS];
     __shared__ int s_an[CH];
     __shared__ int s_perm[CH];
+    __shared__ T s_part[CH][4], s_partD[CH][4];
     const int lane = threadIdx.x;
     const int wi = sub_win[blockIdx.x];
     const WinDesc &win = wd[wi];
@@ -595,14 +612,24 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                         if (DER) td += GD[g][0] * wa;
                     }
                 }
-                const T h = wave_sum(t);
-                const T hd = DER ? wave_sum(td) : T(0);
-                if (lane == 0) {
-                    const int64_t o = (int64_t)s_perm[u] * nrhs + r;
-                    hout[o] = h;
-                    if (DER) dblk[o] = dscale * hd;
+                // sums over the rows of 16 lanes now; the four row sums of
+                // every point are added once the chunk is done
+                const T h = row_sum(t);
+                if ((lane & 15) == 0) s_part[u][lane >> 4] = h;
+                if (DER) {
+                    const T hd = row_sum(td);
+                    if ((lane & 15) == 0) s_partD[u][lane >> 4] = hd;
                 }
             }
+            __builtin_amdgcn_wave_barrier();
+            if (lane < nc) {
+                const int64_t o = (int64_t)s_perm[lane] * nrhs + r;
+                hout[o] = (s_part[lane][0] + s_part[lane][1]) + (s_part[lane][2] + s_part[lane][3]);
+                if (DER)
+                    dblk[o] = dscale * ((s_partD[lane][0] + s_partD[lane][1]) +
+                                        (s_partD[lane][2] + s_partD[lane][3]));
+            }
+            __builtin_amdgcn_wave_barrier();
         }
     }
 }

@@ -97,6 +97,7 @@ struct Group {
     int32_t *rsub_win = nullptr, *rsub_start = nullptr, *rsub_count = nullptr;
     int nrsub = 0;
     double *cinv2 = nullptr;     // N+1 window factors 1 / c(k)^2 (same for the whole group)
+    double *cw = nullptr;        // (N/2+1)^2 weights of the real coefficient transform
 };
 
 }  // namespace nfftgp
@@ -191,12 +192,13 @@ struct CoefParams {
     int32_t kernel[NFFTGP_MAX_WINDOWS];
     int32_t nwin;
 };
-hipError_t launch_window_coef(int N, int m, double *cinv2, hipStream_t s);
+// Window factors 1 / c(k)^2 (N + 1) and the real-transform weights ((N/2+1)^2).
+hipError_t launch_window_coef(int N, int m, double *cinv2, double *cw, hipStream_t s);
 // Scratch (doubles) the coefficient kernel of a group needs.
 int64_t coef_scratch_doubles(const WindowGeom &g, int nwin);
 
 // ---------------------------------------------------------------- apply kernels
-// Coefficients and diagonals of every window of a group (one launch); the
+// Coefficients and diagonals of every window of a group (three launches); the
 // smallest b_k, b^der_k of window s go to minb[2 s], minb[2 s + 1].
 hipError_t launch_coefficients(int prec, const Group &G, const CoefParams &prm, const double *cinv2,
                                double *scratch, double *minb, hipStream_t s);
