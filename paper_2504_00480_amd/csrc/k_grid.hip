@@ -75,7 +75,7 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     T *tiles = reinterpret_cast<T *>(smem_raw);
     int pc = pd;
     for (int q = 1; q < D; ++q) pc *= pd;
-    const int sq = blockIdx.x, r0 = blockIdx.y * R;
+    const int sq = xcd_item(blockIdx.x, gridDim.x), r0 = blockIdx.y * R;
     const WinDesc &win = wd[sub_win[sq]];
     const T *rec = reinterpret_cast<const T *>(win.rec);
     const int *lpos = win.lpos;
@@ -264,7 +264,7 @@ k_fold(const WinDesc *__restrict__ wd, const T *__restrict__ tilebuf, int nrhs, 
        typename Cplx<T>::type *__restrict__ grid)
 {
     // one thread per occupied cell; blockIdx.y = window * nrhs + vector
-    const int ci = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ci = xcd_item(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (ci >= ocells) return;
     const int wr = blockIdx.y;
     const int w = wr / nrhs, r = wr % nrhs;
@@ -336,7 +336,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     int pc = pd;
     for (int q = 1; q < D; ++q) pc *= pd;
     const float inv_pd = 1.0f / (float)pd;
-    const int sq = blockIdx.x;
+    const int sq = xcd_item(blockIdx.x, gridDim.x);
     const int wi = sub_win[sq];
     const WinDesc &win = wd[wi];
     const T *rec = reinterpret_cast<const T *>(win.rec);
@@ -523,10 +523,11 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     __shared__ int s_perm[CH];
     __shared__ T s_part[CH][4], s_partD[CH][4];
     const int lane = threadIdx.x;
-    const int wi = sub_win[blockIdx.x];
+    const int sblk = xcd_item(blockIdx.x, gridDim.x);
+    const int wi = sub_win[sblk];
     const WinDesc &win = wd[wi];
     const T *rec = reinterpret_cast<const T *>(win.rec);
-    const int start = sub_start[blockIdx.x], cnt = sub_count[blockIdx.x];
+    const int start = sub_start[sblk], cnt = sub_count[sblk];
     const int end = start + cnt;
     int i0[NG], i1[NG];
     T actv[NG];
@@ -682,27 +683,22 @@ hipError_t spread_launch(const Group &G, const void *V, int64_t ldv, int nrhs, v
     return hipGetLastError();
 }
 
-int spread_waves_override()
-{
-    const char *e = std::getenv("NFFTGP_SPREAD_W");
-    return e ? std::atoi(e) : 0;
-}
-
 template <typename T, int D, int M>
 hipError_t spread_dm(const Group &G, const void *V, int64_t ldv, int nrhs, void *tilebuf,
                      hipStream_t s)
 {
-    // d = 3: W waves share a tile (2m taps split W ways); two vectors per
-    // group when the two tiles stay within 40 KiB
-    const bool two = nrhs >= 2 && 2 * (size_t)G.g.pc * sizeof(T) <= 40 * 1024;
-    constexpr int W2 = D == 3 ? 2 : 1, W4 = D == 3 ? 4 : 1;
-    const int wv = D == 3 ? spread_waves_override() : 1;
-    if (wv == 1) return two ? spread_launch<T, D, M, 2, 1>(G, V, ldv, nrhs, tilebuf, s)
-                            : spread_launch<T, D, M, 1, 1>(G, V, ldv, nrhs, tilebuf, s);
-    if (wv == 2) return two ? spread_launch<T, D, M, 2, W2>(G, V, ldv, nrhs, tilebuf, s)
-                            : spread_launch<T, D, M, 1, W2>(G, V, ldv, nrhs, tilebuf, s);
-    return two ? spread_launch<T, D, M, 2, W4>(G, V, ldv, nrhs, tilebuf, s)
-               : spread_launch<T, D, M, 1, W4>(G, V, ldv, nrhs, tilebuf, s);
+    // d = 3: four waves share a tile (2m taps split four ways).  R vectors per
+    // work-group share the points' weights; R tiles must fit in 64 KiB, and
+    // R = 4 is taken only when it leaves no partial group of vectors (measured:
+    // 32 vectors 4 > 2 > 1, 17 vectors 2 > 1 > 4, 16 vectors of m = 6: 2 > 1)
+    constexpr int W = D == 3 ? 4 : 1;
+    const size_t tile = (size_t)G.g.pc * sizeof(T);
+    int R = 1;
+    if (nrhs % 4 == 0 && 4 * tile <= 64 * 1024) R = 4;
+    else if (nrhs >= 2 && 2 * tile <= 64 * 1024) R = 2;
+    if (R == 4) return spread_launch<T, D, M, 4, W>(G, V, ldv, nrhs, tilebuf, s);
+    if (R == 2) return spread_launch<T, D, M, 2, W>(G, V, ldv, nrhs, tilebuf, s);
+    return spread_launch<T, D, M, 1, W>(G, V, ldv, nrhs, tilebuf, s);
 }
 
 template <typename T, int D, int M>

@@ -16,4 +16,17 @@ __device__ __forceinline__ int fdiv_small(int i, int d, float inv_d)
     return q;
 }
 
+// The dispatcher deals work-groups round-robin over the 8 XCDs (work-group b
+// runs on XCD b % 8), and each XCD has its own L2.  Work lists are ordered in
+// space (by tile), so giving every XCD one contiguous range of the list keeps
+// the grid region a range reads inside one L2: the b-th work-group takes item
+// xcd_item(b, n), a bijection of [0, n).
+__device__ __forceinline__ int xcd_item(int b, int n)
+{
+    constexpr int X = 8;
+    const int x = b % X, k = b / X;
+    const int q = n / X, r = n % X;
+    return x * q + (x < r ? x : r) + k;
+}
+
 }  // namespace nfftgp
