@@ -529,6 +529,14 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     const T *rec = reinterpret_cast<const T *>(win.rec);
     const int start = sub_start[sblk], cnt = sub_count[sblk];
     const int end = start + cnt;
+    // 3-D windows with 16 items past the last full group of 64 (m = 2, 6):
+    // that group is spread over the wave as (item, quarter of the first
+    // dimension's taps) instead of leaving 48 lanes idle
+    constexpr bool SPLIT = D == 3 && (NITEM % 64) == 16;
+    constexpr int NGF = SPLIT ? NG - 1 : NG;   // groups handled item-per-lane
+    constexpr int QA = TW / 4;
+    const int itL = 64 * NGF + (lane & 15), qL = lane >> 4;
+    const int i0L = itL / TW, i1L = itL % TW;
     int i0[NG], i1[NG];
     T actv[NG];
 #pragma unroll
@@ -565,7 +573,7 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             const typename Cplx<T>::type *gK = grid + ((int64_t)wi * nrhs + r) * cells;
             const typename Cplx<T>::type *gD =
                 DER ? grid + ((int64_t)(nwin + wi) * nrhs + r) * cells : gK;
-            T G[NG][NA], GD[NG][NA];
+            T G[NG][NA], GD[NG][NA], GL[QA], GDL[QA];
             int cur = -1;
             for (int u = 0; u < nc; ++u) {
                 const int an = s_an[u];
@@ -576,8 +584,16 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                         c[q] = cell % ng - M + 1;
                         cell /= ng;
                     }
+                    if (SPLIT) {
 #pragma unroll
-                    for (int g = 0; g < NG; ++g)
+                        for (int k = 0; k < QA; ++k) {
+                            const int64_t gi = ((int64_t)(c[0] + qL * QA + k) * ng + c[1] + i0L) * ng + c[2] + i1L;
+                            GL[k] = gK[gi].x;
+                            if (DER) GDL[k] = gD[gi].x;
+                        }
+                    }
+#pragma unroll
+                    for (int g = 0; g < NGF; ++g)
 #pragma unroll
                         for (int a = 0; a < NA; ++a) {
                             int64_t gi;
@@ -590,8 +606,20 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                 }
                 const T *rp = s_rec + u * RS;
                 T t = T(0), td = T(0);
+                if (SPLIT) {
+                    T sk = T(0), sd = T(0);
 #pragma unroll
-                for (int g = 0; g < NG; ++g) {
+                    for (int k = 0; k < QA; ++k) {
+                        const T w0 = rp[qL * QA + k];
+                        sk += w0 * GL[k];
+                        if (DER) sd += w0 * GDL[k];
+                    }
+                    const T wbc = rp[TW + i0L] * rp[2 * TW + i1L];
+                    t += sk * wbc;
+                    if (DER) td += sd * wbc;
+                }
+#pragma unroll
+                for (int g = 0; g < NGF; ++g) {
                     if (D == 3) {
                         T sk = T(0), sd = T(0);
 #pragma unroll
