@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-derivs", action="store_true", help="time the K-only apply as the step")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain form (one window per plan, one vector per call)")
+    ap.add_argument("--cg-iters", type=int, default=20,
+                    help="CG iterations timed with and without the captured graph (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration under a profiler)")
     return ap.parse_args()
@@ -140,6 +144,67 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+
+    # ---------------- plain form: one window per plan, one vector per call, same outputs
+    plain = None
+    if not args.no_plain:
+        wplans = []
+        for s_ in range(P):
+            pl = AdditiveKernelPlan(X, [w.windows[s_]], [w.ktype[s_]], [w.N[s_]], w.m,
+                                    scale_mode=w.scale_mode, max_nrhs=1)
+            wplans.append(pl)
+        Vc = [V[:, c:c + 1].contiguous() for c in range(nrhs)]
+        outs = [(torch.empty((n, 1), dtype=dt, device=dev),
+                 torch.empty((1, n, 1), dtype=dt, device=dev) if derivs else None,
+                 torch.empty((n, 1), dtype=dt, device=dev) if derivs else None,
+                 torch.empty((n, 1), dtype=dt, device=dev) if derivs else None) for _ in range(P)]
+
+        def plain_step():
+            for s_, pl in enumerate(wplans):
+                pl.set_hyper(w.sigma_f, [w.ell[s_]], w.sigma_eps)
+            for c in range(nrhs):
+                for s_, pl in enumerate(wplans):
+                    o = outs[s_]
+                    st = lib.nfftgp_apply(pl._h, _ptr(Vc[c]), 1, 1, _ptr(o[0]), _ptr(o[1]), _ptr(o[2]),
+                                          _ptr(o[3]))
+                    if st != 0:
+                        _lib.check(st, "nfftgp_apply")
+
+        plain_step()
+        torch.cuda.synchronize()
+        ps = max(1, min(args.steps, 10))
+        t0 = time.perf_counter()
+        for _ in range(ps):
+            plain_step()
+        torch.cuda.synchronize()
+        t_plain = (time.perf_counter() - t0) / ps
+        plain = {"ms_per_step": t_plain * 1e3, "value": n * nrhs / t_plain,
+                 "batched_speedup": (n * nrhs / (t_steps / args.steps)) / (n * nrhs / t_plain),
+                 "form": "one plan per window, one vector per call (P x nrhs applies + P set_hyper), "
+                         "per-window outputs"}
+        del wplans
+        print(f"[bench] plain form {t_plain * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # ---------------- CG iterations with and without the captured graph
+    cgres = None
+    if args.cg_iters > 0:
+        B = V.contiguous()
+        Xs = torch.empty_like(B)
+        timing = {}
+        for mode in ("graph", "eager"):
+            if mode == "eager":
+                os.environ["NFFTGP_CG_GRAPH"] = "0"
+            plan.cg(B, 0.0, args.cg_iters, check_every=args.cg_iters, raise_on=(), out=Xs)   # warm / capture
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.cg(B, 0.0, args.cg_iters, check_every=args.cg_iters, raise_on=(), out=Xs)
+            torch.cuda.synchronize()
+            timing[mode] = (time.perf_counter() - t0) / args.cg_iters
+            os.environ.pop("NFFTGP_CG_GRAPH", None)
+        cgres = {"iters": args.cg_iters, "ms_per_iter_graph": timing["graph"] * 1e3,
+                 "ms_per_iter_eager": timing["eager"] * 1e3,
+                 "note": "tol 0 (fixed iteration count), one K-only apply + FP64 scalars per iteration"}
+        print(f"[bench] CG {cgres}", file=sys.stderr, flush=True)
 
     # ---------------- roofline of the dominant kernel
     geoms = []
@@ -265,6 +330,8 @@ def main():
         "parity": parity,
         "kernels": kern,
         "k_only_apply": {"ms": t_konly * 1e3, "value": n * nrhs / t_konly},
+        "plain_single_vector": plain,
+        "cg": cgres,
         "plan_seconds": t_plan,
         "workspace_bytes": plan.workspace_bytes(),
     }

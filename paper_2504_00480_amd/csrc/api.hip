@@ -51,6 +51,8 @@ void free_plan(nfftgp_plan p)
     for (void *a : p->allocs) (void)hipFree(a);
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     if (p->minb_host) (void)hipHostFree(p->minb_host);
+    if (p->cg_exec) (void)hipGraphExecDestroy(p->cg_exec);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     delete p;
 }
 
@@ -558,19 +560,70 @@ nfftgp_status nfftgp_cg(nfftgp_plan plan, const void *B_dev, int32_t nrhs, void 
     PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_coldots(plan->prec, plan->cg_r, nrhs, plan->cg_r, nrhs, n, nrhs,
                                                          plan->dot_part, sc + kRR * nrhs, st));
     PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_start(nrhs, sc, st));
-    std::vector<double> act(nrhs);
-    int it = 0;
-    for (; it < maxit; ++it) {
+    // one iteration: apply, p^T Khat p, alpha, x/r update, r^T r, beta, p update
+    // (enqueued on the plan's stream, or on the capture stream while capturing)
+    auto iteration = [&]() -> nfftgp_status {
+        const hipStream_t cs = plan->stream;
         nfftgp_status e = apply_impl(plan, plan->cg_p, nrhs, nrhs, plan->cg_ap, nullptr, nullptr, nullptr);
         if (e != NFFTGP_OK) return e;
         PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_coldots(plan->prec, plan->cg_p, nrhs, plan->cg_ap, nrhs, n, nrhs,
-                                                         plan->dot_part, sc + kPAP * nrhs, st));
-        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_alpha(nrhs, sc, st));
-        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_xr(plan->prec, n, nrhs, sc, X_dev, plan->cg_r, plan->cg_p, plan->cg_ap, st));
+                                                         plan->dot_part, sc + kPAP * nrhs, cs));
+        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_alpha(nrhs, sc, cs));
+        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_xr(plan->prec, n, nrhs, sc, X_dev, plan->cg_r, plan->cg_p, plan->cg_ap, cs));
         PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_coldots(plan->prec, plan->cg_r, nrhs, plan->cg_r, nrhs, n, nrhs,
-                                                         plan->dot_part, sc + kRRNew * nrhs, st));
-        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_beta(nrhs, sc, tol, it, hist, st));
-        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_p(plan->prec, n, nrhs, sc, plan->cg_r, plan->cg_p, st));
+                                                         plan->dot_part, sc + kRRNew * nrhs, cs));
+        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_beta(nrhs, sc, tol, hist, cs));
+        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_p(plan->prec, n, nrhs, sc, plan->cg_r, plan->cg_p, cs));
+        return NFFTGP_OK;
+    };
+    // The iteration is captured once into a graph and replayed (all its
+    // arguments are fixed: the iteration index lives on the device).  Not
+    // while profiling (events are per launch), not when n = 0, and not with
+    // NFFTGP_CG_GRAPH=0.
+    const char *ge = std::getenv("NFFTGP_CG_GRAPH");
+    const bool use_graph = maxit > 0 && n > 0 && !plan->prof && !(ge && std::strcmp(ge, "0") == 0);
+    if (use_graph) {
+        const bool hit = plan->cg_exec && plan->cg_key_nrhs == nrhs && plan->cg_key_x == X_dev &&
+                         plan->cg_key_hist == hist && plan->cg_key_tol == tol &&
+                         plan->cg_key_sf == plan->sigma_f && plan->cg_key_se == plan->sigma_eps;
+        if (!hit) {
+            if (plan->cg_exec) {
+                NFFTGP_HIP_TRY(hipGraphExecDestroy(plan->cg_exec));
+                plan->cg_exec = nullptr;
+            }
+            if (!plan->cap_stream)
+                NFFTGP_HIP_TRY(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
+            hipGraph_t graph = nullptr;
+            NFFTGP_HIP_TRY(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeRelaxed));
+            plan->stream = plan->cap_stream;
+            const nfftgp_status ce = iteration();
+            plan->stream = st;
+            const hipError_t ee = hipStreamEndCapture(plan->cap_stream, &graph);
+            if (ce != NFFTGP_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return ce;
+            }
+            NFFTGP_HIP_TRY(ee);
+            const hipError_t ie = hipGraphInstantiate(&plan->cg_exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            NFFTGP_HIP_TRY(ie);
+            plan->cg_key_nrhs = nrhs;
+            plan->cg_key_x = X_dev;
+            plan->cg_key_hist = hist;
+            plan->cg_key_tol = tol;
+            plan->cg_key_sf = plan->sigma_f;
+            plan->cg_key_se = plan->sigma_eps;
+        }
+    }
+    std::vector<double> act(nrhs);
+    int it = 0;
+    for (; it < maxit; ++it) {
+        if (use_graph) {
+            NFFTGP_HIP_TRY(hipGraphLaunch(plan->cg_exec, st));
+        } else {
+            nfftgp_status e = iteration();
+            if (e != NFFTGP_OK) return e;
+        }
         if ((it + 1) % check_every == 0 || it + 1 == maxit) {
             NFFTGP_HIP_TRY(hipMemcpyAsync(act.data(), sc + kActive * nrhs, nrhs * sizeof(double),
                                           hipMemcpyDeviceToHost, st));

@@ -67,6 +67,7 @@ __global__ void k_cg_start(int nrhs, double *__restrict__ sc)
     sc[kNotPD * nrhs + c] = 0.0;
     sc[kAlpha * nrhs + c] = 0.0;
     sc[kBeta * nrhs + c] = 0.0;
+    sc[kStep * nrhs + c] = 0.0;
 }
 
 __global__ void k_cg_alpha(int nrhs, double *__restrict__ sc)
@@ -99,24 +100,31 @@ __global__ void k_cg_xr(int64_t total, int nrhs, const double *__restrict__ sc, 
     R[i] = (T)((double)R[i] - a * (double)AP[i]);
 }
 
-__global__ void k_cg_beta(int nrhs, double *__restrict__ sc, double tol, int it,
-                          double *__restrict__ hist)
+// One block of 64 threads.  The iteration index lives on the device
+// (sc[kStep * nrhs], advanced here), so the same launch serves every
+// iteration -- also when replayed from a captured graph.
+__global__ void __launch_bounds__(64)
+k_cg_beta(int nrhs, double *__restrict__ sc, double tol, double *__restrict__ hist)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nrhs) return;
-    double beta = 0.0;
-    if (sc[kActive * nrhs + c] != 0.0) {
-        double rrn = sc[kRRNew * nrhs + c], rr = sc[kRR * nrhs + c];
-        beta = rrn / rr;
-        if (hist) {
-            hist[((int64_t)it * nrhs + c) * 2] = sc[kAlpha * nrhs + c];
-            hist[((int64_t)it * nrhs + c) * 2 + 1] = beta;
+    const int c = threadIdx.x;
+    const int it = (int)sc[kStep * nrhs];
+    if (c < nrhs) {
+        double beta = 0.0;
+        if (sc[kActive * nrhs + c] != 0.0) {
+            double rrn = sc[kRRNew * nrhs + c], rr = sc[kRR * nrhs + c];
+            beta = rrn / rr;
+            if (hist) {
+                hist[((int64_t)it * nrhs + c) * 2] = sc[kAlpha * nrhs + c];
+                hist[((int64_t)it * nrhs + c) * 2 + 1] = beta;
+            }
+            sc[kRR * nrhs + c] = rrn;
+            sc[kIters * nrhs + c] = (double)(it + 1);
+            if (sqrt(rrn) <= tol * sqrt(sc[kRR0 * nrhs + c])) sc[kActive * nrhs + c] = 0.0;
         }
-        sc[kRR * nrhs + c] = rrn;
-        sc[kIters * nrhs + c] = (double)(it + 1);
-        if (sqrt(rrn) <= tol * sqrt(sc[kRR0 * nrhs + c])) sc[kActive * nrhs + c] = 0.0;
+        sc[kBeta * nrhs + c] = beta;
     }
-    sc[kBeta * nrhs + c] = beta;
+    __syncthreads();
+    if (c == 0) sc[kStep * nrhs] = (double)(it + 1);
 }
 
 template <typename T>
@@ -189,9 +197,9 @@ hipError_t launch_cg_xr(int prec, int64_t n, int nrhs, const double *scal, void 
     return hipGetLastError();
 }
 
-hipError_t launch_cg_beta(int nrhs, double *scal, double tol, int it, double *hist, hipStream_t s)
+hipError_t launch_cg_beta(int nrhs, double *scal, double tol, double *hist, hipStream_t s)
 {
-    k_cg_beta<<<1, 64, 0, s>>>(nrhs, scal, tol, it, hist);
+    k_cg_beta<<<1, 64, 0, s>>>(nrhs, scal, tol, hist);
     return hipGetLastError();
 }
 

@@ -129,6 +129,13 @@ struct nfftgp_plan_s {
     double *cg_hist = nullptr;   // CG (alpha, beta) history
     int cg_hist_cap = 0;
     void *cg_r = nullptr, *cg_p = nullptr, *cg_ap = nullptr;  // n x max_nrhs
+    // one CG iteration captured as a graph, with the arguments it was captured for
+    hipGraphExec_t cg_exec = nullptr;
+    hipStream_t cap_stream = nullptr;   // capture only (the plan's stream may be the null stream)
+    int cg_key_nrhs = 0;
+    const void *cg_key_x = nullptr;
+    const double *cg_key_hist = nullptr;
+    double cg_key_tol = 0.0, cg_key_sf = 0.0, cg_key_se = 0.0;
     size_t bytes = 0;
     std::vector<void *> allocs;
     // kernel timing (nfftgp_profile)
@@ -230,7 +237,7 @@ hipError_t launch_cg_start(int nrhs, double *scal, hipStream_t s);
 hipError_t launch_cg_alpha(int nrhs, double *scal, hipStream_t s);
 hipError_t launch_cg_xr(int prec, int64_t n, int nrhs, const double *scal, void *X, void *R,
                         const void *Pv, const void *AP, hipStream_t s);
-hipError_t launch_cg_beta(int nrhs, double *scal, double tol, int it, double *hist,
+hipError_t launch_cg_beta(int nrhs, double *scal, double tol, double *hist,
                           hipStream_t s);
 hipError_t launch_cg_p(int prec, int64_t n, int nrhs, const double *scal, const void *R, void *Pv,
                        hipStream_t s);
@@ -246,7 +253,8 @@ enum CgSlot {
     kIters = 6,   // iterations done
     kNotPD = 7,   // 1 if p^T Khat p <= 0 was met
     kRRNew = 8,
-    kCgSlots = 9
+    kStep = 9,    // iteration index (element 0 only)
+    kCgSlots = 10
 };
 
 }  // namespace nfftgp

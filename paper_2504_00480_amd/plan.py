@@ -174,11 +174,15 @@ class AdditiveKernelPlan:
         _lib.check(st, "nfftgp_col_dots")
         return out
 
-    def cg(self, B: torch.Tensor, tol: float, maxit: int, check_every: int = 8, raise_on=("notpd",)):
-        """CG on Khat X = B from zero; returns (X, iters, (alpha, beta) history, rel. residuals, status)."""
+    def cg(self, B: torch.Tensor, tol: float, maxit: int, check_every: int = 8, raise_on=("notpd",),
+           out: torch.Tensor | None = None):
+        """CG on Khat X = B from zero; returns (X, iters, (alpha, beta) history, rel. residuals, status).
+        Passing the same `out` again lets the library replay its captured iteration."""
         B = self._check_vec(B).contiguous()
         nrhs = B.shape[1]
-        X = torch.empty_like(B)
+        X = out if out is not None else torch.empty_like(B)
+        if X.shape != B.shape or X.dtype != B.dtype or X.device != B.device or not X.is_contiguous():
+            raise ValueError("out must be a contiguous tensor like B")
         iters = np.zeros(nrhs, dtype=np.int32)
         ab = np.zeros((max(maxit, 1), nrhs, 2))
         res = np.zeros(nrhs)

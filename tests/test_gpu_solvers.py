@@ -177,3 +177,34 @@ def test_indefinite_coefficients_reported(orc):
     assert info["min_b"] < 0
     assert abs(info["min_b"] - b.min()) <= 1e-12
     assert abs(info["min_bder"] - bd.min()) <= 1e-10
+
+
+def test_cg_graph_replay_matches_eager(orc, monkeypatch):
+    """One CG iteration is captured as a graph and replayed; the result equals
+    the eager iteration bit for bit, also when the captured graph is replayed
+    in later calls with other work (applies, synchronisations) in between, and
+    after set_hyper changes sigma (the graph is captured again)."""
+    w = workloads.small(25, 4000, [3, 2], [0, 1], [0.6, 0.5], [32, 32], 4, nrhs=3, sigma_eps=0.4)
+    plan, pb = _setup(orc, w, dtype=torch.float32, nrhs=3)
+    B = torch.tensor(w.V, dtype=torch.float32, device=DEV)
+    monkeypatch.setenv("NFFTGP_CG_GRAPH", "0")
+    Xe, ite, abe, rese, ste = plan.cg(B, 1e-5, 400)
+    monkeypatch.delenv("NFFTGP_CG_GRAPH")
+    X = torch.empty_like(B)
+    V = torch.randn(w.n, 3, dtype=torch.float32, device=DEV)
+    for rep in range(3):
+        plan.apply(V, derivs=True)          # eager work between replays
+        torch.cuda.synchronize()
+        Xg, itg, abg, resg, stg = plan.cg(B, 1e-5, 400, out=X)
+        torch.cuda.synchronize()
+        assert stg == ste
+        assert np.array_equal(itg, ite)
+        assert torch.equal(Xg, Xe), rep
+        assert np.array_equal(abg, abe)
+    plan.set_hyper(1.2, w.ell, 0.5)
+    monkeypatch.setenv("NFFTGP_CG_GRAPH", "0")
+    Xe2, ite2, _, _, _ = plan.cg(B, 1e-5, 400)
+    monkeypatch.delenv("NFFTGP_CG_GRAPH")
+    Xg2, itg2, _, _, _ = plan.cg(B, 1e-5, 400, out=X)
+    assert np.array_equal(itg2, ite2)
+    assert torch.equal(Xg2, Xe2)
