@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-derivs", action="store_true", help="time the K-only apply as the step")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the plan's rule-based settings instead of timing candidates")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain form (one window per plan, one vector per call)")
     ap.add_argument("--cg-iters", type=int, default=20,
@@ -90,6 +92,14 @@ def main():
     plan = AdditiveKernelPlan(X, w.windows, w.ktype, w.N, w.m, scale_mode=w.scale_mode, max_nrhs=nrhs)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
+
+    tune = None
+    if not args.no_autotune:
+        plan.set_hyper(w.sigma_f, w.ell, w.sigma_eps)
+        t0 = time.perf_counter()
+        rep = plan.autotune(nrhs, derivs=not args.no_derivs, reps=3)
+        tune = {"seconds": time.perf_counter() - t0, "report": rep.strip().splitlines()}
+        print(f"[bench] autotune {tune}", file=sys.stderr, flush=True)
 
     KV = torch.empty((n, nrhs), dtype=dt, device=dev)
     dl = torch.empty((P, n, nrhs), dtype=dt, device=dev) if derivs else None
@@ -333,6 +343,7 @@ def main():
         "plain_single_vector": plain,
         "cg": cgres,
         "plan_seconds": t_plan,
+        "autotune": tune,
         "workspace_bytes": plan.workspace_bytes(),
     }
     print(json.dumps(res))

@@ -170,6 +170,19 @@ nfftgp_status nfftgp_slq_logquad(const double *alpha_beta_host, const int32_t *i
 nfftgp_status nfftgp_get_window_info(nfftgp_plan plan, int32_t s, double *c0, double *c,
                                      int32_t *d, int32_t *N, double *min_b, double *min_bder);
 
+/* Autotuning (setup time).  Times nrhs-column applies (with the derivative
+ * outputs when with_derivs != 0) for each window group under candidate
+ * settings -- points per spreading subproblem (64 ... 4096), vectors per
+ * spreading work-group (1, 2, 4) and the interpolation variant -- by
+ * coordinate search, best of two trials of `reps` applies each, and keeps the
+ * fastest settings in the plan.  Requires nfftgp_set_hyper.  Allocates and
+ * frees its own input and output buffers (and may grow the plan's tile
+ * workspace); synchronises the stream; drops a captured CG iteration.  A
+ * one-line summary per group is written to `report` (NUL-terminated,
+ * truncated to report_len; may be NULL). */
+nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_derivs, int32_t reps,
+                              char *report, int64_t report_len);
+
 /* Kernel timing with HIP events (a profiling aid).  While enabled, every
  * kernel the plan enqueues is bracketed by two events on the plan's stream
  * and tagged with one of the categories below; nfftgp_profile_read

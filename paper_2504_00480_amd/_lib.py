@@ -24,7 +24,8 @@ E_NOCONV = -7
 # every symbol declared in include/nfftgp.h
 SYMBOLS = ["nfftgp_plan_create", "nfftgp_set_hyper", "nfftgp_apply", "nfftgp_cg", "nfftgp_col_dots",
            "nfftgp_slq_logquad", "nfftgp_get_window_info", "nfftgp_get_workspace_bytes",
-           "nfftgp_plan_destroy", "nfftgp_last_error", "nfftgp_profile", "nfftgp_profile_read"]
+           "nfftgp_plan_destroy", "nfftgp_last_error", "nfftgp_profile", "nfftgp_profile_read",
+           "nfftgp_autotune"]
 PROF_NAMES = ["fill", "spread", "fold", "fft_fwd", "diag", "fft_inv", "interp", "assemble", "coef", "cg",
               "gather"]
 
@@ -72,6 +73,8 @@ def load():
     lib.nfftgp_profile.restype = ctypes.c_int
     lib.nfftgp_profile_read.argtypes = [P, P, P]
     lib.nfftgp_profile_read.restype = ctypes.c_int
+    lib.nfftgp_autotune.argtypes = [P, i32, i32, i32, ctypes.c_char_p, i64]
+    lib.nfftgp_autotune.restype = ctypes.c_int
     lib.nfftgp_last_error.argtypes = []
     lib.nfftgp_last_error.restype = ctypes.c_char_p
     _lib = lib

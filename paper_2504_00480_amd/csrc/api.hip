@@ -3,6 +3,7 @@
 // quadrature.  See include/nfftgp.h for the contract of every entry point.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -171,6 +172,60 @@ nfftgp_status apply_impl(nfftgp_plan p, const void *V, int64_t ldv, int nrhs, vo
     return NFFTGP_OK;
 }
 
+// Smallest spreading subproblem the tuner tries; list arrays are sized for it.
+constexpr int kMinSubSp = 64;
+
+// (Re)build a group's spreading work list for subproblems of sub_sp points:
+// the list arrays, the per-window tile -> subproblem CSR and the list of
+// split tiles; the tile workspace is grown when the new list needs more.
+nfftgp_status build_spread_lists(nfftgp_plan plan, Group &G, int sub_sp)
+{
+    std::vector<int> sw, sb, ss, sc, fbl;
+    for (int wl = 0; wl < G.nwin; ++wl) {
+        Window &w = plan->win[G.wins[wl]];
+        const std::vector<int> &bs = w.h_bin_start;
+        std::vector<int> bsp(w.g.nbins + 1, 0);
+        bsp[0] = (int)sb.size();
+        for (int b = 0; b < w.g.nbins; ++b) {
+            const int cnt = bs[b + 1] - bs[b];
+            for (int off = 0; off < cnt; off += sub_sp) {
+                sw.push_back(wl);
+                sb.push_back(b);
+                ss.push_back(bs[b] + off);
+                sc.push_back(std::min(sub_sp, cnt - off));
+            }
+            bsp[b + 1] = (int)sb.size();
+            if (bsp[b + 1] - bsp[b] >= 2) fbl.push_back(wl * w.g.nbins + b);
+        }
+        NFFTGP_HIP_TRY(hipMemcpy(w.bin_sub_ptr, bsp.data(), (w.g.nbins + 1) * sizeof(int), hipMemcpyHostToDevice));
+    }
+    if ((int)sb.size() > G.sub_cap) return fail(NFFTGP_E_ARG, "spreading list exceeds its capacity");
+    int32_t *dst[5] = {G.sub_win, G.sub_bin, G.sub_start, G.sub_count, G.fb};
+    std::vector<int> *srcv[5] = {&sw, &sb, &ss, &sc, &fbl};
+    for (int k = 0; k < 5; ++k)
+        if (!srcv[k]->empty())
+            NFFTGP_HIP_TRY(hipMemcpy(dst[k], srcv[k]->data(), srcv[k]->size() * sizeof(int), hipMemcpyHostToDevice));
+    G.nsub = (int)sb.size();
+    G.nfb = (int)fbl.size();
+    G.sub_sp = sub_sp;
+    const size_t need = std::max<size_t>(1, (size_t)G.nsub * G.g.pc);
+    if (need > plan->tile_cap) {
+        const size_t eb = plan->prec == NFFTGP_F32 ? 4 : 8;
+        if (plan->tilebuf) {
+            NFFTGP_HIP_TRY(hipStreamSynchronize(plan->stream));
+            NFFTGP_HIP_TRY(hipFree(plan->tilebuf));
+            for (void *&a : plan->allocs)
+                if (a == plan->tilebuf) a = nullptr;
+            plan->tilebuf = nullptr;
+            plan->bytes -= plan->tile_cap * plan->max_nrhs * eb;
+        }
+        nfftgp_status e = dalloc(plan, &plan->tilebuf, need * plan->max_nrhs * eb);
+        if (e != NFFTGP_OK) return e;
+        plan->tile_cap = need;
+    }
+    return NFFTGP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -274,7 +329,6 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         while (sub_sp < 4096 && (int64_t)sub_sp * 256 < n) sub_sp *= 2;
     }
 
-    size_t tile_need = 0;
     int64_t max_cells = 1, maxK = 1;
     plan->win.resize(P);
     for (int s = 0; s < P; ++s) {
@@ -329,7 +383,7 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         TRYH(launch_bin_keys(prec, t1, n, w.g, keys, st));
         TRYH(launch_sort(prec, n, d, w.g.nbins, keys, ids1, t1, hist, scan_tmp, w.perm, t2,
                          bin_start, st));
-        TRYH(launch_weights(prec, t2, n, w.g, m, kb_knorm(m), w.rec, w.anchor, w.lpos, flags + 2, st));
+        TRYH(launch_weights(prec, t2, n, w.g, m, kb_knorm(m), w.rec, w.anchor, w.lpos, st));
         std::vector<int> bs(w.g.nbins + 1);
         TRYH(hipMemcpyAsync(bs.data(), bin_start, (w.g.nbins + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
         TRYH(hipMemcpyAsync(hflags, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -340,7 +394,6 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
                                           ": a scaled point lies outside [-1/4, 1/4)^d");
         }
         w.h_bin_start = bs;
-        w.h_cells_used = hflags[2];
         TRYS(dalloc(plan, &w.Dk, w.g.dcells * eb));
         TRYS(dalloc(plan, &w.Dder, w.g.dcells * eb));
         int64_t K = 1;
@@ -364,24 +417,16 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
     size_t grid_need = 1, coef_need = 8;
     for (Group &G : plan->groups) {
         G.nwin = (int)G.wins.size();
-        std::vector<int> sw, sb, ss, sc, iw, ib, is, ic, fbl;
+        std::vector<int> iw, ib, is, ic;
         std::vector<WinDesc> hd(G.nwin);
+        int64_t cap = 0;
         for (int wl = 0; wl < G.nwin; ++wl) {
             Window &w = plan->win[G.wins[wl]];
             const std::vector<int> &bs = w.h_bin_start;
-            std::vector<int> bsp(w.g.nbins + 1, 0);
-            bsp[0] = (int)sb.size();
             for (int b = 0; b < w.g.nbins; ++b) {
                 const int cnt = bs[b + 1] - bs[b];
                 G.nbins_used += cnt > 0;
-                for (int off = 0; off < cnt; off += sub_sp) {
-                    sw.push_back(wl);
-                    sb.push_back(b);
-                    ss.push_back(bs[b] + off);
-                    sc.push_back(std::min(sub_sp, cnt - off));
-                }
-                bsp[b + 1] = (int)sb.size();
-                if (bsp[b + 1] - bsp[b] >= 2) fbl.push_back(wl * w.g.nbins + b);
+                cap += (cnt + kMinSubSp - 1) / kMinSubSp;
                 for (int off = 0; off < cnt; off += kInterpSubPoints) {
                     iw.push_back(wl);
                     ib.push_back(b);
@@ -390,30 +435,27 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
                 }
             }
             TRYS(dalloc(plan, (void **)&w.bin_sub_ptr, (w.g.nbins + 1) * sizeof(int)));
-            TRYH(hipMemcpy(w.bin_sub_ptr, bsp.data(), (w.g.nbins + 1) * sizeof(int), hipMemcpyHostToDevice));
             hd[wl] = WinDesc{w.rec, w.anchor, w.lpos, w.perm, w.bin_sub_ptr, w.Dk, w.Dder, G.wins[wl], 0};
         }
-        G.nsub = (int)sb.size();
-        G.nisub = (int)ib.size();
-        // interpolation variant: register-held runs for 3-D windows whose
-        // points per occupied cell are many; in 1-D and 2-D a run's footprint
-        // covers few lanes and the per-point variant is faster
-        // (NFFTGP_INTERP=run or =tile overrides the choice)
+        G.sub_cap = (int)std::max<int64_t>(cap, 1);
         {
-            int64_t pts = 0, cells_used = 0;
-            for (int wl = 0; wl < G.nwin; ++wl) {
-                pts += n;
-                cells_used += plan->win[G.wins[wl]].h_cells_used;
-            }
-            const char *ov = std::getenv("NFFTGP_INTERP");
-            if (ov && std::strcmp(ov, "run") == 0) G.use_run_interp = n > 0;
-            else if (ov && std::strcmp(ov, "tile") == 0) G.use_run_interp = false;
-            else G.use_run_interp = G.g.d == 3 && cells_used > 0 &&
-                                    pts >= (int64_t)kRunInterpMinRun * cells_used;
+            int32_t **sd[4] = {&G.sub_win, &G.sub_bin, &G.sub_start, &G.sub_count};
+            for (int k = 0; k < 4; ++k) TRYS(dalloc(plan, (void **)sd[k], (size_t)G.sub_cap * sizeof(int)));
+            TRYS(dalloc(plan, (void **)&G.fb, std::max<size_t>(1, (size_t)G.nwin * G.g.nbins) * sizeof(int)));
         }
-        if (G.use_run_interp) {
-            // points per wave: up to kRunSubPoints, fewer while that leaves
-            // under 8192 waves for the group
+        TRYS(build_spread_lists(plan, G, sub_sp));
+        G.nisub = (int)ib.size();
+        // interpolation variant: the per-point tile variant by default (the
+        // faster one on every measured workload once its tile staging was
+        // batched); nfftgp_autotune may switch, NFFTGP_INTERP=run|tile forces
+        {
+            const char *ov = std::getenv("NFFTGP_INTERP");
+            G.use_run_interp = ov && std::strcmp(ov, "run") == 0 && n > 0;
+        }
+        {
+            // run-interpolation list (built for every group, so that the
+            // variant can be switched): points per wave up to kRunSubPoints,
+            // fewer while that leaves under 8192 waves for the group
             int rsp = kRunSubPoints;
             while (rsp > 64 && (int64_t)G.nwin * n < (int64_t)rsp * 8192) rsp /= 2;
             std::vector<int> rw, rs, rc;
@@ -432,11 +474,9 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
                     TRYH(hipMemcpy(*rdst[k], rsrc[k]->data(), rsrc[k]->size() * sizeof(int), hipMemcpyHostToDevice));
             }
         }
-        G.nfb = (int)fbl.size();
-        int32_t **dst[9] = {&G.sub_win, &G.sub_bin, &G.sub_start, &G.sub_count,
-                            &G.isub_win, &G.isub_bin, &G.isub_start, &G.isub_count, &G.fb};
-        std::vector<int> *srcv[9] = {&sw, &sb, &ss, &sc, &iw, &ib, &is, &ic, &fbl};
-        for (int k = 0; k < 9; ++k) {
+        int32_t **dst[4] = {&G.isub_win, &G.isub_bin, &G.isub_start, &G.isub_count};
+        std::vector<int> *srcv[4] = {&iw, &ib, &is, &ic};
+        for (int k = 0; k < 4; ++k) {
             TRYS(dalloc(plan, (void **)dst[k], std::max<size_t>(1, srcv[k]->size()) * sizeof(int)));
             if (!srcv[k]->empty())
                 TRYH(hipMemcpy(*dst[k], srcv[k]->data(), srcv[k]->size() * sizeof(int), hipMemcpyHostToDevice));
@@ -447,11 +487,8 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         coef_need = std::max(coef_need, (size_t)coef_scratch_doubles(G.g, G.nwin));
         TRYS(dalloc(plan, (void **)&G.desc, G.nwin * sizeof(WinDesc)));
         TRYH(hipMemcpy(G.desc, hd.data(), G.nwin * sizeof(WinDesc), hipMemcpyHostToDevice));
-        tile_need = std::max(tile_need, (size_t)G.nsub * G.g.pc);
         grid_need = std::max(grid_need, (size_t)2 * G.nwin * G.g.cells);
     }
-    for (Window &w : plan->win) std::vector<int>().swap(w.h_bin_start);
-    TRYS(dalloc(plan, &plan->tilebuf, std::max<size_t>(tile_need, 1) * max_nrhs * eb));
     TRYS(dalloc(plan, &plan->grid, grid_need * max_nrhs * 2 * eb));
     const size_t vec_bytes = std::max<int64_t>(n, 1) * max_nrhs * eb;
     TRYS(dalloc(plan, &plan->hbuf, vec_bytes * P));
@@ -515,6 +552,132 @@ nfftgp_status nfftgp_apply(nfftgp_plan plan, const void *V_dev, int64_t ldv, int
     if (ldv < nrhs) return fail(NFFTGP_E_ARG, "ldv < nrhs");
     if (plan->n > 0 && (!V_dev || !KV_dev)) return fail(NFFTGP_E_ARG, "V or KV is NULL");
     return apply_impl(plan, V_dev, ldv, nrhs, KV_dev, dKV_dell_dev, dKV_dsf_dev, dKV_dse_dev);
+}
+
+nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_derivs, int32_t reps,
+                              char *report, int64_t report_len)
+{
+    set_error("");
+    if (!plan) return fail(NFFTGP_E_ARG, "plan is NULL");
+    if (!plan->have_hyper) return fail(NFFTGP_E_STATE, "nfftgp_set_hyper has not been called");
+    if (nrhs < 1 || nrhs > plan->max_nrhs) return fail(NFFTGP_E_ARG, "nrhs out of range 1..max_nrhs");
+    if (reps < 1) return fail(NFFTGP_E_ARG, "reps must be >= 1");
+    if (report && report_len > 0) report[0] = '\0';
+    const int64_t n = plan->n;
+    if (n == 0) return NFFTGP_OK;
+    const hipStream_t st = plan->stream;
+    const size_t eb = plan->prec == NFFTGP_F32 ? 4 : 8;
+    const size_t vb = (size_t)n * nrhs * eb;
+    // inputs and outputs of the timed applies (tuning-time allocations)
+    void *V = nullptr, *KV = nullptr, *dl = nullptr, *dsf = nullptr, *dse = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto release = [&]() {
+        (void)hipStreamSynchronize(st);
+        for (void *q : {V, KV, dl, dsf, dse})
+            if (q) (void)hipFree(q);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    hipError_t he = hipMalloc(&V, vb);
+    if (he == hipSuccess) he = hipMalloc(&KV, vb);
+    if (he == hipSuccess && with_derivs) he = hipMalloc(&dl, vb * plan->P);
+    if (he == hipSuccess && with_derivs) he = hipMalloc(&dsf, vb);
+    if (he == hipSuccess && with_derivs) he = hipMalloc(&dse, vb);
+    if (he == hipSuccess) he = hipMemsetAsync(V, 0, vb, st);
+    if (he == hipSuccess) he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        release();
+        return fail(NFFTGP_E_HIP, std::string("autotune buffers: ") + hipGetErrorString(he));
+    }
+    if (plan->cg_exec) {   // the captured CG iteration holds the old work lists
+        (void)hipGraphExecDestroy(plan->cg_exec);
+        plan->cg_exec = nullptr;
+    }
+    const bool prof = plan->prof;
+    plan->prof = false;
+    // best of two trials of `reps` applies, in milliseconds
+    auto timed = [&](double &ms) -> nfftgp_status {
+        ms = 1e300;
+        for (int trial = 0; trial < 2; ++trial) {
+            NFFTGP_HIP_TRY(hipEventRecord(e0, st));
+            for (int k = 0; k < reps; ++k) {
+                nfftgp_status e = apply_impl(plan, V, nrhs, nrhs, KV, dl, dsf, dse);
+                if (e != NFFTGP_OK) return e;
+            }
+            NFFTGP_HIP_TRY(hipEventRecord(e1, st));
+            NFFTGP_HIP_TRY(hipEventSynchronize(e1));
+            float t = 0.f;
+            NFFTGP_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+            ms = std::min(ms, (double)t / reps);
+        }
+        return NFFTGP_OK;
+    };
+    std::string rep;
+    nfftgp_status stt = NFFTGP_OK;
+    double ms = 0.0;
+    stt = timed(ms);   // warm-up and reference
+    for (size_t gi = 0; gi < plan->groups.size() && stt == NFFTGP_OK; ++gi) {
+        Group &G = plan->groups[gi];
+        // 1) spreading subproblem size (skipping sizes whose tiles would exceed 8 GiB)
+        double best = 0.0;
+        if ((stt = timed(best)) != NFFTGP_OK) break;
+        int best_sp = G.sub_sp;
+        for (int sp = kMinSubSp; sp <= 4096 && stt == NFFTGP_OK; sp *= 2) {
+            if (sp == best_sp) continue;
+            int64_t nsub = 0;
+            for (int wl = 0; wl < G.nwin; ++wl) {
+                const std::vector<int> &bs = plan->win[G.wins[wl]].h_bin_start;
+                for (int b = 0; b < G.g.nbins; ++b) nsub += (bs[b + 1] - bs[b] + sp - 1) / sp;
+            }
+            if ((double)nsub * G.g.pc * plan->max_nrhs * eb > 8.0 * (1 << 30)) continue;
+            if ((stt = build_spread_lists(plan, G, sp)) != NFFTGP_OK) break;
+            double t = 0.0;
+            if ((stt = timed(t)) != NFFTGP_OK) break;
+            if (t < best) {
+                best = t;
+                best_sp = sp;
+            }
+        }
+        if (stt != NFFTGP_OK) break;
+        if ((stt = build_spread_lists(plan, G, best_sp)) != NFFTGP_OK) break;
+        // 2) vectors per spreading work-group (0 = rule)
+        int best_R = G.spread_R;
+        for (int R : {1, 2, 4}) {
+            if (R > nrhs || R == best_R) continue;
+            G.spread_R = R;
+            double t = 0.0;
+            if ((stt = timed(t)) != NFFTGP_OK) break;
+            if (t < best) {
+                best = t;
+                best_R = R;
+            }
+        }
+        G.spread_R = best_R;
+        if (stt != NFFTGP_OK) break;
+        // 3) interpolation variant
+        const bool cur_run = G.use_run_interp;
+        G.use_run_interp = !cur_run;
+        double t = 0.0;
+        if ((stt = timed(t)) != NFFTGP_OK) break;
+        if (t < best) best = t;
+        else G.use_run_interp = cur_run;
+        char line[200];
+        std::snprintf(line, sizeof(line), "group d=%d N=%d (%d windows): spread subproblem %d, vectors/group %s, "
+                                          "interpolation %s; %.4f ms per apply\n",
+                      G.g.d, G.g.N, G.nwin, G.sub_sp,
+                      G.spread_R > 0 ? std::to_string(G.spread_R).c_str() : "rule",
+                      G.use_run_interp ? "run" : "tile", best);
+        rep += line;
+    }
+    plan->prof = prof;
+    release();
+    if (stt != NFFTGP_OK) return stt;
+    if (report && report_len > 0) {
+        std::strncpy(report, rep.c_str(), (size_t)report_len - 1);
+        report[report_len - 1] = '\0';
+    }
+    return NFFTGP_OK;
 }
 
 nfftgp_status nfftgp_col_dots(nfftgp_plan plan, const void *A_dev, int64_t lda, const void *B_dev,

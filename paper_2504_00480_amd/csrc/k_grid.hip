@@ -722,8 +722,14 @@ hipError_t spread_dm(const Group &G, const void *V, int64_t ldv, int nrhs, void 
     constexpr int W = D == 3 ? 4 : 1;
     const size_t tile = (size_t)G.g.pc * sizeof(T);
     int R = 1;
-    if (nrhs % 4 == 0 && 4 * tile <= 64 * 1024) R = 4;
-    else if (nrhs >= 2 && 2 * tile <= 64 * 1024) R = 2;
+    if (G.spread_R > 0) {
+        R = G.spread_R;
+        if (R * tile > 64 * 1024 || R > nrhs) R = (2 * tile <= 64 * 1024 && nrhs >= 2) ? 2 : 1;
+    } else if (nrhs % 4 == 0 && 4 * tile <= 64 * 1024) {
+        R = 4;
+    } else if (nrhs >= 2 && 2 * tile <= 64 * 1024) {
+        R = 2;
+    }
     if (R == 4) return spread_launch<T, D, M, 4, W>(G, V, ldv, nrhs, tilebuf, s);
     if (R == 2) return spread_launch<T, D, M, 2, W>(G, V, ldv, nrhs, tilebuf, s);
     return spread_launch<T, D, M, 1, W>(G, V, ldv, nrhs, tilebuf, s);

@@ -141,23 +141,18 @@ k_weights(const T *__restrict__ t, int64_t n, int d, int m, int ng, int tb, int 
 }
 
 __global__ void __launch_bounds__(256)
-k_run_ends(int *__restrict__ anchor, int *__restrict__ lpos, int64_t n, int *__restrict__ runs)
+k_run_ends(int *__restrict__ anchor, int *__restrict__ lpos, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool last = false;
-    if (i < n) {
-        // each thread writes only its own entry; the neighbour may already
-        // carry its flag, so compare the cell bits only
-        const int a = anchor[i] & 0x7fffffff;
-        last = (i == n - 1) || ((anchor[i + 1] & 0x7fffffff) != a);
-        if (last) {
-            anchor[i] = a | (int)0x80000000u;
-            lpos[i] = lpos[i] | (int)0x80000000u;
-        }
+    if (i >= n) return;
+    // each thread writes only its own entry; the neighbour may already carry
+    // its flag, so compare the cell bits only
+    const int a = anchor[i] & 0x7fffffff;
+    const bool last = (i == n - 1) || ((anchor[i + 1] & 0x7fffffff) != a);
+    if (last) {
+        anchor[i] = a | (int)0x80000000u;
+        lpos[i] = lpos[i] | (int)0x80000000u;
     }
-    // number of runs (= occupied cells): one atomic per wave
-    const unsigned long long bal = __ballot(last);
-    if ((threadIdx.x & 63) == 0 && bal != 0ull) atomicAdd(runs, (int)__popcll(bal));
 }
 
 // ---- stable counting sort ------------------------------------------------
@@ -359,7 +354,7 @@ hipError_t launch_bin_keys(int prec, const void *t, int64_t n, const WindowGeom 
 }
 
 hipError_t launch_weights(int prec, const void *t, int64_t n, const WindowGeom &g, int m,
-                          double knorm, void *rec, int *anchor, int *lpos, int *runs, hipStream_t s)
+                          double knorm, void *rec, int *anchor, int *lpos, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     unsigned nblk = (unsigned)((n + 255) / 256);
@@ -369,7 +364,7 @@ hipError_t launch_weights(int prec, const void *t, int64_t n, const WindowGeom &
     else
         k_weights<double><<<nblk, 256, 0, s>>>((const double *)t, n, g.d, m, g.ng, g.tb, g.pd,
                                                kb_beta(), knorm, (double *)rec, anchor, lpos);
-    k_run_ends<<<nblk, 256, 0, s>>>(anchor, lpos, n, runs);
+    k_run_ends<<<nblk, 256, 0, s>>>(anchor, lpos, n);
     return hipGetLastError();
 }
 

@@ -23,10 +23,8 @@ inline double kb_beta() { return kPi * (2.0 - 1.0 / kSigma); }
 
 // Points handled by one interpolation work-group at most (one per thread).
 constexpr int kInterpSubPoints = 256;
-// Points per wave in run-based interpolation, and the average run length
-// (points per occupied cell) from which it is used for 3-D windows.
+// Points per wave in run-based interpolation.
 constexpr int kRunSubPoints = 512;
-constexpr int kRunInterpMinRun = 24;
 
 // Geometry of one window's oversampled grid and its tiling.
 struct WindowGeom {
@@ -60,8 +58,7 @@ struct Window {
     void *Dk = nullptr;     // symmetrised diagonal for K_s (dcells, plan precision)
     void *Dder = nullptr;   // same for K_s^der
     // host copies used while the plan is built
-    std::vector<int> h_bin_start;
-    int64_t h_cells_used = 0;   // occupied grid cells (runs of equal cells)
+    std::vector<int> h_bin_start;   // tile -> first sorted point (kept for re-tuning)
 };
 
 // Per-window data a kernel needs, in device memory (one array per group).
@@ -89,9 +86,13 @@ struct Group {
     int32_t *isub_win = nullptr, *isub_bin = nullptr, *isub_start = nullptr, *isub_count = nullptr;
     int nisub = 0;               // interpolation subproblems
     int nbins_used = 0;          // tiles holding at least one point
+    // tunables (rule defaults at plan creation; nfftgp_autotune may change them)
+    int sub_sp = 0;              // points per spreading subproblem
+    int spread_R = 0;            // vectors per spreading work-group (0: rule)
+    int sub_cap = 0;             // capacity of the spreading list arrays
     int32_t *fb = nullptr;       // tiles split into several subproblems (window * nbins + tile)
     int nfb = 0;
-    // interpolation by register-held runs (chosen when runs of equal cells are long):
+    // interpolation by register-held runs (selectable; see use_run_interp):
     // contiguous ranges of at most kRunSubPoints sorted points
     bool use_run_interp = false;
     int32_t *rsub_win = nullptr, *rsub_start = nullptr, *rsub_count = nullptr;
@@ -118,6 +119,7 @@ struct nfftgp_plan_s {
     double sigma_f = 0.0, sigma_eps = 0.0;
     // workspaces (owned)
     void *tilebuf = nullptr;     // spreading tiles
+    size_t tile_cap = 0;         // tilebuf capacity in values per vector
     void *grid = nullptr;        // 2 x (windows of a group) x max_nrhs x cells complex values
     void *hbuf = nullptr;        // P x n x max_nrhs per-window products
     double *coef = nullptr;      // set_hyper scratch (real coefficient transforms)
@@ -184,11 +186,10 @@ hipError_t launch_sort(int prec, int64_t n, int d, int nbins, const int *keys, c
 hipError_t launch_bin_keys(int prec, const void *t, int64_t n, const WindowGeom &g, int *keys,
                            hipStream_t s);
 // Window weights, packed cells and tile positions (with run-end flags) of the
-// sorted points; *runs (zeroed by the caller) is increased by the number of
-// runs of equal cells.
+// sorted points.
 double kb_knorm(int m);
 hipError_t launch_weights(int prec, const void *t, int64_t n, const WindowGeom &g, int m,
-                          double knorm, void *rec, int *anchor, int *lpos, int *runs, hipStream_t s);
+                          double knorm, void *rec, int *anchor, int *lpos, hipStream_t s);
 
 // ---------------------------------------------------------------- per-theta kernels
 // Coefficients b_k, b^der_k of one window (FP64) and the symmetrised diagonals.

@@ -129,6 +129,14 @@ class AdditiveKernelPlan:
         _lib.check(_lib.load().nfftgp_profile_read(self._h, _np_ptr(ms), _np_ptr(cnt)), "nfftgp_profile_read")
         return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(_lib.PROF_NAMES)}
 
+    def autotune(self, nrhs: int, derivs: bool = True, reps: int = 3) -> str:
+        """Choose spreading subproblem size, vectors per spreading group and the
+        interpolation variant per window group by timing applies; returns the report."""
+        buf = ctypes.create_string_buffer(4096)
+        _lib.check(_lib.load().nfftgp_autotune(self._h, int(nrhs), 1 if derivs else 0, int(reps), buf, 4096),
+                   "nfftgp_autotune")
+        return buf.value.decode()
+
     def workspace_bytes(self) -> int:
         b = ctypes.c_size_t()
         _lib.check(_lib.load().nfftgp_get_workspace_bytes(self._h, ctypes.byref(b)), "workspace")

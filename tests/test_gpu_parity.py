@@ -158,3 +158,29 @@ def test_interp_variants_agree(prec, monkeypatch):
     for o in outs[1:]:
         for k in outs[0]:
             assert _rel(o[k], outs[0][k]) <= tol, k
+
+
+def test_autotune_keeps_results(orc):
+    """The autotuner changes only how the work is laid out (subproblem sizes,
+    vectors per group, interpolation variant): outputs agree with the untuned
+    plan to FP32 rounding and stay within the parity bar of the oracle."""
+    from paper_2504_00480_amd import AdditiveKernelPlan
+    w = workloads.small(14, 30000, [3, 3, 2], [0, 1, 0], [0.4, 0.6, 0.5], [32, 32, 32], 4, 2, dist="cluster")
+    X = torch.tensor(w.X, dtype=torch.float32, device="cuda:0")
+    V = torch.tensor(w.V, dtype=torch.float32, device="cuda:0")
+    plan = AdditiveKernelPlan(X, w.windows, w.ktype, w.N, w.m, max_nrhs=2)
+    plan.set_hyper(1.1, w.ell, 0.2)
+    a = {k: v.clone() for k, v in plan.apply(V, derivs=True).items()}
+    rep = plan.autotune(2, derivs=True, reps=2)
+    print(rep)
+    assert len(rep.strip().splitlines()) == 2
+    b = plan.apply(V, derivs=True)
+    torch.cuda.synchronize()
+    for k in a:
+        assert _rel(b[k].double().cpu().numpy(), a[k].double().cpu().numpy()) <= 1e-5, k
+    rows = np.arange(0, w.n, 97)
+    pb = orc.Problem(X.double().cpu().numpy(), w.windows, w.ktype, w.ell, 1.1, 0.2, w.N, w.scale_mode)
+    ref = orc.rf_apply(pb, V.double().cpu().numpy(), rows=rows, derivs=True)
+    assert _rel(b["KV"].double().cpu().numpy()[rows], ref["KV"]) <= 1e-4
+    for s in range(pb.P):
+        assert _rel(b["dKV_dell"][s].double().cpu().numpy()[rows], ref["dKV_dell"][s]) <= 1e-4
