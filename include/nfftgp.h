@@ -173,7 +173,8 @@ nfftgp_status nfftgp_get_window_info(nfftgp_plan plan, int32_t s, double *c0, do
 /* Autotuning (setup time).  Times nrhs-column applies (with the derivative
  * outputs when with_derivs != 0) for each window group under candidate
  * settings -- points per spreading subproblem (64 ... 4096), vectors per
- * spreading work-group (1, 2, 4) and the interpolation variant -- by
+ * spreading work-group (1, 2, 4) and the interpolation variant (per-point
+ * tile reads with 1 or 2 points per thread, or register-held runs) -- by
  * coordinate search, best of two trials of `reps` applies each, and keeps the
  * fastest settings in the plan.  Requires nfftgp_set_hyper.  Allocates and
  * frees its own input and output buffers (and may grow the plan's tile

@@ -226,6 +226,35 @@ nfftgp_status build_spread_lists(nfftgp_plan plan, Group &G, int sub_sp)
     return NFFTGP_OK;
 }
 
+// (Re)build a group's tile-interpolation work list: subproblems of up to
+// 256 * pt points of one tile (pt points per thread).
+nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt)
+{
+    const int isp = kInterpSubPoints * pt;
+    std::vector<int> iw, ib, is, ic;
+    for (int wl = 0; wl < G.nwin; ++wl) {
+        const std::vector<int> &bs = plan->win[G.wins[wl]].h_bin_start;
+        for (int b = 0; b < G.g.nbins; ++b) {
+            const int cnt = bs[b + 1] - bs[b];
+            for (int off = 0; off < cnt; off += isp) {
+                iw.push_back(wl);
+                ib.push_back(b);
+                is.push_back(bs[b] + off);
+                ic.push_back(std::min(isp, cnt - off));
+            }
+        }
+    }
+    if ((int)iw.size() > G.isub_cap) return fail(NFFTGP_E_ARG, "interpolation list exceeds its capacity");
+    int32_t *dst[4] = {G.isub_win, G.isub_bin, G.isub_start, G.isub_count};
+    std::vector<int> *srcv[4] = {&iw, &ib, &is, &ic};
+    for (int k = 0; k < 4; ++k)
+        if (!srcv[k]->empty())
+            NFFTGP_HIP_TRY(hipMemcpy(dst[k], srcv[k]->data(), srcv[k]->size() * sizeof(int), hipMemcpyHostToDevice));
+    G.nisub = (int)iw.size();
+    G.interp_pt = pt;
+    return NFFTGP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -417,9 +446,8 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
     size_t grid_need = 1, coef_need = 8;
     for (Group &G : plan->groups) {
         G.nwin = (int)G.wins.size();
-        std::vector<int> iw, ib, is, ic;
         std::vector<WinDesc> hd(G.nwin);
-        int64_t cap = 0;
+        int64_t cap = 0, icap = 0;
         for (int wl = 0; wl < G.nwin; ++wl) {
             Window &w = plan->win[G.wins[wl]];
             const std::vector<int> &bs = w.h_bin_start;
@@ -427,12 +455,7 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
                 const int cnt = bs[b + 1] - bs[b];
                 G.nbins_used += cnt > 0;
                 cap += (cnt + kMinSubSp - 1) / kMinSubSp;
-                for (int off = 0; off < cnt; off += kInterpSubPoints) {
-                    iw.push_back(wl);
-                    ib.push_back(b);
-                    is.push_back(bs[b] + off);
-                    ic.push_back(std::min(kInterpSubPoints, cnt - off));
-                }
+                icap += (cnt + kInterpSubPoints - 1) / kInterpSubPoints;
             }
             TRYS(dalloc(plan, (void **)&w.bin_sub_ptr, (w.g.nbins + 1) * sizeof(int)));
             hd[wl] = WinDesc{w.rec, w.anchor, w.lpos, w.perm, w.bin_sub_ptr, w.Dk, w.Dder, G.wins[wl], 0};
@@ -444,14 +467,18 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
             TRYS(dalloc(plan, (void **)&G.fb, std::max<size_t>(1, (size_t)G.nwin * G.g.nbins) * sizeof(int)));
         }
         TRYS(build_spread_lists(plan, G, sub_sp));
-        G.nisub = (int)ib.size();
+        G.isub_cap = (int)std::max<int64_t>(icap, 1);
+        {
+            int32_t **id[4] = {&G.isub_win, &G.isub_bin, &G.isub_start, &G.isub_count};
+            for (int k = 0; k < 4; ++k) TRYS(dalloc(plan, (void **)id[k], (size_t)G.isub_cap * sizeof(int)));
+        }
         // interpolation variant: the per-point tile variant by default (the
         // faster one on every measured workload once its tile staging was
-        // batched); nfftgp_autotune may switch, NFFTGP_INTERP=run|tile forces
-        {
-            const char *ov = std::getenv("NFFTGP_INTERP");
-            G.use_run_interp = ov && std::strcmp(ov, "run") == 0 && n > 0;
-        }
+        // batched); nfftgp_autotune may switch, NFFTGP_INTERP=run|tile|tile2
+        // forces (tile2: two points per thread)
+        const char *iov = std::getenv("NFFTGP_INTERP");
+        G.use_run_interp = iov && std::strcmp(iov, "run") == 0 && n > 0;
+        TRYS(build_interp_lists(plan, G, iov && std::strcmp(iov, "tile2") == 0 ? 2 : 1));
         {
             // run-interpolation list (built for every group, so that the
             // variant can be switched): points per wave up to kRunSubPoints,
@@ -473,13 +500,6 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
                 if (!rsrc[k]->empty())
                     TRYH(hipMemcpy(*rdst[k], rsrc[k]->data(), rsrc[k]->size() * sizeof(int), hipMemcpyHostToDevice));
             }
-        }
-        int32_t **dst[4] = {&G.isub_win, &G.isub_bin, &G.isub_start, &G.isub_count};
-        std::vector<int> *srcv[4] = {&iw, &ib, &is, &ic};
-        for (int k = 0; k < 4; ++k) {
-            TRYS(dalloc(plan, (void **)dst[k], std::max<size_t>(1, srcv[k]->size()) * sizeof(int)));
-            if (!srcv[k]->empty())
-                TRYH(hipMemcpy(*dst[k], srcv[k]->data(), srcv[k]->size() * sizeof(int), hipMemcpyHostToDevice));
         }
         TRYS(dalloc(plan, (void **)&G.cinv2, (G.g.N + 1) * sizeof(double)));
         TRYS(dalloc(plan, (void **)&G.cw, (size_t)(G.g.N / 2 + 1) * (G.g.N / 2 + 1) * sizeof(double)));
@@ -655,19 +675,34 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
         }
         G.spread_R = best_R;
         if (stt != NFFTGP_OK) break;
-        // 3) interpolation variant
+        // 3) interpolation variant: tile with 1 or 2 points per thread, or runs
         const bool cur_run = G.use_run_interp;
-        G.use_run_interp = !cur_run;
-        double t = 0.0;
-        if ((stt = timed(t)) != NFFTGP_OK) break;
-        if (t < best) best = t;
-        else G.use_run_interp = cur_run;
+        const int cur_pt = G.interp_pt;
+        bool best_run = cur_run;
+        int best_pt = cur_pt;
+        for (int cand = 0; cand < 3 && stt == NFFTGP_OK; ++cand) {
+            const bool run = cand == 2;
+            const int pt = run ? cur_pt : cand + 1;
+            if (run == cur_run && (run || pt == cur_pt)) continue;
+            G.use_run_interp = run;
+            if (!run && (stt = build_interp_lists(plan, G, pt)) != NFFTGP_OK) break;
+            double t = 0.0;
+            if ((stt = timed(t)) != NFFTGP_OK) break;
+            if (t < best) {
+                best = t;
+                best_run = run;
+                best_pt = pt;
+            }
+        }
+        if (stt != NFFTGP_OK) break;
+        G.use_run_interp = best_run;
+        if ((stt = build_interp_lists(plan, G, best_pt)) != NFFTGP_OK) break;
         char line[200];
         std::snprintf(line, sizeof(line), "group d=%d N=%d (%d windows): spread subproblem %d, vectors/group %s, "
                                           "interpolation %s; %.4f ms per apply\n",
                       G.g.d, G.g.N, G.nwin, G.sub_sp,
                       G.spread_R > 0 ? std::to_string(G.spread_R).c_str() : "rule",
-                      G.use_run_interp ? "run" : "tile", best);
+                      G.use_run_interp ? "run" : (G.interp_pt == 2 ? "tile, 2 points/thread" : "tile"), best);
         rep += line;
     }
     plan->prof = prof;

@@ -20,6 +20,7 @@
 #include "nfftgp_dev.h"
 
 #include <cstdlib>
+#include <type_traits>
 
 namespace nfftgp {
 namespace {
@@ -316,7 +317,7 @@ k_fold(const WinDesc *__restrict__ wd, const T *__restrict__ tilebuf, int nrhs, 
 // one vector at a time; the point's window weights are loaded once and reused
 // for every vector.  Each window writes its own block of the per-window
 // output buffer (one owner thread per entry).
-template <typename T, int D, int M, bool DER>
+template <typename T, int D, int M, bool DER, int PT>
 __global__ void __launch_bounds__(256)
 k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
          const int *__restrict__ sub_bin, const int *__restrict__ sub_start,
@@ -343,19 +344,28 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     const int start = sub_start[sq], cnt = sub_count[sq];
     int org[3] = {0, 0, 0};
     bin_origin<D>(sub_bin[sq], nb, tb, org);
-    const bool mine = (int)threadIdx.x < cnt;
-    const int64_t j = start + (mine ? (int)threadIdx.x : 0);
-    // weights and first-tap position of this thread's point; for d = 3 the
-    // first dimension's weights are re-read inside its (rolled) loop so that no
-    // register array is indexed by a loop variable
-    T w[D][TW];
-    const T *rp = rec + j * RS;
+    // PT points per thread (thread t takes points t, t + 256, ...): weights
+    // and first-tap positions in registers for all vectors; for d = 3 the
+    // first dimension's weights are re-read inside its (rolled) loop so that
+    // no register array is indexed by a loop variable
+    bool mine[PT];
+    const T *rp[PT];
+    T w[PT][D][TW];
+    int lin[PT];
+    int64_t orow[PT];
 #pragma unroll
-    for (int q = (D == 3 ? 1 : 0); q < D; ++q)
+    for (int p = 0; p < PT; ++p) {
+        const int k = (int)threadIdx.x + 256 * p;
+        mine[p] = k < cnt;
+        const int64_t j = start + (mine[p] ? k : 0);
+        rp[p] = rec + j * RS;
 #pragma unroll
-        for (int a = 0; a < TW; ++a) w[q][a] = rp[q * TW + a];
-    const int lin = win.lpos[j] & 0xfffff;   // first tap inside the padded tile
-    const int64_t orow = (int64_t)win.perm[j] * nrhs;
+        for (int q = (D == 3 ? 1 : 0); q < D; ++q)
+#pragma unroll
+            for (int a = 0; a < TW; ++a) w[p][q][a] = rp[p][q * TW + a];
+        lin[p] = win.lpos[j] & 0xfffff;   // first tap inside the padded tile
+        orow[p] = (int64_t)win.perm[j] * nrhs;
+    }
     T *hout = hbuf + (int64_t)win.s_global * n * nrhs;
     T *dblk = DER ? dout + (int64_t)win.s_global * n * nrhs : nullptr;
     // one tap: value times weight into the K (and derivative) sums
@@ -412,41 +422,44 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             }
         }
         __syncthreads();
-        if (!mine) continue;
-        T hK = T(0), hD = T(0);
-        if (D == 1) {
 #pragma unroll
-            for (int aa = 0; aa < TW; ++aa) tap(lin + aa, w[0][aa], hK, hD);
-        } else if (D == 2) {
+        for (int p = 0; p < PT; ++p) {
+            if (!mine[p]) continue;
+            T hK = T(0), hD = T(0);
+            if (D == 1) {
 #pragma unroll
-            for (int aa = 0; aa < TW; ++aa) {
-                T sK = T(0), sD = T(0);
-                const int row = lin + aa * pd;
+                for (int aa = 0; aa < TW; ++aa) tap(lin[p] + aa, w[p][0][aa], hK, hD);
+            } else if (D == 2) {
 #pragma unroll
-                for (int bb = 0; bb < TW; ++bb) tap(row + bb, w[D > 1 ? 1 : 0][bb], sK, sD);
-                hK += sK * w[0][aa];
-                if (DER) hD += sD * w[0][aa];
-            }
-        } else {
-#pragma unroll 1
-            for (int aa = 0; aa < TW; ++aa) {
-                const T w0 = rp[aa];
-                T sK = T(0), sD = T(0);
+                for (int aa = 0; aa < TW; ++aa) {
+                    T sK = T(0), sD = T(0);
+                    const int row = lin[p] + aa * pd;
 #pragma unroll
-                for (int bb = 0; bb < TW; ++bb) {
-                    const int row = lin + (aa * pd + bb) * pd;
-                    T cK = T(0), cD = T(0);
-#pragma unroll
-                    for (int cc = 0; cc < TW; ++cc) tap(row + cc, w[D > 2 ? 2 : 0][cc], cK, cD);
-                    sK += cK * w[D > 1 ? 1 : 0][bb];
-                    if (DER) sD += cD * w[D > 1 ? 1 : 0][bb];
+                    for (int bb = 0; bb < TW; ++bb) tap(row + bb, w[p][D > 1 ? 1 : 0][bb], sK, sD);
+                    hK += sK * w[p][0][aa];
+                    if (DER) hD += sD * w[p][0][aa];
                 }
-                hK += sK * w0;
-                if (DER) hD += sD * w0;
+            } else {
+#pragma unroll 1
+                for (int aa = 0; aa < TW; ++aa) {
+                    const T w0 = rp[p][aa];
+                    T sK = T(0), sD = T(0);
+#pragma unroll
+                    for (int bb = 0; bb < TW; ++bb) {
+                        const int row = lin[p] + (aa * pd + bb) * pd;
+                        T cK = T(0), cD = T(0);
+#pragma unroll
+                        for (int cc = 0; cc < TW; ++cc) tap(row + cc, w[p][D > 2 ? 2 : 0][cc], cK, cD);
+                        sK += cK * w[p][D > 1 ? 1 : 0][bb];
+                        if (DER) sD += cD * w[p][D > 1 ? 1 : 0][bb];
+                    }
+                    hK += sK * w0;
+                    if (DER) hD += sD * w0;
+                }
             }
+            hout[orow[p] + r] = hK;
+            if (DER) dblk[orow[p] + r] = dscale * hD;
         }
-        hout[orow + r] = hK;
-        if (DER) dblk[orow + r] = dscale * hD;
     }
 }
 
@@ -753,17 +766,21 @@ hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool
         return hipGetLastError();
     }
     size_t shm = (size_t)g.pc * sizeof(T) * (with_der ? 2 : 1);
-    hipError_t e = with_der ? allow_lds(k_interp<T, D, M, true>, shm) : allow_lds(k_interp<T, D, M, false>, shm);
-    if (e != hipSuccess) return e;
+    auto go = [&](auto der_tag, auto pt_tag) -> hipError_t {
+        constexpr bool DR = decltype(der_tag)::value;
+        constexpr int PT = decltype(pt_tag)::value;
+        hipError_t e = allow_lds(k_interp<T, D, M, DR, PT>, shm);
+        if (e != hipSuccess) return e;
+        k_interp<T, D, M, DR, PT><<<(unsigned)G.nisub, 256, shm, s>>>(
+            G.desc, G.isub_win, G.isub_bin, G.isub_start, G.isub_count, g.tb, g.nb, g.ng, G.nwin,
+            (const C *)grid, g.cells, nrhs, n, (T *)hbuf, DR ? (T *)dout : nullptr, (T)dscale);
+        return hipGetLastError();
+    };
+    using t1 = std::integral_constant<int, 1>;
+    using t2 = std::integral_constant<int, 2>;
     if (with_der)
-        k_interp<T, D, M, true><<<(unsigned)G.nisub, 256, shm, s>>>(
-            G.desc, G.isub_win, G.isub_bin, G.isub_start, G.isub_count, g.tb, g.nb, g.ng, G.nwin,
-            (const C *)grid, g.cells, nrhs, n, (T *)hbuf, (T *)dout, (T)dscale);
-    else
-        k_interp<T, D, M, false><<<(unsigned)G.nisub, 256, shm, s>>>(
-            G.desc, G.isub_win, G.isub_bin, G.isub_start, G.isub_count, g.tb, g.nb, g.ng, G.nwin,
-            (const C *)grid, g.cells, nrhs, n, (T *)hbuf, nullptr, (T)dscale);
-    return hipGetLastError();
+        return G.interp_pt == 2 ? go(std::true_type(), t2()) : go(std::true_type(), t1());
+    return G.interp_pt == 2 ? go(std::false_type(), t2()) : go(std::false_type(), t1());
 }
 
 #define NFFTGP_DISPATCH_DM(FN, T, D, M, ...)                         \

@@ -90,6 +90,8 @@ struct Group {
     int sub_sp = 0;              // points per spreading subproblem
     int spread_R = 0;            // vectors per spreading work-group (0: rule)
     int sub_cap = 0;             // capacity of the spreading list arrays
+    int interp_pt = 1;           // points per thread of the tile interpolation (1, 2)
+    int isub_cap = 0;            // capacity of the interpolation list arrays
     int32_t *fb = nullptr;       // tiles split into several subproblems (window * nbins + tile)
     int nfb = 0;
     // interpolation by register-held runs (selectable; see use_run_interp):

@@ -68,12 +68,13 @@ SMALL = [
 ]
 
 
-@pytest.mark.parametrize("interp", ["tile", "run"])
+@pytest.mark.parametrize("interp", ["tile", "tile2", "run"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("case", SMALL, ids=[f"case{c[0]}" for c in SMALL])
 def test_small_parity(orc, case, prec, interp, monkeypatch):
-    """Both interpolation variants (per-point tile reads; register-held runs of
-    equal cells), forced through NFFTGP_INTERP at plan creation."""
+    """Every interpolation variant (per-point tile reads with one or two points
+    per thread; register-held runs of equal cells), forced through
+    NFFTGP_INTERP at plan creation."""
     monkeypatch.setenv("NFFTGP_INTERP", interp)
     seed, n, dims, kt, ell, N, m, nrhs, dist = case
     w = workloads.small(seed, n, dims, kt, ell, N, m, nrhs, dist=dist, scale_mode=1 if dist == "box" else 0)
@@ -147,7 +148,7 @@ def test_interp_variants_agree(prec, monkeypatch):
     X = torch.tensor(w.X, dtype=dt, device="cuda:0")
     V = torch.tensor(w.V, dtype=dt, device="cuda:0")
     outs = []
-    for mode in ("tile", "run"):
+    for mode in ("tile", "tile2", "run"):
         monkeypatch.setenv("NFFTGP_INTERP", mode)
         plan = AdditiveKernelPlan(X, w.windows, w.ktype, w.N, w.m, max_nrhs=2)
         plan.set_hyper(1.3, w.ell, 0.2)
