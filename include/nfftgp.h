@@ -109,8 +109,9 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out,
  *   sigma_f, sigma_eps >= 0.
  * Computes, on the device in FP64, the coefficients b_k and b^der_k of every
  * window (eq. discrete_fourier_coefficients1, eq. exact_derivative) and the
- * diagonal applied between the two FFTs.  Asynchronous: min_k b_k per window
- * is copied back in the background and read by nfftgp_get_window_info. */
+ * diagonal applied between the two FFTs.  Asynchronous (no host wait);
+ * min_k b_k per window is reduced from per-block minima when
+ * nfftgp_get_window_info asks for it. */
 nfftgp_status nfftgp_set_hyper(nfftgp_plan plan, double sigma_f, const double *ell,
                                double sigma_eps);
 
@@ -166,7 +167,8 @@ nfftgp_status nfftgp_slq_logquad(const double *alpha_beta_host, const int32_t *i
 /* Per-window information: centre c0 (d_s doubles), factor c, dimension, bandwidth,
  * and the smallest coefficients min_k b_k and min_k b^der_k from the last
  * set_hyper (min_b < 0 means K_{s,RF} can be indefinite).  Any output may be NULL.
- * Synchronises the stream when a set_hyper result has not been read yet. */
+ * When a set_hyper result has not been read yet, enqueues the reduction of
+ * the smallest coefficients and synchronises the stream. */
 nfftgp_status nfftgp_get_window_info(nfftgp_plan plan, int32_t s, double *c0, double *c,
                                      int32_t *d, int32_t *N, double *min_b, double *min_bder);
 

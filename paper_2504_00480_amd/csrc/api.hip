@@ -505,6 +505,7 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         TRYS(dalloc(plan, (void **)&G.cw, (size_t)(G.g.N / 2 + 1) * (G.g.N / 2 + 1) * sizeof(double)));
         TRYH(launch_window_coef(G.g.N, m, G.cinv2, G.cw, st));
         coef_need = std::max(coef_need, (size_t)coef_scratch_doubles(G.g, G.nwin));
+        TRYS(dalloc(plan, (void **)&G.coef_part, (size_t)coef_part_doubles(G.g, G.nwin) * sizeof(double)));
         TRYS(dalloc(plan, (void **)&G.desc, G.nwin * sizeof(WinDesc)));
         TRYH(hipMemcpy(G.desc, hd.data(), G.nwin * sizeof(WinDesc), hipMemcpyHostToDevice));
         grid_need = std::max(grid_need, (size_t)2 * G.nwin * G.g.cells);
@@ -550,10 +551,10 @@ nfftgp_status nfftgp_set_hyper(nfftgp_plan plan, double sigma_f, const double *e
             prm.kernel[wl] = plan->win[s].kernel;
         }
         PROF_LAUNCH(plan, NFFTGP_PROF_COEF,
-                    launch_coefficients(plan->prec, G, prm, G.cinv2, plan->coef, plan->minb_host, st));
+                    launch_coefficients(plan->prec, G, prm, G.cinv2, plan->coef, st));
     }
-    // the kernels write min_k b_k into pinned host memory; it is read after a
-    // stream synchronisation (nfftgp_get_window_info), so set_hyper does not wait
+    // min_k b_k is reduced from the block minima only when asked for
+    // (nfftgp_get_window_info), so set_hyper neither waits nor launches it
     plan->minb_pending = true;
     for (int s = 0; s < plan->P; ++s) plan->win[s].ell = ell[s];
     plan->sigma_f = sigma_f;
@@ -952,6 +953,7 @@ nfftgp_status nfftgp_get_window_info(nfftgp_plan plan, int32_t s, double *c0, do
     if (!plan) return fail(NFFTGP_E_ARG, "plan is NULL");
     if (s < 0 || s >= plan->P) return fail(NFFTGP_E_ARG, "window index out of range");
     if (plan->minb_pending) {
+        for (const Group &G : plan->groups) NFFTGP_HIP_TRY(launch_coef_min(G, plan->minb_host, plan->stream));
         NFFTGP_HIP_TRY(hipStreamSynchronize(plan->stream));
         for (int k = 0; k < plan->P; ++k) {
             plan->win[k].min_b = plan->minb_host[2 * k];

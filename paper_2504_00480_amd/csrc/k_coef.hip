@@ -237,12 +237,19 @@ int64_t coef_scratch_doubles(const WindowGeom &g, int nwin)
         KH *= g.N / 2 + 1;
         KD *= g.N + 1;
     }
-    // slabs, then the per-block minima
-    return 2 * KH * nwin + 2 * ((KD + 255) / 256) * nwin;
+    (void)KD;
+    return 2 * KH * nwin;   // the slabs of every window and array
+}
+
+int64_t coef_part_doubles(const WindowGeom &g, int nwin)
+{
+    int64_t KD = 1;
+    for (int q = 0; q < g.d; ++q) KD *= g.N + 1;
+    return 2 * ((KD + 255) / 256) * nwin;
 }
 
 hipError_t launch_coefficients(int prec, const Group &G, const CoefParams &prm, const double *cinv2,
-                               double *scratch, double *minb, hipStream_t s)
+                               double *scratch, hipStream_t s)
 {
     const int d = G.g.d, N = G.g.N, H = N / 2 + 1;
     int64_t KH = 1, KD = 1;
@@ -251,14 +258,21 @@ hipError_t launch_coefficients(int prec, const Group &G, const CoefParams &prm, 
         KD *= N + 1;
     }
     k_coef_slab<<<dim3((unsigned)H, 2, (unsigned)G.nwin), 256, 0, s>>>(d, N, prm, G.cw, scratch);
-    double *part = scratch + 2 * KH * G.nwin;
     const unsigned nper = (unsigned)((KD + 255) / 256);
     const dim3 dgrid(nper, 2, (unsigned)G.nwin);
     if (prec == NFFTGP_F32)
-        k_coef_diag<float><<<dgrid, 256, 0, s>>>(d, N, cinv2, G.cw, scratch, G.desc, part);
+        k_coef_diag<float><<<dgrid, 256, 0, s>>>(d, N, cinv2, G.cw, scratch, G.desc, G.coef_part);
     else
-        k_coef_diag<double><<<dgrid, 256, 0, s>>>(d, N, cinv2, G.cw, scratch, G.desc, part);
-    k_coef_min<<<dim3(2, (unsigned)G.nwin), 256, 0, s>>>(part, (int)nper, G.desc, minb);
+        k_coef_diag<double><<<dgrid, 256, 0, s>>>(d, N, cinv2, G.cw, scratch, G.desc, G.coef_part);
+    return hipGetLastError();
+}
+
+hipError_t launch_coef_min(const Group &G, double *minb, hipStream_t s)
+{
+    int64_t KD = 1;
+    for (int q = 0; q < G.g.d; ++q) KD *= G.g.N + 1;
+    const int nper = (int)((KD + 255) / 256);
+    k_coef_min<<<dim3(2, (unsigned)G.nwin), 256, 0, s>>>(G.coef_part, nper, G.desc, minb);
     return hipGetLastError();
 }
 

@@ -101,6 +101,7 @@ struct Group {
     int nrsub = 0;
     double *cinv2 = nullptr;     // N+1 window factors 1 / c(k)^2 (same for the whole group)
     double *cw = nullptr;        // (N/2+1)^2 weights of the real coefficient transform
+    double *coef_part = nullptr; // per-block minima of the coefficients (last set_hyper)
 };
 
 }  // namespace nfftgp
@@ -208,10 +209,14 @@ hipError_t launch_window_coef(int N, int m, double *cinv2, double *cw, hipStream
 int64_t coef_scratch_doubles(const WindowGeom &g, int nwin);
 
 // ---------------------------------------------------------------- apply kernels
-// Coefficients and diagonals of every window of a group (three launches); the
-// smallest b_k, b^der_k of window s go to minb[2 s], minb[2 s + 1].
+// Coefficients and diagonals of every window of a group (two launches); the
+// per-block minima of the coefficients go to G.coef_part, from which
+// launch_coef_min writes the smallest b_k, b^der_k of window s to minb[2 s],
+// minb[2 s + 1] when they are asked for.
+int64_t coef_part_doubles(const WindowGeom &g, int nwin);
 hipError_t launch_coefficients(int prec, const Group &G, const CoefParams &prm, const double *cinv2,
-                               double *scratch, double *minb, hipStream_t s);
+                               double *scratch, hipStream_t s);
+hipError_t launch_coef_min(const Group &G, double *minb, hipStream_t s);
 hipError_t launch_spread(int prec, const Group &G, int m, const void *V, int64_t ldv, int nrhs,
                          void *tilebuf, hipStream_t s);
 hipError_t launch_fold(int prec, const Group &G, int m, int nrhs, void *tilebuf, void *grid,
