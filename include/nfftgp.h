@@ -186,12 +186,16 @@ nfftgp_status nfftgp_get_window_info(nfftgp_plan plan, int32_t s, double *c0, do
 nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_derivs, int32_t reps,
                               char *report, int64_t report_len);
 
-/* Kernel timing with HIP events (a profiling aid).  While enabled, every
- * kernel the plan enqueues is bracketed by two events on the plan's stream
- * and tagged with one of the categories below; nfftgp_profile_read
- * synchronises the stream and returns, per category, the summed duration in
- * milliseconds and the number of launches since profiling was (re-)enabled.
- * Enabling allocates events, so do not enable it while capturing a graph. */
+/* Kernel timing with HIP events (a profiling aid).  `categories` is a bit
+ * mask: bit c set times the launches of category c below (NFFTGP_PROF_ALL:
+ * every launch, 0: off).  Every timed kernel is bracketed by two events on
+ * the plan's stream; each event pair adds a few microseconds to the stream,
+ * so time only the categories of interest when the total matters.
+ * nfftgp_profile_read synchronises the stream and returns, per category, the
+ * summed duration in milliseconds and the number of launches since the last
+ * nfftgp_profile call.  Timing allocates events, so do not enable it while
+ * capturing a graph; CG runs its iterations eagerly while any category is
+ * timed. */
 enum {
     NFFTGP_PROF_FILL = 0,     /* reserved (no kernel in this version)         */
     NFFTGP_PROF_SPREAD = 1,   /* window spreading onto the tiles              */
@@ -204,9 +208,10 @@ enum {
     NFFTGP_PROF_COEF = 8,     /* per-theta coefficient kernels                */
     NFFTGP_PROF_CG = 9,       /* CG dot products and vector updates           */
     NFFTGP_PROF_GATHER = 10,  /* reserved (no kernel in this version)         */
-    NFFTGP_PROF_COUNT = 11
+    NFFTGP_PROF_COUNT = 11,
+    NFFTGP_PROF_ALL = (1 << 11) - 1
 };
-nfftgp_status nfftgp_profile(nfftgp_plan plan, int32_t enable);
+nfftgp_status nfftgp_profile(nfftgp_plan plan, int32_t categories);
 nfftgp_status nfftgp_profile_read(nfftgp_plan plan, double *ms_host, int32_t *count_host);
 
 /* Device bytes the plan holds. */

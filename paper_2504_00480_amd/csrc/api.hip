@@ -57,10 +57,10 @@ void free_plan(nfftgp_plan p)
     delete p;
 }
 
-// Event pair around one launch when profiling is on.
-int prof_begin(nfftgp_plan p)
+// Event pair around one launch when its category is being timed.
+int prof_begin(nfftgp_plan p, int cat)
 {
-    if (!p->prof) return -1;
+    if (!((p->prof >> cat) & 1u)) return -1;
     while (p->ev_used + 2 > p->ev_pool.size()) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return -1;
@@ -82,7 +82,7 @@ void prof_end(nfftgp_plan p, int cat, int i)
 
 #define PROF_LAUNCH(plan_, cat_, expr_)                   \
     do {                                                   \
-        int pi_ = prof_begin(plan_);                       \
+        int pi_ = prof_begin(plan_, cat_);                 \
         NFFTGP_HIP_TRY(expr_);                             \
         prof_end(plan_, cat_, pi_);                        \
     } while (0)
@@ -615,8 +615,8 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
         (void)hipGraphExecDestroy(plan->cg_exec);
         plan->cg_exec = nullptr;
     }
-    const bool prof = plan->prof;
-    plan->prof = false;
+    const uint32_t prof = plan->prof;
+    plan->prof = 0;
     // best of two trials of `reps` applies, in milliseconds
     auto timed = [&](double &ms) -> nfftgp_status {
         ms = 1e300;
@@ -980,11 +980,11 @@ nfftgp_status nfftgp_get_workspace_bytes(nfftgp_plan plan, size_t *bytes)
     return NFFTGP_OK;
 }
 
-nfftgp_status nfftgp_profile(nfftgp_plan plan, int32_t enable)
+nfftgp_status nfftgp_profile(nfftgp_plan plan, int32_t categories)
 {
     set_error("");
     if (!plan) return fail(NFFTGP_E_ARG, "plan is NULL");
-    plan->prof = enable != 0;
+    plan->prof = (uint32_t)categories & ((1u << NFFTGP_PROF_COUNT) - 1u);
     plan->ev_used = 0;
     plan->prof_cat.clear();
     plan->prof_ev.clear();

@@ -144,7 +144,7 @@ struct nfftgp_plan_s {
     size_t bytes = 0;
     std::vector<void *> allocs;
     // kernel timing (nfftgp_profile)
-    bool prof = false;
+    uint32_t prof = 0;           // bit c set: launches of category c are timed
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<int> prof_cat;   // one entry per recorded launch: category

@@ -118,9 +118,17 @@ class AdditiveKernelPlan:
         return {"c0": c0[: d.value].copy(), "c": c.value, "d": d.value, "N": N.value,
                 "min_b": mb.value, "min_bder": mbd.value}
 
-    def profile(self, enable: bool = True):
-        """Start (or stop) per-category kernel timing with HIP events."""
-        _lib.check(_lib.load().nfftgp_profile(self._h, int(bool(enable))), "nfftgp_profile")
+    def profile(self, enable=True):
+        """Start (or stop) kernel timing with HIP events: True / False for every
+        category or none, or an iterable of category names to time only those
+        (each timed launch adds an event pair to the stream)."""
+        if isinstance(enable, bool):
+            mask = (1 << len(_lib.PROF_NAMES)) - 1 if enable else 0
+        else:
+            mask = 0
+            for name in enable:
+                mask |= 1 << _lib.PROF_NAMES.index(name)
+        _lib.check(_lib.load().nfftgp_profile(self._h, mask), "nfftgp_profile")
 
     def profile_read(self) -> dict:
         """{category: (total ms, launches)} since profiling was enabled."""

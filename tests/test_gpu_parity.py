@@ -185,3 +185,32 @@ def test_autotune_keeps_results(orc):
     assert _rel(b["KV"].double().cpu().numpy()[rows], ref["KV"]) <= 1e-4
     for s in range(pb.P):
         assert _rel(b["dKV_dell"][s].double().cpu().numpy()[rows], ref["dKV_dell"][s]) <= 1e-4
+
+
+def test_profile_category_mask():
+    """Kernel timing records only the categories asked for and leaves results unchanged."""
+    from paper_2504_00480_amd import AdditiveKernelPlan
+    w = workloads.small(15, 4000, [3, 2], [0, 1], [0.4, 0.6], [32, 32], 4, 2)
+    dev = torch.device("cuda:0")
+    X = torch.tensor(w.X, dtype=torch.float32, device=dev)
+    V = torch.tensor(w.V, dtype=torch.float32, device=dev)
+    print(f"[case] profile mask {w.name}", flush=True)
+    plan = AdditiveKernelPlan(X, w.windows, w.ktype, w.N, w.m, max_nrhs=w.nrhs)
+    plan.set_hyper(w.sigma_f, w.ell, w.sigma_eps)
+    ref = plan.apply(V)["KV"].clone()
+    plan.profile(True)
+    plan.set_hyper(w.sigma_f, w.ell, w.sigma_eps)
+    out_all = plan.apply(V)["KV"].clone()
+    every = plan.profile_read()
+    for cat in ("spread", "fold", "diag", "interp", "assemble", "coef"):
+        assert every[cat][1] > 0 and every[cat][0] > 0.0, cat
+    plan.profile(["spread"])
+    out_one = plan.apply(V)["KV"].clone()
+    one = plan.profile_read()
+    plan.profile(False)
+    assert one["spread"][1] == every["spread"][1]
+    assert all(v[1] == 0 for k, v in one.items() if k != "spread")
+    off = plan.apply(V)["KV"]
+    assert plan.profile_read()["spread"][1] == 0
+    for o in (out_all, out_one, off):
+        assert torch.equal(o, ref)
