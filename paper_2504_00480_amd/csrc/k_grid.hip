@@ -145,14 +145,16 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
         __syncthreads();
         if (cb + CH < end) fetch(cb + CH);
         // run ends inside this chunk (the subproblem's last point ends a run)
-        const bool isend = lane < nc && (s_lp[lane] < 0 || cb + lane == end - 1);
+        // lane u keeps point u's tile position; a run reads it with readlane
+        const int my_lp = lane < nc ? s_lp[lane] : 0;
+        const bool isend = lane < nc && (my_lp < 0 || cb + lane == end - 1);
         const unsigned long long ends = __ballot(isend);
         int u0 = 0;
         while (u0 < nc) {
             const unsigned long long rest = ends >> u0;
             const bool flush = rest != 0ull;
             const int u1 = flush ? u0 + (int)__builtin_ctzll(rest) : nc - 1;
-            const int lp = __builtin_amdgcn_readfirstlane(s_lp[u0] & 0x7fffffff);
+            const int lp = __builtin_amdgcn_readlane(my_lp, u0) & 0x7fffffff;
             // first owned tap along dimension 0 (tile position = wave mod W)
             const int aoff = D == 3 ? ((wave - (lp >> 20)) % W + W) % W : 0;
             // points are accumulated in groups of 4 while the run has that many
@@ -200,7 +202,18 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             for (; u + 3 <= u1; u += 4) accumulate(std::integral_constant<int, 4>(), u);
             for (; u <= u1; ++u) accumulate(std::integral_constant<int, 1>(), u);
             if (flush) {
+                // all reads of the flush first (distinct cells), then the
+                // writes: one LDS wait per run
                 const int base = (lp & 0xfffff) + (D == 3 ? aoff * pd2 : 0);
+                T old[NG][NA][R];
+#pragma unroll
+                for (int g = 0; g < NG; ++g)
+#pragma unroll
+                    for (int k = 0; k < NA; ++k)
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            old[g][k][r] = act[g] ? tiles[r * pc + base + (D == 3 ? k * W * pd2 : 0) + off[g]]
+                                                  : T(0);
 #pragma unroll
                 for (int g = 0; g < NG; ++g) {
                     if (act[g]) {
@@ -208,13 +221,16 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                         for (int k = 0; k < NA; ++k) {
                             const int idx = base + (D == 3 ? k * W * pd2 : 0) + off[g];
 #pragma unroll
-                            for (int r = 0; r < R; ++r) {
-                                tiles[r * pc + idx] += acc[g][k][r];
-                                acc[g][k][r] = T(0);
-                            }
+                            for (int r = 0; r < R; ++r) tiles[r * pc + idx] = old[g][k][r] + acc[g][k][r];
                         }
                     }
                 }
+#pragma unroll
+                for (int g = 0; g < NG; ++g)
+#pragma unroll
+                    for (int k = 0; k < NA; ++k)
+#pragma unroll
+                        for (int r = 0; r < R; ++r) acc[g][k][r] = T(0);
             }
             u0 = u1 + 1;
         }
@@ -378,10 +394,67 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             sK += tK[idx] * wt;
         }
     };
+    // d = 3 staging: thread t takes cells t, t + 256, ... of the tile's
+    // (second, third) plane -- their grid offsets inside a plane are fixed --
+    // and walks the first dimension, so a cell costs one add and no division
+    constexpr int PDM = 8 + 2 * M;                        // largest padded width (tb <= 8)
+    constexpr int NS = D == 3 ? (PDM * PDM + 255) / 256 : 1;
+    int prel[NS];
+    bool pin[NS];
+    if constexpr (D == 3) {
+        const int pd2 = pd * pd;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const int q = (int)threadIdx.x + 256 * j;
+            const int b = fdiv_small(q, pd, inv_pd), c = q - b * pd;
+            const int l1 = org[1] - M + b, l2 = org[2] - M + c;
+            pin[j] = q < pd2 && l1 >= 0 && l1 < ng && l2 >= 0 && l2 < ng;
+            prel[j] = pin[j] ? l1 * ng + l2 : 0;
+        }
+    }
     for (int r = 0; r < nrhs; ++r) {
         const C *gK = grid + ((int64_t)wi * nrhs + r) * cells;
         const C *gD = DER ? grid + ((int64_t)(nwin + wi) * nrhs + r) * cells : nullptr;
         if (r > 0) __syncthreads();
+        if constexpr (D == 3) {
+            const int pd2 = pd * pd;
+            // SA planes per batch: all loads of a batch in flight before the
+            // first LDS store
+            constexpr int SA = NS == 1 ? 8 : (NS == 2 ? 4 : 2);
+            for (int a0 = 0; a0 < pd; a0 += SA) {
+                T vK[SA][NS], vD[SA][NS];
+#pragma unroll
+                for (int aa = 0; aa < SA; ++aa) {
+                    const int la = org[0] - M + a0 + aa;
+                    const bool ina = a0 + aa < pd && la >= 0 && la < ng;
+                    const int64_t pl = (int64_t)(ina ? la : 0) * ng * ng;
+#pragma unroll
+                    for (int j = 0; j < NS; ++j) {
+                        const bool in = ina && pin[j];
+                        vK[aa][j] = in ? gK[pl + prel[j]].x : T(0);
+                        vD[aa][j] = (DER && in) ? gD[pl + prel[j]].x : T(0);
+                    }
+                }
+#pragma unroll
+                for (int aa = 0; aa < SA; ++aa) {
+#pragma unroll
+                    for (int j = 0; j < NS; ++j) {
+                        const int q = (int)threadIdx.x + 256 * j;
+                        if (a0 + aa < pd && q < pd2) {
+                            const int i = (a0 + aa) * pd2 + q;
+                            if constexpr (DER) {
+                                C v;
+                                v.x = vK[aa][j];
+                                v.y = vD[aa][j];
+                                tKD[i] = v;
+                            } else {
+                                tK[i] = vK[aa][j];
+                            }
+                        }
+                    }
+                }
+            }
+        } else {
         // staged in batches of SB cells per thread: the loads of a batch are
         // all in flight before the first LDS store
         constexpr int SB = 8;
@@ -420,6 +493,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                     }
                 }
             }
+        }
         }
         __syncthreads();
 #pragma unroll
@@ -765,6 +839,8 @@ hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool
                 nrhs, n, (T *)hbuf, nullptr, (T)dscale);
         return hipGetLastError();
     }
+    // the 3-D staging covers a padded plane of at most (8 + 2m)^2 cells
+    if (D == 3 && g.pd > 8 + 2 * M) return hipErrorInvalidValue;
     size_t shm = (size_t)g.pc * sizeof(T) * (with_der ? 2 : 1);
     auto go = [&](auto der_tag, auto pt_tag) -> hipError_t {
         constexpr bool DR = decltype(der_tag)::value;
