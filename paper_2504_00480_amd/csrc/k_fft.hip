@@ -20,10 +20,12 @@
 // cleared.  The first axis is transformed forward, multiplied by the diagonal
 // (and by the derivative diagonal) and transformed back in one pass.
 //
-// A work-group transforms LPB lines of one axis in LDS (iterative radix-2
-// after a bit-reversed load).  Lines are numbered with the fastest other axis
-// varying fastest, so for strided axes consecutive lines of a group read
-// consecutive addresses.
+// Line transforms.  A line of n_g = P * Q points is transformed in two passes
+// (the four-step factorisation n = Q n1 + n2, k = k1 + P k2): pass 1 takes,
+// for each n2, the P-point DFT over n1 in registers and multiplies by
+// w^(n2 k1); pass 2 takes, for each k1, the Q-point DFT over n2 in registers.
+// One LDS exchange (padded rows) and one barrier separate the passes; the
+// small DFTs are radix-2 in registers with constant twiddles.
 #include "nfftgp_impl.h"
 #include "nfftgp_dev.h"
 
@@ -48,66 +50,163 @@ struct PruneGeom {
     int64_t cells;
 };
 
-template <typename T, int LOGN, int LPB>
-__device__ __forceinline__ void fft_stages(typename Cplx<T>::type (*buf)[(1 << LOGN) + 1],
-                                           const typename Cplx<T>::type *tw)
+// cos and sin of 2 pi e / 16
+constexpr double kCos16[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                               0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                               -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                               0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+constexpr double kSin16[16] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                               1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                               0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                               -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+
+// d * exp(-+ 2 pi i e / 16) (minus: forward, plus: INV); e is a constant after unrolling
+template <typename T, bool INV>
+__device__ __forceinline__ typename Cplx<T>::type rot16(typename Cplx<T>::type d, int e)
 {
     using C = typename Cplx<T>::type;
-    constexpr int NG = 1 << LOGN;
+    const T sg = INV ? T(1) : T(-1);
+    C o;
+    if (e == 0) return d;
+    if (e == 8) {
+        o.x = -d.x;
+        o.y = -d.y;
+        return o;
+    }
+    if (e == 4 || e == 12) {   // times sg * i (e = 4) or -sg * i (e = 12)
+        const T s = e == 4 ? sg : -sg;
+        o.x = -s * d.y;
+        o.y = s * d.x;
+        return o;
+    }
+    const T c = (T)kCos16[e], s = sg * (T)kSin16[e];
+    o.x = d.x * c - d.y * s;
+    o.y = d.x * s + d.y * c;
+    return o;
+}
+
+constexpr int brev_c(int k, int bits)
+{
+    int r = 0;
+    for (int i = 0; i < bits; ++i) r |= ((k >> i) & 1) << (bits - 1 - i);
+    return r;
+}
+
+constexpr int log2c(int v) { return v <= 1 ? 0 : 1 + log2c(v / 2); }
+
+// In-register DFT of P <= 16 points, natural order in and out (radix-2
+// decimation in frequency, then the bit-reversal permutation by renaming).
+template <typename T, int P, bool INV>
+__device__ __forceinline__ void dft_reg(typename Cplx<T>::type (&x)[P])
+{
+    using C = typename Cplx<T>::type;
 #pragma unroll
-    for (int s = 1; s <= LOGN; ++s) {
-        const int len = 1 << s, half = len >> 1;
-        for (int bfi = threadIdx.x; bfi < LPB * NG / 2; bfi += 256) {
-            const int li = bfi / (NG / 2), rest = bfi % (NG / 2);
-            const int grp = rest / half, j = rest % half;
-            const int i0 = grp * len + j, i1 = i0 + half;
-            const C w = tw[j * (NG / len)];
-            const C u = buf[li][i0], x = buf[li][i1];
-            C v;
-            v.x = x.x * w.x - x.y * w.y;
-            v.y = x.x * w.y + x.y * w.x;
-            C o0, o1;
-            o0.x = u.x + v.x;
-            o0.y = u.y + v.y;
-            o1.x = u.x - v.x;
-            o1.y = u.y - v.y;
-            buf[li][i0] = o0;
-            buf[li][i1] = o1;
+    for (int half = P / 2; half >= 1; half >>= 1) {
+#pragma unroll
+        for (int b = 0; b < P; b += 2 * half) {
+#pragma unroll
+            for (int j = 0; j < half; ++j) {
+                const C u = x[b + j], v = x[b + j + half];
+                C s, d;
+                s.x = u.x + v.x;
+                s.y = u.y + v.y;
+                d.x = u.x - v.x;
+                d.y = u.y - v.y;
+                x[b + j] = s;
+                x[b + j + half] = rot16<T, INV>(d, j * (8 / half));
+            }
         }
-        __syncthreads();
+    }
+    C y[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) y[k] = x[brev_c(k, log2c(P))];
+#pragma unroll
+    for (int k = 0; k < P; ++k) x[k] = y[k];
+}
+
+template <int LOGN> struct Split {
+    static constexpr int NG = 1 << LOGN;
+    static constexpr int P = 1 << ((LOGN + 1) / 2);
+    static constexpr int Q = NG / P;
+    static constexpr int YP = P * (Q + 1) + 1;   // padded row of the exchange buffer
+};
+
+// Twiddles w^t = exp(-+ 2 pi i t / n_g), t < n_g / 2, evaluated in FP64.
+template <typename T, int LOGN, bool INV>
+__device__ __forceinline__ void make_tw(typename Cplx<T>::type *tw)
+{
+    constexpr int NG = 1 << LOGN;
+    for (int t = threadIdx.x; t < NG / 2; t += blockDim.x) {
+        double sn, cs;
+        sincospi((INV ? 2.0 : -2.0) * (double)t / (double)NG, &sn, &cs);
+        tw[t].x = (T)cs;
+        tw[t].y = (T)sn;
     }
 }
 
-// Radix-2 stages over `nl` lines of a buffer with row pitch NG + 1.
-template <typename T, int LOGN>
-__device__ __forceinline__ void fft_stages_n(typename Cplx<T>::type *buf, int nl,
-                                             const typename Cplx<T>::type *tw)
+// Pass 1 for line ln, column n2: x[Q n1 + n2] from load(ln, n), P-point DFT,
+// times w^(n2 k1), into the exchange row at (Q + 1) k1 + n2.
+template <typename T, int LOGN, bool INV, typename Load>
+__device__ __forceinline__ void pass1(int ln, int n2, Load &&load, typename Cplx<T>::type *ybuf,
+                                      const typename Cplx<T>::type *tw)
 {
     using C = typename Cplx<T>::type;
-    constexpr int NG = 1 << LOGN;
+    using S = Split<LOGN>;
+    C x[S::P];
 #pragma unroll
-    for (int s = 1; s <= LOGN; ++s) {
-        const int len = 1 << s, half = len >> 1;
-        for (int bfi = threadIdx.x; bfi < nl * NG / 2; bfi += 256) {
-            const int li = bfi / (NG / 2), rest = bfi % (NG / 2);
-            const int grp = rest / half, j = rest % half;
-            const int i0 = grp * len + j, i1 = i0 + half;
-            C *row = buf + li * (NG + 1);
-            const C w = tw[j * (NG / len)];
-            const C u = row[i0], x = row[i1];
-            C v;
-            v.x = x.x * w.x - x.y * w.y;
-            v.y = x.x * w.y + x.y * w.x;
-            C o0, o1;
-            o0.x = u.x + v.x;
-            o0.y = u.y + v.y;
-            o1.x = u.x - v.x;
-            o1.y = u.y - v.y;
-            row[i0] = o0;
-            row[i1] = o1;
+    for (int n1 = 0; n1 < S::P; ++n1) x[n1] = load(ln, S::Q * n1 + n2);
+    dft_reg<T, S::P, INV>(x);
+#pragma unroll
+    for (int k1 = 1; k1 < S::P; ++k1) {
+        const int e = (n2 * k1) & (S::NG - 1);
+        C w = tw[e & (S::NG / 2 - 1)];
+        if (e >= S::NG / 2) {
+            w.x = -w.x;
+            w.y = -w.y;
         }
-        __syncthreads();
+        const C v = x[k1];
+        x[k1].x = v.x * w.x - v.y * w.y;
+        x[k1].y = v.x * w.y + v.y * w.x;
     }
+    C *row = ybuf + ln * S::YP + n2;
+#pragma unroll
+    for (int k1 = 0; k1 < S::P; ++k1) row[(S::Q + 1) * k1] = x[k1];
+}
+
+// Pass 2 for line ln, row k1: Q-point DFT over n2; emit(ln, k1 + P k2, value).
+template <typename T, int LOGN, bool INV, typename Emit>
+__device__ __forceinline__ void pass2(int ln, int k1, const typename Cplx<T>::type *ybuf, Emit &&emit)
+{
+    using C = typename Cplx<T>::type;
+    using S = Split<LOGN>;
+    C y[S::Q];
+    const C *row = ybuf + ln * S::YP + (S::Q + 1) * k1;
+#pragma unroll
+    for (int n2 = 0; n2 < S::Q; ++n2) y[n2] = row[n2];
+    dft_reg<T, S::Q, INV>(y);
+#pragma unroll
+    for (int k2 = 0; k2 < S::Q; ++k2) emit(ln, k1 + S::P * k2, y[k2]);
+}
+
+// Both passes over nl lines (work-group-wide; contains barriers).  With
+// LINE_FAST the thread index runs over lines first (strided axes, whose
+// adjacent lines are adjacent in memory), otherwise over the column / row.
+template <typename T, int LOGN, bool INV, bool LINE_FAST, typename Load, typename Emit>
+__device__ __forceinline__ void fft_lines(int nl, Load &&load, Emit &&emit, typename Cplx<T>::type *ybuf,
+                                          const typename Cplx<T>::type *tw)
+{
+    using S = Split<LOGN>;
+    const int nt = blockDim.x;
+    for (int t = threadIdx.x; t < nl * S::Q; t += nt) {
+        const int ln = LINE_FAST ? t % nl : t / S::Q, c = LINE_FAST ? t / nl : t % S::Q;
+        pass1<T, LOGN, INV>(ln, c, load, ybuf, tw);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nl * S::P; t += nt) {
+        const int ln = LINE_FAST ? t % nl : t / S::P, r = LINE_FAST ? t / nl : t % S::P;
+        pass2<T, LOGN, INV>(ln, r, ybuf, emit);
+    }
+    __syncthreads();
 }
 
 // 3-D grids with 2N <= 64: axes 2 and 1 of one slab (batch b, first index l0)
@@ -115,81 +214,78 @@ __device__ __forceinline__ void fft_stages_n(typename Cplx<T>::type *buf, int nl
 // along axis 2 (input Omega, kept F), then columns K2 in F along axis 1
 // (input Omega, written F).  Inverse: columns K2 in F along axis 1 (input F,
 // kept Omega), then rows l1 in Omega along axis 2 (input F, written Omega).
-// Grid (on, batch); LDS rows[on][NG + 1] and cols[fn][NG + 1].
+// Grid (on, batch); LDS: exchange rows [on][YP] and a natural-order buffer
+// nat[on][NG + 1] (columns of the intermediate result, then the output).
 template <typename T, int LOGN, bool INV>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_fft_slab(typename Cplx<T>::type *__restrict__ data, PruneGeom pg)
 {
     using C = typename Cplx<T>::type;
-    constexpr int NG = 1 << LOGN;
+    using S = Split<LOGN>;
+    constexpr int NG = S::NG, NP = NG + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C *rows = reinterpret_cast<C *>(smem_raw);            // [on][NG + 1]
-    C *cols = rows + pg.on * (NG + 1);                     // [fn][NG + 1]
+    C *ybuf = reinterpret_cast<C *>(smem_raw);            // [on][YP]
+    C *nat = ybuf + pg.on * S::YP;                         // [on][NG + 1]
     __shared__ C tw[NG / 2];
-    for (int t = threadIdx.x; t < NG / 2; t += 256) {
-        double sn, cs;
-        sincospi((INV ? 2.0 : -2.0) * (double)t / (double)NG, &sn, &cs);
-        tw[t].x = (T)cs;
-        tw[t].y = (T)sn;
-    }
+    make_tw<T, LOGN, INV>(tw);
     const int l0 = pg.olo + blockIdx.x;
     C *slab = data + (int64_t)blockIdx.y * pg.cells + (int64_t)l0 * NG * NG;
-    const int on = pg.on, fn = pg.fn;
+    const int on = pg.on, fn = pg.fn, olo = pg.olo, flo = pg.flo;
     C zero;
     zero.x = T(0);
     zero.y = T(0);
     if (!INV) {
-        // rows: l1 = olo + j, input along axis 2 at Omega
-        for (int idx = threadIdx.x; idx < on * NG; idx += 256) {
-            const int j = idx / NG, k = idx % NG;
-            C v = zero;
-            if (cyc_has(pg.olo, on, k, NG)) v = slab[(pg.olo + j) * NG + k];
-            rows[j * (NG + 1) + (__brev((unsigned)k) >> (32 - LOGN))] = v;
-        }
-        __syncthreads();
-        fft_stages_n<T, LOGN>(rows, on, tw);
-        // columns K2 in F: bit-reversed along l1 (rows outside Omega are zero)
-        for (int idx = threadIdx.x; idx < fn * NG; idx += 256) {
-            const int c = idx / NG, l1 = idx % NG;
-            const int k2 = cyc_pos(pg.flo, c, NG);
-            C v = zero;
-            if (cyc_has(pg.olo, on, l1, NG)) v = rows[(l1 - pg.olo) * (NG + 1) + k2];
-            cols[c * (NG + 1) + (__brev((unsigned)l1) >> (32 - LOGN))] = v;
-        }
-        __syncthreads();
-        fft_stages_n<T, LOGN>(cols, fn, tw);
-        // write (K1 in F, K2 in F)
-        for (int idx = threadIdx.x; idx < fn * fn; idx += 256) {
+        __syncthreads();   // twiddles
+        // rows l1 = olo + j along axis 2: Omega in, F kept -> nat[c][l1]
+        fft_lines<T, LOGN, false, false>(
+            on,
+            [&](int j, int k) { return cyc_has(olo, on, k, NG) ? slab[(olo + j) * NG + k] : zero; },
+            [&](int j, int k2, C v) {
+                if (cyc_has(flo, fn, k2, NG)) nat[((k2 - flo) & (NG - 1)) * NP + olo + j] = v;
+            },
+            ybuf, tw);
+        // columns c (K2 in F) along axis 1: Omega in (zero elsewhere), F kept
+        fft_lines<T, LOGN, false, false>(
+            fn, [&](int c, int l1) { return cyc_has(olo, on, l1, NG) ? nat[c * NP + l1] : zero; },
+            [&](int c, int k1, C v) {
+                if (cyc_has(flo, fn, k1, NG)) nat[c * NP + k1] = v;
+            },
+            ybuf, tw);
+        for (int idx = threadIdx.x; idx < fn * fn; idx += blockDim.x) {
             const int a = idx / fn, c = idx % fn;
-            const int k1 = cyc_pos(pg.flo, a, NG), k2 = cyc_pos(pg.flo, c, NG);
-            slab[k1 * NG + k2] = cols[c * (NG + 1) + k1];
+            const int k1 = cyc_pos(flo, a, NG), k2 = cyc_pos(flo, c, NG);
+            slab[k1 * NG + k2] = nat[c * NP + k1];
         }
     } else {
-        // columns K2 in F along axis 1: input K1 in F
-        for (int idx = threadIdx.x; idx < fn * NG; idx += 256) {
-            const int c = idx / NG, k1 = idx % NG;
-            const int k2 = cyc_pos(pg.flo, c, NG);
-            C v = zero;
-            if (cyc_has(pg.flo, fn, k1, NG)) v = slab[k1 * NG + k2];
-            cols[c * (NG + 1) + (__brev((unsigned)k1) >> (32 - LOGN))] = v;
+        // coalesced load of (K1 in F, K2 in F) into nat[c][k1]
+        for (int idx = threadIdx.x; idx < fn * fn; idx += blockDim.x) {
+            const int a = idx / fn, c = idx % fn;
+            const int k1 = cyc_pos(flo, a, NG), k2 = cyc_pos(flo, c, NG);
+            nat[c * NP + k1] = slab[k1 * NG + k2];
         }
         __syncthreads();
-        fft_stages_n<T, LOGN>(cols, fn, tw);
-        // rows l1 in Omega along axis 2: input K2 in F (others zero)
-        for (int idx = threadIdx.x; idx < on * NG; idx += 256) {
-            const int j = idx / NG, k2 = idx % NG;
-            C v = zero;
-            if (cyc_has(pg.flo, fn, k2, NG)) {
-                const int c = (k2 - pg.flo) & (NG - 1);
-                v = cols[c * (NG + 1) + pg.olo + j];
-            }
-            rows[j * (NG + 1) + (__brev((unsigned)k2) >> (32 - LOGN))] = v;
-        }
-        __syncthreads();
-        fft_stages_n<T, LOGN>(rows, on, tw);
-        for (int idx = threadIdx.x; idx < on * on; idx += 256) {
+        // columns c along axis 1: F in, Omega kept -> nat[c][l1]
+        fft_lines<T, LOGN, true, false>(
+            fn, [&](int c, int k1) { return cyc_has(flo, fn, k1, NG) ? nat[c * NP + k1] : zero; },
+            [&](int c, int l1, C v) {
+                if (cyc_has(olo, on, l1, NG)) nat[c * NP + l1] = v;
+            },
+            ybuf, tw);
+        // rows l1 = olo + j along axis 2: F in (from nat[c][l1]), Omega kept -> nat[j][l2]
+        // (the row pass reads nat only in its first pass, which a barrier
+        // separates from the writes of its second)
+        fft_lines<T, LOGN, true, false>(
+            on,
+            [&](int j, int k2) {
+                return cyc_has(flo, fn, k2, NG) ? nat[((k2 - flo) & (NG - 1)) * NP + olo + j] : zero;
+            },
+            [&](int j, int l2, C v) {
+                if (cyc_has(olo, on, l2, NG)) nat[j * NP + l2] = v;
+            },
+            ybuf, tw);
+        for (int idx = threadIdx.x; idx < on * on; idx += blockDim.x) {
             const int j = idx / on, c = idx % on;
-            slab[(pg.olo + j) * NG + pg.olo + c] = rows[j * (NG + 1) + pg.olo + c];
+            slab[(olo + j) * NG + olo + c] = nat[j * NP + olo + c];
         }
     }
 }
@@ -198,31 +294,26 @@ k_fft_slab(typename Cplx<T>::type *__restrict__ data, PruneGeom pg)
 // MODE 1: inverse transform of axis ax (reads F, writes Omega);
 // MODE 2: axis 0 forward, diagonal, inverse (reads Omega, writes Omega of the
 //         K block and, with DER, of the derivative block der_off batches on).
+// LPB lines per work-group of LPB * Q threads; the first pass reads the grid
+// and the last writes it directly.
 template <typename T, int LOGN, int LPB, int MODE, bool DER>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(LPB * Split<LOGN>::Q)
 k_fft_pruned(typename Cplx<T>::type *__restrict__ data, PruneGeom pg, int ax, int64_t nlines,
              int64_t lines_per_batch, const WinDesc *__restrict__ wd, int nrhs, int64_t der_off)
 {
     using C = typename Cplx<T>::type;
-    constexpr int NG = 1 << LOGN;
-    __shared__ C buf[LPB][NG + 1];
-    __shared__ C buf2[MODE == 2 ? LPB : 1][MODE == 2 ? NG + 1 : 1];
+    using Sp = Split<LOGN>;
+    constexpr int NG = Sp::NG;
+    __shared__ C ybuf[LPB * Sp::YP];
+    __shared__ C spec[MODE == 2 ? LPB : 1][MODE == 2 ? NG + 1 : 1];
     __shared__ C twf[NG / 2];
     __shared__ C twi[MODE == 2 ? NG / 2 : 1];
     __shared__ int64_t s_base[LPB];
     __shared__ int s_ok[LPB];
     __shared__ int s_di[LPB];
     __shared__ int s_win[LPB];
-    for (int t = threadIdx.x; t < NG / 2; t += blockDim.x) {
-        double sn, cs;
-        sincospi((MODE == 1 ? 2.0 : -2.0) * (double)t / (double)NG, &sn, &cs);
-        twf[t].x = (T)cs;
-        twf[t].y = (T)sn;
-        if (MODE == 2) {
-            twi[t].x = (T)cs;
-            twi[t].y = (T)(-sn);
-        }
-    }
+    make_tw<T, LOGN, MODE == 1>(twf);
+    if (MODE == 2) make_tw<T, LOGN, true>(twi);
     const int ng = NG;
     int64_t S = 1;
     for (int q = ax + 1; q < pg.d; ++q) S *= ng;
@@ -261,68 +352,58 @@ k_fft_pruned(typename Cplx<T>::type *__restrict__ data, PruneGeom pg, int ax, in
         s_win[li] = (int)(b / nrhs);
     }
     __syncthreads();
+    C zero;
+    zero.x = T(0);
+    zero.y = T(0);
     const bool in_om = MODE != 1;                    // input set: Omega or F
     const int ilo = in_om ? pg.olo : pg.flo, ilen = in_om ? pg.on : pg.fn;
-    for (int idx = threadIdx.x; idx < LPB * NG; idx += 256) {
-        int li, k;
-        if (S == 1) {
-            li = idx / NG;
-            k = idx % NG;
-        } else {
-            k = idx / LPB;
-            li = idx % LPB;
-        }
-        C v;
-        v.x = T(0);
-        v.y = T(0);
-        if (s_ok[li] && cyc_has(ilo, ilen, k, ng)) v = data[s_base[li] + (int64_t)k * S];
-        buf[li][__brev((unsigned)k) >> (32 - LOGN)] = v;
-    }
-    __syncthreads();
-    fft_stages<T, LOGN, LPB>(buf, twf);
+    auto load = [&](int li, int k) {
+        return (s_ok[li] && cyc_has(ilo, ilen, k, ng)) ? data[s_base[li] + (int64_t)k * S] : zero;
+    };
     if constexpr (MODE != 2) {
         const int olo2 = MODE == 0 ? pg.flo : pg.olo, olen = MODE == 0 ? pg.fn : pg.on;
-        for (int idx = threadIdx.x; idx < LPB * NG; idx += 256) {
-            int li, k;
-            if (S == 1) {
-                li = idx / NG;
-                k = idx % NG;
-            } else {
-                k = idx / LPB;
-                li = idx % LPB;
-            }
-            if (s_ok[li] && cyc_has(olo2, olen, k, ng)) data[s_base[li] + (int64_t)k * S] = buf[li][k];
-        }
+        auto emit = [&](int li, int k, C v) {
+            if (s_ok[li] && cyc_has(olo2, olen, k, ng)) data[s_base[li] + (int64_t)k * S] = v;
+        };
+        if (S == 1)
+            fft_lines<T, LOGN, MODE == 1, false>(LPB, load, emit, ybuf, twf);
+        else
+            fft_lines<T, LOGN, MODE == 1, true>(LPB, load, emit, ybuf, twf);
     } else {
-    // MODE 2 (ax == 0, stride S): diagonal of axis 0 frequency k times the
-    // line's offset in the (N+1)^d diagonal, then the inverse transform
-    int64_t dstr0 = 1;
-    for (int q = 1; q < pg.d; ++q) dstr0 *= (pg.N + 1);
+        // MODE 2 (ax == 0, stride S): forward spectrum into spec, then per
+        // block the diagonal at axis-0 frequency k times the line's offset in
+        // the (N+1)^d diagonal, and the inverse transform
+        auto keep = [&](int li, int k, C v) { spec[li][k] = v; };
+        if (S == 1)
+            fft_lines<T, LOGN, false, false>(LPB, load, keep, ybuf, twf);
+        else
+            fft_lines<T, LOGN, false, true>(LPB, load, keep, ybuf, twf);
+        int64_t dstr0 = 1;
+        for (int q = 1; q < pg.d; ++q) dstr0 *= (pg.N + 1);
 #pragma unroll 1
-    for (int pass = 0; pass < (DER ? 2 : 1); ++pass) {
-        for (int idx = threadIdx.x; idx < LPB * NG; idx += 256) {
-            const int k = S == 1 ? idx % NG : idx / LPB, li = S == 1 ? idx / NG : idx % LPB;
-            const int f = k < pg.N ? k : k - ng;
-            T dv = T(0);
-            if (s_ok[li] && f >= -pg.N / 2 && f <= pg.N / 2) {
-                const WinDesc &w = wd[s_win[li]];
-                const T *D = reinterpret_cast<const T *>(pass == 0 ? w.Dk : w.Dder);
-                dv = D[(int64_t)(f + pg.N / 2) * dstr0 + s_di[li]];
-            }
-            C v = buf[li][k];
-            v.x *= dv;
-            v.y *= dv;
-            buf2[li][__brev((unsigned)k) >> (32 - LOGN)] = v;
+        for (int pass = 0; pass < (DER ? 2 : 1); ++pass) {
+            auto dload = [&](int li, int k) {
+                const int f = k < pg.N ? k : k - ng;
+                C v = zero;
+                if (s_ok[li] && f >= -pg.N / 2 && f <= pg.N / 2) {
+                    const WinDesc &w = wd[s_win[li]];
+                    const T *D = reinterpret_cast<const T *>(pass == 0 ? w.Dk : w.Dder);
+                    const T dv = D[(int64_t)(f + pg.N / 2) * dstr0 + s_di[li]];
+                    v = spec[li][k];
+                    v.x *= dv;
+                    v.y *= dv;
+                }
+                return v;
+            };
+            const int64_t off = pass == 0 ? 0 : der_off * pg.cells;
+            auto emit = [&](int li, int k, C v) {
+                if (s_ok[li] && cyc_has(pg.olo, pg.on, k, ng)) data[off + s_base[li] + (int64_t)k * S] = v;
+            };
+            if (S == 1)
+                fft_lines<T, LOGN, true, false>(LPB, dload, emit, ybuf, twi);
+            else
+                fft_lines<T, LOGN, true, true>(LPB, dload, emit, ybuf, twi);
         }
-        __syncthreads();
-        fft_stages<T, LOGN, LPB>(buf2, twi);
-        const int64_t off = pass == 0 ? 0 : der_off * pg.cells;
-        for (int idx = threadIdx.x; idx < LPB * NG; idx += 256) {
-            const int k = S == 1 ? idx % NG : idx / LPB, li = S == 1 ? idx / NG : idx % LPB;
-            if (s_ok[li] && cyc_has(pg.olo, pg.on, k, ng)) data[off + s_base[li] + (int64_t)k * S] = buf2[li][k];
-        }
-        __syncthreads();
-    }
     }
 }
 
@@ -348,16 +429,26 @@ int64_t lines_of(const PruneGeom &pg, int ax)
     return l;
 }
 
+// Lines per work-group: enough for 128 threads in the first pass; halved for
+// FP64 at n_g >= 128 to stay within the static LDS limit.
+template <typename T, int LOGN>
+constexpr int lines_per_group()
+{
+    constexpr int NG = 1 << LOGN;
+    constexpr int base = NG <= 32 ? 32 : (NG <= 128 ? 16 : 8);
+    return (sizeof(T) == 8 && NG >= 128) ? base / 2 : base;
+}
+
 template <typename T, int LOGN, int MODE, bool DER>
 hipError_t fft_launch(void *grid, const PruneGeom &pg, int ax, int64_t batch, const WinDesc *wd,
                       int nrhs, int64_t der_off, hipStream_t s)
 {
-    constexpr int LPB = (1 << LOGN) >= 256 ? 4 : ((1 << LOGN) >= 128 ? 8 : 16);
+    constexpr int LPB = lines_per_group<T, LOGN>();
     const int64_t lpb = lines_of(pg, ax);
     const int64_t nlines = batch * lpb;
     const unsigned nblk = (unsigned)((nlines + LPB - 1) / LPB);
     if (nblk == 0) return hipSuccess;
-    k_fft_pruned<T, LOGN, LPB, MODE, DER><<<nblk, 256, 0, s>>>(
+    k_fft_pruned<T, LOGN, LPB, MODE, DER><<<nblk, LPB * Split<LOGN>::Q, 0, s>>>(
         (typename Cplx<T>::type *)grid, pg, ax, nlines, lpb, wd, nrhs, der_off);
     return hipGetLastError();
 }
@@ -384,32 +475,32 @@ int log2i(int v)
 }
 
 // Slab pass of a 3-D group (2N <= 64): one launch for axes 2 and 1.
+template <typename T, int LOGN, bool INV>
+hipError_t slab_go(const PruneGeom &pg, void *grid, int64_t batch, hipStream_t s)
+{
+    using C = typename Cplx<T>::type;
+    using S = Split<LOGN>;
+    const size_t shm = (size_t)pg.on * (S::YP + S::NG + 1) * sizeof(C);
+    // one thread per (line, column) of the larger pass, whole waves, <= 512
+    int nt = pg.on * (S::P > S::Q ? S::P : S::Q);
+    nt = ((nt + 63) / 64) * 64;
+    nt = nt > 512 ? 512 : nt;
+    hipError_t e = hipFuncSetAttribute((const void *)k_fft_slab<T, LOGN, INV>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    k_fft_slab<T, LOGN, INV><<<dim3((unsigned)pg.on, (unsigned)batch), nt, shm, s>>>((C *)grid, pg);
+    return hipGetLastError();
+}
+
 template <typename T, bool INV>
 hipError_t slab_t(const Group &G, const PruneGeom &pg, void *grid, int64_t batch, hipStream_t s)
 {
-    using C = typename Cplx<T>::type;
-    const size_t shm = (size_t)(pg.on + pg.fn) * (G.g.ng + 1) * sizeof(C);
-    const dim3 grd((unsigned)pg.on, (unsigned)batch);
-    hipError_t e;
     switch (G.g.ng) {
-    case 16:
-        e = hipFuncSetAttribute((const void *)k_fft_slab<T, 4, INV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        if (e != hipSuccess) return e;
-        k_fft_slab<T, 4, INV><<<grd, 256, shm, s>>>((C *)grid, pg);
-        break;
-    case 32:
-        e = hipFuncSetAttribute((const void *)k_fft_slab<T, 5, INV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        if (e != hipSuccess) return e;
-        k_fft_slab<T, 5, INV><<<grd, 256, shm, s>>>((C *)grid, pg);
-        break;
-    case 64:
-        e = hipFuncSetAttribute((const void *)k_fft_slab<T, 6, INV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        if (e != hipSuccess) return e;
-        k_fft_slab<T, 6, INV><<<grd, 256, shm, s>>>((C *)grid, pg);
-        break;
+    case 16: return slab_go<T, 4, INV>(pg, grid, batch, s);
+    case 32: return slab_go<T, 5, INV>(pg, grid, batch, s);
+    case 64: return slab_go<T, 6, INV>(pg, grid, batch, s);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 bool use_slab(const Group &G) { return G.g.d == 3 && G.g.ng <= 64; }

@@ -65,6 +65,7 @@ SMALL = [
     (6, 6000, [3, 2], [0, 1], [0.2, 0.4], [16, 16], 4, 2, "cluster"),
     (7, 1200, [3], 0, 1.2, 32, 6, 1, "normal"),
     (8, 1000, [3, 1], [1, 0], [0.5, 0.5], [8, 8], 2, 1, "normal"),
+    (9, 1200, [3, 2], [0, 1], [0.3, 0.5], [64, 128], 4, 2, "normal"),   # line passes on strided axes
 ]
 
 
