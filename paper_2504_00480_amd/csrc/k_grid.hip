@@ -259,9 +259,21 @@ k_fold_bins(const WinDesc *__restrict__ wd, const int *__restrict__ fb, T *__res
     if (s1 - s0 < 2) return;
     const int ci = threadIdx.x & 63, slice = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + ci;
+    // four independent partial sums per thread: four loads in flight
     T sum = T(0);
     if (i < pc) {
-        for (int s = s0 + 1 + slice; s < s1; s += 4) sum += tilebuf[((int64_t)s * nrhs + r) * pc + i];
+        const T *src = tilebuf + (int64_t)r * pc + i;
+        const int64_t step = (int64_t)nrhs * pc;
+        T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+        int s = s0 + 1 + slice;
+        for (; s + 12 < s1; s += 16) {
+            a0 += src[(int64_t)s * step];
+            a1 += src[(int64_t)(s + 4) * step];
+            a2 += src[(int64_t)(s + 8) * step];
+            a3 += src[(int64_t)(s + 12) * step];
+        }
+        for (; s < s1; s += 4) a0 += src[(int64_t)s * step];
+        sum = (a0 + a1) + (a2 + a3);
     }
     part[slice][ci] = sum;
     __syncthreads();
@@ -305,10 +317,19 @@ k_fold(const WinDesc *__restrict__ wd, const T *__restrict__ tilebuf, int nrhs, 
         lo[q] = blo < 0 ? 0 : blo;
         hi[q] = bhi > nb - 1 ? nb - 1 : bhi;
     }
-    T sum = T(0);
-    for (int b0 = lo[0]; b0 <= hi[0]; ++b0)
-        for (int b1 = (D > 1 ? lo[1] : 0); b1 <= (D > 1 ? hi[1] : 0); ++b1)
-            for (int b2 = (D > 2 ? lo[2] : 0); b2 <= (D > 2 ? hi[2] : 0); ++b2) {
+    // at most 3 covering tiles per axis (pd <= 3 tb): the loops are unrolled
+    // over 3 with predicates, so all CSR and tile loads are issued together
+    constexpr int K1 = D > 1 ? 3 : 1, K2 = D > 2 ? 3 : 1;
+    int sidx[3 * K1 * K2], lidx[3 * K1 * K2];
+#pragma unroll
+    for (int u0 = 0; u0 < 3; ++u0)
+#pragma unroll
+        for (int u1 = 0; u1 < K1; ++u1)
+#pragma unroll
+            for (int u2 = 0; u2 < K2; ++u2) {
+                const int t = (u0 * K1 + u1) * K2 + u2;
+                const int b0 = lo[0] + u0, b1 = lo[1] + u1, b2 = lo[2] + u2;
+                const bool ok = b0 <= hi[0] && (D < 2 || b1 <= hi[1]) && (D < 3 || b2 <= hi[2]);
                 int bin = b0, li = l[0] - b0 * tb + m;
                 if (D > 1) {
                     bin = bin * nb + b1;
@@ -318,9 +339,15 @@ k_fold(const WinDesc *__restrict__ wd, const T *__restrict__ tilebuf, int nrhs, 
                     bin = bin * nb + b2;
                     li = li * pd + (l[2] - b2 * tb + m);
                 }
-                const int s0 = bsp[bin];
-                if (bsp[bin + 1] > s0) sum += tilebuf[((int64_t)s0 * nrhs + r) * pc + li];
+                int s0 = -1;
+                if (ok && bsp[bin + 1] > bsp[bin]) s0 = bsp[bin];
+                sidx[t] = s0;
+                lidx[t] = li;
             }
+    T sum = T(0);
+#pragma unroll
+    for (int t = 0; t < 3 * K1 * K2; ++t)
+        if (sidx[t] >= 0) sum += tilebuf[((int64_t)sidx[t] * nrhs + r) * pc + lidx[t]];
     typename Cplx<T>::type o;
     o.x = sum;
     o.y = T(0);
@@ -897,6 +924,8 @@ hipError_t fold_t(const Group &G, int m, int nrhs, void *tilebuf, void *grid, hi
 {
     const WindowGeom &g = G.g;
     using C = typename Cplx<T>::type;
+    // k_fold visits at most 3 covering tiles per axis
+    if (g.pd > 3 * g.tb) return hipErrorInvalidValue;
     if (G.nfb > 0)
         k_fold_bins<T><<<dim3((unsigned)((g.pc + 63) / 64), (unsigned)G.nfb, (unsigned)nrhs), 256, 0, s>>>(
             G.desc, G.fb, (T *)tilebuf, g.nbins, nrhs, g.pc);

@@ -215,3 +215,32 @@ def test_profile_category_mask():
     assert plan.profile_read()["spread"][1] == 0
     for o in (out_all, out_one, off):
         assert torch.equal(o, ref)
+
+
+def test_set_hyper_between_applies_without_waits():
+    """Coefficients run on a second stream: back-to-back set_hyper / apply
+    calls with no host wait give exactly the results of a fresh plan."""
+    from paper_2504_00480_amd import AdditiveKernelPlan
+    w = workloads.small(16, 30000, [3, 3, 2], [0, 1, 0], [0.4, 0.6, 0.5], [32, 32, 32], 4, 2)
+    dev = torch.device("cuda:0")
+    X = torch.tensor(w.X, dtype=torch.float32, device=dev)
+    V = torch.tensor(w.V, dtype=torch.float32, device=dev)
+    print(f"[case] set_hyper ordering {w.name}", flush=True)
+    th1 = [0.4, 0.6, 0.5]
+    th2 = [0.9, 0.2, 1.3]
+    plan = AdditiveKernelPlan(X, w.windows, w.ktype, w.N, w.m, max_nrhs=w.nrhs)
+    outs = []
+    for th in (th1, th2, th1, th2):
+        plan.set_hyper(1.3, th, 0.2)
+        o = plan.apply(V)
+        outs.append({k: v.clone() for k, v in o.items()})
+    torch.cuda.synchronize()
+    ref = {}
+    for name, th in (("a", th1), ("b", th2)):
+        p2 = AdditiveKernelPlan(X, w.windows, w.ktype, w.N, w.m, max_nrhs=w.nrhs)
+        p2.set_hyper(1.3, th, 0.2)
+        ref[name] = {k: v.clone() for k, v in p2.apply(V).items()}
+    for o, name in zip(outs, ("a", "b", "a", "b")):
+        for k in o:
+            assert torch.equal(o[k], ref[name][k]), (name, k)
+    assert not torch.equal(ref["a"]["KV"], ref["b"]["KV"])
