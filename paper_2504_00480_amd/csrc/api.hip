@@ -228,20 +228,55 @@ nfftgp_status build_spread_lists(nfftgp_plan plan, Group &G, int sub_sp)
 
 // (Re)build a group's tile-interpolation work list: subproblems of up to
 // 256 * pt points of one tile (pt points per thread).
-nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt)
+nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt, int rows)
 {
+    // 3-D: a subproblem stages only `rows` first-axis rows of the padded tile
+    // (points of first-tap rows f0..f1 read rows f0 .. f1 + 2m - 1, since the
+    // points of a tile are sorted by cell, first axis slowest), so it is cut
+    // where its rows would no longer fit; its first staged row a0 is packed
+    // into bits 24-31 of the tile index
     const int isp = kInterpSubPoints * pt;
+    const WindowGeom &g = G.g;
+    const int m = plan->m;
+    const bool cut = g.d == 3 && rows < g.pd;
+    if (g.d != 3) rows = g.pd;
+    if (rows < 2 * m || rows > g.pd) return fail(NFFTGP_E_ARG, "bad interpolation row count");
     std::vector<int> iw, ib, is, ic;
+    auto push = [&](int wl, int b, int start, int cnt, int f0) {
+        const int a0 = cut ? std::min(f0, g.pd - rows) : 0;
+        iw.push_back(wl);
+        ib.push_back(b | (a0 << 24));
+        is.push_back(start);
+        ic.push_back(cnt);
+    };
     for (int wl = 0; wl < G.nwin; ++wl) {
-        const std::vector<int> &bs = plan->win[G.wins[wl]].h_bin_start;
-        for (int b = 0; b < G.g.nbins; ++b) {
+        const Window &w = plan->win[G.wins[wl]];
+        const std::vector<int> &bs = w.h_bin_start;
+        for (int b = 0; b < g.nbins; ++b) {
             const int cnt = bs[b + 1] - bs[b];
-            for (int off = 0; off < cnt; off += isp) {
-                iw.push_back(wl);
-                ib.push_back(b);
-                is.push_back(bs[b] + off);
-                ic.push_back(std::min(isp, cnt - off));
+            if (cnt == 0) continue;
+            if (!cut) {
+                for (int off = 0; off < cnt; off += isp) push(wl, b, bs[b] + off, std::min(isp, cnt - off), 0);
+                continue;
             }
+            int start = bs[b], k = 0, f0 = 0;   // open subproblem: k points from row f0
+            for (int r = 0; r < g.tb; ++r) {
+                int left = w.h_row_cnt[(size_t)b * g.tb + r];
+                const int f = r + 1;             // first-tap row of the points of cell row r
+                while (left > 0) {
+                    if (k > 0 && (k == isp || f - f0 + 2 * m > rows)) {
+                        push(wl, b, start, k, f0);
+                        start += k;
+                        k = 0;
+                    }
+                    if (k == 0) f0 = f;
+                    const int take = std::min(left, isp - k);
+                    k += take;
+                    left -= take;
+                }
+            }
+            if (k > 0) push(wl, b, start, k, f0);
+            if (start + k != bs[b + 1]) return fail(NFFTGP_E_ARG, "row counts do not match the tile");
         }
     }
     if ((int)iw.size() > G.isub_cap) return fail(NFFTGP_E_ARG, "interpolation list exceeds its capacity");
@@ -252,7 +287,17 @@ nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt)
             NFFTGP_HIP_TRY(hipMemcpy(dst[k], srcv[k]->data(), srcv[k]->size() * sizeof(int), hipMemcpyHostToDevice));
     G.nisub = (int)iw.size();
     G.interp_pt = pt;
+    G.interp_rows = rows;
     return NFFTGP_OK;
+}
+
+// Staged rows of the 3-D tile interpolation by rule: a window of half a tile
+// of first-tap rows plus the taps (tb/2 + 2m - 1; 11 of 16 rows at m = 4),
+// which lets more work-groups share a CU's LDS.
+int interp_rows_rule(const WindowGeom &g, int m)
+{
+    if (g.d != 3) return g.pd;
+    return std::min(g.pd, g.tb / 2 + 2 * m - 1);
 }
 
 }  // namespace
@@ -337,6 +382,12 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         max_keys = std::max(max_keys, std::max(g.nbins, local));
     }
     int64_t hist_len = (int64_t)max_keys * nblk;
+    int64_t rowc_len = 1;   // 3-D windows: points per (tile, first-axis row)
+    for (int s = 0; s < P; ++s) {
+        WindowGeom g = make_geom(win_ptr[s + 1] - win_ptr[s], N[s], m);
+        if (g.d == 3) rowc_len = std::max<int64_t>(rowc_len, (int64_t)g.nbins * g.tb);
+    }
+    int *rowc = nullptr;
     const int64_t n1 = std::max<int64_t>(n, 1);
     TRYH(tmp.get((void **)&part, kPartBlocks * 6 * sizeof(double)));
     TRYH(tmp.get((void **)&mm, 8 * sizeof(double)));
@@ -346,6 +397,7 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
     TRYH(tmp.get((void **)&hist, (hist_len + 1) * sizeof(int)));
     TRYH(tmp.get((void **)&scan_tmp, scan_scratch_ints(hist_len) * sizeof(int)));
     TRYH(tmp.get((void **)&bin_start, (max_keys + 1) * sizeof(int)));
+    TRYH(tmp.get((void **)&rowc, rowc_len * sizeof(int)));
     TRYH(tmp.get(&t_uns, n1 * 3 * eb));
     TRYH(tmp.get(&t1, n1 * 3 * eb));
     TRYH(tmp.get(&t2, n1 * 3 * eb));
@@ -415,6 +467,13 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         TRYH(launch_weights(prec, t2, n, w.g, m, kb_knorm(m), w.rec, w.anchor, w.lpos, st));
         std::vector<int> bs(w.g.nbins + 1);
         TRYH(hipMemcpyAsync(bs.data(), bin_start, (w.g.nbins + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+        if (d == 3 && n > 0) {
+            w.h_row_cnt.assign((size_t)w.g.nbins * w.g.tb, 0);
+            TRYH(hipMemsetAsync(rowc, 0, w.h_row_cnt.size() * sizeof(int), st));
+            TRYH(launch_row_counts(w.anchor, n, w.g, rowc, st));
+            TRYH(hipMemcpyAsync(w.h_row_cnt.data(), rowc, w.h_row_cnt.size() * sizeof(int),
+                                hipMemcpyDeviceToHost, st));
+        }
         TRYH(hipMemcpyAsync(hflags, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
         TRYH(hipStreamSynchronize(st));
         if (hflags[1]) {
@@ -448,6 +507,7 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         G.nwin = (int)G.wins.size();
         std::vector<WinDesc> hd(G.nwin);
         int64_t cap = 0, icap = 0;
+        const bool d3 = G.g.d == 3;
         for (int wl = 0; wl < G.nwin; ++wl) {
             Window &w = plan->win[G.wins[wl]];
             const std::vector<int> &bs = w.h_bin_start;
@@ -455,7 +515,7 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
                 const int cnt = bs[b + 1] - bs[b];
                 G.nbins_used += cnt > 0;
                 cap += (cnt + kMinSubSp - 1) / kMinSubSp;
-                icap += (cnt + kInterpSubPoints - 1) / kInterpSubPoints;
+                icap += (cnt + kInterpSubPoints - 1) / kInterpSubPoints + (d3 && cnt > 0 ? G.g.tb : 0);
             }
             TRYS(dalloc(plan, (void **)&w.bin_sub_ptr, (w.g.nbins + 1) * sizeof(int)));
             hd[wl] = WinDesc{w.rec, w.anchor, w.lpos, w.perm, w.bin_sub_ptr, w.Dk, w.Dder, G.wins[wl], 0};
@@ -474,11 +534,13 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         }
         // interpolation variant: the per-point tile variant by default (the
         // faster one on every measured workload once its tile staging was
-        // batched); nfftgp_autotune may switch, NFFTGP_INTERP=run|tile|tile2
-        // forces (tile2: two points per thread)
+        // batched); nfftgp_autotune may switch, NFFTGP_INTERP=run|tile|tile2|tilefull
+        // forces (tile2: two points per thread; tilefull: whole padded tiles staged)
         const char *iov = std::getenv("NFFTGP_INTERP");
         G.use_run_interp = iov && std::strcmp(iov, "run") == 0 && n > 0;
-        TRYS(build_interp_lists(plan, G, iov && std::strcmp(iov, "tile2") == 0 ? 2 : 1));
+        const bool full = iov && std::strcmp(iov, "tilefull") == 0;
+        TRYS(build_interp_lists(plan, G, iov && std::strcmp(iov, "tile2") == 0 ? 2 : 1,
+                                full ? G.g.pd : interp_rows_rule(G.g, m)));
         {
             // run-interpolation list (built for every group, so that the
             // variant can be switched): points per wave up to kRunSubPoints,
@@ -676,34 +738,47 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
         }
         G.spread_R = best_R;
         if (stt != NFFTGP_OK) break;
-        // 3) interpolation variant: tile with 1 or 2 points per thread, or runs
+        // 3) interpolation variant: tile with 1 or 2 points per thread, whole
+        //    padded tile or the rule's row window (3-D), or runs
         const bool cur_run = G.use_run_interp;
-        const int cur_pt = G.interp_pt;
+        const int cur_pt = G.interp_pt, cur_rows = G.interp_rows;
         bool best_run = cur_run;
-        int best_pt = cur_pt;
-        for (int cand = 0; cand < 3 && stt == NFFTGP_OK; ++cand) {
-            const bool run = cand == 2;
-            const int pt = run ? cur_pt : cand + 1;
-            if (run == cur_run && (run || pt == cur_pt)) continue;
-            G.use_run_interp = run;
-            if (!run && (stt = build_interp_lists(plan, G, pt)) != NFFTGP_OK) break;
+        int best_pt = cur_pt, best_rows = cur_rows;
+        struct Cand { bool run; int pt, rows; };
+        std::vector<Cand> cands;
+        const int rr = interp_rows_rule(G.g, plan->m);
+        for (int pt : {1, 2}) {
+            cands.push_back({false, pt, rr});
+            if (rr != G.g.pd) cands.push_back({false, pt, G.g.pd});
+        }
+        cands.push_back({true, cur_pt, cur_rows});
+        for (const Cand &c : cands) {
+            if (stt != NFFTGP_OK) break;
+            if (c.run == cur_run && (c.run || (c.pt == cur_pt && c.rows == cur_rows))) continue;
+            G.use_run_interp = c.run;
+            if (!c.run && (stt = build_interp_lists(plan, G, c.pt, c.rows)) != NFFTGP_OK) break;
             double t = 0.0;
             if ((stt = timed(t)) != NFFTGP_OK) break;
             if (t < best) {
                 best = t;
-                best_run = run;
-                best_pt = pt;
+                best_run = c.run;
+                best_pt = c.pt;
+                best_rows = c.rows;
             }
         }
         if (stt != NFFTGP_OK) break;
         G.use_run_interp = best_run;
-        if ((stt = build_interp_lists(plan, G, best_pt)) != NFFTGP_OK) break;
-        char line[200];
+        if ((stt = build_interp_lists(plan, G, best_pt, best_rows)) != NFFTGP_OK) break;
+        std::string ivar = "run";
+        if (!G.use_run_interp) {
+            ivar = G.interp_pt == 2 ? "tile, 2 points/thread" : "tile";
+            if (G.g.d == 3) ivar += ", " + std::to_string(G.interp_rows) + " of " + std::to_string(G.g.pd) + " rows";
+        }
+        char line[240];
         std::snprintf(line, sizeof(line), "group d=%d N=%d (%d windows): spread subproblem %d, vectors/group %s, "
                                           "interpolation %s; %.4f ms per apply\n",
                       G.g.d, G.g.N, G.nwin, G.sub_sp,
-                      G.spread_R > 0 ? std::to_string(G.spread_R).c_str() : "rule",
-                      G.use_run_interp ? "run" : (G.interp_pt == 2 ? "tile, 2 points/thread" : "tile"), best);
+                      G.spread_R > 0 ? std::to_string(G.spread_R).c_str() : "rule", ivar.c_str(), best);
         rep += line;
     }
     plan->prof = prof;

@@ -364,7 +364,7 @@ template <typename T, int D, int M, bool DER, int PT>
 __global__ void __launch_bounds__(256)
 k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
          const int *__restrict__ sub_bin, const int *__restrict__ sub_start,
-         const int *__restrict__ sub_count, int tb, int nb, int ng, int nwin,
+         const int *__restrict__ sub_count, int tb, int nb, int ng, int nwin, int rows,
          const typename Cplx<T>::type *__restrict__ grid, int64_t cells, int nrhs, int64_t n,
          T *__restrict__ hbuf, T *__restrict__ dout, T dscale)
 {
@@ -385,8 +385,12 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     const WinDesc &win = wd[wi];
     const T *rec = reinterpret_cast<const T *>(win.rec);
     const int start = sub_start[sq], cnt = sub_count[sq];
+    // 3-D: only first-axis rows a0 .. a0 + rows - 1 of the padded tile are
+    // staged (a0 in bits 24-31 of the tile index)
     int org[3] = {0, 0, 0};
-    bin_origin<D>(sub_bin[sq], nb, tb, org);
+    const int bw = sub_bin[sq];
+    const int a0 = D == 3 ? (bw >> 24) : 0;
+    bin_origin<D>(bw & 0xffffff, nb, tb, org);
     // PT points per thread (thread t takes points t, t + 256, ...): weights
     // and first-tap positions in registers for all vectors; for d = 3 the
     // first dimension's weights are re-read inside its (rolled) loop so that
@@ -406,7 +410,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
         for (int q = (D == 3 ? 1 : 0); q < D; ++q)
 #pragma unroll
             for (int a = 0; a < TW; ++a) w[p][q][a] = rp[p][q * TW + a];
-        lin[p] = win.lpos[j] & 0xfffff;   // first tap inside the padded tile
+        lin[p] = (win.lpos[j] & 0xfffff) - a0 * pd * pd * (D == 3);   // first tap inside the staged rows
         orow[p] = (int64_t)win.perm[j] * nrhs;
     }
     T *hout = hbuf + (int64_t)win.s_global * n * nrhs;
@@ -448,12 +452,12 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             // SA planes per batch: all loads of a batch in flight before the
             // first LDS store
             constexpr int SA = NS == 1 ? 8 : (NS == 2 ? 4 : 2);
-            for (int a0 = 0; a0 < pd; a0 += SA) {
+            for (int ab = 0; ab < rows; ab += SA) {
                 T vK[SA][NS], vD[SA][NS];
 #pragma unroll
                 for (int aa = 0; aa < SA; ++aa) {
-                    const int la = org[0] - M + a0 + aa;
-                    const bool ina = a0 + aa < pd && la >= 0 && la < ng;
+                    const int la = org[0] - M + a0 + ab + aa;
+                    const bool ina = ab + aa < rows && la >= 0 && la < ng;
                     const int64_t pl = (int64_t)(ina ? la : 0) * ng * ng;
 #pragma unroll
                     for (int j = 0; j < NS; ++j) {
@@ -467,8 +471,8 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
 #pragma unroll
                     for (int j = 0; j < NS; ++j) {
                         const int q = (int)threadIdx.x + 256 * j;
-                        if (a0 + aa < pd && q < pd2) {
-                            const int i = (a0 + aa) * pd2 + q;
+                        if (ab + aa < rows && q < pd2) {
+                            const int i = (ab + aa) * pd2 + q;
                             if constexpr (DER) {
                                 C v;
                                 v.x = vK[aa][j];
@@ -866,16 +870,19 @@ hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool
                 nrhs, n, (T *)hbuf, nullptr, (T)dscale);
         return hipGetLastError();
     }
-    // the 3-D staging covers a padded plane of at most (8 + 2m)^2 cells
-    if (D == 3 && g.pd > 8 + 2 * M) return hipErrorInvalidValue;
-    size_t shm = (size_t)g.pc * sizeof(T) * (with_der ? 2 : 1);
+    // the 3-D staging covers a padded plane of at most (8 + 2m)^2 cells and
+    // rows <= pd first-axis rows of it
+    const int rows = D == 3 ? G.interp_rows : g.pd;
+    if (D == 3 && (g.pd > 8 + 2 * M || rows < 2 * M || rows > g.pd)) return hipErrorInvalidValue;
+    const size_t cells_staged = D == 3 ? (size_t)rows * g.pd * g.pd : (size_t)g.pc;
+    size_t shm = cells_staged * sizeof(T) * (with_der ? 2 : 1);
     auto go = [&](auto der_tag, auto pt_tag) -> hipError_t {
         constexpr bool DR = decltype(der_tag)::value;
         constexpr int PT = decltype(pt_tag)::value;
         hipError_t e = allow_lds(k_interp<T, D, M, DR, PT>, shm);
         if (e != hipSuccess) return e;
         k_interp<T, D, M, DR, PT><<<(unsigned)G.nisub, 256, shm, s>>>(
-            G.desc, G.isub_win, G.isub_bin, G.isub_start, G.isub_count, g.tb, g.nb, g.ng, G.nwin,
+            G.desc, G.isub_win, G.isub_bin, G.isub_start, G.isub_count, g.tb, g.nb, g.ng, G.nwin, rows,
             (const C *)grid, g.cells, nrhs, n, (T *)hbuf, DR ? (T *)dout : nullptr, (T)dscale);
         return hipGetLastError();
     };

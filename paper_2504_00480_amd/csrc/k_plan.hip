@@ -140,6 +140,19 @@ k_weights(const T *__restrict__ t, int64_t n, int d, int m, int ng, int tb, int 
     lpos[i] = lin | (l0 << 20);
 }
 
+// counts[tile * tb + row] += 1 for every point, row = first cell coordinate
+// inside the tile (3-D).
+__global__ void __launch_bounds__(256)
+k_row_counts(const int *__restrict__ anchor, int64_t n, int ng, int tb, int nb, int *__restrict__ counts)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a = anchor[i] & 0x7fffffff;
+    const int c2 = a % ng, c1 = (a / ng) % ng, c0 = a / (ng * ng);
+    const int bin = ((c0 / tb) * nb + c1 / tb) * nb + c2 / tb;
+    atomicAdd(&counts[bin * tb + c0 % tb], 1);
+}
+
 __global__ void __launch_bounds__(256)
 k_run_ends(int *__restrict__ anchor, int *__restrict__ lpos, int64_t n)
 {
@@ -350,6 +363,14 @@ hipError_t launch_bin_keys(int prec, const void *t, int64_t n, const WindowGeom 
         k_bin_keys<float><<<nblk, 256, 0, s>>>((const float *)t, n, g.d, g.ng, g.tb, g.nb, keys);
     else
         k_bin_keys<double><<<nblk, 256, 0, s>>>((const double *)t, n, g.d, g.ng, g.tb, g.nb, keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_counts(const int *anchor, int64_t n, const WindowGeom &g, int *counts,
+                             hipStream_t s)
+{
+    if (n == 0 || g.d != 3) return hipSuccess;
+    k_row_counts<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(anchor, n, g.ng, g.tb, g.nb, counts);
     return hipGetLastError();
 }
 

@@ -59,6 +59,7 @@ struct Window {
     void *Dder = nullptr;   // same for K_s^der
     // host copies used while the plan is built
     std::vector<int> h_bin_start;   // tile -> first sorted point (kept for re-tuning)
+    std::vector<int> h_row_cnt;     // 3-D: points per (tile, first-axis cell row), nbins x tb
 };
 
 // Per-window data a kernel needs, in device memory (one array per group).
@@ -91,6 +92,7 @@ struct Group {
     int spread_R = 0;            // vectors per spreading work-group (0: rule)
     int sub_cap = 0;             // capacity of the spreading list arrays
     int interp_pt = 1;           // points per thread of the tile interpolation (1, 2)
+    int interp_rows = 0;         // 3-D: first-axis rows of the padded tile staged per subproblem
     int isub_cap = 0;            // capacity of the interpolation list arrays
     int32_t *fb = nullptr;       // tiles split into several subproblems (window * nbins + tile)
     int nfb = 0;
@@ -193,6 +195,10 @@ hipError_t launch_bin_keys(int prec, const void *t, int64_t n, const WindowGeom 
 double kb_knorm(int m);
 hipError_t launch_weights(int prec, const void *t, int64_t n, const WindowGeom &g, int m,
                           double knorm, void *rec, int *anchor, int *lpos, hipStream_t s);
+// Points per (tile, first-axis cell row of the tile) of a 3-D window, from the
+// packed cells; counts (nbins x tb ints) must be zero on entry.
+hipError_t launch_row_counts(const int *anchor, int64_t n, const WindowGeom &g, int *counts,
+                             hipStream_t s);
 
 // ---------------------------------------------------------------- per-theta kernels
 // Coefficients b_k, b^der_k of one window (FP64) and the symmetrised diagonals.

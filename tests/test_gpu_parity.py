@@ -69,7 +69,7 @@ SMALL = [
 ]
 
 
-@pytest.mark.parametrize("interp", ["tile", "tile2", "run"])
+@pytest.mark.parametrize("interp", ["tile", "tile2", "tilefull", "run"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("case", SMALL, ids=[f"case{c[0]}" for c in SMALL])
 def test_small_parity(orc, case, prec, interp, monkeypatch):
@@ -149,7 +149,7 @@ def test_interp_variants_agree(prec, monkeypatch):
     X = torch.tensor(w.X, dtype=dt, device="cuda:0")
     V = torch.tensor(w.V, dtype=dt, device="cuda:0")
     outs = []
-    for mode in ("tile", "tile2", "run"):
+    for mode in ("tile", "tile2", "tilefull", "run"):
         monkeypatch.setenv("NFFTGP_INTERP", mode)
         plan = AdditiveKernelPlan(X, w.windows, w.ktype, w.N, w.m, max_nrhs=2)
         plan.set_hyper(1.3, w.ell, 0.2)
