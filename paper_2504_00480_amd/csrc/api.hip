@@ -536,6 +536,8 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         // faster one on every measured workload once its tile staging was
         // batched); nfftgp_autotune may switch, NFFTGP_INTERP=run|tile|tile2|tilefull
         // forces (tile2: two points per thread; tilefull: whole padded tiles staged)
+        const char *swv = std::getenv("NFFTGP_SPREAD_W");   // "2": two waves per 3-D tile
+        G.spread_W = swv && std::strcmp(swv, "2") == 0 ? 2 : 0;
         const char *iov = std::getenv("NFFTGP_INTERP");
         G.use_run_interp = iov && std::strcmp(iov, "run") == 0 && n > 0;
         const bool full = iov && std::strcmp(iov, "tilefull") == 0;
@@ -738,6 +740,17 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
         }
         G.spread_R = best_R;
         if (stt != NFFTGP_OK) break;
+        // 2b) 3-D: waves sharing a spreading tile (4 by rule, or 2)
+        if (G.g.d == 3) {
+            const int cur_W = G.spread_W;
+            G.spread_W = cur_W == 2 ? 0 : 2;
+            double t = 0.0;
+            if ((stt = timed(t)) != NFFTGP_OK) break;
+            if (t < best)
+                best = t;
+            else
+                G.spread_W = cur_W;
+        }
         // 3) interpolation variant: tile with 1 or 2 points per thread, whole
         //    padded tile or the rule's row window (3-D), or runs
         const bool cur_run = G.use_run_interp;
@@ -775,10 +788,11 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
             if (G.g.d == 3) ivar += ", " + std::to_string(G.interp_rows) + " of " + std::to_string(G.g.pd) + " rows";
         }
         char line[240];
-        std::snprintf(line, sizeof(line), "group d=%d N=%d (%d windows): spread subproblem %d, vectors/group %s, "
+        std::snprintf(line, sizeof(line), "group d=%d N=%d (%d windows): spread subproblem %d, vectors/group %s%s, "
                                           "interpolation %s; %.4f ms per apply\n",
                       G.g.d, G.g.N, G.nwin, G.sub_sp,
-                      G.spread_R > 0 ? std::to_string(G.spread_R).c_str() : "rule", ivar.c_str(), best);
+                      G.spread_R > 0 ? std::to_string(G.spread_R).c_str() : "rule",
+                      G.spread_W == 2 ? ", 2 waves/tile" : "", ivar.c_str(), best);
         rep += line;
     }
     plan->prof = prof;

@@ -837,7 +837,6 @@ hipError_t spread_dm(const Group &G, const void *V, int64_t ldv, int nrhs, void 
     // work-group share the points' weights; R tiles must fit in 64 KiB, and
     // R = 4 is taken only when it leaves no partial group of vectors (measured:
     // 32 vectors 4 > 2 > 1, 17 vectors 2 > 1 > 4, 16 vectors of m = 6: 2 > 1)
-    constexpr int W = D == 3 ? 4 : 1;
     const size_t tile = (size_t)G.g.pc * sizeof(T);
     int R = 1;
     if (G.spread_R > 0) {
@@ -848,9 +847,19 @@ hipError_t spread_dm(const Group &G, const void *V, int64_t ldv, int nrhs, void 
     } else if (nrhs >= 2 && 2 * tile <= 64 * 1024) {
         R = 2;
     }
-    if (R == 4) return spread_launch<T, D, M, 4, W>(G, V, ldv, nrhs, tilebuf, s);
-    if (R == 2) return spread_launch<T, D, M, 2, W>(G, V, ldv, nrhs, tilebuf, s);
-    return spread_launch<T, D, M, 1, W>(G, V, ldv, nrhs, tilebuf, s);
+    // waves sharing a tile: 4 for d = 3 unless the group asks for 2
+    auto go = [&](auto w_tag) -> hipError_t {
+        constexpr int W = decltype(w_tag)::value;
+        if (R == 4) return spread_launch<T, D, M, 4, W>(G, V, ldv, nrhs, tilebuf, s);
+        if (R == 2) return spread_launch<T, D, M, 2, W>(G, V, ldv, nrhs, tilebuf, s);
+        return spread_launch<T, D, M, 1, W>(G, V, ldv, nrhs, tilebuf, s);
+    };
+    if constexpr (D == 3) {
+        if (G.spread_W == 2) return go(std::integral_constant<int, 2>());
+        return go(std::integral_constant<int, 4>());
+    } else {
+        return go(std::integral_constant<int, 1>());
+    }
 }
 
 template <typename T, int D, int M>

@@ -90,6 +90,7 @@ struct Group {
     // tunables (rule defaults at plan creation; nfftgp_autotune may change them)
     int sub_sp = 0;              // points per spreading subproblem
     int spread_R = 0;            // vectors per spreading work-group (0: rule)
+    int spread_W = 0;            // 3-D: waves sharing a spreading tile (0: rule, 4; or 2)
     int sub_cap = 0;             // capacity of the spreading list arrays
     int interp_pt = 1;           // points per thread of the tile interpolation (1, 2)
     int interp_rows = 0;         // 3-D: first-axis rows of the padded tile staged per subproblem
