@@ -538,6 +538,8 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         // forces (tile2: two points per thread; tilefull: whole padded tiles staged)
         const char *swv = std::getenv("NFFTGP_SPREAD_W");   // "2": two waves per 3-D tile
         G.spread_W = swv && std::strcmp(swv, "2") == 0 ? 2 : 0;
+        const char *sfv = std::getenv("NFFTGP_SPREAD_FORM");   // "quad" | "run"
+        G.spread_form = !sfv ? 0 : (std::strcmp(sfv, "quad") == 0 ? 1 : (std::strcmp(sfv, "run") == 0 ? 2 : 0));
         const char *iov = std::getenv("NFFTGP_INTERP");
         G.use_run_interp = iov && std::strcmp(iov, "run") == 0 && n > 0;
         const bool full = iov && std::strcmp(iov, "tilefull") == 0;
@@ -740,6 +742,22 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
         }
         G.spread_R = best_R;
         if (stt != NFFTGP_OK) break;
+        // 2a) spreading form: the one the rule did not take
+        {
+            const int cur_F = G.spread_form;
+            G.spread_form = 1;
+            double t1 = 0.0, t2 = 0.0;
+            if ((stt = timed(t1)) != NFFTGP_OK) break;
+            G.spread_form = 2;
+            if ((stt = timed(t2)) != NFFTGP_OK) break;
+            const double tb_ = std::min(t1, t2);
+            if (tb_ < best) {
+                best = tb_;
+                G.spread_form = t1 <= t2 ? 1 : 2;
+            } else {
+                G.spread_form = cur_F;
+            }
+        }
         // 2b) 3-D: waves sharing a spreading tile (4 by rule, or 2)
         if (G.g.d == 3) {
             const int cur_W = G.spread_W;
@@ -792,7 +810,9 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
                                           "interpolation %s; %.4f ms per apply\n",
                       G.g.d, G.g.N, G.nwin, G.sub_sp,
                       G.spread_R > 0 ? std::to_string(G.spread_R).c_str() : "rule",
-                      G.spread_W == 2 ? ", 2 waves/tile" : "", ivar.c_str(), best);
+                      (std::string(G.spread_form == 1 ? ", four-point form" : (G.spread_form == 2 ? ", run form" : "")) +
+                       (G.spread_W == 2 ? ", 2 waves/tile" : "")).c_str(),
+                      ivar.c_str(), best);
         rep += line;
     }
     plan->prof = prof;

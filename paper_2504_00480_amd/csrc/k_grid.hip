@@ -51,13 +51,226 @@ __device__ __forceinline__ void bin_origin(int bin, int nb, int tb, int *org)
 // position in the padded tile is w modulo W, so no two waves ever touch the
 // same cell.  Within a flush every lane touches a distinct cell and the
 // flushes of one wave are ordered, so the tile is updated with plain loads and
-// stores and the result does not depend on scheduling.  The points' weights,
-// tile positions and vector values are staged in LDS in chunks of 64 with
-// coalesced loads; the run boundaries of a chunk come from one ballot over its
-// run-end flags, so the per-point loop has no branches.
+// stores and the result does not depend on scheduling.
+//
+// The points' weights and vector values are staged in LDS in chunks of 64,
+// transposed (tap-major, point-minor), so one 16-byte read gives a value for
+// four consecutive points; the first-dimension weights of a 3-D point are
+// stored rotated by its tile position (slot (L + a) mod 2m for tap a), so
+// wave w finds its taps in the fixed slots w, w + W, ... for every point.  Points are taken four at a time whatever the run boundaries
+// (one ballot over the run-end flags of the chunk gives them); the reads of
+// the next four are issued before the current four are accumulated and their
+// runs flushed.
 template <typename T, int D, int M, int R, int W>
 __global__ void __launch_bounds__(64 * W)
 k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
+         const int *__restrict__ sub_start, const int *__restrict__ sub_count,
+         const T *__restrict__ V, int64_t ldv, int nrhs, int pd, T *__restrict__ tilebuf)
+{
+    constexpr int TW = 2 * M;
+    constexpr int RS = D * TW;                                  // weights per point
+    constexpr int NITEM = D == 1 ? TW : TW * TW;                // lane work items
+    constexpr int NG = (NITEM + 63) / 64;
+    static_assert(D == 3 || W == 1, "tap splitting across waves is for d = 3");
+    static_assert(TW % W == 0, "waves must divide the taps");
+    constexpr int NA = D == 3 ? TW / W : 1;                     // registers per item
+    constexpr int CH = 64;                                      // points staged per chunk
+    constexpr int CP = CH + 4;                                  // row pitch (conflict-free 16-byte reads)
+    constexpr int NQ = D == 3 ? 3 : D;                          // staged weight rows of TW
+    using T4 = typename std::conditional<sizeof(T) == 4, float4, double4>::type;
+    // rows: [0, TW) first-dimension taps rotated (d = 3: residue rho * NA + k),
+    // then the (b) and (c) taps; vector values after them
+    __shared__ __align__(16) T s_w[NQ * TW * CP];
+    __shared__ __align__(16) T s_v[R * CP];
+    __shared__ int s_lp[CH];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *tiles = reinterpret_cast<T *>(smem_raw);
+    int pc = pd;
+    for (int q = 1; q < D; ++q) pc *= pd;
+    const int sq = xcd_item(blockIdx.x, gridDim.x), r0 = blockIdx.y * R;
+    const WinDesc &win = wd[sub_win[sq]];
+    const T *rec = reinterpret_cast<const T *>(win.rec);
+    const int *lpos = win.lpos;
+    const int *perm = win.perm;
+    const int start = sub_start[sq], cnt = sub_count[sq];
+    const int end = start + cnt;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < R * pc; i += 64 * W) tiles[i] = T(0);
+    // per lane: item indices and the item's offset inside the padded tile
+    int i0[NG], i1[NG], off[NG];
+    bool act[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const int it = lane + 64 * g;
+        act[g] = it < NITEM;
+        const int itc = act[g] ? it : 0;
+        i0[g] = D == 1 ? itc : itc / TW;
+        i1[g] = D == 1 ? 0 : itc % TW;
+        off[g] = D == 3 ? i0[g] * pd + i1[g] : (D == 2 ? i0[g] * pd + i1[g] : i0[g]);
+    }
+    const int pd2 = D == 3 ? pd * pd : 0;
+    T acc[NG][NA][R];
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int k = 0; k < NA; ++k)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[g][k][r] = T(0);
+    const int nr = min(R, nrhs - r0);
+    // the next chunk's global data is loaded into registers while the current
+    // chunk is processed
+    constexpr int NT = 64 * W;
+    constexpr int NREC = (CH * RS + NT - 1) / NT, NV = (CH * R + NT - 1) / NT;
+    T g_rec[NREC], g_v[NV];
+    int g_lp = 0;
+    auto fetch = [&](int cb) {
+        const int nc = min(CH, end - cb);
+#pragma unroll
+        for (int k = 0; k < NREC; ++k) {
+            const int i = tid + k * NT;
+            const bool in = i < nc * RS;
+            g_rec[k] = in ? rec[(int64_t)cb * RS + i] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const int i = tid + k * NT;
+            const int u = i / R, r = i % R;
+            g_v[k] = (i < nc * R && r < nr) ? V[(int64_t)perm[cb + u] * ldv + r0 + r] : T(0);
+        }
+        g_lp = tid < nc ? lpos[cb + tid] : 0;
+    };
+    if (cnt > 0) fetch(start);
+    for (int cb = start; cb < end; cb += CH) {
+        const int nc = min(CH, end - cb);
+        __syncthreads();   // tiles cleared / previous chunk consumed
+#pragma unroll
+        for (int k = 0; k < NREC; ++k) {
+            const int i = tid + k * NT;
+            if (i < CH * RS) {
+                const int u = i / RS, e = i % RS;   // weight slot e of point u -> row e
+                s_w[e * CP + u] = g_rec[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const int i = tid + k * NT;
+            if (i < CH * R) s_v[(i % R) * CP + i / R] = g_v[k];
+        }
+        if (tid < CH) s_lp[tid] = g_lp;
+        __syncthreads();
+        if (cb + CH < end) fetch(cb + CH);
+        // lane u keeps point u's tile position; run ends of the chunk (the
+        // subproblem's last point ends a run)
+        const int my_lp = lane < nc ? s_lp[lane] : 0;
+        const bool isend = lane < nc && (my_lp < 0 || cb + lane == end - 1);
+        const unsigned long long ends = __ballot(isend);
+        // values of four points u .. u + 3 (16-byte reads)
+        struct Grp {
+            T w0[NA][4], wa[NG][4], wb[NG][4], v[R][4];
+        };
+        auto load = [&](Grp &G4, int u) {
+#pragma unroll
+            for (int k = 0; k < NA; ++k) {
+                if (D == 3) {
+                    const T4 x = *reinterpret_cast<const T4 *>(s_w + (wave + k * W) * CP + u);
+                    G4.w0[k][0] = x.x; G4.w0[k][1] = x.y; G4.w0[k][2] = x.z; G4.w0[k][3] = x.w;
+                } else {
+                    G4.w0[k][0] = G4.w0[k][1] = G4.w0[k][2] = G4.w0[k][3] = T(1);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                // d = 3: rows TW + b and 2 TW + c; d = 2: rows a and TW + b; d = 1: row a
+                const int ra = (D == 3 ? TW : 0) + i0[g];
+                const T4 x = *reinterpret_cast<const T4 *>(s_w + ra * CP + u);
+                G4.wa[g][0] = x.x; G4.wa[g][1] = x.y; G4.wa[g][2] = x.z; G4.wa[g][3] = x.w;
+                if (D > 1) {
+                    const int rb = (D == 3 ? 2 * TW : TW) + i1[g];
+                    const T4 y = *reinterpret_cast<const T4 *>(s_w + rb * CP + u);
+                    G4.wb[g][0] = y.x; G4.wb[g][1] = y.y; G4.wb[g][2] = y.z; G4.wb[g][3] = y.w;
+                } else {
+                    G4.wb[g][0] = G4.wb[g][1] = G4.wb[g][2] = G4.wb[g][3] = T(1);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const T4 x = *reinterpret_cast<const T4 *>(s_v + r * CP + u);
+                G4.v[r][0] = x.x; G4.v[r][1] = x.y; G4.v[r][2] = x.z; G4.v[r][3] = x.w;
+            }
+        };
+        Grp cur, nxt;
+        load(cur, 0);
+        for (int u = 0; u < nc; u += 4) {
+            if (u + 4 < nc) load(nxt, u + 4);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                if (u + p < nc) {
+#pragma unroll
+                    for (int g = 0; g < NG; ++g) {
+                        const T wbc = cur.wa[g][p] * cur.wb[g][p];
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const T z = wbc * cur.v[r][p];
+#pragma unroll
+                            for (int k = 0; k < NA; ++k) acc[g][k][r] += cur.w0[k][p] * z;
+                        }
+                    }
+                    if ((ends >> (u + p)) & 1ull) {
+                        // flush the run: all reads first (distinct cells), then
+                        // the writes
+                        // register k holds slot w + kW, i.e. tap (w + kW - L) mod 2m
+                        const int lp = __builtin_amdgcn_readlane(my_lp, u + p) & 0x7fffffff;
+                        const int base = lp & 0xfffff, L = lp >> 20;
+                        int koff[NA];
+#pragma unroll
+                        for (int k = 0; k < NA; ++k)
+                            koff[k] = D == 3 ? (((wave + k * W - L) % TW + TW) % TW) * pd2 : 0;
+                        T old[NG][NA][R];
+#pragma unroll
+                        for (int g = 0; g < NG; ++g)
+#pragma unroll
+                            for (int k = 0; k < NA; ++k)
+#pragma unroll
+                                for (int r = 0; r < R; ++r)
+                                    old[g][k][r] = act[g] ? tiles[r * pc + base + koff[k] + off[g]] : T(0);
+#pragma unroll
+                        for (int g = 0; g < NG; ++g) {
+                            if (act[g]) {
+#pragma unroll
+                                for (int k = 0; k < NA; ++k) {
+                                    const int idx = base + koff[k] + off[g];
+#pragma unroll
+                                    for (int r = 0; r < R; ++r) tiles[r * pc + idx] = old[g][k][r] + acc[g][k][r];
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int g = 0; g < NG; ++g)
+#pragma unroll
+                            for (int k = 0; k < NA; ++k)
+#pragma unroll
+                                for (int r = 0; r < R; ++r) acc[g][k][r] = T(0);
+                    }
+                }
+            }
+            cur = nxt;
+        }
+    }
+    __syncthreads();
+    for (int r = 0; r < nr; ++r) {
+        T *out = tilebuf + ((int64_t)sq * nrhs + r0 + r) * pc;
+        for (int i = tid; i < pc; i += 64 * W) out[i] = tiles[r * pc + i];
+    }
+}
+
+// Run-ordered form of the same spreading (selectable per window group): the
+// points' weights are staged point-major, and each run of equal cells is
+// accumulated in groups of four points inside the run, then flushed.  It holds
+// fewer registers than the four-point form above, which pays off when a
+// work-group carries several vectors and runs are long.
+template <typename T, int D, int M, int R, int W>
+__global__ void __launch_bounds__(64 * W)
+k_spread_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
          const int *__restrict__ sub_start, const int *__restrict__ sub_count,
          const T *__restrict__ V, int64_t ldv, int nrhs, int pd, T *__restrict__ tilebuf)
 {
@@ -155,8 +368,6 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             const bool flush = rest != 0ull;
             const int u1 = flush ? u0 + (int)__builtin_ctzll(rest) : nc - 1;
             const int lp = __builtin_amdgcn_readlane(my_lp, u0) & 0x7fffffff;
-            // first owned tap along dimension 0 (tile position = wave mod W)
-            const int aoff = D == 3 ? ((wave - (lp >> 20)) % W + W) % W : 0;
             // points are accumulated in groups of 4 while the run has that many
             // left, then one by one: the LDS reads of a group are issued
             // together, so one wait covers the group
@@ -169,7 +380,7 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
 #pragma unroll
                     for (int r = 0; r < R; ++r) v[p][r] = s_v[(u + p) * R + r];
 #pragma unroll
-                    for (int k = 0; k < NA; ++k) w0[p][k] = D == 3 ? rp[aoff + k * W] : T(1);
+                    for (int k = 0; k < NA; ++k) w0[p][k] = D == 3 ? rp[wave + k * W] : T(1);
 #pragma unroll
                     for (int g = 0; g < NG; ++g) {
                         if (D == 3) {
@@ -204,7 +415,11 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             if (flush) {
                 // all reads of the flush first (distinct cells), then the
                 // writes: one LDS wait per run
-                const int base = (lp & 0xfffff) + (D == 3 ? aoff * pd2 : 0);
+                // register k holds slot w + kW, i.e. tap (w + kW - L) mod 2m
+                const int base = lp & 0xfffff, L = lp >> 20;
+                int koff[NA];
+#pragma unroll
+                for (int k = 0; k < NA; ++k) koff[k] = D == 3 ? (((wave + k * W - L) % TW + TW) % TW) * pd2 : 0;
                 T old[NG][NA][R];
 #pragma unroll
                 for (int g = 0; g < NG; ++g)
@@ -212,14 +427,13 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                     for (int k = 0; k < NA; ++k)
 #pragma unroll
                         for (int r = 0; r < R; ++r)
-                            old[g][k][r] = act[g] ? tiles[r * pc + base + (D == 3 ? k * W * pd2 : 0) + off[g]]
-                                                  : T(0);
+                            old[g][k][r] = act[g] ? tiles[r * pc + base + koff[k] + off[g]] : T(0);
 #pragma unroll
                 for (int g = 0; g < NG; ++g) {
                     if (act[g]) {
 #pragma unroll
                         for (int k = 0; k < NA; ++k) {
-                            const int idx = base + (D == 3 ? k * W * pd2 : 0) + off[g];
+                            const int idx = base + koff[k] + off[g];
 #pragma unroll
                             for (int r = 0; r < R; ++r) tiles[r * pc + idx] = old[g][k][r] + acc[g][k][r];
                         }
@@ -398,7 +612,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     bool mine[PT];
     const T *rp[PT];
     T w[PT][D][TW];
-    int lin[PT];
+    int lin[PT], f0[PT];
     int64_t orow[PT];
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
@@ -410,7 +624,9 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
         for (int q = (D == 3 ? 1 : 0); q < D; ++q)
 #pragma unroll
             for (int a = 0; a < TW; ++a) w[p][q][a] = rp[p][q * TW + a];
-        lin[p] = (win.lpos[j] & 0xfffff) - a0 * pd * pd * (D == 3);   // first tap inside the staged rows
+        const int lpj = win.lpos[j];
+        lin[p] = (lpj & 0xfffff) - a0 * pd * pd * (D == 3);   // first tap inside the staged rows
+        f0[p] = (lpj >> 20) & 0x7f;                         // first-dimension weights sit rotated by it
         orow[p] = (int64_t)win.perm[j] * nrhs;
     }
     T *hout = hbuf + (int64_t)win.s_global * n * nrhs;
@@ -547,7 +763,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             } else {
 #pragma unroll 1
                 for (int aa = 0; aa < TW; ++aa) {
-                    const T w0 = rp[p][aa];
+                    const T w0 = rp[p][(f0[p] + aa) % TW];
                     T sK = T(0), sD = T(0);
 #pragma unroll
                     for (int bb = 0; bb < TW; ++bb) {
@@ -626,7 +842,7 @@ __device__ __forceinline__ double row_sum(double v)
 template <typename T, int D, int M, bool DER>
 __global__ void __launch_bounds__(64)
 k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
-             const int *__restrict__ sub_start, const int *__restrict__ sub_count, int ng, int nwin,
+             const int *__restrict__ sub_start, const int *__restrict__ sub_count, int ng, int tb, int nwin,
              const typename Cplx<T>::type *__restrict__ grid, int64_t cells, int nrhs, int64_t n,
              T *__restrict__ hbuf, T *__restrict__ dout, T dscale)
 {
@@ -692,7 +908,7 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             const typename Cplx<T>::type *gD =
                 DER ? grid + ((int64_t)(nwin + wi) * nrhs + r) * cells : gK;
             T G[NG][NA], GD[NG][NA], GL[QA], GDL[QA];
-            int cur = -1;
+            int cur = -1, fr = 0;   // fr: first tap's tile position (first-dimension weights sit rotated by it)
             for (int u = 0; u < nc; ++u) {
                 const int an = s_an[u];
                 if (an != cur) {
@@ -702,6 +918,7 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                         c[q] = cell % ng - M + 1;
                         cell /= ng;
                     }
+                    fr = (c[0] + M - 1) % tb + 1;
                     if (SPLIT) {
 #pragma unroll
                         for (int k = 0; k < QA; ++k) {
@@ -728,7 +945,7 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                     T sk = T(0), sd = T(0);
 #pragma unroll
                     for (int k = 0; k < QA; ++k) {
-                        const T w0 = rp[qL * QA + k];
+                        const T w0 = rp[(fr + qL * QA + k) % TW];
                         sk += w0 * GL[k];
                         if (DER) sd += w0 * GDL[k];
                     }
@@ -742,7 +959,7 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                         T sk = T(0), sd = T(0);
 #pragma unroll
                         for (int a = 0; a < NA; ++a) {
-                            const T w0 = rp[a];
+                            const T w0 = rp[(fr + a) % TW];
                             sk += w0 * G[g][a];
                             if (DER) sd += w0 * GD[g][a];
                         }
@@ -821,11 +1038,22 @@ hipError_t spread_launch(const Group &G, const void *V, int64_t ldv, int nrhs, v
 {
     const WindowGeom &g = G.g;
     const size_t shm = (size_t)g.pc * sizeof(T) * R;
-    hipError_t e = allow_lds(k_spread<T, D, M, R, W>, shm);
-    if (e != hipSuccess) return e;
     dim3 grid((unsigned)G.nsub, (unsigned)((nrhs + R - 1) / R));
-    k_spread<T, D, M, R, W><<<grid, 64 * W, shm, s>>>(G.desc, G.sub_win, G.sub_start, G.sub_count,
-                                                        (const T *)V, ldv, nrhs, g.pd, (T *)tilebuf);
+    // four-point form for one vector per work-group unless the group asks
+    // for the run-ordered form (spread_form: 0 rule, 1 four-point, 2 runs)
+    const bool quad = G.spread_form == 1 || (G.spread_form == 0 && R == 1);
+    hipError_t e;
+    if (quad) {
+        e = allow_lds(k_spread<T, D, M, R, W>, shm);
+        if (e != hipSuccess) return e;
+        k_spread<T, D, M, R, W><<<grid, 64 * W, shm, s>>>(G.desc, G.sub_win, G.sub_start, G.sub_count,
+                                                            (const T *)V, ldv, nrhs, g.pd, (T *)tilebuf);
+    } else {
+        e = allow_lds(k_spread_run<T, D, M, R, W>, shm);
+        if (e != hipSuccess) return e;
+        k_spread_run<T, D, M, R, W><<<grid, 64 * W, shm, s>>>(G.desc, G.sub_win, G.sub_start, G.sub_count,
+                                                                (const T *)V, ldv, nrhs, g.pd, (T *)tilebuf);
+    }
     return hipGetLastError();
 }
 
@@ -871,11 +1099,11 @@ hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool
     if (G.use_run_interp) {
         if (with_der)
             k_interp_run<T, D, M, true><<<(unsigned)G.nrsub, 64, 0, s>>>(
-                G.desc, G.rsub_win, G.rsub_start, G.rsub_count, g.ng, G.nwin, (const C *)grid, g.cells,
+                G.desc, G.rsub_win, G.rsub_start, G.rsub_count, g.ng, g.tb, G.nwin, (const C *)grid, g.cells,
                 nrhs, n, (T *)hbuf, (T *)dout, (T)dscale);
         else
             k_interp_run<T, D, M, false><<<(unsigned)G.nrsub, 64, 0, s>>>(
-                G.desc, G.rsub_win, G.rsub_start, G.rsub_count, g.ng, G.nwin, (const C *)grid, g.cells,
+                G.desc, G.rsub_win, G.rsub_start, G.rsub_count, g.ng, g.tb, G.nwin, (const C *)grid, g.cells,
                 nrhs, n, (T *)hbuf, nullptr, (T)dscale);
         return hipGetLastError();
     }

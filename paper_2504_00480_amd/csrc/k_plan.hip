@@ -104,7 +104,10 @@ k_bin_keys(const T *__restrict__ t, int64_t n, int d, int ng, int tb, int nb, in
 
 // Window weights of every sorted point, evaluated in FP64 from the stored
 // coordinate: record j holds psi(t_q - l) for the 2m taps l = floor(t_q)-m+1+a
-// of each dimension q (a = 0..2m-1), dimension-major.  anchor[j] packs the
+// of each dimension q (a = 0..2m-1), dimension-major; for d = 3 the first
+// dimension's taps are rotated: tap a sits in slot (L + a) mod 2m, L being the
+// first tap's position in the padded tile, so that the taps of one position
+// class modulo a divisor of 2m sit in fixed slots for every point.  anchor[j] packs the
 // cell floor(t) (row-major over the (2N)^d grid); lpos[j] packs the position
 // of the first tap inside the point's padded tile (edge pd = tb + 2m, origin
 // one tile edge tb * bin - m): bits 0-19 the row-major offset, bits 20-26 the
@@ -133,7 +136,10 @@ k_weights(const T *__restrict__ t, int64_t n, int d, int m, int ng, int tb, int 
             s2 = s2 > 0.0 ? s2 : 0.0;
             double sq = sqrt(s2), z = beta * sq;
             double r = z < 1e-6 ? beta * (1.0 + z * z / 6.0) : sinh(z) / sq;
-            rec[(i * d + q) * tw + a] = (T)(r * knorm);
+            // d = 3, first dimension: stored rotated by the first tap's tile
+            // position, at (L + a) mod 2m
+            const int slot = (d == 3 && q == 0) ? (L + a) % tw : a;
+            rec[(i * d + q) * tw + slot] = (T)(r * knorm);
         }
     }
     anchor[i] = an;

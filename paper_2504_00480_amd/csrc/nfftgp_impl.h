@@ -91,6 +91,8 @@ struct Group {
     int sub_sp = 0;              // points per spreading subproblem
     int spread_R = 0;            // vectors per spreading work-group (0: rule)
     int spread_W = 0;            // 3-D: waves sharing a spreading tile (0: rule, 4; or 2)
+    int spread_form = 0;         // spreading kernel: 0 rule (four-point form for one vector
+                                 // per work-group, else run-ordered), 1 four-point, 2 run-ordered
     int sub_cap = 0;             // capacity of the spreading list arrays
     int interp_pt = 1;           // points per thread of the tile interpolation (1, 2)
     int interp_rows = 0;         // 3-D: first-axis rows of the padded tile staged per subproblem

@@ -149,10 +149,14 @@ def test_interp_variants_agree(prec, monkeypatch):
     X = torch.tensor(w.X, dtype=dt, device="cuda:0")
     V = torch.tensor(w.V, dtype=dt, device="cuda:0")
     outs = []
-    for mode in ("tile", "tile2", "tilefull", "run", "tile+w2"):
+    for mode in ("tile", "tile2", "tilefull", "run", "tile+w2", "tile+quad", "tile+quad+w2"):
         monkeypatch.setenv("NFFTGP_INTERP", mode.split("+")[0])
-        if mode.endswith("+w2"):
+        monkeypatch.delenv("NFFTGP_SPREAD_W", raising=False)
+        monkeypatch.delenv("NFFTGP_SPREAD_FORM", raising=False)
+        if "+w2" in mode:
             monkeypatch.setenv("NFFTGP_SPREAD_W", "2")   # two waves per spreading tile
+        if "+quad" in mode:
+            monkeypatch.setenv("NFFTGP_SPREAD_FORM", "quad")   # four-point spreading with 2 vectors
         plan = AdditiveKernelPlan(X, w.windows, w.ktype, w.N, w.m, max_nrhs=2)
         plan.set_hyper(1.3, w.ell, 0.2)
         outs.append({k: (v.double().cpu().numpy() if not isinstance(v, list) else
