@@ -175,10 +175,13 @@ nfftgp_status nfftgp_get_window_info(nfftgp_plan plan, int32_t s, double *c0, do
 /* Autotuning (setup time).  Times nrhs-column applies (with the derivative
  * outputs when with_derivs != 0) for each window group under candidate
  * settings -- points per spreading subproblem (64 ... 4096), vectors per
- * spreading work-group (1, 2, 4) and the interpolation variant (per-point
- * tile reads with 1 or 2 points per thread, or register-held runs) -- by
- * coordinate search, best of two trials of `reps` applies each, and keeps the
- * fastest settings in the plan.  Requires nfftgp_set_hyper.  Allocates and
+ * spreading work-group (1, 2, 4), the spreading form (four-point or
+ * run-ordered), waves per 3-D spreading tile (4 or 2) and the interpolation
+ * variant (per-point tile reads with 1 or 2 points per thread and, for 3-D
+ * windows, the whole padded tile or a window of its rows; or register-held
+ * runs) -- by coordinate search, best of two trials of `reps` applies each
+ * (more when an apply is short: about 5 ms per trial), and keeps the fastest
+ * settings in the plan.  Requires nfftgp_set_hyper.  Allocates and
  * frees its own input and output buffers (and may grow the plan's tile
  * workspace); synchronises the stream; drops a captured CG iteration.  A
  * one-line summary per group is written to `report` (NUL-terminated,

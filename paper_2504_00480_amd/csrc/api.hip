@@ -704,6 +704,9 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
     nfftgp_status stt = NFFTGP_OK;
     double ms = 0.0;
     stt = timed(ms);   // warm-up and reference
+    // short applies: enough repetitions for about 5 ms per trial, so that
+    // launch jitter does not decide between candidates
+    if (stt == NFFTGP_OK && ms > 0.0) reps = std::max(reps, std::min(200, (int)std::ceil(5.0 / ms)));
     for (size_t gi = 0; gi < plan->groups.size() && stt == NFFTGP_OK; ++gi) {
         Group &G = plan->groups[gi];
         // 1) spreading subproblem size (skipping sizes whose tiles would exceed 8 GiB)
