@@ -208,3 +208,17 @@ def test_cg_graph_replay_matches_eager(orc, monkeypatch):
     Xg2, itg2, _, _, _ = plan.cg(B, 1e-5, 400, out=X)
     assert np.array_equal(itg2, ite2)
     assert torch.equal(Xg2, Xe2)
+
+
+@pytest.mark.parametrize("kt", [[0, 0], [1, 1], [0, 1]])
+def test_smallest_coefficients_match_oracle(orc, kt):
+    """Smallest b_k and b^der_k of every window against the oracle's FFT
+    coefficients, for Gaussian-only groups (product of 1-D transforms), Matern
+    groups and mixed groups (transform of all axes)."""
+    w = workloads.small(27, 800, [3, 3], kt, [0.4, 0.7], [32, 32], 4, nrhs=1, dist="normal")
+    plan, pb = _setup(orc, w)
+    for s in range(2):
+        info = plan.window_info(s)
+        b, bd = pb.coef(s)
+        assert abs(info["min_b"] - b.min()) <= 1e-12 * max(1.0, abs(b).max())
+        assert abs(info["min_bder"] - bd.min()) <= 1e-10 * max(1.0, abs(bd).max())
