@@ -154,7 +154,7 @@ __device__ __forceinline__ void pass1(int ln, int n2, Load &&load, typename Cplx
     using S = Split<LOGN>;
     C x[S::P];
 #pragma unroll
-    for (int n1 = 0; n1 < S::P; ++n1) x[n1] = load(ln, S::Q * n1 + n2);
+    for (int n1 = 0; n1 < S::P; ++n1) x[n1] = load(ln, S::Q * n1 + n2, n1);
     dft_reg<T, S::P, INV>(x);
 #pragma unroll
     for (int k1 = 1; k1 < S::P; ++k1) {
@@ -239,14 +239,14 @@ k_fft_slab(typename Cplx<T>::type *__restrict__ data, PruneGeom pg)
         // rows l1 = olo + j along axis 2: Omega in, F kept -> nat[c][l1]
         fft_lines<T, LOGN, false, false>(
             on,
-            [&](int j, int k) { return cyc_has(olo, on, k, NG) ? slab[(olo + j) * NG + k] : zero; },
+            [&](int j, int k, int) { return cyc_has(olo, on, k, NG) ? slab[(olo + j) * NG + k] : zero; },
             [&](int j, int k2, C v) {
                 if (cyc_has(flo, fn, k2, NG)) nat[((k2 - flo) & (NG - 1)) * NP + olo + j] = v;
             },
             ybuf, tw);
         // columns c (K2 in F) along axis 1: Omega in (zero elsewhere), F kept
         fft_lines<T, LOGN, false, false>(
-            fn, [&](int c, int l1) { return cyc_has(olo, on, l1, NG) ? nat[c * NP + l1] : zero; },
+            fn, [&](int c, int l1, int) { return cyc_has(olo, on, l1, NG) ? nat[c * NP + l1] : zero; },
             [&](int c, int k1, C v) {
                 if (cyc_has(flo, fn, k1, NG)) nat[c * NP + k1] = v;
             },
@@ -266,7 +266,7 @@ k_fft_slab(typename Cplx<T>::type *__restrict__ data, PruneGeom pg)
         __syncthreads();
         // columns c along axis 1: F in, Omega kept -> nat[c][l1]
         fft_lines<T, LOGN, true, false>(
-            fn, [&](int c, int k1) { return cyc_has(flo, fn, k1, NG) ? nat[c * NP + k1] : zero; },
+            fn, [&](int c, int k1, int) { return cyc_has(flo, fn, k1, NG) ? nat[c * NP + k1] : zero; },
             [&](int c, int l1, C v) {
                 if (cyc_has(olo, on, l1, NG)) nat[c * NP + l1] = v;
             },
@@ -276,7 +276,7 @@ k_fft_slab(typename Cplx<T>::type *__restrict__ data, PruneGeom pg)
         // separates from the writes of its second)
         fft_lines<T, LOGN, true, false>(
             on,
-            [&](int j, int k2) {
+            [&](int j, int k2, int) {
                 return cyc_has(flo, fn, k2, NG) ? nat[((k2 - flo) & (NG - 1)) * NP + olo + j] : zero;
             },
             [&](int j, int l2, C v) {
@@ -357,7 +357,7 @@ k_fft_pruned(typename Cplx<T>::type *__restrict__ data, PruneGeom pg, int ax, in
     zero.y = T(0);
     const bool in_om = MODE != 1;                    // input set: Omega or F
     const int ilo = in_om ? pg.olo : pg.flo, ilen = in_om ? pg.on : pg.fn;
-    auto load = [&](int li, int k) {
+    auto load = [&](int li, int k, int) {
         return (s_ok[li] && cyc_has(ilo, ilen, k, ng)) ? data[s_base[li] + (int64_t)k * S] : zero;
     };
     if constexpr (MODE != 2) {
@@ -373,26 +373,39 @@ k_fft_pruned(typename Cplx<T>::type *__restrict__ data, PruneGeom pg, int ax, in
         // MODE 2 (ax == 0, stride S): forward spectrum into spec, then per
         // block the diagonal at axis-0 frequency k times the line's offset in
         // the (N+1)^d diagonal, and the inverse transform
+        // the diagonal values this thread's inverse first pass needs (one
+        // task per thread: line li, column n2, frequencies Q n1 + n2) are
+        // loaded before the forward transform, so their latency is hidden
+        static_assert(LPB * Sp::Q >= 1, "");
+        int64_t dstr0 = 1;
+        for (int q = 1; q < pg.d; ++q) dstr0 *= (pg.N + 1);
+        const int tli = S == 1 ? (int)threadIdx.x / Sp::Q : (int)threadIdx.x % LPB;
+        const int tn2 = S == 1 ? (int)threadIdx.x % Sp::Q : (int)threadIdx.x / LPB;
+        T dpre[DER ? 2 : 1][Sp::P];
+#pragma unroll
+        for (int pass = 0; pass < (DER ? 2 : 1); ++pass) {
+            const WinDesc &w = wd[s_win[tli]];
+            const T *D = reinterpret_cast<const T *>(pass == 0 ? w.Dk : w.Dder);
+#pragma unroll
+            for (int n1 = 0; n1 < Sp::P; ++n1) {
+                const int k = Sp::Q * n1 + tn2;
+                const int f = k < pg.N ? k : k - ng;
+                const bool in = s_ok[tli] && f >= -pg.N / 2 && f <= pg.N / 2;
+                dpre[pass][n1] = in ? D[(int64_t)(f + pg.N / 2) * dstr0 + s_di[tli]] : T(0);
+            }
+        }
         auto keep = [&](int li, int k, C v) { spec[li][k] = v; };
         if (S == 1)
             fft_lines<T, LOGN, false, false>(LPB, load, keep, ybuf, twf);
         else
             fft_lines<T, LOGN, false, true>(LPB, load, keep, ybuf, twf);
-        int64_t dstr0 = 1;
-        for (int q = 1; q < pg.d; ++q) dstr0 *= (pg.N + 1);
-#pragma unroll 1
+#pragma unroll
         for (int pass = 0; pass < (DER ? 2 : 1); ++pass) {
-            auto dload = [&](int li, int k) {
-                const int f = k < pg.N ? k : k - ng;
-                C v = zero;
-                if (s_ok[li] && f >= -pg.N / 2 && f <= pg.N / 2) {
-                    const WinDesc &w = wd[s_win[li]];
-                    const T *D = reinterpret_cast<const T *>(pass == 0 ? w.Dk : w.Dder);
-                    const T dv = D[(int64_t)(f + pg.N / 2) * dstr0 + s_di[li]];
-                    v = spec[li][k];
-                    v.x *= dv;
-                    v.y *= dv;
-                }
+            auto dload = [&](int li, int k, int n1) {
+                C v = spec[li][k];
+                const T dv = dpre[pass][n1];
+                v.x *= dv;
+                v.y *= dv;
                 return v;
             };
             const int64_t off = pass == 0 ? 0 : der_off * pg.cells;
