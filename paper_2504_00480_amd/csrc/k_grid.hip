@@ -1008,16 +1008,34 @@ __global__ void k_assemble(int64_t n, int nrhs, int P, const T *__restrict__ V, 
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tot = n * nrhs;
     if (idx >= tot) return;
-    int64_t i = idx / nrhs;
-    int r = (int)(idx % nrhs);
-    T s = T(0), c = T(0);
-    for (int w = 0; w < P; ++w) {
-        const T y = hbuf[(int64_t)w * tot + idx] - c;
-        const T t = s + y;
-        c = (t - s) - y;
-        s = t;
+    int64_t i;
+    int r;
+    if (tot < (int64_t(1) << 31)) {   // 32-bit division suffices
+        const unsigned q = (unsigned)idx / (unsigned)nrhs;
+        i = q;
+        r = (int)((unsigned)idx - q * (unsigned)nrhs);
+    } else {
+        i = idx / nrhs;
+        r = (int)(idx % nrhs);
     }
-    T v = V[i * ldv + r];
+    const T v = V[i * ldv + r];
+    // windows in order (compensated sum); the loads of eight windows are
+    // issued together
+    T s = T(0), c = T(0);
+    for (int w0 = 0; w0 < P; w0 += 8) {
+        T h[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) h[j] = w0 + j < P ? hbuf[(int64_t)(w0 + j) * tot + idx] : T(0);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (w0 + j < P) {
+                const T y = h[j] - c;
+                const T t = s + y;
+                c = (t - s) - y;
+                s = t;
+            }
+        }
+    }
     KV[idx] = sf2 * s + se2 * v;
     if (dsf) dsf[idx] = two_sf * s;
     if (dse) dse[idx] = two_se * v;
