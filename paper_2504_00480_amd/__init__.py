@@ -10,4 +10,5 @@ in hand-written HIP kernels behind the C ABI declared in include/nfftgp.h.
 from .plan import (AdditiveKernelPlan, GAUSS, MATERN12, SCALE_AUTO, SCALE_NONE,  # noqa: F401
                    slq_logquad)
 from .gp import khat_apply, lml_estimate, lml_surrogate  # noqa: F401
+from .model import AdditiveGP  # noqa: F401
 from ._lib import NfftgpError, LIB_PATH  # noqa: F401

@@ -99,3 +99,25 @@ def test_slq_matches_oracle(orc):
     exact = Z[:, 0] @ (Q @ (np.log(w) * (Q.T @ Z[:, 0])))
     got = slq_logquad(ab, np.array([len(h[0])], np.int32), np.array([float(n)]))
     assert abs(got[0] - exact) < 1e-6 * abs(exact)
+
+
+def test_model_box_scaling_matches_oracle(orc):
+    """The training/prediction model scales each window into [-1/4, 1/4)^d by
+    the same rule as the oracle (midrange centre, isotropic factor), on the
+    union of training and test points."""
+    import workloads
+    from paper_2504_00480_amd.model import window_box_scale, _softplus, _sigmoid
+    g = workloads.rng(71)
+    X = np.vstack([3.0 * g.standard_normal((500, 6)), g.uniform(-0.2, 0.2, (20, 6))])
+    for feats in ([0, 1, 2], [3], [4, 5]):
+        c0, c = window_box_scale(X, feats)
+        r0, rc = orc.window_scale(X, feats)
+        assert np.allclose(c0, r0, rtol=0, atol=0) and c == rc
+        xs = c * (X[:, feats] - c0)
+        assert xs.min() >= -0.25 and xs.max() < 0.25
+    inside = g.uniform(-0.24, 0.24, (50, 2))
+    c0, c = window_box_scale(inside, [0, 1])
+    assert c == 1.0 and np.all(c0 == 0.0)
+    r = np.linspace(-30, 30, 61)
+    assert np.allclose(_softplus(r), np.log1p(np.exp(r)), rtol=1e-14, atol=1e-300)
+    assert np.allclose(_sigmoid(r), np.exp(r) / (1 + np.exp(r)), rtol=1e-14)
