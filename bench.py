@@ -50,6 +50,9 @@ def parse():
                     help="skip the plain form (one window per plan, one vector per call)")
     ap.add_argument("--cg-iters", type=int, default=20,
                     help="CG iterations timed with and without the captured graph (0: skip)")
+    ap.add_argument("--train-steps", type=int, default=2,
+                    help="training steps timed (10 probes, 10 CG iterations) and one posterior-mean "
+                         "prediction on held-out points (0: skip both)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration under a profiler)")
     return ap.parse_args()
@@ -227,6 +230,38 @@ def main():
                  "note": "tol 0 (fixed iteration count), one K-only apply + FP64 scalars per iteration"}
         print(f"[bench] CG {cgres}", file=sys.stderr, flush=True)
 
+    # ---------------- training step and prediction (separate model and plans)
+    train = None
+    if args.train_steps > 0:
+        from paper_2504_00480_amd import AdditiveGP
+        g = workloads.rng(9001)
+        nt = max(1, n // 10)
+        Xt = w.X[g.integers(0, n, nt)] + 0.01 * g.standard_normal((nt, w.X.shape[1]))
+        yv = w.y if w.y is not None else w.V[:, 0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        model = AdditiveGP(w.X, yv, w.windows, w.ktype, w.N, w.m, X_test=Xt, dtype=dt, n_probes=10)
+        torch.cuda.synchronize()
+        t_model = time.perf_counter() - t0
+        model.fit(steps=1, lr=0.01, cg_iters=10)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        model.fit(steps=args.train_steps, lr=0.01, cg_iters=10)
+        torch.cuda.synchronize()
+        t_step = (time.perf_counter() - t0) / args.train_steps
+        t0 = time.perf_counter()
+        mean = model.predict_mean(tol=1e-6, maxit=200)
+        torch.cuda.synchronize()
+        t_pred = time.perf_counter() - t0
+        train = {"ms_per_train_step": t_step * 1e3, "probes": 10, "cg_iters": 10,
+                 "model_setup_s": t_model, "predict_s": t_pred, "n_test": nt,
+                 "predict_finite": bool(torch.isfinite(mean).all().item()),
+                 "note": "train step: Z and gradient estimate (batched CG on [y, 10 probes], SLQ, one apply "
+                         "with derivative outputs) + Adam update; predict: CG to 1e-6 (at most 200 iterations), union plan "
+                         "creation and one cross apply"}
+        del model
+        print(f"[bench] train {train}", file=sys.stderr, flush=True)
+
     # ---------------- roofline of the dominant kernel
     geoms = []
     for s, win in enumerate(w.windows):
@@ -355,6 +390,7 @@ def main():
         "k_only_apply": {"ms": t_konly * 1e3, "value": n * nrhs / t_konly},
         "plain_single_vector": plain,
         "cg": cgres,
+        "train": train,
         "plan_seconds": t_plan,
         "autotune": tune,
         "workspace_bytes": plan.workspace_bytes(),
