@@ -243,6 +243,7 @@ def main():
         model = AdditiveGP(w.X, yv, w.windows, w.ktype, w.N, w.m, X_test=Xt, dtype=dt, n_probes=10)
         torch.cuda.synchronize()
         t_model = time.perf_counter() - t0
+        from paper_2504_00480_amd import NfftgpError
         model.fit(steps=1, lr=0.01, cg_iters=10)   # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -250,12 +251,17 @@ def main():
         torch.cuda.synchronize()
         t_step = (time.perf_counter() - t0) / args.train_steps
         t0 = time.perf_counter()
-        mean = model.predict_mean(tol=1e-6, maxit=200)
+        pstat = "ok"
+        try:
+            mean = model.predict_mean(tol=1e-6, maxit=200)
+            pstat = "ok" if bool(torch.isfinite(mean).all().item()) else "non-finite"
+        except NfftgpError as e:   # e.g. an indefinite interpolated kernel at this theta
+            pstat = str(e)
         torch.cuda.synchronize()
         t_pred = time.perf_counter() - t0
         train = {"ms_per_train_step": t_step * 1e3, "probes": 10, "cg_iters": 10,
-                 "model_setup_s": t_model, "predict_s": t_pred, "n_test": nt,
-                 "predict_finite": bool(torch.isfinite(mean).all().item()),
+                 "model_setup_s": t_model, "predict_s": t_pred, "n_test": nt, "predict_status": pstat,
+                 "theta": model.theta,
                  "note": "train step: Z and gradient estimate (batched CG on [y, 10 probes], SLQ, one apply "
                          "with derivative outputs) + Adam update; predict: CG to 1e-6 (at most 200 iterations), union plan "
                          "creation and one cross apply"}
