@@ -403,8 +403,9 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
     TRYH(tmp.get(&t2, n1 * 3 * eb));
     // points per spreading work-group: short runs for small n (enough groups to
     // fill the device), longer runs for large n (fewer partial tiles to fold);
-    // measured on 1e5..2e6 points: 128 at 1e5, 1024 at 2e5, 2048 at 5e5, 4096 at 2e6
-    int sub_sp = 128;
+    // measured on 1e5..2e6 points: 256 at 1e5 (four-point form), 1024 at 2e5,
+    // 2048 at 5e5, 4096 at 2e6
+    int sub_sp = n <= 65536 ? 128 : 256;
     if (n > 131072) {
         sub_sp = 256;
         while (sub_sp < 4096 && (int64_t)sub_sp * 256 < n) sub_sp *= 2;
