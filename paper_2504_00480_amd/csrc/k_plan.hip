@@ -146,17 +146,27 @@ k_weights(const T *__restrict__ t, int64_t n, int d, int m, int ng, int tb, int 
     lpos[i] = lin | (l0 << 20);
 }
 
-// counts[tile * tb + row] += 1 for every point, row = first cell coordinate
-// inside the tile (3-D).
+// counts[tile * tb + row] = points of the tile whose first cell coordinate
+// inside the tile is row (3-D).  The points are sorted by tile and, inside a
+// tile, by cell with the first coordinate slowest, so each (tile, row) key is
+// one contiguous range [s, e): its first point adds -s and its last e, two
+// atomics per range instead of one per point.
+__device__ __forceinline__ int row_key(const int *anchor, int64_t i, int ng, int tb, int nb)
+{
+    const int a = anchor[i] & 0x7fffffff;
+    const int c2 = a % ng, c1 = (a / ng) % ng, c0 = a / (ng * ng);
+    const int bin = ((c0 / tb) * nb + c1 / tb) * nb + c2 / tb;
+    return bin * tb + c0 % tb;
+}
+
 __global__ void __launch_bounds__(256)
 k_row_counts(const int *__restrict__ anchor, int64_t n, int ng, int tb, int nb, int *__restrict__ counts)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int a = anchor[i] & 0x7fffffff;
-    const int c2 = a % ng, c1 = (a / ng) % ng, c0 = a / (ng * ng);
-    const int bin = ((c0 / tb) * nb + c1 / tb) * nb + c2 / tb;
-    atomicAdd(&counts[bin * tb + c0 % tb], 1);
+    const int key = row_key(anchor, i, ng, tb, nb);
+    if (i == 0 || row_key(anchor, i - 1, ng, tb, nb) != key) atomicAdd(&counts[key], -(int)i);
+    if (i == n - 1 || row_key(anchor, i + 1, ng, tb, nb) != key) atomicAdd(&counts[key], (int)(i + 1));
 }
 
 __global__ void __launch_bounds__(256)
