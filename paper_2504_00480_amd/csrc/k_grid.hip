@@ -9,7 +9,9 @@
 // point touches the 2m cells floor(t)-m+1 .. floor(t)+m per dimension.  psi is
 // the Kaiser-Bessel window of Appendix A in grid units, normalised so that its
 // Fourier coefficient at frequency 0 is 1 / (2N); the plan stores psi at the
-// 2m taps of every point (record `rec`, dimension-major).
+// 2m taps of every point (record `rec`, dimension-major; for d = 3 the first
+// dimension's taps rotated, tap a in slot (L + a) mod 2m with L the first
+// tap's position in the padded tile).
 //
 // All windows of one group (same dimension and bandwidth) go through each
 // kernel in a single launch: work items (subproblems, tiles, grid cells) of the
