@@ -10,7 +10,7 @@ initialised at 0 (theta = log 2), 10 probe vectors and 10 CG iterations per
 training step.
 
 Prediction returns the posterior mean K(X*, X) alpha with alpha = Khat^-1 y
-(zero prior mean).  The cross product is the fast summation on the union of
+(zero prior mean) and the posterior variance k(x*, x*) - k*^T Khat^-1 k*.  The cross product is the fast summation on the union of
 the training and test points with a vector that is zero on the test rows:
 the test rows of that product are exactly sum_j k(x*_i - x_j) alpha_j.  For
 the kernel to be the same function in both products, every window is scaled
@@ -176,3 +176,39 @@ class AdditiveGP:
     def predict_mean(self, X_test=None, tol: float = 1e-8, maxit: int = 1000) -> torch.Tensor:
         """Posterior mean K(X*, X) Khat^-1 y at the current theta (zero prior mean)."""
         return self.cross_apply(self.solve(tol, maxit), X_test)
+
+    def predict_var(self, X_test=None, tol: float = 1e-8, maxit: int = 1000, noise: bool = False) -> torch.Tensor:
+        """Posterior variance k(x*, x*) - k*^T Khat^-1 k* of every test point at
+        the current theta (plus sigma_eps^2 with noise=True).  Test points go in
+        batches of b <= max_nrhs of the training plan: one product on the union
+        of training and test points with unit vectors at the batch's test rows
+        gives the columns k*_j = K(X, x*_j) (training rows) and k(x*_j, x*_j)
+        (its own row, less the sigma_eps^2 of the unit vector); batched CG on
+        the training plan gives Khat^-1 k*_j, and FP64 column dots finish."""
+        Xt = self.X_test if X_test is None else np.ascontiguousarray(
+            torch.as_tensor(X_test).double().cpu().numpy())
+        if Xt is None:
+            raise ValueError("no test points")
+        nt = Xt.shape[0]
+        b = self.plan.max_nrhs
+        th = self.theta
+        ellb = [self.c[s] * th["ell"][s] for s in range(self.P)]
+        self.plan.set_hyper(th["sigma_f"], ellb, th["sigma_eps"])
+        up = AdditiveKernelPlan(self._prescaled(np.vstack([self.X, Xt])), self.windows, self.kernel, self.N,
+                                self.m, scale_mode=SCALE_NONE, max_nrhs=b)
+        up.set_hyper(th["sigma_f"], ellb, th["sigma_eps"])
+        out = torch.empty(nt, dtype=torch.float64, device=self.device)
+        se2 = th["sigma_eps"] ** 2
+        for j0 in range(0, nt, b):
+            jb = min(b, nt - j0)
+            E = torch.zeros((self.n + nt, jb), dtype=self.dtype, device=self.device)
+            rows = torch.arange(self.n + j0, self.n + j0 + jb, device=self.device)
+            E[rows, torch.arange(jb, device=self.device)] = 1.0
+            KE = up.apply(E)["KV"]
+            Kc = KE[: self.n].contiguous()
+            kss = KE[rows, torch.arange(jb, device=self.device)].double() - se2
+            A, _, _, _, _ = self.plan.cg(Kc, tol, maxit)
+            q = torch.tensor(self.plan.col_dots(Kc, A), dtype=torch.float64, device=self.device)
+            out[j0:j0 + jb] = kss - q + (se2 if noise else 0.0)
+        up.close()
+        return out

@@ -111,3 +111,27 @@ def test_fit_lowers_exact_nll(orc):
     z1 = exact_z(model.theta)
     assert len(hist) == 60 and all(np.isfinite(h["Z"]) for h in hist)
     assert z1 < z0 - 0.1 * abs(z0), (z0, z1, model.theta)
+
+
+def test_posterior_variance_matches_oracle(orc):
+    """Posterior variances against the oracle's dense posterior of the
+    trigonometric-interpolant kernel on the union points (O2 matrices)."""
+    from paper_2504_00480_amd import AdditiveGP
+    X, Xt, g = _data(64, 700, 30, 4)
+    windows, kt, N, m = [[0, 1], [2, 3]], [0, 1], [32, 32], 6
+    sf, se, ell = 1.1, 0.3, [1.0, 1.6]
+    y = g.standard_normal(700)
+    print("[case] posterior variance", flush=True)
+    model = AdditiveGP(X, y, windows, kt, N, m, X_test=Xt, dtype=torch.float64, n_probes=10)
+    _set_theta(model, sf, se, ell)
+    got = model.predict_var(tol=1e-13, maxit=3000).cpu().numpy()
+    got_noise = model.predict_var(tol=1e-13, maxit=3000, noise=True).cpu().numpy()
+    U = np.vstack([X, Xt])
+    pu = orc.Problem(U, windows, kt, ell, sf, se, N)
+    K = sf ** 2 * sum(orc.rf_matrix(pu, s) for s in range(2))
+    Ktr = K[:700, :700] + se ** 2 * np.eye(700)
+    Kx = K[700:, :700]
+    ref = np.diag(K[700:, 700:]) - np.einsum("ij,ji->i", Kx, np.linalg.solve(Ktr, Kx.T))
+    assert np.all(ref > 0)
+    assert np.abs(got - ref).max() <= 1e-8 * sf ** 2 * 2, np.abs(got - ref).max()
+    assert np.allclose(got_noise - got, se ** 2, rtol=0, atol=1e-12)
