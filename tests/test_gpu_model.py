@@ -135,3 +135,47 @@ def test_posterior_variance_matches_oracle(orc):
     assert np.all(ref > 0)
     assert np.abs(got - ref).max() <= 1e-8 * sf ** 2 * 2, np.abs(got - ref).max()
     assert np.allclose(got_noise - got, se ** 2, rtol=0, atol=1e-12)
+
+
+def test_grf_1d_training_matches_exact_gp(orc):
+    """The 1-D Gaussian-random-field setting of Sec. 5 (Fig. 7): n = 1000
+    uniform in [0, 1], labels drawn from the GP with sigma_f^2 = 1, ell = 0.1,
+    sigma_eps^2 = 0.01, 800 / 200 split.  The fast-summation model and an exact
+    dense GP (oracle likelihood gradient) are trained from theta = log 2 with
+    the same Adam settings; their test RMSEs agree and approach the noise level."""
+    from paper_2504_00480_amd import AdditiveGP
+    g = workloads.rng(65)
+    n, ntr = 1000, 800
+    x = g.uniform(0.0, 1.0, (n, 1))
+    pb_all = orc.Problem(x, [[0]], [0], [0.1], 1.0, 0.1, [64])
+    Kall = orc.dense_matrix(pb_all, 0)
+    f = np.linalg.cholesky(Kall + 1e-8 * np.eye(n)) @ g.standard_normal(n)
+    y = f + 0.1 * g.standard_normal(n)
+    Xtr, ytr, Xte, yte = x[:ntr], y[:ntr], x[ntr:], y[ntr:]
+    steps, lr = 80, 0.05
+    print("[case] 1-D GRF training", flush=True)
+    model = AdditiveGP(Xtr, ytr, [[0]], [0], [64], 4, X_test=Xte, dtype=torch.float64, n_probes=10, seed=3)
+    model.fit(steps=steps, lr=lr, cg_iters=2000, cg_tol=1e-8)
+    mean = model.predict_mean(tol=1e-10, maxit=4000).cpu().numpy()
+    rmse_nfft = float(np.sqrt(np.mean((mean - yte) ** 2)))
+    # exact GP: same parametrisation and optimiser, exact gradient
+    raw = np.zeros(3)                      # sigma_f, sigma_eps, ell
+    m1 = np.zeros(3); m2 = np.zeros(3)
+    sp = lambda r: np.log1p(np.exp(-np.abs(r))) + np.maximum(r, 0.0)
+    for t in range(1, steps + 1):
+        th = sp(raw)
+        pb = orc.Problem(Xtr, [[0]], [0], [th[2]], th[0], th[1], [64])
+        gr = orc.dense_nll(pb, ytr)["grad"]
+        gvec = np.array([gr["sigma_f"], gr["sigma_eps"], gr[("ell", 0)]]) / (1.0 + np.exp(-raw))
+        m1 = 0.9 * m1 + 0.1 * gvec
+        m2 = 0.999 * m2 + 0.001 * gvec * gvec
+        raw -= lr * (m1 / (1 - 0.9 ** t)) / (np.sqrt(m2 / (1 - 0.999 ** t)) + 1e-8)
+    th = sp(raw)
+    pu = orc.Problem(x, [[0]], [0], [th[2]], th[0], th[1], [64])
+    Ku = orc.dense_matrix(pu, 0)
+    alpha = np.linalg.solve(th[0] ** 2 * Ku[:ntr, :ntr] + th[1] ** 2 * np.eye(ntr), ytr)
+    mean_ex = th[0] ** 2 * Ku[ntr:, :ntr] @ alpha
+    rmse_exact = float(np.sqrt(np.mean((mean_ex - yte) ** 2)))
+    print(f"RMSE fast {rmse_nfft:.4f} exact {rmse_exact:.4f}; theta fast {model.theta} exact {th}", flush=True)
+    assert rmse_nfft <= 1.1 * rmse_exact + 0.01, (rmse_nfft, rmse_exact)
+    assert rmse_nfft < 0.2
