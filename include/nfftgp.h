@@ -109,7 +109,10 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out,
  *   sigma_f, sigma_eps >= 0.
  * Computes, on the device in FP64, the coefficients b_k and b^der_k of every
  * window (eq. discrete_fourier_coefficients1, eq. exact_derivative) and the
- * diagonal applied between the two FFTs.  Asynchronous (no host wait);
+ * diagonal applied between the two FFTs (for window groups whose kernels are
+ * all Gaussian the samples factor over dimensions, and the coefficients are
+ * computed as products of 1-D transforms: the same values up to rounding,
+ * one launch).  Asynchronous (no host wait);
  * min_k b_k per window is reduced from per-block minima when
  * nfftgp_get_window_info asks for it. */
 nfftgp_status nfftgp_set_hyper(nfftgp_plan plan, double sigma_f, const double *ell,
