@@ -111,8 +111,11 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out,
  * window (eq. discrete_fourier_coefficients1, eq. exact_derivative) and the
  * diagonal applied between the two FFTs (for window groups whose kernels are
  * all Gaussian the samples factor over dimensions, and the coefficients are
- * computed as products of 1-D transforms: the same values up to rounding,
- * one launch).  Asynchronous (no host wait);
+ * computed as products of 1-D transforms: the same values up to rounding;
+ * for such groups this call only records theta, and the coefficients are
+ * computed by the next nfftgp_apply in extra work-groups of its fold launch,
+ * or by their own launch when nfftgp_cg or nfftgp_get_window_info comes
+ * first).  Asynchronous (no host wait);
  * min_k b_k per window is reduced from per-block minima when
  * nfftgp_get_window_info asks for it. */
 nfftgp_status nfftgp_set_hyper(nfftgp_plan plan, double sigma_f, const double *ell,

@@ -148,15 +148,33 @@ struct Scratch {
     } while (0)
 
 // Enqueue one additive apply; no validation, no allocation, no host sync.
+// Coefficients recorded by set_hyper but not yet computed (they are computed
+// by the next apply's fold launch) are computed now by their own launch.
+hipError_t resolve_coef(nfftgp_plan p)
+{
+    for (Group &G : p->groups) {
+        if (!G.coef_pending) continue;
+        const int pi_ = prof_begin(p, NFFTGP_PROF_COEF);
+        const hipError_t e = launch_coefficients(p->prec, G, G.prm, G.cinv2, p->coef, p->stream);
+        if (e != hipSuccess) return e;
+        prof_end(p, NFFTGP_PROF_COEF, pi_);
+        G.coef_pending = false;
+    }
+    return hipSuccess;
+}
+
 nfftgp_status apply_impl(nfftgp_plan p, const void *V, int64_t ldv, int nrhs, void *KV,
                          void *dell, void *dsf, void *dse)
 {
     const hipStream_t s = p->stream;
     const bool with_der = dell != nullptr;
     if (p->n == 0) return NFFTGP_OK;
-    for (const Group &G : p->groups) {
+    for (Group &G : p->groups) {
         PROF_LAUNCH(p, NFFTGP_PROF_SPREAD, launch_spread(p->prec, G, p->m, V, ldv, nrhs, p->tilebuf, s));
-        PROF_LAUNCH(p, NFFTGP_PROF_FOLD, launch_fold(p->prec, G, p->m, nrhs, p->tilebuf, p->grid, s));
+        // the fold launch also computes coefficients recorded by set_hyper
+        PROF_LAUNCH(p, NFFTGP_PROF_FOLD,
+                    launch_fold(p->prec, G, p->m, nrhs, p->tilebuf, p->grid, G.coef_pending, s));
+        G.coef_pending = false;
         if (G.g.d > 1)
             PROF_LAUNCH(p, NFFTGP_PROF_FFT_FWD, launch_fft_fwd(p->prec, G, p->m, p->grid, nrhs, s));
         PROF_LAUNCH(p, NFFTGP_PROF_DIAG, launch_fft_diag(p->prec, G, p->m, p->grid, nrhs, with_der, s));
@@ -506,6 +524,8 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
     size_t grid_need = 1, coef_need = 8;
     for (Group &G : plan->groups) {
         G.nwin = (int)G.wins.size();
+        G.sep = true;
+        for (int s : G.wins) G.sep = G.sep && plan->win[s].kernel == NFFTGP_GAUSS;
         std::vector<WinDesc> hd(G.nwin);
         int64_t cap = 0, icap = 0;
         const bool d3 = G.g.d == 3;
@@ -607,7 +627,7 @@ nfftgp_status nfftgp_set_hyper(nfftgp_plan plan, double sigma_f, const double *e
     for (int s = 0; s < plan->P; ++s)
         if (!(ell[s] > 0.0) || !std::isfinite(ell[s])) return fail(NFFTGP_E_ARG, "ell must be finite and > 0");
     const hipStream_t st = plan->stream;
-    for (const Group &G : plan->groups) {
+    for (Group &G : plan->groups) {
         CoefParams prm;
         std::memset(&prm, 0, sizeof(prm));
         prm.nwin = G.nwin;
@@ -617,8 +637,14 @@ nfftgp_status nfftgp_set_hyper(nfftgp_plan plan, double sigma_f, const double *e
             prm.c[wl] = plan->win[s].c;
             prm.kernel[wl] = plan->win[s].kernel;
         }
-        PROF_LAUNCH(plan, NFFTGP_PROF_COEF,
-                    launch_coefficients(plan->prec, G, prm, G.cinv2, plan->coef, st));
+        G.prm = prm;
+        if (G.sep) {
+            G.coef_pending = true;   // computed by the next apply's fold launch
+        } else {
+            G.coef_pending = false;
+            PROF_LAUNCH(plan, NFFTGP_PROF_COEF,
+                        launch_coefficients(plan->prec, G, prm, G.cinv2, plan->coef, st));
+        }
     }
     // min_k b_k is reduced from the block minima only when asked for
     // (nfftgp_get_window_info), so set_hyper neither waits nor launches it
@@ -857,6 +883,9 @@ nfftgp_status nfftgp_cg(nfftgp_plan plan, const void *B_dev, int32_t nrhs, void 
     if (maxit < 0 || !(tol >= 0.0)) return fail(NFFTGP_E_ARG, "bad tol or maxit");
     if (plan->n > 0 && (!B_dev || !X_dev)) return fail(NFFTGP_E_ARG, "B or X is NULL");
     if (check_every <= 0) check_every = 8;
+    // coefficients pending from set_hyper are computed before the iteration is
+    // enqueued or captured (a captured iteration never computes them)
+    NFFTGP_HIP_TRY(resolve_coef(plan));
     const hipStream_t st = plan->stream;
     const int64_t n = plan->n;
     double *sc = plan->cg_scal;
@@ -1066,6 +1095,7 @@ nfftgp_status nfftgp_get_window_info(nfftgp_plan plan, int32_t s, double *c0, do
     if (!plan) return fail(NFFTGP_E_ARG, "plan is NULL");
     if (s < 0 || s >= plan->P) return fail(NFFTGP_E_ARG, "window index out of range");
     if (plan->minb_pending) {
+        NFFTGP_HIP_TRY(resolve_coef(plan));
         for (const Group &G : plan->groups) NFFTGP_HIP_TRY(launch_coef_min(G, plan->minb_host, plan->stream));
         NFFTGP_HIP_TRY(hipStreamSynchronize(plan->stream));
         for (int k = 0; k < plan->P; ++k) {

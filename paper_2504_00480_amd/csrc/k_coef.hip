@@ -13,6 +13,7 @@
 // which is the symmetric matrix sum_k b_k cos(2 pi k.(x_i - x_j)).
 #include "nfftgp_impl.h"
 #include "nfftgp_dev.h"
+#include "nfftgp_coef_sep.h"
 
 namespace nfftgp {
 namespace {
@@ -178,76 +179,15 @@ k_coef_diag(int d, int N, const double *__restrict__ cinv2, const double *__rest
     if (threadIdx.x == 0) part[((int64_t)w * 2 + arr) * gridDim.x + blockIdx.x] = red[0];
 }
 
-// Separable kernels (every window of the group Gaussian).  The samples are a
-// product over dimensions, g(x_0) ... g(x_{d-1}) with g(x) = exp(-(x/c)^2 /
-// (2 ell^2)), so b(k) = prod_q B1(|k_q|) / N^d with B1 the real transform of
-// g on the H magnitudes, and the ell-derivative, whose samples are
-// sum_q g'(x_q) prod_{p != q} g(x_p) with g'(x) = (x/c)^2 / ell^3 g(x), has
-// b^der(k) = sum_q B1'(|k_q|) prod_{p != q} B1(|k_p|) / N^d -- the same
-// coefficients as the transform of all d axes, in one launch.  Each block
-// builds the 1-D transforms of its window in LDS, then fills its share of
-// D(k) (and the block minimum of b, as stage 2).  Grid (ceil((N+1)^d / 256), 2, nwin).
+// Separable kernels (every window of the group Gaussian): one launch of
+// coef_sep_block (nfftgp_coef_sep.h).  Grid (ceil((N+1)^d / 256), 2, nwin).
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_coef_sep(int d, int N, CoefParams prm, const double *__restrict__ cinv2, const double *__restrict__ cwg,
            const WinDesc *__restrict__ wd, double *__restrict__ part)
 {
-    __shared__ double g1[kMaxH], gd1[kMaxH], B1[kMaxH], Bd1[kMaxH];
-    __shared__ double red[256];
-    const int arr = blockIdx.y, w = blockIdx.z;
-    const int H = N / 2 + 1;
-    const float invN1 = 1.0f / (float)(N + 1);
-    const double ell = prm.ell[w], cs = prm.c[w];
-    for (int l = threadIdx.x; l < H; l += 256) {
-        const double x = (double)l / (double)N / cs;
-        const double v = exp(-(x * x) / (2.0 * ell * ell));
-        g1[l] = v;
-        gd1[l] = (x * x) / (ell * ell * ell) * v;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < H; k += 256) {
-        double a = 0.0, ad = 0.0;
-        for (int l = 0; l < H; ++l) {
-            const double c = cwg[l * H + k];
-            a += c * g1[l];
-            ad += c * gd1[l];
-        }
-        B1[k] = a / (double)N;
-        Bd1[k] = ad / (double)N;
-    }
-    __syncthreads();
-    int KD = 1;
-    for (int q = 0; q < d; ++q) KD *= N + 1;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    double b = INFINITY;
-    if (i < KD) {
-        int rem = i;
-        bool in_pos = true, in_neg = true;
-        double f = 1.0, prod = 1.0, dsum = 0.0;
-        for (int q = d - 1; q >= 0; --q) {
-            const int qt = fdiv_small(rem, N + 1, invN1);
-            const int k = rem - qt * (N + 1) - N / 2;
-            rem = qt;
-            in_pos = in_pos && k < N / 2;
-            in_neg = in_neg && k > -N / 2;
-            const int ka = k < 0 ? -k : k;
-            // derivative: product rule over the factors taken so far
-            dsum = dsum * B1[ka] + prod * Bd1[ka];
-            prod *= B1[ka];
-            f *= cinv2[k + N / 2];
-        }
-        b = arr == 0 ? prod : dsum;
-        const double c = (in_pos ? 1.0 : 0.0) + (in_neg ? 1.0 : 0.0);
-        T *Dout = reinterpret_cast<T *>(const_cast<void *>(arr == 0 ? wd[w].Dk : wd[w].Dder));
-        Dout[i] = (T)(0.5 * c * b * f);
-    }
-    red[threadIdx.x] = b;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[((int64_t)w * 2 + arr) * gridDim.x + blockIdx.x] = red[0];
+    __shared__ double lds[4 * kCoefMaxH + 256];
+    coef_sep_block<T>(d, N, prm, cinv2, cwg, wd, part, blockIdx.x, gridDim.x, blockIdx.y, blockIdx.z, lds);
 }
 
 // Stage 3: smallest coefficient of every window (blockIdx.y) and array

@@ -20,6 +20,7 @@
 // tile ("bin", tb cells per dimension) in the window's sorted order.
 #include "nfftgp_impl.h"
 #include "nfftgp_dev.h"
+#include "nfftgp_coef_sep.h"
 
 #include <cstdlib>
 #include <type_traits>
@@ -506,8 +507,20 @@ template <typename T, int D>
 __global__ void __launch_bounds__(256)
 k_fold(const WinDesc *__restrict__ wd, const T *__restrict__ tilebuf, int nrhs, int tb, int nb,
        int ng, int m, int pd, int pc, int64_t cells, int olo, int on, int ocells,
-       typename Cplx<T>::type *__restrict__ grid)
+       typename Cplx<T>::type *__restrict__ grid, int nwr, int coef_blocks, int coef_nper, int cd, int cN,
+       CoefParams prm, const double *__restrict__ cinv2, const double *__restrict__ cw,
+       double *__restrict__ cpart)
 {
+    // rows blockIdx.y >= nwr: the group's separable coefficients (coef_sep_block),
+    // block (blk, arr, w) numbered row-major after the fold rows
+    if ((int)blockIdx.y >= nwr) {
+        __shared__ double lds[4 * kCoefMaxH + 256];
+        const int cb = ((int)blockIdx.y - nwr) * (int)gridDim.x + (int)blockIdx.x;
+        if (cb >= coef_blocks) return;
+        const int blk = cb % coef_nper, aw = cb / coef_nper;
+        coef_sep_block<T>(cd, cN, prm, cinv2, cw, wd, cpart, blk, coef_nper, aw % 2, aw / 2, lds);
+        return;
+    }
     // one thread per occupied cell; blockIdx.y = window * nrhs + vector
     const int ci = xcd_item(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (ci >= ocells) return;
@@ -1184,7 +1197,7 @@ hipError_t interp_t(const Group &G, int m, int64_t n, int nrhs, const void *grid
 }
 
 template <typename T>
-hipError_t fold_t(const Group &G, int m, int nrhs, void *tilebuf, void *grid, hipStream_t s)
+hipError_t fold_t(const Group &G, int m, int nrhs, void *tilebuf, void *grid, bool with_coef, hipStream_t s)
 {
     const WindowGeom &g = G.g;
     using C = typename Cplx<T>::type;
@@ -1197,10 +1210,18 @@ hipError_t fold_t(const Group &G, int m, int nrhs, void *tilebuf, void *grid, hi
     const int olo = g.N / 2 - m + 1, on = g.N + 2 * m;
     int64_t ocells = 1;
     for (int q = 0; q < g.d; ++q) ocells *= on;
-    const dim3 fgrid((unsigned)((ocells + 255) / 256), (unsigned)(G.nwin * nrhs));
+    const int gx = (int)((ocells + 255) / 256), nwr = G.nwin * nrhs;
+    // coefficient blocks: (N+1)^d / 256 per window and array, in extra rows
+    int64_t KD = 1;
+    for (int q = 0; q < g.d; ++q) KD *= g.N + 1;
+    const int nper = (int)((KD + 255) / 256);
+    const int coef_blocks = with_coef ? nper * 2 * G.nwin : 0;
+    const int crows = (coef_blocks + gx - 1) / gx;
+    const dim3 fgrid((unsigned)gx, (unsigned)(nwr + crows));
 #define NFFTGP_FOLD(DD)                                                                              \
     k_fold<T, DD><<<fgrid, 256, 0, s>>>(G.desc, (const T *)tilebuf, nrhs, g.tb, g.nb, g.ng, m, g.pd, \
-                                        g.pc, g.cells, olo, on, (int)ocells, (C *)grid);
+                                        g.pc, g.cells, olo, on, (int)ocells, (C *)grid, nwr,      \
+                                        coef_blocks, nper, g.d, g.N, G.prm, G.cinv2, G.cw, G.coef_part);
     switch (g.d) {
     case 1: NFFTGP_FOLD(1) break;
     case 2: NFFTGP_FOLD(2) break;
@@ -1234,10 +1255,10 @@ hipError_t launch_spread(int prec, const Group &G, int m, const void *V, int64_t
 }
 
 hipError_t launch_fold(int prec, const Group &G, int m, int nrhs, void *tilebuf, void *grid,
-                       hipStream_t s)
+                       bool with_coef, hipStream_t s)
 {
-    return prec == NFFTGP_F32 ? fold_t<float>(G, m, nrhs, tilebuf, grid, s)
-                              : fold_t<double>(G, m, nrhs, tilebuf, grid, s);
+    return prec == NFFTGP_F32 ? fold_t<float>(G, m, nrhs, tilebuf, grid, with_coef, s)
+                              : fold_t<double>(G, m, nrhs, tilebuf, grid, with_coef, s);
 }
 
 hipError_t launch_interp(int prec, const Group &G, int m, int64_t n, int nrhs, const void *grid,

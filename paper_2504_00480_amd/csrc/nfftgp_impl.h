@@ -77,6 +77,14 @@ struct WinDesc {
 
 // Windows of equal dimension and bandwidth go through every apply kernel in
 // one launch; their work lists are concatenated.
+// Per-window parameters of one group's coefficient kernels (passed by value).
+struct CoefParams {
+    double ell[NFFTGP_MAX_WINDOWS];
+    double c[NFFTGP_MAX_WINDOWS];
+    int32_t kernel[NFFTGP_MAX_WINDOWS];
+    int32_t nwin;
+};
+
 struct Group {
     WindowGeom g;
     int nwin = 0;
@@ -93,6 +101,11 @@ struct Group {
     int spread_W = 0;            // 3-D: waves sharing a spreading tile (0: rule, 4; or 2)
     int spread_form = 0;         // spreading kernel: 0 rule (four-point form for one vector
                                  // per work-group, else run-ordered), 1 four-point, 2 run-ordered
+    // every window Gaussian: set_hyper only records theta (prm) and the next
+    // apply computes the coefficients in extra work-groups of its fold launch
+    bool sep = false;
+    bool coef_pending = false;
+    CoefParams prm{};
     int sub_cap = 0;             // capacity of the spreading list arrays
     int interp_pt = 1;           // points per thread of the tile interpolation (1, 2)
     int interp_rows = 0;         // 3-D: first-axis rows of the padded tile staged per subproblem
@@ -205,13 +218,6 @@ hipError_t launch_row_counts(const int *anchor, int64_t n, const WindowGeom &g, 
 
 // ---------------------------------------------------------------- per-theta kernels
 // Coefficients b_k, b^der_k of one window (FP64) and the symmetrised diagonals.
-// Per-window parameters of one group's coefficient kernels (passed by value).
-struct CoefParams {
-    double ell[NFFTGP_MAX_WINDOWS];
-    double c[NFFTGP_MAX_WINDOWS];
-    int32_t kernel[NFFTGP_MAX_WINDOWS];
-    int32_t nwin;
-};
 // Window factors 1 / c(k)^2 (N + 1) and the real-transform weights ((N/2+1)^2).
 hipError_t launch_window_coef(int N, int m, double *cinv2, double *cw, hipStream_t s);
 // Scratch (doubles) the coefficient kernel of a group needs.
@@ -228,8 +234,10 @@ hipError_t launch_coefficients(int prec, const Group &G, const CoefParams &prm, 
 hipError_t launch_coef_min(const Group &G, double *minb, hipStream_t s);
 hipError_t launch_spread(int prec, const Group &G, int m, const void *V, int64_t ldv, int nrhs,
                          void *tilebuf, hipStream_t s);
+// with_coef: the fold launch also computes the group's (separable)
+// coefficients, diagonals and block minima from G.prm.
 hipError_t launch_fold(int prec, const Group &G, int m, int nrhs, void *tilebuf, void *grid,
-                       hipStream_t s);
+                       bool with_coef, hipStream_t s);
 // Pruned FFT pipeline of one group: forward transforms of axes d-1..1, then
 // axis 0 forward + diagonal (and derivative diagonal) + axis 0 inverse, then
 // inverse transforms of axes 1..d-1 over the K (and derivative) blocks.

@@ -217,8 +217,15 @@ def test_smallest_coefficients_match_oracle(orc, kt):
     groups and mixed groups (transform of all axes)."""
     w = workloads.small(27, 800, [3, 3], kt, [0.4, 0.7], [32, 32], 4, nrhs=1, dist="normal")
     plan, pb = _setup(orc, w)
-    for s in range(2):
-        info = plan.window_info(s)
-        b, bd = pb.coef(s)
-        assert abs(info["min_b"] - b.min()) <= 1e-12 * max(1.0, abs(b).max())
-        assert abs(info["min_bder"] - bd.min()) <= 1e-10 * max(1.0, abs(bd).max())
+    V = torch.tensor(w.V, dtype=torch.float64, device=DEV)
+    # first read right after set_hyper (own launch), then after an apply that
+    # computed the coefficients inside its fold launch (Gaussian-only groups)
+    for route in ("window_info first", "apply first"):
+        if route == "apply first":
+            plan.set_hyper(w.sigma_f, w.ell, w.sigma_eps)
+            plan.apply(V)
+        for s in range(2):
+            info = plan.window_info(s)
+            b, bd = pb.coef(s)
+            assert abs(info["min_b"] - b.min()) <= 1e-12 * max(1.0, abs(b).max()), route
+            assert abs(info["min_bder"] - bd.min()) <= 1e-10 * max(1.0, abs(bd).max()), route
