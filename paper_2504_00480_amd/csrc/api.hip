@@ -907,13 +907,12 @@ nfftgp_status nfftgp_cg(nfftgp_plan plan, const void *B_dev, int32_t nrhs, void 
         const hipStream_t cs = plan->stream;
         nfftgp_status e = apply_impl(plan, plan->cg_p, nrhs, nrhs, plan->cg_ap, nullptr, nullptr, nullptr);
         if (e != NFFTGP_OK) return e;
-        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_coldots(plan->prec, plan->cg_p, nrhs, plan->cg_ap, nrhs, n, nrhs,
-                                                         plan->dot_part, sc + kPAP * nrhs, cs));
-        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_alpha(nrhs, sc, cs));
-        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_xr(plan->prec, n, nrhs, sc, X_dev, plan->cg_r, plan->cg_p, plan->cg_ap, cs));
-        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_coldots(plan->prec, plan->cg_r, nrhs, plan->cg_r, nrhs, n, nrhs,
-                                                         plan->dot_part, sc + kRRNew * nrhs, cs));
-        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_beta(nrhs, sc, tol, hist, cs));
+        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_dot_part(plan->prec, plan->cg_p, nrhs, plan->cg_ap, nrhs, n, nrhs,
+                                                          plan->dot_part, cs));
+        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_alpha(nrhs, plan->dot_part, sc, cs));
+        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_xr(plan->prec, n, nrhs, sc, X_dev, plan->cg_r, plan->cg_p,
+                                                       plan->cg_ap, plan->dot_part, cs));
+        PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_beta(nrhs, plan->dot_part, sc, tol, hist, cs));
         PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_p(plan->prec, n, nrhs, sc, plan->cg_r, plan->cg_p, cs));
         return NFFTGP_OK;
     };

@@ -67,26 +67,11 @@ __global__ void k_cg_start(int nrhs, double *__restrict__ sc)
     sc[kNotPD * nrhs + c] = 0.0;
     sc[kAlpha * nrhs + c] = 0.0;
     sc[kBeta * nrhs + c] = 0.0;
-    sc[kStep * nrhs + c] = 0.0;
+    sc[kStep * nrhs + c] = -1.0;   // advanced at the start of every iteration
 }
 
-__global__ void k_cg_alpha(int nrhs, double *__restrict__ sc)
-{
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nrhs) return;
-    double alpha = 0.0;
-    if (sc[kActive * nrhs + c] != 0.0) {
-        double pap = sc[kPAP * nrhs + c];
-        if (!(pap > 0.0)) {
-            sc[kNotPD * nrhs + c] = 1.0;
-            sc[kActive * nrhs + c] = 0.0;
-        } else {
-            alpha = sc[kRR * nrhs + c] / pap;
-        }
-    }
-    sc[kAlpha * nrhs + c] = alpha;
-}
-
+// x += alpha p, r -= alpha Khat p over the flat n x nrhs array (coalesced);
+// used with a separate pass for the r^T r partials when nrhs > 2.
 template <typename T>
 __global__ void k_cg_xr(int64_t total, int nrhs, const double *__restrict__ sc, T *__restrict__ X,
                         T *__restrict__ R, const T *__restrict__ P, const T *__restrict__ AP)
@@ -98,33 +83,6 @@ __global__ void k_cg_xr(int64_t total, int nrhs, const double *__restrict__ sc, 
     if (a == 0.0) return;
     X[i] = (T)((double)X[i] + a * (double)P[i]);
     R[i] = (T)((double)R[i] - a * (double)AP[i]);
-}
-
-// One block of 64 threads.  The iteration index lives on the device
-// (sc[kStep * nrhs], advanced here), so the same launch serves every
-// iteration -- also when replayed from a captured graph.
-__global__ void __launch_bounds__(64)
-k_cg_beta(int nrhs, double *__restrict__ sc, double tol, double *__restrict__ hist)
-{
-    const int c = threadIdx.x;
-    const int it = (int)sc[kStep * nrhs];
-    if (c < nrhs) {
-        double beta = 0.0;
-        if (sc[kActive * nrhs + c] != 0.0) {
-            double rrn = sc[kRRNew * nrhs + c], rr = sc[kRR * nrhs + c];
-            beta = rrn / rr;
-            if (hist) {
-                hist[((int64_t)it * nrhs + c) * 2] = sc[kAlpha * nrhs + c];
-                hist[((int64_t)it * nrhs + c) * 2 + 1] = beta;
-            }
-            sc[kRR * nrhs + c] = rrn;
-            sc[kIters * nrhs + c] = (double)(it + 1);
-            if (sqrt(rrn) <= tol * sqrt(sc[kRR0 * nrhs + c])) sc[kActive * nrhs + c] = 0.0;
-        }
-        sc[kBeta * nrhs + c] = beta;
-    }
-    __syncthreads();
-    if (c == 0) sc[kStep * nrhs] = (double)(it + 1);
 }
 
 template <typename T>
@@ -141,6 +99,107 @@ __global__ void k_cg_p(int64_t total, int nrhs, const double *__restrict__ sc,
     P[i] = (T)((double)R[i] + sc[kBeta * nrhs + c] * (double)P[i]);
 }
 
+// ---- fused forms of the iteration (five launches besides the apply)
+
+// Column c = blockIdx.x: p^T Khat p from the partials (the reduction of
+// k_dot_final), then alpha as k_cg_alpha.  Block 0 also advances the
+// iteration index (no other kernel of this launch reads it).
+__global__ void __launch_bounds__(128)
+k_dot_final_alpha(const double *__restrict__ part, int nblk, int nrhs, double *__restrict__ sc)
+{
+    __shared__ double s[128];
+    const int c = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 128) acc += part[(int64_t)c * nblk + b];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 64; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double pap = s[0];
+        sc[kPAP * nrhs + c] = pap;
+        double alpha = 0.0;
+        if (sc[kActive * nrhs + c] != 0.0) {
+            if (!(pap > 0.0)) {
+                sc[kNotPD * nrhs + c] = 1.0;
+                sc[kActive * nrhs + c] = 0.0;
+            } else {
+                alpha = sc[kRR * nrhs + c] / pap;
+            }
+        }
+        sc[kAlpha * nrhs + c] = alpha;
+        if (c == 0) sc[kStep * nrhs] += 1.0;
+    }
+}
+
+// x += alpha p, r -= alpha Khat p for column blockIdx.y (as k_cg_xr), and the
+// partials of the new r^T r (the loop and reduction of k_dot_part).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_cg_xr_dot(int64_t n, int nrhs, const double *__restrict__ sc, T *__restrict__ X, T *__restrict__ R,
+            const T *__restrict__ P, const T *__restrict__ AP, double *__restrict__ part)
+{
+    __shared__ double s[256];
+    const int c = blockIdx.y;
+    const double a = sc[kAlpha * nrhs + c];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int64_t e = i * nrhs + c;
+        T r = R[e];
+        if (a != 0.0) {
+            X[e] = (T)((double)X[e] + a * (double)P[e]);
+            r = (T)((double)r - a * (double)AP[e]);
+            R[e] = r;
+        }
+        acc += (double)r * (double)r;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)c * gridDim.x + blockIdx.x] = s[0];
+}
+
+// Column c = blockIdx.x: the new r^T r from the partials, then beta, the
+// convergence test and the Lanczos history entry (as k_cg_beta).
+__global__ void __launch_bounds__(128)
+k_dot_final_beta(const double *__restrict__ part, int nblk, int nrhs, double *__restrict__ sc, double tol,
+                 double *__restrict__ hist)
+{
+    __shared__ double s[128];
+    const int c = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 128) acc += part[(int64_t)c * nblk + b];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 64; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int it = (int)sc[kStep * nrhs];
+        const double rrn = s[0];
+        sc[kRRNew * nrhs + c] = rrn;
+        double beta = 0.0;
+        if (sc[kActive * nrhs + c] != 0.0) {
+            const double rr = sc[kRR * nrhs + c];
+            beta = rrn / rr;
+            if (hist) {
+                hist[((int64_t)it * nrhs + c) * 2] = sc[kAlpha * nrhs + c];
+                hist[((int64_t)it * nrhs + c) * 2 + 1] = beta;
+            }
+            sc[kRR * nrhs + c] = rrn;
+            sc[kIters * nrhs + c] = (double)(it + 1);
+            if (sqrt(rrn) <= tol * sqrt(sc[kRR0 * nrhs + c])) sc[kActive * nrhs + c] = 0.0;
+        }
+        sc[kBeta * nrhs + c] = beta;
+    }
+}
+
 inline unsigned blocks(int64_t total) { return (unsigned)((total + 255) / 256); }
 
 }  // namespace
@@ -154,6 +213,17 @@ hipError_t launch_coldots(int prec, const void *A, int64_t lda, const void *B, i
     else
         k_dot_part<double><<<g, 256, 0, s>>>((const double *)A, lda, (const double *)B, ldb, n, part);
     k_dot_final<<<(unsigned)ncol, 128, 0, s>>>(part, kDotBlocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot_part(int prec, const void *A, int64_t lda, const void *B, int64_t ldb, int64_t n,
+                           int ncol, double *part, hipStream_t s)
+{
+    dim3 g(kDotBlocks, (unsigned)ncol);
+    if (prec == NFFTGP_F32)
+        k_dot_part<float><<<g, 256, 0, s>>>((const float *)A, lda, (const float *)B, ldb, n, part);
+    else
+        k_dot_part<double><<<g, 256, 0, s>>>((const double *)A, lda, (const double *)B, ldb, n, part);
     return hipGetLastError();
 }
 
@@ -177,29 +247,41 @@ hipError_t launch_cg_start(int nrhs, double *scal, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_cg_alpha(int nrhs, double *scal, hipStream_t s)
+hipError_t launch_cg_alpha(int nrhs, const double *part, double *scal, hipStream_t s)
 {
-    k_cg_alpha<<<1, 64, 0, s>>>(nrhs, scal);
+    k_dot_final_alpha<<<(unsigned)nrhs, 128, 0, s>>>(part, kDotBlocks, nrhs, scal);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_xr(int prec, int64_t n, int nrhs, const double *scal, void *X, void *R,
-                        const void *Pv, const void *AP, hipStream_t s)
+                        const void *Pv, const void *AP, double *part, hipStream_t s)
 {
-    int64_t tot = n * nrhs;
-    if (tot == 0) return hipSuccess;
+    if (n * nrhs == 0) return hipSuccess;
+    if (nrhs > 2) {
+        // column-strided updates would waste the coalescing of the flat form:
+        // flat update, then the partials as a separate pass (same values)
+        const int64_t tot = n * nrhs;
+        if (prec == NFFTGP_F32)
+            k_cg_xr<float><<<blocks(tot), 256, 0, s>>>(tot, nrhs, scal, (float *)X, (float *)R,
+                                                        (const float *)Pv, (const float *)AP);
+        else
+            k_cg_xr<double><<<blocks(tot), 256, 0, s>>>(tot, nrhs, scal, (double *)X, (double *)R,
+                                                         (const double *)Pv, (const double *)AP);
+        return launch_dot_part(prec, R, nrhs, R, nrhs, n, nrhs, part, s);
+    }
+    const dim3 g(kDotBlocks, (unsigned)nrhs);
     if (prec == NFFTGP_F32)
-        k_cg_xr<float><<<blocks(tot), 256, 0, s>>>(tot, nrhs, scal, (float *)X, (float *)R,
-                                                    (const float *)Pv, (const float *)AP);
+        k_cg_xr_dot<float><<<g, 256, 0, s>>>(n, nrhs, scal, (float *)X, (float *)R, (const float *)Pv,
+                                              (const float *)AP, part);
     else
-        k_cg_xr<double><<<blocks(tot), 256, 0, s>>>(tot, nrhs, scal, (double *)X, (double *)R,
-                                                     (const double *)Pv, (const double *)AP);
+        k_cg_xr_dot<double><<<g, 256, 0, s>>>(n, nrhs, scal, (double *)X, (double *)R, (const double *)Pv,
+                                               (const double *)AP, part);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_beta(int nrhs, double *scal, double tol, double *hist, hipStream_t s)
+hipError_t launch_cg_beta(int nrhs, const double *part, double *scal, double tol, double *hist, hipStream_t s)
 {
-    k_cg_beta<<<1, 64, 0, s>>>(nrhs, scal, tol, hist);
+    k_dot_final_beta<<<(unsigned)nrhs, 128, 0, s>>>(part, kDotBlocks, nrhs, scal, tol, hist);
     return hipGetLastError();
 }
 

@@ -259,11 +259,16 @@ hipError_t launch_coldots(int prec, const void *A, int64_t lda, const void *B, i
 hipError_t launch_cg_init(int prec, int64_t n, int nrhs, const void *B, void *X, void *R, void *Pv,
                           hipStream_t s);
 hipError_t launch_cg_start(int nrhs, double *scal, hipStream_t s);
-hipError_t launch_cg_alpha(int nrhs, double *scal, hipStream_t s);
+// One CG iteration besides the apply: partials of p^T Khat p (launch_dot_part),
+// their sum and alpha (launch_cg_alpha, also advances the iteration index),
+// the x/r update with the partials of the new r^T r (launch_cg_xr), their sum,
+// beta, the convergence test and the Lanczos history (launch_cg_beta), then p.
+hipError_t launch_dot_part(int prec, const void *A, int64_t lda, const void *B, int64_t ldb, int64_t n,
+                           int ncol, double *part, hipStream_t s);
+hipError_t launch_cg_alpha(int nrhs, const double *part, double *scal, hipStream_t s);
 hipError_t launch_cg_xr(int prec, int64_t n, int nrhs, const double *scal, void *X, void *R,
-                        const void *Pv, const void *AP, hipStream_t s);
-hipError_t launch_cg_beta(int nrhs, double *scal, double tol, double *hist,
-                          hipStream_t s);
+                        const void *Pv, const void *AP, double *part, hipStream_t s);
+hipError_t launch_cg_beta(int nrhs, const double *part, double *scal, double tol, double *hist, hipStream_t s);
 hipError_t launch_cg_p(int prec, int64_t n, int nrhs, const double *scal, const void *R, void *Pv,
                        hipStream_t s);
 
