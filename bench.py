@@ -374,10 +374,28 @@ def main():
             if t_cpu >= 8.0 or nr >= n:
                 break
             nr = int(min(n, nr * max(2.0, 12.0 / max(t_cpu, 1e-3))))
-        cpu = {"value": len(rows) * nrhs / t_cpu, "unit": "n×RHS/s", "cores": oracle.num_threads(),
+        cores = oracle.num_threads()
+        # one thread on a smaller sample (about 2 s) for the per-core rate
+        rows1 = rows[: max(1, len(rows) // max(1, 4 * cores))]
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        oracle.dense_apply(pb, Vo, rows=rows1)
+        t_one = time.perf_counter() - t0
+        oracle.set_threads(cores)
+        model_name = ""
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model_name = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+        cpu = {"value": len(rows) * nrhs / t_cpu, "unit": "n×RHS/s", "cores": cores,
                "kind": "oracle",
                "sample": f"exact dense additive product (O1, FP64, all derivative blocks) for {len(rows)} "
-                         f"random target rows x all {n} source points x {nrhs} vector(s); {t_cpu:.1f} s"}
+                         f"random target rows x all {n} source points x {nrhs} vector(s); {t_cpu:.1f} s",
+               "one_thread": {"value": len(rows1) * nrhs / t_one, "rows": len(rows1), "seconds": t_one},
+               "cpu_model": model_name}
 
     res = {
         "metric": METRIC, "value": value, "unit": "n×RHS/s", "n_gpus": 1, "steps": args.steps,
