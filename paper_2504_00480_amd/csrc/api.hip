@@ -562,6 +562,10 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         const char *sfv = std::getenv("NFFTGP_SPREAD_FORM");   // "quad" | "run"
         G.spread_form = !sfv ? 0 : (std::strcmp(sfv, "quad") == 0 ? 1 : (std::strcmp(sfv, "run") == 0 ? 2 : 0));
         const char *iov = std::getenv("NFFTGP_INTERP");
+        // d <= 2: LDS bytes of the several-vector staging, NFFTGP_INTERP_VB=<bytes>
+        // overrides ("0": one vector per staging)
+        const char *ivb = std::getenv("NFFTGP_INTERP_VB");
+        G.interp_vb_lds = ivb ? std::max(0, std::atoi(ivb)) : (80 << 10);
         G.use_run_interp = iov && std::strcmp(iov, "run") == 0 && n > 0;
         const bool full = iov && std::strcmp(iov, "tilefull") == 0;
         TRYS(build_interp_lists(plan, G, iov && std::strcmp(iov, "tile2") == 0 ? 2 : 1,

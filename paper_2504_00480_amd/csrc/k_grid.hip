@@ -22,6 +22,7 @@
 #include "nfftgp_dev.h"
 #include "nfftgp_coef_sep.h"
 
+#include <cstdint>
 #include <cstdlib>
 #include <type_traits>
 
@@ -799,6 +800,174 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     }
 }
 
+// d <= 2 with at least 16 / sizeof(T) vectors: the tiles of up to vb vectors
+// are staged at once, cell-major (a cell's vb values, for DER then its vb
+// derivative values, then 16 bytes of padding that put neighbouring cells on
+// different LDS banks; vectors past nrhs in the last chunk are staged as
+// zeros).  One barrier serves vb vectors, one 16-byte LDS read gives a tap for
+// 16 / sizeof(T) vectors, and a point's outputs fill its output row in order,
+// in 16-byte stores when vst (rows 16-byte aligned), else element by element.
+// Taps are summed in the order of k_interp.
+template <typename T, int D, int M, bool DER, int PT>
+__global__ void __launch_bounds__(256)
+k_interp_vb(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
+            const int *__restrict__ sub_bin, const int *__restrict__ sub_start,
+            const int *__restrict__ sub_count, int tb, int nb, int ng, int nwin,
+            const typename Cplx<T>::type *__restrict__ grid, int64_t cells, int nrhs, int vb,
+            int vst, int64_t n, T *__restrict__ hbuf, T *__restrict__ dout, T dscale)
+{
+    static_assert(D <= 2, "d <= 2 only");
+    using C = typename Cplx<T>::type;
+    constexpr int CH = 16 / (int)sizeof(T);
+    struct alignas(16) V { T x[CH]; };
+    constexpr int TW = 2 * M;
+    constexpr int RS = D * TW;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *tile = reinterpret_cast<T *>(smem_raw);
+    const int pd = tb + 2 * M;
+    const int pc = D == 1 ? pd : pd * pd;
+    const int S = vb * (DER ? 2 : 1) + CH;   // values per staged cell
+    const float inv_pd = 1.0f / (float)pd, inv_pc = 1.0f / (float)pc;
+    const int sq = xcd_item(blockIdx.x, gridDim.x);
+    const int wi = sub_win[sq];
+    const WinDesc &win = wd[wi];
+    const T *rec = reinterpret_cast<const T *>(win.rec);
+    const int start = sub_start[sq], cnt = sub_count[sq];
+    int org[3] = {0, 0, 0};
+    bin_origin<D>(sub_bin[sq] & 0xffffff, nb, tb, org);
+    bool mine[PT];
+    T w[PT][D][TW];
+    int lin[PT];
+    int64_t orow[PT];
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+        const int k = (int)threadIdx.x + 256 * p;
+        mine[p] = k < cnt;
+        const int64_t j = start + (mine[p] ? k : 0);
+        const T *rp = rec + j * RS;
+#pragma unroll
+        for (int q = 0; q < D; ++q)
+#pragma unroll
+            for (int a = 0; a < TW; ++a) w[p][q][a] = rp[q * TW + a];
+        lin[p] = win.lpos[j] & 0xfffff;
+        orow[p] = (int64_t)win.perm[j] * nrhs;
+    }
+    T *hout = hbuf + (int64_t)win.s_global * n * nrhs;
+    T *dblk = DER ? dout + (int64_t)win.s_global * n * nrhs : nullptr;
+    for (int r0 = 0; r0 < nrhs; r0 += vb) {
+        const int nv = min(vb, nrhs - r0);
+        const int nch = (nv + CH - 1) / CH;   // 16-byte chunks of vectors in this batch
+        if (r0 > 0) __syncthreads();
+        // staging: unit u = (chunk, cell), cells fastest so that a wave's
+        // grid reads run along grid rows; UB units per thread in flight
+        constexpr int UB = 4;
+        const int nu = nch * pc;
+        for (int u0 = 0; u0 < nu; u0 += UB * 256) {
+            V vK[UB], vD[UB];
+            int dst[UB];
+#pragma unroll
+            for (int b = 0; b < UB; ++b) {
+                const int u = u0 + b * 256 + (int)threadIdx.x;
+                const bool ok = u < nu;
+                const int ch = fdiv_small(ok ? u : 0, pc, inv_pc);
+                const int cell = (ok ? u : 0) - ch * pc;
+                bool in = ok;
+                int64_t g;
+                if constexpr (D == 1) {
+                    const int l = org[0] - M + cell;
+                    in = in && l >= 0 && l < ng;
+                    g = l;
+                } else {
+                    const int a = fdiv_small(cell, pd, inv_pd);
+                    const int l0 = org[0] - M + a, l1 = org[1] - M + (cell - a * pd);
+                    in = in && l0 >= 0 && l0 < ng && l1 >= 0 && l1 < ng;
+                    g = (int64_t)l0 * ng + l1;
+                }
+                dst[b] = ok ? cell * S + ch * CH : -1;
+                const int vrow = r0 + ch * CH;
+                const C *gK = grid + ((int64_t)wi * nrhs + vrow) * cells + (in ? g : 0);
+                const C *gD = grid + ((int64_t)(nwin + wi) * nrhs + vrow) * cells + (in ? g : 0);
+#pragma unroll
+                for (int e = 0; e < CH; ++e) {
+                    const bool ine = in && vrow + e < nrhs;
+                    vK[b].x[e] = ine ? gK[(int64_t)e * cells].x : T(0);
+                    vD[b].x[e] = (DER && ine) ? gD[(int64_t)e * cells].x : T(0);
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < UB; ++b) {
+                if (dst[b] < 0) continue;
+                *reinterpret_cast<V *>(tile + dst[b]) = vK[b];
+                if (DER) *reinterpret_cast<V *>(tile + dst[b] + vb) = vD[b];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < PT; ++p) {
+            if (!mine[p]) continue;
+#pragma unroll 1
+            for (int c = 0; c < nch; ++c) {
+                const T *tc = tile + c * CH;
+                V hK, hD;
+#pragma unroll
+                for (int e = 0; e < CH; ++e) hK.x[e] = hD.x[e] = T(0);
+                if constexpr (D == 1) {
+#pragma unroll
+                    for (int aa = 0; aa < TW; ++aa) {
+                        const T *cp = tc + (lin[p] + aa) * S;
+                        const V xK = *reinterpret_cast<const V *>(cp);
+#pragma unroll
+                        for (int e = 0; e < CH; ++e) hK.x[e] += xK.x[e] * w[p][0][aa];
+                        if constexpr (DER) {
+                            const V xD = *reinterpret_cast<const V *>(cp + vb);
+#pragma unroll
+                            for (int e = 0; e < CH; ++e) hD.x[e] += xD.x[e] * w[p][0][aa];
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int aa = 0; aa < TW; ++aa) {
+                        V sK, sD;
+#pragma unroll
+                        for (int e = 0; e < CH; ++e) sK.x[e] = sD.x[e] = T(0);
+                        const int row = lin[p] + aa * pd;
+#pragma unroll
+                        for (int bb = 0; bb < TW; ++bb) {
+                            const T *cp = tc + (row + bb) * S;
+                            const V xK = *reinterpret_cast<const V *>(cp);
+#pragma unroll
+                            for (int e = 0; e < CH; ++e) sK.x[e] += xK.x[e] * w[p][D - 1][bb];
+                            if constexpr (DER) {
+                                const V xD = *reinterpret_cast<const V *>(cp + vb);
+#pragma unroll
+                                for (int e = 0; e < CH; ++e) sD.x[e] += xD.x[e] * w[p][D - 1][bb];
+                            }
+                        }
+#pragma unroll
+                        for (int e = 0; e < CH; ++e) {
+                            hK.x[e] += sK.x[e] * w[p][0][aa];
+                            if (DER) hD.x[e] += sD.x[e] * w[p][0][aa];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < CH; ++e) hD.x[e] *= dscale;
+                const int64_t o = orow[p] + r0 + c * CH;
+                if (vst) {
+                    *reinterpret_cast<V *>(hout + o) = hK;
+                    if (DER) *reinterpret_cast<V *>(dblk + o) = hD;
+                } else {
+                    const int ne = min(CH, nv - c * CH);
+                    for (int e = 0; e < ne; ++e) {
+                        hout[o + e] = hK.x[e];
+                        if (DER) dblk[o + e] = hD.x[e];
+                    }
+                }
+            }
+        }
+    }
+}
+
 // Sum over the 64 lanes of a wave, returned in every lane.  FP32: DPP moves
 // inside rows of 16 lanes (swap neighbours, swap pairs, rotate by 4 and by 8),
 // then the four row sums are read with readlane; FP64 uses shuffles.
@@ -1057,6 +1226,25 @@ __global__ void k_assemble(int64_t n, int nrhs, int P, const T *__restrict__ V, 
 }
 
 // Kernels that need more than 64 KiB of dynamic LDS must say so before launch.
+// Vectors per staging of k_interp_vb: the batch count is the smallest whose
+// tiles (pc cells of vb values, twice that with derivatives, plus 16 bytes of
+// padding per cell) fit lds bytes, and the vectors are then dealt evenly in
+// 16-byte chunks.  0 (one vector per staging) when nrhs is below a chunk or
+// one chunk does not fit.
+int interp_vectors_per_batch(int pc, int nrhs, bool der, int tsize, size_t lds)
+{
+    const int ch = 16 / tsize;
+    if (nrhs < ch || pc <= 0) return 0;
+    const long per_cell = (long)(lds / (size_t)pc) - 16;
+    int vmax = (int)(per_cell / ((der ? 2 : 1) * tsize));
+    vmax -= vmax % ch;
+    if (vmax < ch) return 0;
+    const int nbatch = (nrhs + vmax - 1) / vmax;
+    int vb = (nrhs + nbatch - 1) / nbatch;
+    vb += (ch - vb % ch) % ch;
+    return vb;
+}
+
 template <typename K>
 hipError_t allow_lds(K kernel, size_t bytes)
 {
@@ -1139,6 +1327,34 @@ hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool
                 G.desc, G.rsub_win, G.rsub_start, G.rsub_count, g.ng, g.tb, G.nwin, (const C *)grid, g.cells,
                 nrhs, n, (T *)hbuf, nullptr, (T)dscale);
         return hipGetLastError();
+    }
+    if constexpr (D <= 2) {
+        // several vectors per staging when they come in 16-byte chunks and
+        // the outputs are 16-byte aligned
+        const int vb = G.interp_vb_lds > 0
+                           ? interp_vectors_per_batch(g.pc, nrhs, with_der, (int)sizeof(T), G.interp_vb_lds)
+                           : 0;
+        const int vst = nrhs % (16 / (int)sizeof(T)) == 0 && reinterpret_cast<uintptr_t>(hbuf) % 16 == 0 &&
+                        (!with_der || reinterpret_cast<uintptr_t>(dout) % 16 == 0);
+        if (vb > 0) {
+            const size_t shm = (size_t)g.pc * (vb * (with_der ? 2 : 1) + 16 / sizeof(T)) * sizeof(T);
+            auto go = [&](auto der_tag, auto pt_tag) -> hipError_t {
+                constexpr bool DR = decltype(der_tag)::value;
+                constexpr int PT = decltype(pt_tag)::value;
+                hipError_t e = allow_lds(k_interp_vb<T, D, M, DR, PT>, shm);
+                if (e != hipSuccess) return e;
+                k_interp_vb<T, D, M, DR, PT><<<(unsigned)G.nisub, 256, shm, s>>>(
+                    G.desc, G.isub_win, G.isub_bin, G.isub_start, G.isub_count, g.tb, g.nb, g.ng, G.nwin,
+                    (const C *)grid, g.cells, nrhs, vb, vst, n, (T *)hbuf, DR ? (T *)dout : nullptr,
+                    (T)dscale);
+                return hipGetLastError();
+            };
+            using t1 = std::integral_constant<int, 1>;
+            using t2 = std::integral_constant<int, 2>;
+            if (with_der)
+                return G.interp_pt == 2 ? go(std::true_type(), t2()) : go(std::true_type(), t1());
+            return G.interp_pt == 2 ? go(std::false_type(), t2()) : go(std::false_type(), t1());
+        }
     }
     // the 3-D staging covers a padded plane of at most (8 + 2m)^2 cells and
     // rows <= pd first-axis rows of it

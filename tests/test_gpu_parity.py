@@ -66,6 +66,8 @@ SMALL = [
     (7, 1200, [3], 0, 1.2, 32, 6, 1, "normal"),
     (8, 1000, [3, 1], [1, 0], [0.5, 0.5], [8, 8], 2, 1, "normal"),
     (9, 1200, [3, 2], [0, 1], [0.3, 0.5], [64, 128], 4, 2, "normal"),   # line passes on strided axes
+    # d <= 2 with 36 vectors: several vectors per tile staging, in ragged batches
+    (10, 1500, [2, 1, 2], [1, 0, 0], [0.4, 0.3, 0.7], [64, 64, 32], 6, 36, "normal"),
 ]
 
 
@@ -166,6 +168,41 @@ def test_interp_variants_agree(prec, monkeypatch):
     for o in outs[1:]:
         for k in outs[0]:
             assert _rel(o[k], outs[0][k]) <= tol, k
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("nrhs", [4, 17, 40])
+def test_interp_vector_batches_agree(prec, nrhs, monkeypatch):
+    """d <= 2: staging several vectors per tile (the default from 16 bytes of
+    vectors on) sums every tap in the same order as one vector per staging, so
+    both give the same outputs, with and without the derivative outputs; 17
+    vectors end in a partial chunk with element stores, 40 take several
+    batches at m = 6."""
+    from paper_2504_00480_amd import AdditiveKernelPlan
+    w = workloads.small(14, 30000, [2, 1, 2], [0, 1, 0], [0.5, 0.3, 0.8], [64, 128, 32], 6, nrhs,
+                        dist="cluster")
+    dt = torch.float64 if prec == "f64" else torch.float32
+    X = torch.tensor(w.X, dtype=dt, device="cuda:0")
+    V = torch.tensor(w.V, dtype=dt, device="cuda:0")
+    for derivs in (False, True):
+        outs = []
+        # default staging budget, a small one (more batches), one vector per staging
+        for vb in (None, "40000", "0"):
+            if vb is None:
+                monkeypatch.delenv("NFFTGP_INTERP_VB", raising=False)
+            else:
+                monkeypatch.setenv("NFFTGP_INTERP_VB", vb)
+            plan = AdditiveKernelPlan(X, w.windows, w.ktype, w.N, w.m, max_nrhs=nrhs)
+            plan.set_hyper(1.1, w.ell, 0.3)
+            o = plan.apply(V, derivs=derivs)
+            outs.append({k: (v.double().cpu().numpy() if not isinstance(v, list) else
+                             np.stack([x.double().cpu().numpy() for x in v])) for k, v in o.items()})
+        print(f"[case] nrhs={nrhs} prec={prec} derivs={derivs}", flush=True)
+        tol = 1e-13 if prec == "f64" else 1e-6
+        for o in outs[1:]:
+            for k in outs[0]:
+                assert _rel(o[k], outs[0][k]) <= tol, k
+    monkeypatch.delenv("NFFTGP_INTERP_VB")
 
 
 def test_autotune_keeps_results(orc):
