@@ -555,8 +555,9 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         }
         // interpolation variant: the per-point tile variant by default (the
         // faster one on every measured workload once its tile staging was
-        // batched); nfftgp_autotune may switch, NFFTGP_INTERP=run|tile|tile2|tilefull
-        // forces (tile2: two points per thread; tilefull: whole padded tiles staged)
+        // batched); nfftgp_autotune may switch, NFFTGP_INTERP=run|tile|tile2|tilepair|tilefull
+        // forces (tile2: two points per thread; tilepair: two adjacent sorted points
+        // per thread sharing tap reads, 3-D; tilefull: whole padded tiles staged)
         const char *swv = std::getenv("NFFTGP_SPREAD_W");   // "2": two waves per 3-D tile
         G.spread_W = swv && std::strcmp(swv, "2") == 0 ? 2 : 0;
         const char *sfv = std::getenv("NFFTGP_SPREAD_FORM");   // "quad" | "run"
@@ -568,7 +569,9 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         G.interp_vb_lds = ivb ? std::max(0, std::atoi(ivb)) : (80 << 10);
         G.use_run_interp = iov && std::strcmp(iov, "run") == 0 && n > 0;
         const bool full = iov && std::strcmp(iov, "tilefull") == 0;
-        TRYS(build_interp_lists(plan, G, iov && std::strcmp(iov, "tile2") == 0 ? 2 : 1,
+        const bool pair = iov && std::strcmp(iov, "tilepair") == 0;
+        G.interp_adj = pair && G.g.d == 3;
+        TRYS(build_interp_lists(plan, G, iov && (pair || std::strcmp(iov, "tile2") == 0) ? 2 : 1,
                                 full ? G.g.pd : interp_rows_rule(G.g, m)));
         {
             // run-interpolation list (built for every group, so that the
@@ -805,22 +808,26 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
         }
         // 3) interpolation variant: tile with 1 or 2 points per thread, whole
         //    padded tile or the rule's row window (3-D), or runs
-        const bool cur_run = G.use_run_interp;
+        const bool cur_run = G.use_run_interp, cur_adj = G.interp_adj;
         const int cur_pt = G.interp_pt, cur_rows = G.interp_rows;
-        bool best_run = cur_run;
+        bool best_run = cur_run, best_adj = cur_adj;
         int best_pt = cur_pt, best_rows = cur_rows;
-        struct Cand { bool run; int pt, rows; };
+        struct Cand { bool run; int pt, rows; bool adj; };
         std::vector<Cand> cands;
         const int rr = interp_rows_rule(G.g, plan->m);
         for (int pt : {1, 2}) {
-            cands.push_back({false, pt, rr});
-            if (rr != G.g.pd) cands.push_back({false, pt, G.g.pd});
+            cands.push_back({false, pt, rr, false});
+            if (rr != G.g.pd) cands.push_back({false, pt, G.g.pd, false});
         }
-        cands.push_back({true, cur_pt, cur_rows});
+        if (G.g.d == 3) cands.push_back({false, 2, rr, true});
+        cands.push_back({true, cur_pt, cur_rows, cur_adj});
         for (const Cand &c : cands) {
             if (stt != NFFTGP_OK) break;
-            if (c.run == cur_run && (c.run || (c.pt == cur_pt && c.rows == cur_rows))) continue;
+            if (c.run == cur_run &&
+                (c.run || (c.pt == cur_pt && c.rows == cur_rows && c.adj == cur_adj)))
+                continue;
             G.use_run_interp = c.run;
+            G.interp_adj = c.adj;
             if (!c.run && (stt = build_interp_lists(plan, G, c.pt, c.rows)) != NFFTGP_OK) break;
             double t = 0.0;
             if ((stt = timed(t)) != NFFTGP_OK) break;
@@ -829,14 +836,16 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
                 best_run = c.run;
                 best_pt = c.pt;
                 best_rows = c.rows;
+                best_adj = c.adj;
             }
         }
         if (stt != NFFTGP_OK) break;
         G.use_run_interp = best_run;
+        G.interp_adj = best_adj;
         if ((stt = build_interp_lists(plan, G, best_pt, best_rows)) != NFFTGP_OK) break;
         std::string ivar = "run";
         if (!G.use_run_interp) {
-            ivar = G.interp_pt == 2 ? "tile, 2 points/thread" : "tile";
+            ivar = G.interp_adj ? "tile, adjacent point pairs" : (G.interp_pt == 2 ? "tile, 2 points/thread" : "tile");
             if (G.g.d == 3) ivar += ", " + std::to_string(G.interp_rows) + " of " + std::to_string(G.g.pd) + " rows";
         }
         char line[240];

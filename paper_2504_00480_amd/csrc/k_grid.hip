@@ -585,12 +585,14 @@ k_fold(const WinDesc *__restrict__ wd, const T *__restrict__ tilebuf, int nrhs, 
 }
 
 // ---------------------------------------------------------------- interpolation
-// One thread per point (subproblems of at most 256 points of one tile).  The
-// padded tile of the grid (and of the derivative grid) is staged in LDS for
-// one vector at a time; the point's window weights are loaded once and reused
-// for every vector.  Each window writes its own block of the per-window
-// output buffer (one owner thread per entry).
-template <typename T, int D, int M, bool DER, int PT>
+// One thread per PT points (subproblems of at most 256 PT points of one
+// tile): points t, t + 256, ..., or with ADJ (d = 3, PT = 2) the adjacent
+// sorted points 2t and 2t + 1.  The padded tile of the grid (and of the
+// derivative grid) is staged in LDS for one vector at a time; the point's
+// window weights are loaded once and reused for every vector.  Each window
+// writes its own block of the per-window output buffer (one owner thread per
+// entry).
+template <typename T, int D, int M, bool DER, int PT, bool ADJ = false>
 __global__ void __launch_bounds__(256)
 k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
          const int *__restrict__ sub_bin, const int *__restrict__ sub_start,
@@ -632,7 +634,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     int64_t orow[PT];
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
-        const int k = (int)threadIdx.x + 256 * p;
+        const int k = ADJ ? 2 * (int)threadIdx.x + p : (int)threadIdx.x + 256 * p;
         mine[p] = k < cnt;
         const int64_t j = start + (mine[p] ? k : 0);
         rp[p] = rec + j * RS;
@@ -759,6 +761,86 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
         }
         }
         __syncthreads();
+        if constexpr (ADJ && D == 3 && PT == 2) {
+            // two adjacent sorted points per thread: where they share a cell
+            // (same first tap) each tap value read serves both; the second
+            // point's rows are read again only in lanes whose cells differ
+            if (mine[0]) {
+                const bool same = lin[0] == lin[1];
+                T hK[2] = {T(0), T(0)}, hD[2] = {T(0), T(0)};
+#pragma unroll 1
+                for (int aa = 0; aa < TW; ++aa) {
+                    const T wa[2] = {rp[0][(f0[0] + aa) % TW], rp[1][(f0[1] + aa) % TW]};
+                    T sK[2] = {T(0), T(0)}, sD[2] = {T(0), T(0)};
+#pragma unroll
+                    for (int bb = 0; bb < TW; ++bb) {
+                        const int off = (aa * pd + bb) * pd;
+                        T aK[TW], aD[TW];
+#pragma unroll
+                        for (int cc = 0; cc < TW; ++cc) {
+                            if constexpr (DER) {
+                                const C v = tKD[lin[0] + off + cc];
+                                aK[cc] = v.x;
+                                aD[cc] = v.y;
+                            } else {
+                                aK[cc] = tK[lin[0] + off + cc];
+                                aD[cc] = T(0);
+                            }
+                        }
+                        T bK[TW], bD[TW];
+#pragma unroll
+                        for (int cc = 0; cc < TW; ++cc) {
+                            bK[cc] = aK[cc];
+                            bD[cc] = aD[cc];
+                        }
+                        if (!same) {
+#pragma unroll
+                            for (int cc = 0; cc < TW; ++cc) {
+                                if constexpr (DER) {
+                                    const C v = tKD[lin[1] + off + cc];
+                                    bK[cc] = v.x;
+                                    bD[cc] = v.y;
+                                } else {
+                                    bK[cc] = tK[lin[1] + off + cc];
+                                }
+                            }
+                        }
+                        T cK0 = T(0), cD0 = T(0), cK1 = T(0), cD1 = T(0);
+#pragma unroll
+                        for (int cc = 0; cc < TW; ++cc) {
+                            cK0 += aK[cc] * w[0][2][cc];
+                            cK1 += bK[cc] * w[1][2][cc];
+                            if (DER) {
+                                cD0 += aD[cc] * w[0][2][cc];
+                                cD1 += bD[cc] * w[1][2][cc];
+                            }
+                        }
+                        sK[0] += cK0 * w[0][1][bb];
+                        sK[1] += cK1 * w[1][1][bb];
+                        if (DER) {
+                            sD[0] += cD0 * w[0][1][bb];
+                            sD[1] += cD1 * w[1][1][bb];
+                        }
+                        // the row's sums are complete here, before the next
+                        // row's reads (else the compiler defers every row's
+                        // FMAs until all rows are loaded)
+                        asm volatile("" : "+v"(sK[0]), "+v"(sK[1]), "+v"(sD[0]), "+v"(sD[1]));
+                    }
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        hK[q] += sK[q] * wa[q];
+                        if (DER) hD[q] += sD[q] * wa[q];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    if (!mine[q]) continue;
+                    hout[orow[q] + r] = hK[q];
+                    if (DER) dblk[orow[q] + r] = dscale * hD[q];
+                }
+            }
+            continue;
+        }
 #pragma unroll
         for (int p = 0; p < PT; ++p) {
             if (!mine[p]) continue;
@@ -1365,6 +1447,16 @@ hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool
     auto go = [&](auto der_tag, auto pt_tag) -> hipError_t {
         constexpr bool DR = decltype(der_tag)::value;
         constexpr int PT = decltype(pt_tag)::value;
+        if constexpr (D == 3 && PT == 2) {
+            if (G.interp_adj) {
+                hipError_t e = allow_lds(k_interp<T, D, M, DR, 2, true>, shm);
+                if (e != hipSuccess) return e;
+                k_interp<T, D, M, DR, 2, true><<<(unsigned)G.nisub, 256, shm, s>>>(
+                    G.desc, G.isub_win, G.isub_bin, G.isub_start, G.isub_count, g.tb, g.nb, g.ng, G.nwin, rows,
+                    (const C *)grid, g.cells, nrhs, n, (T *)hbuf, DR ? (T *)dout : nullptr, (T)dscale);
+                return hipGetLastError();
+            }
+        }
         hipError_t e = allow_lds(k_interp<T, D, M, DR, PT>, shm);
         if (e != hipSuccess) return e;
         k_interp<T, D, M, DR, PT><<<(unsigned)G.nisub, 256, shm, s>>>(

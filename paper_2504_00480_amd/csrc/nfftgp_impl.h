@@ -108,6 +108,7 @@ struct Group {
     CoefParams prm{};
     int sub_cap = 0;             // capacity of the spreading list arrays
     int interp_pt = 1;           // points per thread of the tile interpolation (1, 2)
+    bool interp_adj = false;     // 3-D, 2 points per thread: adjacent sorted points share tap reads
     int interp_vb_lds = 80 << 10;   // d <= 2: LDS bytes for several vectors per staging (0: one vector)
     int interp_rows = 0;         // 3-D: first-axis rows of the padded tile staged per subproblem
     int isub_cap = 0;            // capacity of the interpolation list arrays
