@@ -807,7 +807,9 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
                 G.spread_W = cur_W;
         }
         // 3) interpolation variant: tile with 1 or 2 points per thread, whole
-        //    padded tile or the rule's row window (3-D), or runs
+        //    padded tile or the rule's row window (3-D), or runs (the pair form
+        //    is not a candidate: the tuner times applies with derivative outputs,
+        //    and the pair form's K-only launches, which CG makes, are slower)
         const bool cur_run = G.use_run_interp, cur_adj = G.interp_adj;
         const int cur_pt = G.interp_pt, cur_rows = G.interp_rows;
         bool best_run = cur_run, best_adj = cur_adj;
@@ -819,7 +821,6 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
             cands.push_back({false, pt, rr, false});
             if (rr != G.g.pd) cands.push_back({false, pt, G.g.pd, false});
         }
-        if (G.g.d == 3) cands.push_back({false, 2, rr, true});
         cands.push_back({true, cur_pt, cur_rows, cur_adj});
         for (const Cand &c : cands) {
             if (stt != NFFTGP_OK) break;
