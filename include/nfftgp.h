@@ -58,7 +58,13 @@ typedef enum {
     NFFTGP_E_STATE = -8   /* call order violated (e.g. apply before set_hyper)     */
 } nfftgp_status;
 
-typedef enum { NFFTGP_GAUSS = 0, NFFTGP_MATERN12 = 1 } nfftgp_kernel;
+/* Sub-kernels (unit variance, distance r, length-scale ell; eq. kernel_definition):
+ * GAUSS     exp(-r^2 / (2 ell^2))
+ * MATERN12  exp(-r / ell)
+ * MATERN32  (1 + sqrt(3) r / ell) exp(-sqrt(3) r / ell), the order-3/2 Matern
+ *           kernel of Sec. 4 (generalization to other orders); same pipeline,
+ *           only the sampled kernel and its ell-derivative differ. */
+typedef enum { NFFTGP_GAUSS = 0, NFFTGP_MATERN12 = 1, NFFTGP_MATERN32 = 2 } nfftgp_kernel;
 typedef enum { NFFTGP_F32 = 0, NFFTGP_F64 = 1 } nfftgp_prec;
 
 /* Scaling of each window into the box [-1/4, 1/4)^d required by Sec. 3.1.

@@ -43,6 +43,7 @@ _lib = None
 
 GAUSS = 0
 MATERN12 = 1
+MATERN32 = 2
 
 
 def build(force: bool = True) -> str:
@@ -96,11 +97,18 @@ def kernel(ktype: int, r, ell: float):
 
     Gaussian  exp(-r^2/(2 ell^2)),  d/d ell = r^2/ell^3 * exp(...)
     Matern-1/2 exp(-r/ell),         d/d ell = r/ell^2   * exp(...)
+    Matern-3/2 (1 + a) exp(-a), a = sqrt(3) r / ell,  d/d ell = 3 r^2/ell^3 * exp(-a)
+    (the order-3/2 member of the Matern family that Sec. 4 names as a further
+    kernel for the same method; ell is its length-scale)
     """
     r = np.asarray(r, dtype=np.float64)
     if ktype == GAUSS:
         e = np.exp(-(r * r) / (2.0 * ell * ell))
         return e, (r * r) / ell ** 3 * e
+    if ktype == MATERN32:
+        a = np.sqrt(3.0) * r / ell
+        e = np.exp(-a)
+        return (1.0 + a) * e, 3.0 * r * r / ell ** 3 * e
     e = np.exp(-r / ell)
     return e, r / ell ** 2 * e
 

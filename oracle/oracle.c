@@ -41,18 +41,25 @@
 
 #define ORC_PI 3.14159265358979323846264338327950288
 
-enum { ORC_GAUSS = 0, ORC_MATERN12 = 1 };
+enum { ORC_GAUSS = 0, ORC_MATERN12 = 1, ORC_MATERN32 = 2 };
 
 /* Kernel value and its derivative with respect to ell, for distance r >= 0.
  * Gaussian:   exp(-r^2/(2 ell^2)),   derivative (r^2/ell^3) exp(...)
  * Matern-1/2: exp(-r/ell),           derivative (r/ell^2)   exp(...)
- * (eq. kernel_definition with unit variance, eq. def_der_additive_kernels). */
+ * Matern-3/2: (1 + a) exp(-a) with a = sqrt(3) r / ell,
+ *             derivative (3 r^2/ell^3) exp(-a)
+ * (eq. kernel_definition with unit variance, eq. def_der_additive_kernels;
+ * the order-3/2 Matern kernel of Sec. 4, generalization to other orders). */
 void orc_kernel(int type, double r, double ell, double *val, double *dval)
 {
     if (type == ORC_GAUSS) {
         double e = exp(-(r * r) / (2.0 * ell * ell));
         *val = e;
         *dval = (r * r) / (ell * ell * ell) * e;
+    } else if (type == ORC_MATERN32) {
+        double a = sqrt(3.0) * r / ell, e = exp(-a);
+        *val = (1.0 + a) * e;
+        *dval = 3.0 * r * r / (ell * ell * ell) * e;
     } else {
         double e = exp(-r / ell);
         *val = e;

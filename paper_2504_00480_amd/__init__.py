@@ -7,7 +7,7 @@ hyper-parameter derivatives, batched CG with FP64 scalars, stochastic Lanczos
 quadrature and the log-marginal-likelihood gradient.  The numerical work runs
 in hand-written HIP kernels behind the C ABI declared in include/nfftgp.h.
 """
-from .plan import (AdditiveKernelPlan, GAUSS, MATERN12, SCALE_AUTO, SCALE_NONE,  # noqa: F401
+from .plan import (AdditiveKernelPlan, GAUSS, MATERN12, MATERN32, SCALE_AUTO, SCALE_NONE,  # noqa: F401
                    slq_logquad)
 from .gp import khat_apply, lml_estimate, lml_surrogate  # noqa: F401
 from .model import AdditiveGP  # noqa: F401

@@ -40,6 +40,11 @@ __device__ __forceinline__ void sample_pair(const CoefParams &prm, int w, double
     if (prm.kernel[w] == NFFTGP_GAUSS) {
         v = exp(-(r * r) / (2.0 * ell * ell));
         dv = (r * r) / (ell * ell * ell) * v;
+    } else if (prm.kernel[w] == NFFTGP_MATERN32) {
+        // (1 + a) e^-a with a = sqrt(3) r / ell; d/d ell = (3 r^2 / ell^3) e^-a
+        const double a = 1.7320508075688772 * r / ell, e = exp(-a);
+        v = (1.0 + a) * e;
+        dv = 3.0 * r * r / (ell * ell * ell) * e;
     } else {
         v = exp(-r / ell);
         dv = r / (ell * ell) * v;

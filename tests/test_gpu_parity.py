@@ -68,6 +68,8 @@ SMALL = [
     (9, 1200, [3, 2], [0, 1], [0.3, 0.5], [64, 128], 4, 2, "normal"),   # line passes on strided axes
     # d <= 2 with 36 vectors: several vectors per tile staging, in ragged batches
     (10, 1500, [2, 1, 2], [1, 0, 0], [0.4, 0.3, 0.7], [64, 64, 32], 6, 36, "normal"),
+    # Matern-3/2 windows (the order-3/2 kernel of Sec. 4) beside a Gaussian one
+    (11, 2500, [3, 2, 1, 2], [2, 2, 2, 0], [0.7, 0.5, 0.4, 0.6], [32, 64, 64, 32], 4, 4, "normal"),
 ]
 
 

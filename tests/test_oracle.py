@@ -35,7 +35,14 @@ def test_fig2_interpolates_samples(orc):
     np.testing.assert_allclose(orc.kappa_rf(b, x[:, None]), np.exp(-np.abs(x) / 0.3), atol=1e-15)
 
 
-@pytest.mark.parametrize("kt", [0, 1])
+def _sk_matern32(r, ell):
+    """Matern nu = 3/2 from scikit-learn (an independent implementation)."""
+    from sklearn.gaussian_process.kernels import Matern
+    r = np.atleast_1d(np.asarray(r, dtype=np.float64))
+    return Matern(length_scale=ell, nu=1.5)(np.zeros((1, 1)), r[:, None])[0]
+
+
+@pytest.mark.parametrize("kt", [0, 1, 2])
 @pytest.mark.parametrize("d,N", [(1, 64), (2, 16), (3, 8)])
 def test_interpolation_property_and_sums(orc, kt, d, N):
     """kappa_RF(l/N) = kappa(l/N) on the grid; sum_k b_k = kappa(0) = 1 and
@@ -46,7 +53,10 @@ def test_interpolation_property_and_sums(orc, kt, d, N):
     assert abs(bd.sum()) < 1e-12
     g = np.random.default_rng(0).integers(-N // 2, N // 2, size=(20, d)) / N
     r = np.sqrt((g * g).sum(1))
-    want = np.exp(-r * r / (2 * ell * ell)) if kt == 0 else np.exp(-r / ell)
+    if kt == 2:
+        want = _sk_matern32(r, ell)
+    else:
+        want = np.exp(-r * r / (2 * ell * ell)) if kt == 0 else np.exp(-r / ell)
     np.testing.assert_allclose(orc.kappa_rf(b, g), want, atol=1e-13)
 
 
@@ -108,7 +118,7 @@ def test_matern_coefficients_are_aliased_fourier_transform(orc, ell):
     assert err < 0.02 * b.max()
 
 
-@pytest.mark.parametrize("kt", [0, 1])
+@pytest.mark.parametrize("kt", [0, 1, 2])
 def test_derivative_coefficients_finite_difference(orc, kt):
     """Sec. 3.2 eq. exact_derivative: b^der = d b / d ell (central differences)."""
     N, ell, h = 16, 0.12, 1e-5
@@ -118,7 +128,7 @@ def test_derivative_coefficients_finite_difference(orc, kt):
     np.testing.assert_allclose(bd, (bp - bm) / (2 * h), atol=1e-8 * np.abs(bd).max() + 1e-14)
 
 
-@pytest.mark.parametrize("kt", [0, 1])
+@pytest.mark.parametrize("kt", [0, 1, 2])
 def test_box_scaling_of_coefficients(orc, kt):
     """Chain rule for the box units: kappa(r/c; ell) = kappa(r; c ell), and the
     ell-derivative in caller units carries a factor c."""
@@ -148,8 +158,27 @@ def test_matern3d_error_within_theorems(orc, N, ell):
 # --------------------------------------------------------------------------
 # kernels and O1
 # --------------------------------------------------------------------------
+def test_matern32_against_library(orc):
+    """The order-3/2 Matern kernel (Sec. 4, other orders) against scikit-learn's
+    Matern(nu=1.5); its ell-derivative against central differences of the value;
+    the C oracle's kernel against the same library values."""
+    r = np.linspace(0.0, 4.0, 401)
+    for ell in (0.05, 0.3, 1.7):
+        v, dv = orc.kernel(orc.MATERN32, r, ell)
+        np.testing.assert_allclose(v, _sk_matern32(r, ell), rtol=1e-13, atol=1e-16)
+        h = 1e-6 * ell
+        fd = (orc.kernel(orc.MATERN32, r, ell + h)[0] - orc.kernel(orc.MATERN32, r, ell - h)[0]) / (2 * h)
+        np.testing.assert_allclose(dv, fd, rtol=1e-6, atol=1e-9 / ell)
+    # the C oracle's dense matrix of a 1-D Matern-3/2 window is the library's Gram matrix
+    x = np.random.default_rng(7).uniform(-0.25, 0.25, size=(40, 1))
+    pb = orc.Problem(x, [[0]], [orc.MATERN32], [0.11], 1.0, 0.0, [16], orc.SCALE_NONE)
+    from sklearn.gaussian_process.kernels import Matern
+    np.testing.assert_allclose(orc.dense_matrix(pb, 0), Matern(length_scale=0.11, nu=1.5)(x),
+                               rtol=1e-13, atol=1e-15)
+
+
 def test_kernel_closed_forms(orc):
-    for kt, at_ell in [(0, np.exp(-0.5)), (1, np.exp(-1.0))]:
+    for kt, at_ell in [(0, np.exp(-0.5)), (1, np.exp(-1.0)), (2, (1 + np.sqrt(3)) * np.exp(-np.sqrt(3)))]:
         v, dv = orc.kernel(kt, np.array([0.0, 0.7]), 0.7)
         assert v[0] == 1.0 and dv[0] == 0.0
         assert abs(v[1] - at_ell) < 1e-16

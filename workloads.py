@@ -17,6 +17,7 @@ import numpy as np
 
 GAUSS = 0
 MATERN12 = 1
+MATERN32 = 2
 
 
 def rng(seed: int) -> np.random.Generator:
