@@ -113,15 +113,17 @@ def test_fit_lowers_exact_nll(orc):
     assert z1 < z0 - 0.1 * abs(z0), (z0, z1, model.theta)
 
 
-def test_posterior_variance_matches_oracle(orc):
+@pytest.mark.parametrize("kt", [[0, 1], [2, 2]], ids=["gauss+matern12", "matern32"])
+def test_posterior_variance_matches_oracle(orc, kt):
     """Posterior variances against the oracle's dense posterior of the
-    trigonometric-interpolant kernel on the union points (O2 matrices)."""
+    trigonometric-interpolant kernel on the union points (O2 matrices), for
+    Gaussian + Matern-1/2 windows and for Matern-3/2 windows."""
     from paper_2504_00480_amd import AdditiveGP
     X, Xt, g = _data(64, 700, 30, 4)
-    windows, kt, N, m = [[0, 1], [2, 3]], [0, 1], [32, 32], 6
+    windows, N, m = [[0, 1], [2, 3]], [32, 32], 6
     sf, se, ell = 1.1, 0.3, [1.0, 1.6]
     y = g.standard_normal(700)
-    print("[case] posterior variance", flush=True)
+    print(f"[case] posterior variance kernels {kt}", flush=True)
     model = AdditiveGP(X, y, windows, kt, N, m, X_test=Xt, dtype=torch.float64, n_probes=10)
     _set_theta(model, sf, se, ell)
     got = model.predict_var(tol=1e-13, maxit=3000).cpu().numpy()
