@@ -174,15 +174,15 @@ def test_interp_variants_agree(prec, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("nrhs", [4, 17, 40])
-def test_interp_vector_batches_agree(prec, nrhs, monkeypatch):
+@pytest.mark.parametrize("nrhs,m", [(4, 6), (17, 6), (40, 6), (8, 2), (12, 8)])
+def test_interp_vector_batches_agree(prec, nrhs, m, monkeypatch):
     """d <= 2: staging several vectors per tile (the default from 16 bytes of
     vectors on) sums every tap in the same order as one vector per staging, so
     both give the same outputs, with and without the derivative outputs; 17
     vectors end in a partial chunk with element stores, 40 take several
-    batches at m = 6."""
+    batches at m = 6; m = 2 and 8 cover the other tap widths."""
     from paper_2504_00480_amd import AdditiveKernelPlan
-    w = workloads.small(14, 30000, [2, 1, 2], [0, 1, 0], [0.5, 0.3, 0.8], [64, 128, 32], 6, nrhs,
+    w = workloads.small(14, 30000, [2, 1, 2], [0, 1, 0], [0.5, 0.3, 0.8], [64, 128, 32], m, nrhs,
                         dist="cluster")
     dt = torch.float64 if prec == "f64" else torch.float32
     X = torch.tensor(w.X, dtype=dt, device="cuda:0")
@@ -200,7 +200,7 @@ def test_interp_vector_batches_agree(prec, nrhs, monkeypatch):
             o = plan.apply(V, derivs=derivs)
             outs.append({k: (v.double().cpu().numpy() if not isinstance(v, list) else
                              np.stack([x.double().cpu().numpy() for x in v])) for k, v in o.items()})
-        print(f"[case] nrhs={nrhs} prec={prec} derivs={derivs}", flush=True)
+        print(f"[case] nrhs={nrhs} m={m} prec={prec} derivs={derivs}", flush=True)
         tol = 1e-13 if prec == "f64" else 1e-6
         for o in outs[1:]:
             for k in outs[0]:
