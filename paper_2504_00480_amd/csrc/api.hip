@@ -560,6 +560,11 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         // per thread sharing tap reads, 3-D; tilefull: whole padded tiles staged)
         const char *swv = std::getenv("NFFTGP_SPREAD_W");   // "2": two waves per 3-D tile
         G.spread_W = swv && std::strcmp(swv, "2") == 0 ? 2 : 0;
+        const char *srv = std::getenv("NFFTGP_SPREAD_R");   // vectors per work-group: 1, 2, 4
+        if (srv) {
+            const int rv = std::atoi(srv);
+            G.spread_R = (rv == 1 || rv == 2 || rv == 4) ? rv : 0;
+        }
         const char *sfv = std::getenv("NFFTGP_SPREAD_FORM");   // "quad" | "run"
         G.spread_form = !sfv ? 0 : (std::strcmp(sfv, "quad") == 0 ? 1 : (std::strcmp(sfv, "run") == 0 ? 2 : 0));
         const char *iov = std::getenv("NFFTGP_INTERP");

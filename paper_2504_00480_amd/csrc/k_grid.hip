@@ -1411,8 +1411,8 @@ hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool
         return hipGetLastError();
     }
     if constexpr (D <= 2) {
-        // several vectors per staging when they come in 16-byte chunks and
-        // the outputs are 16-byte aligned
+        // several vectors per staging from 16 bytes of vectors on; 16-byte
+        // output stores when the output rows are 16-byte aligned
         const int vb = G.interp_vb_lds > 0
                            ? interp_vectors_per_batch(g.pc, nrhs, with_der, (int)sizeof(T), G.interp_vb_lds)
                            : 0;

@@ -208,6 +208,37 @@ def test_interp_vector_batches_agree(prec, nrhs, m, monkeypatch):
     monkeypatch.delenv("NFFTGP_INTERP_VB")
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_spread_vector_groups_agree(prec, monkeypatch):
+    """d <= 2 spreading with 1, 2 or 4 vectors per work-group (forced with
+    NFFTGP_SPREAD_R), in both the run-ordered and the four-point form: every
+    vector's sums are formed in the same order, so the outputs agree to
+    rounding."""
+    from paper_2504_00480_amd import AdditiveKernelPlan
+    w = workloads.small(15, 20000, [2, 1, 2], [1, 0, 0], [0.6, 0.4, 0.9], [64, 64, 32], 4, 19,
+                        dist="cluster")
+    dt = torch.float64 if prec == "f64" else torch.float32
+    X = torch.tensor(w.X, dtype=dt, device="cuda:0")
+    V = torch.tensor(w.V, dtype=dt, device="cuda:0")
+    outs = []
+    for rv in ("1", "2", "4"):
+        for form in ("run", "quad"):
+            monkeypatch.setenv("NFFTGP_SPREAD_R", rv)
+            monkeypatch.setenv("NFFTGP_SPREAD_FORM", form)
+            print(f"[case] spread R={rv} form={form} prec={prec}", flush=True)
+            plan = AdditiveKernelPlan(X, w.windows, w.ktype, w.N, w.m, max_nrhs=w.nrhs)
+            plan.set_hyper(1.2, w.ell, 0.25)
+            outs.append({k: (v.double().cpu().numpy() if not isinstance(v, list) else
+                             np.stack([x.double().cpu().numpy() for x in v]))
+                         for k, v in plan.apply(V, derivs=True).items()})
+    monkeypatch.delenv("NFFTGP_SPREAD_R")
+    monkeypatch.delenv("NFFTGP_SPREAD_FORM")
+    tol = 1e-12 if prec == "f64" else 2e-6
+    for o in outs[1:]:
+        for k in outs[0]:
+            assert _rel(o[k], outs[0][k]) <= tol, k
+
+
 def test_autotune_keeps_results(orc):
     """The autotuner changes only how the work is laid out (subproblem sizes,
     vectors per group, interpolation variant): outputs agree with the untuned
