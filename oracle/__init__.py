@@ -527,6 +527,15 @@ def matern3d_bound(ell: float, N: int) -> float:
     return 8.0 / (np.pi ** 2 * ell * (N - 2.0 * np.sqrt(3.0)))
 
 
+def matern32_3d_bound(ell: float, N: int) -> float:
+    """Fourier error estimate of the periodised trivariate Matern-3/2 kernel
+    (proof of the derivative-kernel theorem, Sec. 4.2): 2^5 / (3 pi^4 l^3 (N - 2 sqrt 3)^3)
+    in the proof's parameter l, which is this kernel's ell / sqrt 3 (the proof
+    writes the kernel with sqrt(3) r / (sqrt(3) l))."""
+    lp = ell / np.sqrt(3.0)
+    return 32.0 / (3.0 * np.pi ** 4 * lp ** 3 * (N - 2.0 * np.sqrt(3.0)) ** 3)
+
+
 def matern3d_der_bound(ell: float, N: int) -> float:
     """Theorem (periodised trivariate derivative Matern-1/2)."""
     a = N - 2.0 * np.sqrt(3.0)

@@ -177,6 +177,38 @@ def test_matern32_against_library(orc):
                                rtol=1e-13, atol=1e-15)
 
 
+def test_matern12_derivative_is_matern32_difference(orc):
+    """The identity used in the proof of the derivative-kernel theorem (Sec. 4.2):
+    d/d ell of the Matern-1/2 kernel equals (1/ell)(Matern-3/2 at length-scale
+    sqrt(3) ell - Matern-1/2 at ell); by linearity the same holds for the
+    Fourier coefficients of the periodised kernels."""
+    r = np.linspace(0.0, 3.0, 301)
+    for ell in (0.07, 0.4, 1.3):
+        _, d12 = orc.kernel(orc.MATERN12, r, ell)
+        v32, _ = orc.kernel(orc.MATERN32, r, np.sqrt(3.0) * ell)
+        v12, _ = orc.kernel(orc.MATERN12, r, ell)
+        np.testing.assert_allclose(d12, (v32 - v12) / ell, rtol=1e-12, atol=1e-15)
+    ell = 0.11
+    _, bd12 = orc.coefficients(orc.MATERN12, 3, 16, ell)
+    b32, _ = orc.coefficients(orc.MATERN32, 3, 16, np.sqrt(3.0) * ell)
+    b12, _ = orc.coefficients(orc.MATERN12, 3, 16, ell)
+    np.testing.assert_allclose(bd12, (b32 - b12) / ell, atol=1e-12 * np.abs(bd12).max())
+
+
+@pytest.mark.parametrize("N", [16, 32])
+@pytest.mark.parametrize("ell", [0.05, 0.1, 0.2])
+def test_matern32_3d_error_within_estimate(orc, N, ell):
+    """Measured sup |kappa - kappa_RF| of the Matern-3/2 kernel on points uniform
+    in [-1/4, 1/4)^3 stays below the Fourier error estimate derived for it in
+    Sec. 4.2 (proof of the derivative-kernel theorem)."""
+    x = np.random.default_rng(6).uniform(-0.25, 0.25, size=(60, 3))
+    r = (x[:, None, :] - x[None, :, :]).reshape(-1, 3)
+    rn = np.sqrt((r * r).sum(1))
+    b, _ = orc.coefficients(orc.MATERN32, 3, N, ell)
+    e = np.abs(_sk_matern32(rn, ell) - orc.kappa_rf(b, r)).max()
+    assert e <= orc.matern32_3d_bound(ell, N), (e, orc.matern32_3d_bound(ell, N))
+
+
 def test_kernel_closed_forms(orc):
     for kt, at_ell in [(0, np.exp(-0.5)), (1, np.exp(-1.0)), (2, (1 + np.sqrt(3)) * np.exp(-np.sqrt(3)))]:
         v, dv = orc.kernel(kt, np.array([0.0, 0.7]), 0.7)
