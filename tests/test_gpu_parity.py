@@ -239,6 +239,38 @@ def test_spread_vector_groups_agree(prec, monkeypatch):
             assert _rel(o[k], outs[0][k]) <= tol, k
 
 
+def test_matern_identity_at_scale():
+    """A property that holds at any size (Sec. 4.2, proof of the derivative
+    theorem): the ell-derivative of the Matern-1/2 kernel is
+    (Matern-3/2 at sqrt(3) ell - Matern-1/2 at ell) / ell.  The samples, and so
+    the coefficients of the interpolated kernels, obey it exactly, so the GPU
+    products of three plans at n = 200 000 (3-D and 2-D windows, FP64) satisfy it
+    to rounding."""
+    from paper_2504_00480_amd import AdditiveKernelPlan
+    w = workloads.small(16, 200000, [3, 2], [1, 1], [0.5, 0.8], [32, 64], 6, 2)
+    X = torch.tensor(w.X, dtype=torch.float64, device="cuda:0")
+    V = torch.tensor(w.V, dtype=torch.float64, device="cuda:0")
+    print("[case] Matern identity n=200000", flush=True)
+    ell = np.array(w.ell)
+    a = AdditiveKernelPlan(X, w.windows, [1, 1], w.N, w.m, max_nrhs=2)
+    a.set_hyper(1.0, list(ell), 0.0)
+    oa = a.apply(V, derivs=True)
+    got = [oa["dKV_dell"][s].cpu().numpy() for s in range(2)]
+    for s in range(2):
+        # window s alone changes kernel: K_b - K_a leaves only window s's difference
+        kt = [1, 1]
+        kt[s] = 2
+        e2 = ell.copy()
+        e2[s] = np.sqrt(3.0) * ell[s]
+        b = AdditiveKernelPlan(X, w.windows, kt, w.N, w.m, max_nrhs=2)
+        b.set_hyper(1.0, list(e2), 0.0)
+        kb = b.apply(V)["KV"].cpu().numpy()
+        ref = (kb - oa["KV"].cpu().numpy()) / ell[s]
+        err = np.abs(got[s] - ref).max() / np.abs(ref).max()
+        print(f"  window {s}: rel err {err:.2e}")
+        assert err <= 1e-9, err
+
+
 def test_autotune_keeps_results(orc):
     """The autotuner changes only how the work is laid out (subproblem sizes,
     vectors per group, interpolation variant): outputs agree with the untuned
