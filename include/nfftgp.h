@@ -80,6 +80,10 @@ enum { NFFTGP_SCALE_AUTO = 0, NFFTGP_SCALE_NONE = 1 };
 /* Limits of this build. */
 #define NFFTGP_MAX_WINDOWS 64
 #define NFFTGP_MAX_WINDOW_DIM 3
+/* CG iterations whose Lanczos coefficients nfftgp_cg can record (the history
+ * buffer, NFFTGP_MAX_CG_HISTORY x max_nrhs x 2 doubles, is allocated with the
+ * plan, so that nfftgp_cg allocates nothing). */
+#define NFFTGP_MAX_CG_HISTORY 4096
 
 typedef struct nfftgp_plan_s *nfftgp_plan;
 
@@ -108,6 +112,22 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out,
                                  const int32_t *kernel, const int32_t *N, int32_t m,
                                  nfftgp_prec prec, int32_t scale_mode, int32_t max_nrhs,
                                  void *stream);
+
+/* As nfftgp_plan_create, with the scaling of every window into
+ * [-1/4, 1/4)^d given by the caller instead of computed from X (Sec. 3.1):
+ * x~ = c_s (x - c0_s).  Lets several plans on different point sets (e.g.
+ * training points, and training plus test points for a cross product) share
+ * one kernel in box units.
+ *   c0  host, sum_s d_s doubles: centre of window s at c0[win_ptr[s] ...].
+ *   c   host, P doubles: factor of window s, finite and > 0.
+ * Every scaled coordinate must lie in [-1/4, 1/4) (E_BOX otherwise).
+ * Length-scales stay in the caller's units, as for nfftgp_plan_create. */
+nfftgp_status nfftgp_plan_create_scaled(nfftgp_plan *out,
+                                        const void *X_dev, int64_t n, int32_t p, int64_t ldx,
+                                        int32_t P, const int32_t *win_ptr, const int32_t *win_idx,
+                                        const int32_t *kernel, const int32_t *N, int32_t m,
+                                        nfftgp_prec prec, const double *c0, const double *c,
+                                        int32_t max_nrhs, void *stream);
 
 /* Set the hyper-parameters theta = (sigma_f, ell, sigma_eps) (Sec. 1).
  *   ell   host, P length-scales in caller units (one per window; the paper's
@@ -148,12 +168,14 @@ nfftgp_status nfftgp_apply(nfftgp_plan plan, const void *V_dev, int64_t ldv, int
  *   iters_host     host or NULL: nrhs iteration counts.
  *   alpha_beta_host host or NULL: maxit x nrhs x 2 doubles; entry [j][c] holds
  *                  (alpha_j, beta_j) of column c for j < iters[c] -- the Lanczos
- *                  coefficients used by stochastic Lanczos quadrature.
+ *                  coefficients used by stochastic Lanczos quadrature.  Needs
+ *                  maxit <= NFFTGP_MAX_CG_HISTORY (E_ARG otherwise).
  *   resid_host     host or NULL: nrhs final relative residuals ||r||/||b||.
  * Returns NFFTGP_E_NOTPD if some column met p^T Khat p <= 0 (that column is
  * frozen at its last iterate), NFFTGP_E_NOCONV if a column did not reach tol,
  * NFFTGP_OK otherwise.  Synchronises the stream every check_every iterations
- * (check_every <= 0 means 8). */
+ * (check_every <= 0 means 8).  Allocates no device memory: its vectors,
+ * scalars and history are plan workspaces. */
 nfftgp_status nfftgp_cg(nfftgp_plan plan, const void *B_dev, int32_t nrhs, void *X_dev,
                         double tol, int32_t maxit, int32_t check_every,
                         int32_t *iters_host, double *alpha_beta_host, double *resid_host);

@@ -20,9 +20,10 @@ STATUS = {0: "NFFTGP_OK", -1: "NFFTGP_E_ARG", -2: "NFFTGP_E_DIM", -3: "NFFTGP_E_
           -8: "NFFTGP_E_STATE"}
 E_NOTPD = -6
 E_NOCONV = -7
+MAX_CG_HISTORY = 4096   # NFFTGP_MAX_CG_HISTORY
 
 # every symbol declared in include/nfftgp.h
-SYMBOLS = ["nfftgp_plan_create", "nfftgp_set_hyper", "nfftgp_apply", "nfftgp_cg", "nfftgp_col_dots",
+SYMBOLS = ["nfftgp_plan_create", "nfftgp_plan_create_scaled", "nfftgp_set_hyper", "nfftgp_apply", "nfftgp_cg", "nfftgp_col_dots",
            "nfftgp_slq_logquad", "nfftgp_get_window_info", "nfftgp_get_workspace_bytes",
            "nfftgp_plan_destroy", "nfftgp_last_error", "nfftgp_profile", "nfftgp_profile_read",
            "nfftgp_autotune"]
@@ -53,6 +54,9 @@ def load():
     lib.nfftgp_plan_create.argtypes = [ctypes.POINTER(P), P, i64, i32, i64, i32, P, P, P, P, i32,
                                        ctypes.c_int, i32, i32, P]
     lib.nfftgp_plan_create.restype = ctypes.c_int
+    lib.nfftgp_plan_create_scaled.argtypes = [ctypes.POINTER(P), P, i64, i32, i64, i32, P, P, P, P, i32,
+                                              ctypes.c_int, P, P, i32, P]
+    lib.nfftgp_plan_create_scaled.restype = ctypes.c_int
     lib.nfftgp_set_hyper.argtypes = [P, f64, P, f64]
     lib.nfftgp_set_hyper.restype = ctypes.c_int
     lib.nfftgp_apply.argtypes = [P, P, i64, i32, P, P, P, P]

@@ -318,19 +318,15 @@ int interp_rows_rule(const WindowGeom &g, int m)
     return std::min(g.pd, g.tb / 2 + 2 * m - 1);
 }
 
-}  // namespace
-
-extern "C" {
-
-const char *nfftgp_last_error(void) { return g_err.c_str(); }
-
-nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n, int32_t p,
-                                 int64_t ldx, int32_t P, const int32_t *win_ptr,
-                                 const int32_t *win_idx, const int32_t *kernel, const int32_t *N,
-                                 int32_t m, nfftgp_prec prec, int32_t scale_mode,
-                                 int32_t max_nrhs, void *stream)
+// Plan creation; given_c0 / given_c (both host, or both NULL) carry a scaling
+// chosen by the caller (nfftgp_plan_create_scaled), otherwise scale_mode rules.
+nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, int32_t p,
+                               int64_t ldx, int32_t P, const int32_t *win_ptr,
+                               const int32_t *win_idx, const int32_t *kernel, const int32_t *N,
+                               int32_t m, nfftgp_prec prec, int32_t scale_mode,
+                               const double *given_c0, const double *given_c,
+                               int32_t max_nrhs, void *stream)
 {
-    set_error("");
     if (!out) return fail(NFFTGP_E_ARG, "out is NULL");
     *out = nullptr;
     if (n < 0 || n >= (int64_t(1) << 31)) return fail(NFFTGP_E_ARG, "n out of range");
@@ -361,6 +357,12 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
         if (!is_pow2(N[s]) || N[s] < 8 || N[s] > Nmax)
             return fail(NFFTGP_E_DIM, "bandwidth must be a power of two in 8..64 (d=3) or 8..128");
         if (2 * m >= N[s]) return fail(NFFTGP_E_DIM, "cutoff must satisfy m < N/2");
+        if (given_c && !(given_c[s] > 0.0 && std::isfinite(given_c[s])))
+            return fail(NFFTGP_E_ARG, "scale factors must be finite and > 0");
+    }
+    if (given_c) {
+        for (int q = 0; q < win_ptr[P]; ++q)
+            if (!std::isfinite(given_c0[q])) return fail(NFFTGP_E_ARG, "scale centres must be finite");
     }
 
     nfftgp_plan plan = new nfftgp_plan_s();
@@ -457,7 +459,10 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
             }
         }
         w.c = 1.0;
-        if (scale_mode == NFFTGP_SCALE_AUTO && n > 0) {
+        if (given_c) {
+            w.c = given_c[s];
+            for (int q = 0; q < d; ++q) w.c0[q] = given_c0[win_ptr[s] + q];
+        } else if (scale_mode == NFFTGP_SCALE_AUTO && n > 0) {
             bool inside = true;
             for (int q = 0; q < d; ++q) inside = inside && lo[q] >= -0.25 && hi[q] < 0.25;
             if (!inside) {
@@ -620,12 +625,45 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
     }
     TRYS(dalloc(plan, (void **)&plan->dot_part, (size_t)kDotBlocks * 64 * sizeof(double) + 64 * sizeof(double)));
     TRYS(dalloc(plan, (void **)&plan->cg_scal, (size_t)kCgSlots * 64 * sizeof(double)));
+    TRYS(dalloc(plan, (void **)&plan->cg_hist, (size_t)NFFTGP_MAX_CG_HISTORY * max_nrhs * 2 * sizeof(double)));
     TRYS(dalloc(plan, &plan->cg_r, vec_bytes));
     TRYS(dalloc(plan, &plan->cg_p, vec_bytes));
     TRYS(dalloc(plan, &plan->cg_ap, vec_bytes));
     TRYH(hipStreamSynchronize(st));
     *out = plan;
     return NFFTGP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nfftgp_last_error(void) { return g_err.c_str(); }
+
+nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n, int32_t p,
+                                 int64_t ldx, int32_t P, const int32_t *win_ptr,
+                                 const int32_t *win_idx, const int32_t *kernel, const int32_t *N,
+                                 int32_t m, nfftgp_prec prec, int32_t scale_mode,
+                                 int32_t max_nrhs, void *stream)
+{
+    set_error("");
+    if (scale_mode != NFFTGP_SCALE_AUTO && scale_mode != NFFTGP_SCALE_NONE)
+        return fail(NFFTGP_E_ARG, "bad scale_mode");
+    return plan_create_impl(out, X_dev, n, p, ldx, P, win_ptr, win_idx, kernel, N, m, prec, scale_mode,
+                            nullptr, nullptr, max_nrhs, stream);
+}
+
+nfftgp_status nfftgp_plan_create_scaled(nfftgp_plan *out, const void *X_dev, int64_t n, int32_t p,
+                                        int64_t ldx, int32_t P, const int32_t *win_ptr,
+                                        const int32_t *win_idx, const int32_t *kernel,
+                                        const int32_t *N, int32_t m, nfftgp_prec prec,
+                                        const double *c0, const double *c, int32_t max_nrhs,
+                                        void *stream)
+{
+    set_error("");
+    if (!c0 || !c) return fail(NFFTGP_E_ARG, "c0 or c is NULL");
+    return plan_create_impl(out, X_dev, n, p, ldx, P, win_ptr, win_idx, kernel, N, m, prec,
+                            NFFTGP_SCALE_NONE, c0, c, max_nrhs, stream);
 }
 
 nfftgp_status nfftgp_set_hyper(nfftgp_plan plan, double sigma_f, const double *ell,
@@ -901,6 +939,8 @@ nfftgp_status nfftgp_cg(nfftgp_plan plan, const void *B_dev, int32_t nrhs, void 
     if (nrhs < 1 || nrhs > plan->max_nrhs) return fail(NFFTGP_E_ARG, "nrhs out of range 1..max_nrhs");
     if (maxit < 0 || !(tol >= 0.0)) return fail(NFFTGP_E_ARG, "bad tol or maxit");
     if (plan->n > 0 && (!B_dev || !X_dev)) return fail(NFFTGP_E_ARG, "B or X is NULL");
+    if (alpha_beta_host && maxit > NFFTGP_MAX_CG_HISTORY)
+        return fail(NFFTGP_E_ARG, "maxit exceeds NFFTGP_MAX_CG_HISTORY while the Lanczos history is asked for");
     if (check_every <= 0) check_every = 8;
     // coefficients pending from set_hyper are computed before the iteration is
     // enqueued or captured (a captured iteration never computes them)
@@ -908,13 +948,6 @@ nfftgp_status nfftgp_cg(nfftgp_plan plan, const void *B_dev, int32_t nrhs, void 
     const hipStream_t st = plan->stream;
     const int64_t n = plan->n;
     double *sc = plan->cg_scal;
-    if (alpha_beta_host && maxit > 0 && (int64_t)maxit * nrhs > plan->cg_hist_cap) {
-        void *h = nullptr;
-        nfftgp_status e = dalloc(plan, &h, (size_t)maxit * nrhs * 2 * sizeof(double));
-        if (e != NFFTGP_OK) return e;
-        plan->cg_hist = (double *)h;
-        plan->cg_hist_cap = maxit * nrhs;
-    }
     double *hist = alpha_beta_host ? plan->cg_hist : nullptr;
     PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_init(plan->prec, n, nrhs, B_dev, X_dev, plan->cg_r, plan->cg_p, st));
     PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_coldots(plan->prec, plan->cg_r, nrhs, plan->cg_r, nrhs, n, nrhs,

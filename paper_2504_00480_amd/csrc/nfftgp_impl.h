@@ -151,8 +151,7 @@ struct nfftgp_plan_s {
     bool minb_pending = false;
     double *dot_part = nullptr;  // dot-product partials
     double *cg_scal = nullptr;   // CG per-column scalars
-    double *cg_hist = nullptr;   // CG (alpha, beta) history
-    int cg_hist_cap = 0;
+    double *cg_hist = nullptr;   // CG (alpha, beta) history, NFFTGP_MAX_CG_HISTORY x max_nrhs x 2
     void *cg_r = nullptr, *cg_p = nullptr, *cg_ap = nullptr;  // n x max_nrhs
     // one CG iteration captured as a graph, with the arguments it was captured for
     hipGraphExec_t cg_exec = nullptr;

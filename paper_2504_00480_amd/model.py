@@ -10,13 +10,14 @@ initialised at 0 (theta = log 2), 10 probe vectors and 10 CG iterations per
 training step.
 
 Prediction returns the posterior mean K(X*, X) alpha with alpha = Khat^-1 y
-(zero prior mean) and the posterior variance k(x*, x*) - k*^T Khat^-1 k*.  The cross product is the fast summation on the union of
-the training and test points with a vector that is zero on the test rows:
+(zero prior mean) and the posterior variance k(x*, x*) - k*^T Khat^-1 k*.
+The cross product is the fast summation on the union of the training and
+test points with a vector that is zero on the test rows:
 the test rows of that product are exactly sum_j k(x*_i - x_j) alpha_j.  For
 the kernel to be the same function in both products, every window is scaled
-into the box [-1/4, 1/4)^d (Sec. 3.1) once, from the union of the training
-and test points, and both plans receive pre-scaled coordinates
-(SCALE_NONE) with box length-scales c_s ell_s.
+into the box [-1/4, 1/4)^d (Sec. 3.1) once: the library computes the scaling
+of the union of the training and test points (a plan on the union), and
+every other plan is created with that scaling (``scale=``).
 """
 from __future__ import annotations
 
@@ -27,9 +28,7 @@ import numpy as np
 import torch
 
 from .gp import lml_estimate
-from .plan import SCALE_NONE, AdditiveKernelPlan
-
-_SHRINK = 1.0 - 2.0 ** -20
+from .plan import AdditiveKernelPlan
 
 
 def _softplus(r: np.ndarray) -> np.ndarray:
@@ -38,22 +37,6 @@ def _softplus(r: np.ndarray) -> np.ndarray:
 
 def _sigmoid(r: np.ndarray) -> np.ndarray:
     return 1.0 / (1.0 + np.exp(-r))
-
-
-def window_box_scale(X: np.ndarray, feats: Sequence[int]):
-    """Centre (per feature) and isotropic factor that map the points of one
-    window into [-1/4, 1/4)^d: midrange centre and factor (1/4)(1 - 2^-20) /
-    max ||x - c0||_inf; points already inside the box are kept (c0 = 0, c = 1)."""
-    sub = np.asarray(X, dtype=np.float64)[:, list(feats)]
-    d = sub.shape[1]
-    if sub.shape[0] == 0:
-        return np.zeros(d), 1.0
-    lo, hi = sub.min(axis=0), sub.max(axis=0)
-    if np.all(lo >= -0.25) and np.all(hi < 0.25):
-        return np.zeros(d), 1.0
-    c0 = 0.5 * (lo + hi)
-    h = float(np.max(np.maximum(hi - c0, c0 - lo)))
-    return (c0, 1.0) if h == 0.0 else (c0, 0.25 * _SHRINK / h)
 
 
 class AdditiveGP:
@@ -81,12 +64,21 @@ class AdditiveGP:
         self.seed = int(seed)
         self.X_test = None if X_test is None else np.ascontiguousarray(
             torch.as_tensor(X_test).double().cpu().numpy())
-        U = self.X if self.X_test is None else np.vstack([self.X, self.X_test])
-        sc = [window_box_scale(U, w) for w in self.windows]
-        self.c0 = [s[0] for s in sc]
-        self.c = np.array([s[1] for s in sc])
-        self.plan = AdditiveKernelPlan(self._prescaled(self.X), self.windows, kernel, N, self.m,
-                                       scale_mode=SCALE_NONE, max_nrhs=1 + self.n_probes)
+        nb = 1 + self.n_probes
+        self._union = None   # plan on training + test points (cross products)
+        if self.X_test is None:
+            self.plan = AdditiveKernelPlan(self._dev(self.X), self.windows, kernel, N, self.m, max_nrhs=nb)
+            ref = self.plan
+        else:
+            self._union = AdditiveKernelPlan(self._dev(np.vstack([self.X, self.X_test])), self.windows,
+                                             kernel, N, self.m, max_nrhs=nb)
+            ref = self._union
+        info = [ref.window_info(s) for s in range(self.P)]
+        self.c0 = [i["c0"] for i in info]
+        self.c = np.array([i["c"] for i in info])
+        if self.X_test is not None:
+            self.plan = AdditiveKernelPlan(self._dev(self.X), self.windows, kernel, N, self.m, max_nrhs=nb,
+                                           scale=(self.c0, self.c))
         self.y = torch.tensor(self.y_host, dtype=dtype, device=self.device)
         # raw parameters [sigma_f, sigma_eps, ell_1..ell_P]; theta = softplus(raw)
         self.raw = np.zeros(2 + self.P)
@@ -94,11 +86,15 @@ class AdditiveGP:
         self.history = []
 
     # ------------------------------------------------------------------
-    def _prescaled(self, X: np.ndarray) -> torch.Tensor:
-        Xs = np.array(X, dtype=np.float64, copy=True)
-        for s, w in enumerate(self.windows):
-            Xs[:, w] = self.c[s] * (Xs[:, w] - self.c0[s][None, :])
-        return torch.tensor(Xs, dtype=self.dtype, device=self.device)
+    def _dev(self, X: np.ndarray) -> torch.Tensor:
+        return torch.tensor(X, dtype=self.dtype, device=self.device)
+
+    def _union_plan(self, Xt) -> AdditiveKernelPlan:
+        """Plan on training + test points with the training plan's scaling."""
+        if Xt is self.X_test and self._union is not None:
+            return self._union
+        return AdditiveKernelPlan(self._dev(np.vstack([self.X, Xt])), self.windows, self.kernel, self.N,
+                                  self.m, max_nrhs=self.plan.max_nrhs, scale=(self.c0, self.c))
 
     @property
     def theta(self) -> dict:
@@ -115,14 +111,13 @@ class AdditiveGP:
         """Estimated negative log marginal likelihood at the current theta and
         its gradient with respect to (sigma_f, sigma_eps, ell_s) in caller units."""
         th = self.theta
-        ell_box = [self.c[s] * th["ell"][s] for s in range(self.P)]
-        est = lml_estimate(self.plan, self.y, self._probes(step), th["sigma_f"], ell_box, th["sigma_eps"],
+        est = lml_estimate(self.plan, self.y, self._probes(step), th["sigma_f"], th["ell"], th["sigma_eps"],
                            tol=tol, maxit=maxit, check_every=max(1, maxit) if tol == 0.0 else 8)
         g = np.empty(2 + self.P)
         g[0] = est["grad"]["sigma_f"]
         g[1] = est["grad"]["sigma_eps"]
         for s in range(self.P):
-            g[2 + s] = self.c[s] * est["grad"][("ell", s)]   # d ell_box / d ell = c_s
+            g[2 + s] = est["grad"][("ell", s)]
         return {"Z": est["Z"], "grad": g, "iters": est["iters"]}
 
     def fit(self, steps: int = 500, lr: float = 0.01, cg_iters: int = 10, cg_tol: float = 0.0,
@@ -151,8 +146,8 @@ class AdditiveGP:
     def solve(self, tol: float = 1e-8, maxit: int = 1000) -> torch.Tensor:
         """alpha = Khat^-1 y at the current theta (CG to relative residual tol)."""
         th = self.theta
-        self.plan.set_hyper(th["sigma_f"], [self.c[s] * th["ell"][s] for s in range(self.P)], th["sigma_eps"])
-        X, iters, _, resid, st = self.plan.cg(self.y.reshape(-1, 1).contiguous(), tol, maxit)
+        self.plan.set_hyper(th["sigma_f"], th["ell"], th["sigma_eps"])
+        X, iters, _, resid, st = self.plan.cg(self.y.reshape(-1, 1).contiguous(), tol, maxit, history=False)
         return X[:, 0].contiguous()
 
     def cross_apply(self, alpha: torch.Tensor, X_test=None) -> torch.Tensor:
@@ -164,13 +159,13 @@ class AdditiveGP:
             raise ValueError("no test points")
         nt = Xt.shape[0]
         th = self.theta
-        up = AdditiveKernelPlan(self._prescaled(np.vstack([self.X, Xt])), self.windows, self.kernel, self.N,
-                                self.m, scale_mode=SCALE_NONE, max_nrhs=1)
-        up.set_hyper(th["sigma_f"], [self.c[s] * th["ell"][s] for s in range(self.P)], th["sigma_eps"])
+        up = self._union_plan(Xt)
+        up.set_hyper(th["sigma_f"], th["ell"], th["sigma_eps"])
         V = torch.zeros((self.n + nt, 1), dtype=self.dtype, device=self.device)
         V[: self.n, 0] = alpha.to(self.dtype)
         out = up.apply(V)["KV"][self.n:, 0].clone()
-        up.close()
+        if up is not self._union:
+            up.close()
         return out
 
     def predict_mean(self, X_test=None, tol: float = 1e-8, maxit: int = 1000) -> torch.Tensor:
@@ -192,11 +187,9 @@ class AdditiveGP:
         nt = Xt.shape[0]
         b = self.plan.max_nrhs
         th = self.theta
-        ellb = [self.c[s] * th["ell"][s] for s in range(self.P)]
-        self.plan.set_hyper(th["sigma_f"], ellb, th["sigma_eps"])
-        up = AdditiveKernelPlan(self._prescaled(np.vstack([self.X, Xt])), self.windows, self.kernel, self.N,
-                                self.m, scale_mode=SCALE_NONE, max_nrhs=b)
-        up.set_hyper(th["sigma_f"], ellb, th["sigma_eps"])
+        self.plan.set_hyper(th["sigma_f"], th["ell"], th["sigma_eps"])
+        up = self._union_plan(Xt)
+        up.set_hyper(th["sigma_f"], th["ell"], th["sigma_eps"])
         out = torch.empty(nt, dtype=torch.float64, device=self.device)
         se2 = th["sigma_eps"] ** 2
         for j0 in range(0, nt, b):
@@ -207,8 +200,9 @@ class AdditiveGP:
             KE = up.apply(E)["KV"]
             Kc = KE[: self.n].contiguous()
             kss = KE[rows, torch.arange(jb, device=self.device)].double() - se2
-            A, _, _, _, _ = self.plan.cg(Kc, tol, maxit)
+            A, _, _, _, _ = self.plan.cg(Kc, tol, maxit, history=False)
             q = torch.tensor(self.plan.col_dots(Kc, A), dtype=torch.float64, device=self.device)
             out[j0:j0 + jb] = kss - q + (se2 if noise else 0.0)
-        up.close()
+        if up is not self._union:
+            up.close()
         return out

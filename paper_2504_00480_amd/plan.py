@@ -43,10 +43,14 @@ class AdditiveKernelPlan:
     m : window cutoff (2, 4, 6 or 8).
     scale_mode : SCALE_AUTO (scale each window into [-1/4, 1/4)^d) or SCALE_NONE.
     max_nrhs : largest number of vectors per apply / CG call (<= 64).
+    scale : optional (c0, c) -- per window the centre (d_s values) and factor of
+        the map x -> c (x - c0) into the box, e.g. taken from another plan's
+        ``window_info`` so that both plans share one kernel (scale_mode is then
+        ignored).
     """
 
     def __init__(self, X: torch.Tensor, windows: Sequence[Sequence[int]], kernel, N, m: int,
-                 scale_mode: int = SCALE_AUTO, max_nrhs: int = 1):
+                 scale_mode: int = SCALE_AUTO, max_nrhs: int = 1, scale=None):
         lib = _lib.load()
         if not X.is_cuda:
             raise ValueError("X must be a device tensor")
@@ -75,10 +79,20 @@ class AdditiveKernelPlan:
         self._stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            st = lib.nfftgp_plan_create(ctypes.byref(h), _ptr(X), self.n, self.p, X.stride(0), P,
-                                        _np_ptr(ptr), _np_ptr(idx), _np_ptr(kt), _np_ptr(Ns), self.m,
-                                        self.prec, int(scale_mode), self.max_nrhs,
-                                        ctypes.c_void_p(self._stream.cuda_stream))
+            if scale is None:
+                st = lib.nfftgp_plan_create(ctypes.byref(h), _ptr(X), self.n, self.p, X.stride(0), P,
+                                            _np_ptr(ptr), _np_ptr(idx), _np_ptr(kt), _np_ptr(Ns), self.m,
+                                            self.prec, int(scale_mode), self.max_nrhs,
+                                            ctypes.c_void_p(self._stream.cuda_stream))
+            else:
+                c0 = np.array([float(v) for s_ in range(P) for v in np.ravel(scale[0][s_])] or [0.0])
+                cf = np.array([float(v) for v in scale[1]], dtype=np.float64)
+                if c0.shape[0] != max(1, int(ptr[-1])) or cf.shape[0] != P:
+                    raise ValueError("scale needs d_s centres and one factor per window")
+                st = lib.nfftgp_plan_create_scaled(ctypes.byref(h), _ptr(X), self.n, self.p, X.stride(0), P,
+                                                   _np_ptr(ptr), _np_ptr(idx), _np_ptr(kt), _np_ptr(Ns),
+                                                   self.m, self.prec, _np_ptr(c0), _np_ptr(cf), self.max_nrhs,
+                                                   ctypes.c_void_p(self._stream.cuda_stream))
         _lib.check(st, "nfftgp_plan_create")
         self._h = h
         self.sigma_f = None
@@ -193,19 +207,23 @@ class AdditiveKernelPlan:
         return out
 
     def cg(self, B: torch.Tensor, tol: float, maxit: int, check_every: int = 8, raise_on=("notpd",),
-           out: torch.Tensor | None = None):
+           out: torch.Tensor | None = None, history: bool = True):
         """CG on Khat X = B from zero; returns (X, iters, (alpha, beta) history, rel. residuals, status).
-        Passing the same `out` again lets the library replay its captured iteration."""
+        Passing the same `out` again lets the library replay its captured iteration.  The
+        Lanczos history (needs maxit <= MAX_CG_HISTORY) is None with history=False."""
         B = self._check_vec(B).contiguous()
         nrhs = B.shape[1]
         X = out if out is not None else torch.empty_like(B)
         if X.shape != B.shape or X.dtype != B.dtype or X.device != B.device or not X.is_contiguous():
             raise ValueError("out must be a contiguous tensor like B")
         iters = np.zeros(nrhs, dtype=np.int32)
-        ab = np.zeros((max(maxit, 1), nrhs, 2))
+        if history and maxit > _lib.MAX_CG_HISTORY:
+            raise ValueError(f"the Lanczos history holds at most {_lib.MAX_CG_HISTORY} iterations; "
+                             "pass history=False for longer solves")
+        ab = np.zeros((max(maxit, 1), nrhs, 2)) if history else None
         res = np.zeros(nrhs)
         st = _lib.load().nfftgp_cg(self._h, _ptr(B), nrhs, _ptr(X), float(tol), int(maxit), int(check_every),
-                                   _np_ptr(iters), _np_ptr(ab), _np_ptr(res))
+                                   _np_ptr(iters), _np_ptr(ab) if history else None, _np_ptr(res))
         if st not in (_lib.OK, _lib.E_NOCONV, _lib.E_NOTPD) or \
                 (st == _lib.E_NOTPD and "notpd" in raise_on) or (st == _lib.E_NOCONV and "noconv" in raise_on):
             _lib.check(st, "nfftgp_cg")

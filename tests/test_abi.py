@@ -101,23 +101,32 @@ def test_slq_matches_oracle(orc):
     assert abs(got[0] - exact) < 1e-6 * abs(exact)
 
 
-def test_model_box_scaling_matches_oracle(orc):
-    """The training/prediction model scales each window into [-1/4, 1/4)^d by
-    the same rule as the oracle (midrange centre, isotropic factor), on the
-    union of training and test points."""
-    import workloads
-    from paper_2504_00480_amd.model import window_box_scale, _softplus, _sigmoid
-    g = workloads.rng(71)
-    X = np.vstack([3.0 * g.standard_normal((500, 6)), g.uniform(-0.2, 0.2, (20, 6))])
-    for feats in ([0, 1, 2], [3], [4, 5]):
-        c0, c = window_box_scale(X, feats)
-        r0, rc = orc.window_scale(X, feats)
-        assert np.allclose(c0, r0, rtol=0, atol=0) and c == rc
-        xs = c * (X[:, feats] - c0)
-        assert xs.min() >= -0.25 and xs.max() < 0.25
-    inside = g.uniform(-0.24, 0.24, (50, 2))
-    c0, c = window_box_scale(inside, [0, 1])
-    assert c == 1.0 and np.all(c0 == 0.0)
+def test_model_softplus_helpers():
+    """Parameter transforms of the training model (theta = softplus(raw))."""
+    from paper_2504_00480_amd.model import _softplus, _sigmoid
     r = np.linspace(-30, 30, 61)
     assert np.allclose(_softplus(r), np.log1p(np.exp(r)), rtol=1e-14, atol=1e-300)
     assert np.allclose(_sigmoid(r), np.exp(r) / (1 + np.exp(r)), rtol=1e-14)
+
+
+@pytest.mark.parametrize("c0,c,status", [
+    (None, [0.5], -1),                    # NULL centre
+    ([0.0, 0.0, 0.0], None, -1),          # NULL factor
+    ([0.0, 0.0, 0.0], [0.0], -1),         # factor must be > 0
+    ([0.0, 0.0, 0.0], [np.inf], -1),
+    ([0.0, np.nan, 0.0], [0.5], -1),      # centre must be finite
+])
+def test_scaled_create_argument_errors(lib, c0, c, status):
+    P = ctypes.c_void_p
+    ptr, idx = np.array([0, 3], np.int32), np.array([0, 1, 2], np.int32)
+    kt, N = np.array([0], np.int32), np.array([32], np.int32)
+    c0a = None if c0 is None else np.array(c0, np.float64)
+    ca = None if c is None else np.array(c, np.float64)
+    h = P()
+    st = lib.nfftgp_plan_create_scaled(ctypes.byref(h), P(0), 0, 3, 3, 1, ptr.ctypes.data_as(P),
+                                       idx.ctypes.data_as(P), kt.ctypes.data_as(P), N.ctypes.data_as(P), 4, 0,
+                                       None if c0a is None else c0a.ctypes.data_as(P),
+                                       None if ca is None else ca.ctypes.data_as(P), 1, P(0))
+    assert st == status
+    assert not h.value
+    assert len(lib.nfftgp_last_error()) > 0
