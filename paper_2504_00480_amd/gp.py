@@ -30,9 +30,10 @@ from .plan import AdditiveKernelPlan, slq_logquad
 class _KhatApply(torch.autograd.Function):
     @staticmethod
     def forward(ctx, V, sigma_f, ell, sigma_eps, plan):
-        plan.set_hyper(float(sigma_f), [float(e) for e in ell.detach().cpu().reshape(-1)],
-                       float(sigma_eps))
+        theta = (float(sigma_f), [float(e) for e in ell.detach().cpu().reshape(-1)], float(sigma_eps))
+        plan.set_hyper(*theta)
         ctx.plan = plan
+        ctx.theta = theta
         ctx.save_for_backward(V)
         return plan.apply(V)["KV"]
 
@@ -40,6 +41,11 @@ class _KhatApply(torch.autograd.Function):
     def backward(ctx, gY):
         (V,) = ctx.saved_tensors
         plan = ctx.plan
+        sf, ell, se = ctx.theta
+        # the derivative products are taken at the forward's theta (Sec. 3.2),
+        # whatever set_hyper ran on the plan in between
+        if plan.sigma_f != sf or plan.sigma_eps != se or plan.ell is None or list(plan.ell) != ell:
+            plan.set_hyper(sf, ell, se)
         gY = gY.contiguous()
         res = plan.apply(gY, derivs=True)
         gV = res["KV"] if ctx.needs_input_grad[0] else None

@@ -166,6 +166,43 @@ def test_autograd_matches_direct_and_fd(orc):
         assert abs(ell.grad[s].item() - est["grad"][("ell", s)]) <= 1e-9 * max(1, abs(est["grad"][("ell", s)]))
 
 
+def test_autograd_backward_uses_forward_theta(orc):
+    """Two forwards at different theta on one plan, then the backward of the
+    first: its gradients are those of the first theta (the plan's theta at
+    backward time is the second one), and likewise for the second."""
+    from paper_2504_00480_amd import khat_apply
+    w = workloads.small(28, 1500, [3, 2], [0, 1], [0.7, 0.5], [16, 32], 6, nrhs=2, sigma_eps=0.2)
+    plan, pb = _setup(orc, w, nrhs=2)
+    V = torch.tensor(w.V, device=DEV)
+    G = torch.tensor(workloads.rng(29).standard_normal((w.n, 2)), device=DEV)
+    thetas = [(1.1, [0.7, 0.5], 0.2), (0.6, [0.3, 0.9], 0.5)]
+    leaves, outs = [], []
+    for sf, ell, se in thetas:
+        t = (torch.tensor(sf, dtype=torch.float64, device=DEV, requires_grad=True),
+             torch.tensor(ell, dtype=torch.float64, device=DEV, requires_grad=True),
+             torch.tensor(se, dtype=torch.float64, device=DEV, requires_grad=True))
+        leaves.append(t)
+        outs.append((khat_apply(plan, V, *t) * G).sum())
+    for k in (0, 1):
+        outs[k].backward()
+        sf, ell, se = thetas[k]
+        ref = _fresh_theta_grads(orc, w, V, G, sf, ell, se)
+        got = [leaves[k][0].grad.item(), *leaves[k][1].grad.tolist(), leaves[k][2].grad.item()]
+        print(f"  theta {k}: autograd {got} fresh plan {ref}", flush=True)
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12)
+
+
+def _fresh_theta_grads(orc, w, V, G, sf, ell, se):
+    """<G, dKhat/dtheta V> from a fresh plan at theta: (sigma_f, ell_s..., sigma_eps)."""
+    plan, _ = _setup(orc, w, nrhs=2)
+    plan.set_hyper(sf, ell, se)
+    d = plan.apply(V, derivs=True)
+    out = [float((d["dKV_dsf"] * G).sum())]
+    out += [float((d["dKV_dell"][s] * G).sum()) for s in range(plan.P)]
+    out.append(float((d["dKV_dse"] * G).sum()))
+    return out
+
+
 def test_indefinite_coefficients_reported(orc):
     """A Gaussian window whose box length-scale is large has negative
     coefficients b_k: the plan reports min b_k < 0 (the paper is silent on
