@@ -340,6 +340,27 @@ def ndft_adjoint(pb: Problem, s: int, V):
     return A[..., 0] + 1j * A[..., 1]
 
 
+def rf_bilinear(pb: Problem, s: int, U, W):
+    """u_c^T K_{s,RF} w_c and u_c^T K^der_{s,RF} w_c for every column c.
+
+    With the inner sums a_k(v) = sum_j v_j e^{-2 pi i k.x~_j} of eq.
+    Fourier_sum the double sum over points factors:
+        sum_{i,j} u_i w_j Re sum_k b_k e^{2 pi i k.(x~_i - x~_j)}
+      = Re sum_k b_k conj(a_k(u)) a_k(w),
+    so the bilinear form needs only the inner sums of both vectors (no sum
+    over target rows); b^der (eq. exact_derivative) gives the derivative form.
+    Returns (kernel values, derivative-kernel values), one per column.
+    """
+    Au = ndft_adjoint(pb, s, U)
+    Aw = ndft_adjoint(pb, s, W)
+    prod = np.conj(Au) * Aw
+    out = []
+    for which in (0, 1):
+        b = np.ascontiguousarray(pb.coef(s)[which]).reshape(-1)
+        out.append(np.real((b[:, None] * prod).sum(axis=0)))
+    return out[0], out[1]
+
+
 def rf_apply(pb: Problem, V, rows=None, method="ndft", derivs=True):
     """O2 product on target rows, all windows (same keys as ``dense_apply``).
 
@@ -529,9 +550,10 @@ def matern3d_bound(ell: float, N: int) -> float:
 
 def matern32_3d_bound(ell: float, N: int) -> float:
     """Fourier error estimate of the periodised trivariate Matern-3/2 kernel
-    (proof of the derivative-kernel theorem, Sec. 4.2): 2^5 / (3 pi^4 l^3 (N - 2 sqrt 3)^3)
-    in the proof's parameter l, which is this kernel's ell / sqrt 3 (the proof
-    writes the kernel with sqrt(3) r / (sqrt(3) l))."""
+    (proof of the derivative-kernel theorem, Sec. 4.2): 2^5 / (3 pi^4 ell_p^3 (N - 2 sqrt 3)^3),
+    stated in the Matern-1/2 length-scale ell_p = l / sqrt 3, where l is this
+    kernel's own length-scale (the ell argument): the proof writes the
+    order-3/2 kernel with length-scale sqrt(3) ell_p."""
     lp = ell / np.sqrt(3.0)
     return 32.0 / (3.0 * np.pi ** 4 * lp ** 3 * (N - 2.0 * np.sqrt(3.0)) ** 3)
 

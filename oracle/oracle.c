@@ -23,8 +23,8 @@
  *         h_i = Re sum_{k in I_N} b_k ( sum_j v_j e^{-2 pi i k.x~_j} ) e^{2 pi i k.x~_i}
  *       evaluated either pairwise (tiny n) or through the inner sums
  *       a_k = sum_j v_j e^{-2 pi i k.x~_j} (direct non-equispaced DFT).
- *       The coefficients b_k are an input (computed by oracle/coefficients.py
- *       from eq. discrete_fourier_coefficients1).
+ *       The coefficients b_k are an input (computed by coefficients() in
+ *       oracle/__init__.py from eq. discrete_fourier_coefficients1).
  *
  * Layouts: X is row-major n x p (leading dimension ldx), V is row-major
  * n x nrhs, windows are given in CSR form (win_ptr[P+1], win_idx[...],
@@ -182,14 +182,46 @@ void orc_rf_pairwise(int64_t n, int32_t d, const double *Xs, int32_t N,
     }
 }
 
+/* Per-dimension exponentials e^{sign 2 pi i k x_q}, k in I_N (index k + N/2),
+ * for one point x (d coordinates): ec/es[q * N + k] = cos/sin. */
+static void orc_exp_tables(int32_t d, int32_t N, const double *x, double sign, double *ec, double *es)
+{
+    for (int q = 0; q < d; ++q)
+        for (int k = 0; k < N; ++k) {
+            double ang = sign * 2.0 * ORC_PI * (double)(k - N / 2) * x[q];
+            ec[q * N + k] = cos(ang);
+            es[q * N + k] = sin(ang);
+        }
+}
+
+/* Product of the exponentials of all dimensions but the last, for the
+ * row-major index `outer` over those dimensions (the exponential of k.x is
+ * the product of the d one-dimensional exponentials). */
+static void orc_exp_prefix(int32_t d, int32_t N, int64_t outer, const double *ec, const double *es,
+                           double *pr, double *pi)
+{
+    double er = 1.0, ei = 0.0;
+    for (int q = d - 2; q >= 0; --q) {
+        int k = (int)(outer % N);
+        outer /= N;
+        double cr = ec[q * N + k], ci = es[q * N + k];
+        double tr = er * cr - ei * ci;
+        ei = er * ci + ei * cr;
+        er = tr;
+    }
+    *pr = er;
+    *pi = ei;
+}
+
 /* Inner sums of eq. Fourier_sum (adjoint non-equispaced DFT), one window:
  *   A[k][r] = sum_j v_j^r e^{-2 pi i k.x~_j},  k in I_N^d,
- * stored interleaved (re, im) as A[(kk * nrhs + r) * 2 + {0,1}].
+ * stored interleaved (re, im) as A[(kk * nrhs + r) * 2 + {0,1}], kk row-major
+ * over (k_1 + N/2, ..., k_d + N/2), last fastest.
  * Only points with a non-zero row in V contribute, so a sparse V is cheap.
- * The exponential of the sum k.x is formed as the product of the d
- * one-dimensional exponentials e^{-2 pi i k_q x_q}.  Each thread sums a
- * disjoint range of points into a private array; the partial arrays are then
- * added in thread order. */
+ * The exponential of k.x is formed as the product of the d one-dimensional
+ * exponentials e^{-2 pi i k_q x_q}.  Each thread sums a disjoint range of
+ * points into a private array; the partial arrays are then added in thread
+ * order. */
 void orc_ndft_adjoint(int64_t n, int32_t d, const double *Xs, int32_t N,
                       const double *V, int32_t nrhs, double *A)
 {
@@ -208,32 +240,25 @@ void orc_ndft_adjoint(int64_t n, int32_t d, const double *Xs, int32_t N,
         double *acc = part + (int64_t)tid * len;
         double *ec = (double *)malloc(sizeof(double) * 3 * N);
         double *es = (double *)malloc(sizeof(double) * 3 * N);
+        const int last = d - 1;
 #pragma omp for schedule(static)
         for (int64_t j = 0; j < n; ++j) {
+            const double *v = V + j * nrhs;
             int nz = 0;
-            for (int r = 0; r < nrhs; ++r) nz |= (V[j * nrhs + r] != 0.0);
+            for (int r = 0; r < nrhs; ++r) nz |= (v[r] != 0.0);
             if (!nz) continue;
-            for (int q = 0; q < d; ++q)
+            orc_exp_tables(d, N, Xs + j * d, -1.0, ec, es);
+            for (int64_t outer = 0; outer < K / N; ++outer) {
+                double pr, pi;
+                orc_exp_prefix(d, N, outer, ec, es, &pr, &pi);
                 for (int k = 0; k < N; ++k) {
-                    double ang = -2.0 * ORC_PI * (double)(k - N / 2) * Xs[j * d + q];
-                    ec[q * N + k] = cos(ang);
-                    es[q * N + k] = sin(ang);
-                }
-            for (int64_t kk = 0; kk < K; ++kk) {
-                int64_t rem = kk;
-                double er = 1.0, ei = 0.0;
-                for (int q = d - 1; q >= 0; --q) {
-                    int k = (int)(rem % N);
-                    rem /= N;
-                    double cr = ec[q * N + k], ci = es[q * N + k];
-                    double tr = er * cr - ei * ci;
-                    ei = er * ci + ei * cr;
-                    er = tr;
-                }
-                for (int r = 0; r < nrhs; ++r) {
-                    double v = V[j * nrhs + r];
-                    acc[(kk * nrhs + r) * 2 + 0] += v * er;
-                    acc[(kk * nrhs + r) * 2 + 1] += v * ei;
+                    double cr = ec[last * N + k], ci = es[last * N + k];
+                    double er = pr * cr - pi * ci, ei = pr * ci + pi * cr;
+                    double *a = acc + (outer * N + k) * nrhs * 2;
+                    for (int r = 0; r < nrhs; ++r) {
+                        a[2 * r + 0] += v[r] * er;
+                        a[2 * r + 1] += v[r] * ei;
+                    }
                 }
             }
         }
@@ -257,30 +282,23 @@ void orc_ndft_forward(int32_t d, const double *Xs, int32_t N, const double *b,
     {
         double *ec = (double *)malloc(sizeof(double) * 3 * N);
         double *es = (double *)malloc(sizeof(double) * 3 * N);
+        const int last = d - 1;
 #pragma omp for schedule(dynamic, 4)
         for (int64_t t = 0; t < nrows; ++t) {
             const int64_t i = rows[t];
-            for (int q = 0; q < d; ++q)
+            double *h = H + t * nrhs;
+            orc_exp_tables(d, N, Xs + i * d, 1.0, ec, es);
+            for (int r = 0; r < nrhs; ++r) h[r] = 0.0;
+            for (int64_t outer = 0; outer < K / N; ++outer) {
+                double pr, pi;
+                orc_exp_prefix(d, N, outer, ec, es, &pr, &pi);
                 for (int k = 0; k < N; ++k) {
-                    double ang = 2.0 * ORC_PI * (double)(k - N / 2) * Xs[i * d + q];
-                    ec[q * N + k] = cos(ang);
-                    es[q * N + k] = sin(ang);
-                }
-            for (int r = 0; r < nrhs; ++r) H[t * nrhs + r] = 0.0;
-            for (int64_t kk = 0; kk < K; ++kk) {
-                int64_t rem = kk;
-                double er = 1.0, ei = 0.0;
-                for (int q = d - 1; q >= 0; --q) {
-                    int k = (int)(rem % N);
-                    rem /= N;
-                    double cr = ec[q * N + k], ci = es[q * N + k];
-                    double tr = er * cr - ei * ci;
-                    ei = er * ci + ei * cr;
-                    er = tr;
-                }
-                for (int r = 0; r < nrhs; ++r) {
-                    double ar = A[(kk * nrhs + r) * 2 + 0], ai = A[(kk * nrhs + r) * 2 + 1];
-                    H[t * nrhs + r] += b[kk] * (ar * er - ai * ei);
+                    double cr = ec[last * N + k], ci = es[last * N + k];
+                    double er = pr * cr - pi * ci, ei = pr * ci + pi * cr;
+                    const int64_t kk = outer * N + k;
+                    const double *a = A + kk * nrhs * 2;
+                    for (int r = 0; r < nrhs; ++r)
+                        h[r] += b[kk] * (a[2 * r + 0] * er - a[2 * r + 1] * ei);
                 }
             }
         }

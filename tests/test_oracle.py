@@ -314,6 +314,24 @@ def test_o2_sparse_rhs_linearity(orc):
     np.testing.assert_allclose(a, b, atol=1e-12 * np.abs(b).max())
 
 
+@pytest.mark.parametrize("dims,kt", [([3], 0), ([2], 1), ([1], 2)])
+def test_o2_bilinear_form_equals_row_sums(orc, dims, kt):
+    """u^T K_RF w from the two inner sums (eq. Fourier_sum factored) equals
+    the plain sum over rows of u_i (K_RF w)_i by the pairwise form, for the
+    kernel and its derivative kernel."""
+    w = workloads.small(17, 80, dims, kt, 0.7, 8, 4, nrhs=3)
+    pb = _problem(orc, w)
+    U = workloads.rng(18).standard_normal((80, 3))
+    both = orc.rf_bilinear(pb, 0, U, w.V)
+    swapped = orc.rf_bilinear(pb, 0, w.V, U)
+    for deriv in (False, True):
+        got = both[int(deriv)]
+        want = (U * orc.rf_window(pb, 0, w.V, deriv=deriv, method="pairwise")).sum(axis=0)
+        np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-12 * np.abs(want).max())
+        # symmetric kernel: swapping the vectors changes nothing
+        np.testing.assert_allclose(swapped[int(deriv)], got, rtol=1e-11, atol=1e-12 * np.abs(want).max())
+
+
 def test_o2_approaches_o1(orc):
     """For a well-resolved Gaussian the trigonometric kernel reproduces the kernel
     (error bounded by ||v||_1 max|kappa - kappa_RF|, eq. Fourier_approx_error)."""
