@@ -7,13 +7,17 @@ one additive apply that returns Khat V and every derivative product
 dKhat/d ell_s V, dKhat/d sigma_f V, dKhat/d sigma_eps V.  The value is
 n * nrhs / (seconds per step).  Inputs are resident in HBM before timing.
 
-Default workload: n = 100,000 points, p = 9 standard-normal features, three
-3-D Gaussian windows, ell = 0.5, sigma_f = 1, sigma_eps = 0.1, N = 32, m = 4,
-one vector, FP32.  Other workloads: --workload C1..C5.
+Default workload (the largest single-GPU configuration): n = 2,000,000
+points, p = 20 standard-normal features, six 3-D windows (Gaussian and
+Matern-1/2 alternating) and one 2-D Gaussian window, ell = 1.0, sigma_f = 1,
+sigma_eps = 0.1, N = 64, m = 6, 16 vectors, FP32, autotuned.  Other
+workloads: --workload C1..C4.
 
 The JSON line also carries the roofline of the dominant kernel (timed with HIP
-events on the plan's stream inside the timed region), the oracle's CPU
-throughput on a bounded sample, and the parity of the timed result.
+events on the plan's stream inside the timed region) against the FP32 vector
+peak, its LDS rate against the LDS peak and its measured HBM rate, the
+oracle's CPU throughput on a bounded sample, and the parity of the timed
+result.
 """
 from __future__ import annotations
 
@@ -32,6 +36,8 @@ METRIC = "kernel matvecs/sec (n×RHS/s) at ≤1e-4 rel err vs FP64; % HBM peak"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
+# LDS: 128 bytes per clock per compute unit, 256 compute units at 2.4 GHz
+LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12
 
 
 def parse():
@@ -39,7 +45,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"])
+    ap.add_argument("--workload", default="C5", choices=["C1", "C2", "C3", "C4", "C5"])
     ap.add_argument("--prec", default=None, choices=[None, "f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
@@ -303,23 +309,48 @@ def main():
     else:
         achieved = work / avg_s / 1e12
         peak = FP32_PEAK_TFLOPS if prec == "f32" else FP64_PEAK_TFLOPS
-    traffic = None
+    # measured HBM bytes per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
+    # a plain copy's counts), valid while the kernel's source is unchanged
+    tj = {}
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tfile):
         try:
             tj = json.load(open(tfile))
-            ent = tj.get(f"{args.workload}:{prec}:{dom}")
-            srcs = {"spread": ["k_grid.hip"], "interp": ["k_grid.hip"], "fold": ["k_grid.hip"],
-                    "fft_fwd": ["k_fft.hip"], "fft_inv": ["k_fft.hip"], "diag": ["k_fft.hip"],
-                    "assemble": ["k_grid.hip"], "fill": ["k_grid.hip"], "gather": ["k_grid.hip"]}[dom]
-            if ent and ent.get("source_sha") == src_sha(*srcs):
-                traffic = ent["bytes_per_launch"]
-        except Exception:
-            traffic = None
+        except ValueError:
+            tj = {}
+    srcs = {"spread": ["k_grid.hip"], "interp": ["k_grid.hip"], "fold": ["k_grid.hip"],
+            "fft_fwd": ["k_fft.hip"], "fft_inv": ["k_fft.hip"], "diag": ["k_fft.hip"],
+            "assemble": ["k_grid.hip"], "fill": ["k_grid.hip"], "gather": ["k_grid.hip"],
+            "coef": ["k_coef.hip"], "cg": ["k_cg.hip"]}
+
+    def measured_bytes(cat):
+        ent = tj.get(f"{args.workload}:{prec}:{cat}")
+        if ent and ent.get("source_sha") == src_sha(*srcs[cat]):
+            return ent["bytes_per_launch"]
+        return None
+
+    traffic = measured_bytes(dom)
+    for cat, kv in kern.items():
+        tb = measured_bytes(cat)
+        if tb is not None and kv["avg_us"] > 0:
+            kv["hbm_bytes_per_launch"] = tb
+            kv["hbm_GBps"] = tb / (kv["avg_us"] * 1e-6) / 1e9
+            kv["hbm_frac"] = kv["hbm_GBps"] / HBM_PEAK_GBS
     roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak, "traffic": traffic,
                 "work_per_launch": work, "avg_launch_us": avg_s * 1e6,
                 "timing": f"HIP events around the {dom_launches} {dom} launches of the timed region only"}
+    if dom == "interp":
+        # the tile kernels read one LDS value per tap, vector and grid (K and
+        # dK grids with derivative outputs)
+        lds_bytes = taps * eb * nout * args.steps / dom_launches
+        roofline["lds"] = {"bytes_per_launch": lds_bytes, "achieved_TBps": lds_bytes / avg_s / 1e12,
+                           "peak_TBps": LDS_PEAK_TBS, "frac": lds_bytes / avg_s / 1e12 / LDS_PEAK_TBS,
+                           "note": "one LDS value per tap, vector and grid read; peak 128 B/clock/CU"}
+    if traffic is not None:
+        roofline["hbm"] = {"achieved_GBps": traffic / avg_s / 1e9, "peak_GBps": HBM_PEAK_GBS,
+                           "frac": traffic / avg_s / 1e9 / HBM_PEAK_GBS,
+                           "note": "measured bytes per launch (profiles/traffic.json) / launch duration"}
 
     # ---------------- parity of the timed result (O2 on sampled rows)
     parity = None

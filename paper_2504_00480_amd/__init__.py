@@ -1,8 +1,8 @@
 """MI355X (gfx950) additive-kernel Fourier fast summation for Gaussian processes.
 
 Implements the hot path of "Preconditioned Additive Gaussian Processes with
-Fourier Acceleration": NFFT-based products of additive Gaussian / Matern-1/2
-kernel matrices on feature windows of dimension <= 3 and of their
+Fourier Acceleration": NFFT-based products of additive Gaussian, Matern-1/2
+and Matern-3/2 kernel matrices on feature windows of dimension <= 3 and of their
 hyper-parameter derivatives, batched CG with FP64 scalars, stochastic Lanczos
 quadrature and the log-marginal-likelihood gradient.  The numerical work runs
 in hand-written HIP kernels behind the C ABI declared in include/nfftgp.h.

@@ -327,8 +327,10 @@ def test_profile_category_mask():
 
 
 def test_set_hyper_between_applies_without_waits():
-    """Coefficients run on a second stream: back-to-back set_hyper / apply
-    calls with no host wait give exactly the results of a fresh plan."""
+    """set_hyper records theta and enqueues the coefficient work on the plan's
+    stream (for Gaussian-only groups inside the next apply's fold launch):
+    back-to-back set_hyper / apply calls with no host wait give exactly the
+    results of a fresh plan."""
     from paper_2504_00480_amd import AdditiveKernelPlan
     w = workloads.small(16, 30000, [3, 3, 2], [0, 1, 0], [0.4, 0.6, 0.5], [32, 32, 32], 4, 2)
     dev = torch.device("cuda:0")
