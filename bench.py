@@ -395,7 +395,8 @@ def main():
     # ---------------- CPU baseline: exact dense product (O1) on sampled target rows
     if not args.no_cpu_baseline:
         rng = np.random.default_rng(0)
-        nr = 1000
+        # a first small sample sizes the second to about 12 s of host work
+        nr = max(8, min(n, int(2e8 / max(1, n * P))))
         t_cpu = 0.0
         while True:
             rows = np.sort(rng.choice(n, size=min(nr, n), replace=False)).astype(np.int64)
@@ -404,7 +405,7 @@ def main():
             t_cpu = time.perf_counter() - t0
             if t_cpu >= 8.0 or nr >= n:
                 break
-            nr = int(min(n, nr * max(2.0, 12.0 / max(t_cpu, 1e-3))))
+            nr = int(min(n, nr * min(64.0, max(2.0, 12.0 / max(t_cpu, 1e-3)))))
         cores = oracle.num_threads()
         # one thread on a smaller sample (about 2 s) for the per-core rate
         rows1 = rows[: max(1, len(rows) // max(1, 4 * cores))]

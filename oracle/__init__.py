@@ -409,6 +409,28 @@ def rf_matrix(pb: Problem, s: int, deriv: bool = False) -> np.ndarray:
     return H
 
 
+def rf_matrix_trig(pb: Problem, s: int, deriv: bool = False, chunk: int = 2048) -> np.ndarray:
+    """K_{s,RF} (or its derivative kernel) as a dense matrix through the
+    cosine expansion of eq. Fourier_sum (real part):
+        kappa_RF(x_i - x_j) = sum_k b_k [cos(2 pi k.x_i) cos(2 pi k.x_j)
+                                        + sin(2 pi k.x_i) sin(2 pi k.x_j)],
+    i.e. C diag(b) C^T + S diag(b) S^T with C_ik = cos(2 pi k.x_i) and
+    S_ik = sin(2 pi k.x_i); the products over k are BLAS matrix products (a
+    library step), taken over chunks of frequencies.  O(n^2 N^d)."""
+    xs = pb.xs(s)
+    n, d = xs.shape
+    N = pb.N[s]
+    b = np.ascontiguousarray(pb.coef(s)[1 if deriv else 0]).reshape(-1)
+    ks = np.stack(np.meshgrid(*([np.arange(N) - N // 2] * d), indexing="ij"), -1).reshape(-1, d)
+    M = np.zeros((n, n))
+    for k0 in range(0, ks.shape[0], chunk):
+        ph = 2.0 * np.pi * (xs @ ks[k0:k0 + chunk].T.astype(np.float64))
+        C, S = np.cos(ph), np.sin(ph)
+        bb = b[k0:k0 + chunk]
+        M += (C * bb) @ C.T + (S * bb) @ S.T
+    return M
+
+
 # ----------------------------------------------------------------------------
 # dense likelihood and gradient (Sec. 1 eq. GP_objective, eq. div with M = I)
 # ----------------------------------------------------------------------------

@@ -346,6 +346,18 @@ def test_o2_approaches_o1(orc):
     assert np.abs(o1 - o2).max() < 1e-5 * np.abs(o1).max()
 
 
+@pytest.mark.parametrize("dims,kt,N", [([3], 0, 8), ([2], 1, 16), ([1], 2, 32)])
+def test_rf_matrix_cosine_form_equals_pairwise(orc, dims, kt, N):
+    """The dense trigonometric-kernel matrix through the cosine expansion
+    equals the pairwise form, for the kernel and its derivative kernel."""
+    w = workloads.small(19, 60, dims, kt, 0.6, N, 4, nrhs=1)
+    pb = _problem(orc, w)
+    for deriv in (False, True):
+        a = orc.rf_matrix(pb, 0, deriv=deriv)
+        b = orc.rf_matrix_trig(pb, 0, deriv=deriv, chunk=100)
+        np.testing.assert_allclose(b, a, rtol=0, atol=1e-12 * np.abs(a).max())
+
+
 def test_rf_matrix_symmetric(orc):
     w = workloads.small(10, 30, [2], 1, 0.9, 8, 4, nrhs=1)
     pb = _problem(orc, w)
