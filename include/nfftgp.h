@@ -188,6 +188,22 @@ nfftgp_status nfftgp_col_dots(nfftgp_plan plan, const void *A_dev, int64_t lda,
                               const void *B_dev, int64_t ldb, int64_t n, int32_t ncol,
                               double *out_host);
 
+/* Allocation-free variant of nfftgp_col_dots, for callers that cannot
+ * allocate (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): needs no plan, allocates nothing, does not synchronise.
+ * The partial sums live in a static device array of the library (61 440
+ * bytes per device, held until the process ends); it is looked up once per
+ * device on the first call there.  Calls that overlap on one device (other
+ * streams or threads) race on that array.
+ *   prec         precision of A and B (NFFTGP_F32 or NFFTGP_F64).
+ *   A_dev, B_dev device, n x ncol with leading dimensions lda, ldb.
+ *   ncol         1..64 (E_ARG beyond: the array holds 64 columns).
+ *   out_dev      device, ncol doubles: out[c] = sum_i A[i][c] B[i][c] in FP64.
+ *   stream       hipStream_t to enqueue on (NULL = null stream). */
+nfftgp_status nfftgp_col_dots_noalloc(nfftgp_prec prec, const void *A_dev, int64_t lda,
+                                      const void *B_dev, int64_t ldb, int64_t n, int32_t ncol,
+                                      double *out_dev, void *stream);
+
 /* Stochastic Lanczos quadrature (Sec. 1): for each column c,
  *   out[c] = znorm2[c] * e_1^T log(T_c) e_1,
  * where T_c is the Lanczos tridiagonal matrix built from the CG coefficients

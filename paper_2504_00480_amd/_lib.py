@@ -26,7 +26,7 @@ MAX_CG_HISTORY = 4096   # NFFTGP_MAX_CG_HISTORY
 SYMBOLS = ["nfftgp_plan_create", "nfftgp_plan_create_scaled", "nfftgp_set_hyper", "nfftgp_apply", "nfftgp_cg", "nfftgp_col_dots",
            "nfftgp_slq_logquad", "nfftgp_get_window_info", "nfftgp_get_workspace_bytes",
            "nfftgp_plan_destroy", "nfftgp_last_error", "nfftgp_profile", "nfftgp_profile_read",
-           "nfftgp_autotune"]
+           "nfftgp_autotune", "nfftgp_col_dots_noalloc"]
 PROF_NAMES = ["fill", "spread", "fold", "fft_fwd", "diag", "fft_inv", "interp", "assemble", "coef", "cg",
               "gather"]
 
@@ -65,6 +65,8 @@ def load():
     lib.nfftgp_cg.restype = ctypes.c_int
     lib.nfftgp_col_dots.argtypes = [P, P, i64, P, i64, i64, i32, P]
     lib.nfftgp_col_dots.restype = ctypes.c_int
+    lib.nfftgp_col_dots_noalloc.argtypes = [ctypes.c_int, P, i64, P, i64, i64, i32, P, P]
+    lib.nfftgp_col_dots_noalloc.restype = ctypes.c_int
     lib.nfftgp_slq_logquad.argtypes = [P, P, i32, i32, P, P]
     lib.nfftgp_slq_logquad.restype = ctypes.c_int
     lib.nfftgp_get_window_info.argtypes = [P, i32, P, P, P, P, P, P]
