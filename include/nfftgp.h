@@ -261,11 +261,82 @@ enum {
     NFFTGP_PROF_COEF = 8,     /* per-theta coefficient kernels                */
     NFFTGP_PROF_CG = 9,       /* CG dot products and vector updates           */
     NFFTGP_PROF_GATHER = 10,  /* reserved (no kernel in this version)         */
-    NFFTGP_PROF_COUNT = 11,
-    NFFTGP_PROF_ALL = (1 << 11) - 1
+    NFFTGP_PROF_PRECOND = 11, /* preconditioner factors and applications      */
+    NFFTGP_PROF_COUNT = 12,
+    NFFTGP_PROF_ALL = (1 << 12) - 1
 };
 nfftgp_status nfftgp_profile(nfftgp_plan plan, int32_t categories);
 nfftgp_status nfftgp_profile_read(nfftgp_plan plan, double *ms_host, int32_t *count_host);
+
+/* ---------------------------------------------------------------- AAFN
+ * Additive adaptive factorised Nystrom preconditioner (Sec. 2.3) and
+ * preconditioned CG (Sec. 1; Sec. 2.3; eq. log_det_decomp,
+ * eq. GP_approx_objective, eq. div).
+ *
+ * Landmarks: in every window, farthest point sampling of per_window points
+ * (the first is the point farthest from the window centre c0, every further
+ * one maximises the distance to those already chosen; ties to the smallest
+ * index); the windows' lists are merged rank by rank, duplicates skipped, up
+ * to max_rank points, held in ascending index order.  The other points,
+ * ordered by their grid cell of window 0 (tiles, then cells), are cut into
+ * blocks of at most `block` points.  With the landmarks first,
+ *   M = [[K11, K12], [K21, K21 K11^-1 K12 + blockdiag(S_BB)]] = F F^T,
+ *   F = [[L11, 0], [K21 L11^-T, blockdiag(L_B)]],
+ * K11 = L11 L11^T (Cholesky of the landmark block), S_BB = L_B L_B^T the
+ * diagonal blocks of the Schur complement K22 - K21 K11^-1 K12 (the
+ * approximate inverse of the Schur complement keeps them).  Kernel entries
+ * are those of the exact kernel (Sec. 1, eq. kernel_definition) at the
+ * plan's theta, in FP64; M approximates Khat.
+ *
+ * Attach once per plan; every nfftgp_set_hyper then enqueues the factors
+ * for the new theta (asynchronously).  nfftgp_pcg, nfftgp_precond_apply and
+ * nfftgp_precond_dquad allocate nothing. */
+
+/* Attach the preconditioner.  X_dev: the same n x p points (device, plan
+ * precision, leading dimension ldx) the plan was created from.  Limits:
+ * plan windows <= 16, 1 <= max_rank <= 512, 1 <= block <= 128, per_window
+ * >= 1.  Allocates the preconditioner's workspaces (FP64: about
+ * (4 k + 2 block) doubles per point, k the number of landmarks).  E_STATE if
+ * a preconditioner is already attached.  Synchronises the stream. */
+nfftgp_status nfftgp_precond_attach(nfftgp_plan plan, const void *X_dev, int64_t ldx, int32_t per_window,
+                                    int32_t max_rank, int32_t block);
+
+/* k (landmarks), number of Schur-complement blocks, log det M and
+ * tr(M^-1 dM/dtheta_j) for theta = (sigma_f, ell_1, ..., ell_P, sigma_eps)
+ * (the second term of eq. div); any output may be NULL.  Synchronises the
+ * stream when log det M or the traces are asked for; E_NOTPD if a Cholesky
+ * pivot of the landmark block or of a Schur-complement block was not
+ * positive. */
+nfftgp_status nfftgp_precond_info(nfftgp_plan plan, int32_t *k, int32_t *nblocks, double *logdet,
+                                  double *dlogdet);
+
+/* The k landmark indices (host, ascending).  Synchronises the stream. */
+nfftgp_status nfftgp_precond_landmarks(nfftgp_plan plan, int32_t *idx_host);
+
+/* out = op(V) for nrhs vectors (device, n x nrhs, leading dimension nrhs,
+ * plan precision; out must not overlap V):
+ *   NFFTGP_PC_MINV   M^-1 V
+ *   NFFTGP_PC_FINVT  F^-T V          (= M^-1 F V)
+ *   NFFTGP_PC_F      F V             (probes with covariance M from V)
+ * Asynchronous. */
+enum { NFFTGP_PC_MINV = 0, NFFTGP_PC_FINVT = 1, NFFTGP_PC_F = 2 };
+nfftgp_status nfftgp_precond_apply(nfftgp_plan plan, int32_t op, const void *V_dev, int32_t nrhs,
+                                   void *out_dev);
+
+/* out_host[j * nrhs + c] = w_c^T (dM/dtheta_j) w_c for the nrhs columns of W
+ * (device, n x nrhs, leading dimension nrhs), theta as for
+ * nfftgp_precond_info: the control-variate term of the trace estimator of
+ * eq. div.  Synchronises the stream. */
+nfftgp_status nfftgp_precond_dquad(nfftgp_plan plan, const void *W_dev, int32_t nrhs, double *out_host);
+
+/* Preconditioned CG with the attached M, otherwise as nfftgp_cg (same
+ * arguments, stopping rule ||r_c|| <= tol ||b_c||, FP64 scalars, Lanczos
+ * coefficients (alpha_j, beta_j) of the preconditioned iteration in
+ * alpha_beta_host).  E_STATE without a preconditioner.  Runs its iterations
+ * eagerly. */
+nfftgp_status nfftgp_pcg(nfftgp_plan plan, const void *B_dev, int32_t nrhs, void *X_dev, double tol,
+                         int32_t maxit, int32_t check_every, int32_t *iters_host, double *alpha_beta_host,
+                         double *resid_host);
 
 /* Device bytes the plan holds. */
 nfftgp_status nfftgp_get_workspace_bytes(nfftgp_plan plan, size_t *bytes);

@@ -26,9 +26,11 @@ MAX_CG_HISTORY = 4096   # NFFTGP_MAX_CG_HISTORY
 SYMBOLS = ["nfftgp_plan_create", "nfftgp_plan_create_scaled", "nfftgp_set_hyper", "nfftgp_apply", "nfftgp_cg", "nfftgp_col_dots",
            "nfftgp_slq_logquad", "nfftgp_get_window_info", "nfftgp_get_workspace_bytes",
            "nfftgp_plan_destroy", "nfftgp_last_error", "nfftgp_profile", "nfftgp_profile_read",
-           "nfftgp_autotune", "nfftgp_col_dots_noalloc"]
+           "nfftgp_autotune", "nfftgp_col_dots_noalloc", "nfftgp_precond_attach", "nfftgp_precond_info",
+           "nfftgp_precond_landmarks", "nfftgp_precond_apply", "nfftgp_precond_dquad", "nfftgp_pcg"]
 PROF_NAMES = ["fill", "spread", "fold", "fft_fwd", "diag", "fft_inv", "interp", "assemble", "coef", "cg",
-              "gather"]
+              "gather", "precond"]
+PC_MINV, PC_FINVT, PC_F = 0, 1, 2
 
 
 class NfftgpError(RuntimeError):
@@ -81,6 +83,15 @@ def load():
     lib.nfftgp_profile_read.restype = ctypes.c_int
     lib.nfftgp_autotune.argtypes = [P, i32, i32, i32, ctypes.c_char_p, i64]
     lib.nfftgp_autotune.restype = ctypes.c_int
+    lib.nfftgp_precond_attach.argtypes = [P, P, i64, i32, i32, i32]
+    lib.nfftgp_precond_info.argtypes = [P, P, P, P, P]
+    lib.nfftgp_precond_landmarks.argtypes = [P, P]
+    lib.nfftgp_precond_apply.argtypes = [P, i32, P, i32, P]
+    lib.nfftgp_precond_dquad.argtypes = [P, P, i32, P]
+    lib.nfftgp_pcg.argtypes = [P, P, i32, P, f64, i32, i32, P, P, P]
+    for fn in ("nfftgp_precond_attach", "nfftgp_precond_info", "nfftgp_precond_landmarks", "nfftgp_precond_apply",
+               "nfftgp_precond_dquad", "nfftgp_pcg"):
+        getattr(lib, fn).restype = ctypes.c_int
     lib.nfftgp_last_error.argtypes = []
     lib.nfftgp_last_error.restype = ctypes.c_char_p
     _lib = lib

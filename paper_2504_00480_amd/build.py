@@ -19,7 +19,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnfftgp.so")
 ARCH = os.environ.get("NFFTGP_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "k_plan.hip", "k_coef.hip", "k_grid.hip", "k_fft.hip", "k_cg.hip", "noalloc.hip"]
+SOURCES = ["api.hip", "k_plan.hip", "k_coef.hip", "k_grid.hip", "k_fft.hip", "k_cg.hip", "noalloc.hip",
+           "k_precond.hip", "precond_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

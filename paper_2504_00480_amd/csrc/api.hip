@@ -50,6 +50,7 @@ void free_plan(nfftgp_plan p)
     if (!p) return;
     (void)hipStreamSynchronize(p->stream);
     for (void *a : p->allocs) (void)hipFree(a);
+    for (void *a : p->host_allocs) (void)hipHostFree(a);
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     if (p->minb_host) (void)hipHostFree(p->minb_host);
     if (p->cg_exec) (void)hipGraphExecDestroy(p->cg_exec);
@@ -147,7 +148,10 @@ struct Scratch {
         }                                                                           \
     } while (0)
 
-// Enqueue one additive apply; no validation, no allocation, no host sync.
+}  // namespace
+
+namespace nfftgp {
+
 // Coefficients recorded by set_hyper but not yet computed (they are computed
 // by the next apply's fold launch) are computed now by their own launch.
 hipError_t resolve_coef(nfftgp_plan p)
@@ -163,6 +167,7 @@ hipError_t resolve_coef(nfftgp_plan p)
     return hipSuccess;
 }
 
+// Enqueue one additive apply; no validation, no allocation, no host sync.
 nfftgp_status apply_impl(nfftgp_plan p, const void *V, int64_t ldv, int nrhs, void *KV,
                          void *dell, void *dsf, void *dse)
 {
@@ -189,6 +194,13 @@ nfftgp_status apply_impl(nfftgp_plan p, const void *V, int64_t ldv, int nrhs, vo
                                 KV, dsf, dse, s));
     return NFFTGP_OK;
 }
+
+int prof_begin_cat(nfftgp_plan p, int cat) { return prof_begin(p, cat); }
+void prof_end_cat(nfftgp_plan p, int cat, int i) { prof_end(p, cat, i); }
+
+}  // namespace nfftgp
+
+namespace {
 
 // Smallest spreading subproblem the tuner tries; list arrays are sized for it.
 constexpr int kMinSubSp = 64;
@@ -623,7 +635,7 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
         TRYH(hipHostMalloc(&h, 2 * P * sizeof(double), hipHostMallocDefault));
         plan->minb_host = (double *)h;
     }
-    TRYS(dalloc(plan, (void **)&plan->dot_part, (size_t)kDotBlocks * 64 * sizeof(double) + 64 * sizeof(double)));
+    TRYS(dalloc(plan, (void **)&plan->dot_part, (size_t)2 * kDotBlocks * 64 * sizeof(double) + 64 * sizeof(double)));
     TRYS(dalloc(plan, (void **)&plan->cg_scal, (size_t)kCgSlots * 64 * sizeof(double)));
     TRYS(dalloc(plan, (void **)&plan->cg_hist, (size_t)NFFTGP_MAX_CG_HISTORY * max_nrhs * 2 * sizeof(double)));
     TRYS(dalloc(plan, &plan->cg_r, vec_bytes));
@@ -703,6 +715,8 @@ nfftgp_status nfftgp_set_hyper(nfftgp_plan plan, double sigma_f, const double *e
     plan->sigma_f = sigma_f;
     plan->sigma_eps = sigma_eps;
     plan->have_hyper = true;
+    // the preconditioner's factors follow theta
+    if (plan->pc.on) return precond_refresh(plan);
     return NFFTGP_OK;
 }
 

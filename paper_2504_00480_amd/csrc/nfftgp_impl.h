@@ -124,6 +124,57 @@ struct Group {
     double *coef_part = nullptr; // per-block minima of the coefficients (last set_hyper)
 };
 
+// ---------------------------------------------------------------- AAFN
+// Windows the preconditioner handles at most (one derivative per window is
+// carried in registers).
+constexpr int kPcMaxWin = 16;
+constexpr int kPcMaxRank = 512;
+constexpr int kPcMaxBlock = 128;
+// Application operators: M^-1 v, F^-T v, F v (M = F F^T).
+enum { kPcMinv = 0, kPcFinvT = 1, kPcFac = 2 };
+
+// Exact-kernel parameters of the preconditioner (passed by value).
+struct PcKer {
+    int32_t P, ptot;
+    int32_t d[kPcMaxWin], off[kPcMaxWin], type[kPcMaxWin];
+    double ell[kPcMaxWin];
+    double sf, se;
+};
+
+// Additive AFN preconditioner state (FP64, all device arrays owned by the plan).
+struct Precond {
+    bool on = false;
+    bool ready = false;          // factors of the current theta enqueued
+    bool info_pending = false;   // log det / traces not yet copied to the host
+    int k = 0;                   // landmarks
+    int64_t np = 0;              // other points
+    int f = 0;                   // Schur-complement block size
+    int nblk = 0, nzpart = 0;
+    int64_t zrows = 0;           // rows per partial sum of Y^T Y
+    int per_window = 0, max_rank = 0, ptot = 0;
+    double *X = nullptr;         // n x ptot window features, caller units
+    int32_t *lm = nullptr;       // k landmark indices, ascending
+    int32_t *ord = nullptr;      // np other points in block order
+    double *K11 = nullptr, *dK11 = nullptr, *L11 = nullptr, *L11inv = nullptr, *K11inv = nullptr;
+    double *V = nullptr, *Y = nullptr, *Wt = nullptr, *G = nullptr;   // np x k each
+    double *LB = nullptr, *LBinv = nullptr;                             // nblk x f x f each
+    double *part = nullptr;      // nblk x (P + 3): block log det and trace shares
+    double *zpart = nullptr;     // nzpart x k x k
+    double *Zk = nullptr, *Tk = nullptr;   // k x k scratch
+    double *acc = nullptr;       // log det K11
+    int *flag = nullptr;         // non-positive pivot met
+    double *out_dev = nullptr;   // log det M, then P + 2 traces
+    double *out_host = nullptr;  // pinned copy
+    // application scratch (max_nrhs vectors)
+    double *T1 = nullptr, *R1 = nullptr, *ABAR = nullptr, *W1 = nullptr;   // max_nrhs x k
+    double *Q = nullptr;         // nblk x max_nrhs x k
+    double *lmt = nullptr;       // max_nrhs x (P + 2)
+    double *dqp = nullptr;       // nblk x max_nrhs x (P + 2)
+    double *dq_dev = nullptr;    // (P + 2) x max_nrhs
+    void *pz = nullptr;          // PCG z vectors (n x max_nrhs, plan precision)
+    PcKer ker{};
+};
+
 }  // namespace nfftgp
 
 struct nfftgp_plan_s {
@@ -160,8 +211,10 @@ struct nfftgp_plan_s {
     const void *cg_key_x = nullptr;
     const double *cg_key_hist = nullptr;
     double cg_key_tol = 0.0, cg_key_sf = 0.0, cg_key_se = 0.0;
+    nfftgp::Precond pc;          // AAFN preconditioner (nfftgp_precond_attach)
     size_t bytes = 0;
     std::vector<void *> allocs;
+    std::vector<void *> host_allocs;   // pinned host memory (hipHostFree)
     // kernel timing (nfftgp_profile)
     uint32_t prof = 0;           // bit c set: launches of category c are timed
     std::vector<hipEvent_t> ev_pool;
@@ -272,6 +325,33 @@ hipError_t launch_cg_xr(int prec, int64_t n, int nrhs, const double *scal, void 
 hipError_t launch_cg_beta(int nrhs, const double *part, double *scal, double tol, double *hist, hipStream_t s);
 hipError_t launch_cg_p(int prec, int64_t n, int nrhs, const double *scal, const void *R, void *Pv,
                        hipStream_t s);
+
+// AAFN preconditioner kernels (k_precond.hip).
+hipError_t launch_pc_gather(int prec, const void *X, int64_t ldx, int64_t n, int ptot, const int *feat, double *Xw,
+                            hipStream_t s);
+hipError_t launch_pc_fps(const double *X, int64_t n, int ptot, const PcKer &kp, const double *centre, int kw,
+                         double *mind, int *sel, hipStream_t s);
+hipError_t launch_pc_keys(const double *X, int64_t n, int ptot, int d, int N, int tb, double c, const double *c0,
+                          int64_t *key, hipStream_t s);
+// factors of M at kp's theta, log det M and tr(M^-1 dM/dtheta_j) into pc.out_dev
+hipError_t launch_pc_setup(const Precond &pc, const PcKer &kp, hipStream_t s);
+// out = op(v) for nrhs vectors (n x nrhs, plan precision; out must not alias v)
+hipError_t launch_pc_apply(int prec, const Precond &pc, int op, const void *v, int nrhs, void *out, hipStream_t s);
+// out[j * nrhs + c] = w_c^T dM/dtheta_j w_c (device, FP64)
+hipError_t launch_pc_dquad(int prec, const Precond &pc, const PcKer &kp, const void *w, int nrhs, double *out,
+                           hipStream_t s);
+hipError_t launch_pcg_start(int nrhs, double *scal, hipStream_t s);
+hipError_t launch_pcg_beta(int nrhs, const double *prr, const double *prz, double *scal, double tol, double *hist,
+                           hipStream_t s);
+
+// Shared between the C ABI translation units (api.hip, precond_api.hip).
+hipError_t resolve_coef(nfftgp_plan p);
+nfftgp_status apply_impl(nfftgp_plan p, const void *V, int64_t ldv, int nrhs, void *KV, void *dell, void *dsf,
+                         void *dse);
+int prof_begin_cat(nfftgp_plan p, int cat);
+void prof_end_cat(nfftgp_plan p, int cat, int i);
+// Enqueue the preconditioner's factorisation at the plan's current theta.
+nfftgp_status precond_refresh(nfftgp_plan p);
 
 // Layout of the per-column CG scalar block (doubles, each an array of nrhs).
 enum CgSlot {

@@ -206,11 +206,60 @@ class AdditiveKernelPlan:
         _lib.check(st, "nfftgp_col_dots")
         return out
 
+    # ------------------------------------------------------------------ AAFN
+    def attach_precond(self, X: torch.Tensor, per_window: int = 10, max_rank: int = 300, block: int = 100):
+        """Attach the additive AFN preconditioner (Sec. 2.3): per_window landmarks
+        per window by farthest point sampling, merged up to max_rank; Schur
+        complement kept in diagonal blocks of at most `block` points.  X: the
+        points the plan was created from."""
+        if X.dtype != self.dtype or X.device != self.device or X.shape != (self.n, self.p) or X.stride(1) != 1:
+            raise ValueError("X must be the plan's n x p points (same dtype and device)")
+        st = _lib.load().nfftgp_precond_attach(self._h, _ptr(X), X.stride(0), int(per_window), int(max_rank),
+                                               int(block))
+        _lib.check(st, "nfftgp_precond_attach")
+
+    def precond_info(self) -> dict:
+        """{'k', 'nblocks', 'logdet' (log det M), 'dlogdet' (tr(M^-1 dM/dtheta_j), theta =
+        sigma_f, ell_1..ell_P, sigma_eps)} at the current theta."""
+        k = ctypes.c_int32()
+        nb = ctypes.c_int32()
+        ld = ctypes.c_double()
+        dl = np.zeros(self.P + 2)
+        st = _lib.load().nfftgp_precond_info(self._h, ctypes.byref(k), ctypes.byref(nb), ctypes.byref(ld),
+                                             _np_ptr(dl))
+        _lib.check(st, "nfftgp_precond_info")
+        return {"k": k.value, "nblocks": nb.value, "logdet": ld.value, "dlogdet": dl}
+
+    def precond_landmarks(self) -> np.ndarray:
+        k = ctypes.c_int32()
+        _lib.check(_lib.load().nfftgp_precond_info(self._h, ctypes.byref(k), None, None, None), "nfftgp_precond_info")
+        idx = np.zeros(max(1, k.value), dtype=np.int32)
+        _lib.check(_lib.load().nfftgp_precond_landmarks(self._h, _np_ptr(idx)), "nfftgp_precond_landmarks")
+        return idx[: k.value]
+
+    def precond_apply(self, V: torch.Tensor, op: str = "minv") -> torch.Tensor:
+        """op = 'minv' (M^-1 V), 'finvt' (F^-T V) or 'f' (F V), M = F F^T."""
+        V = self._check_vec(V).contiguous()
+        out = torch.empty_like(V)
+        code = {"minv": _lib.PC_MINV, "finvt": _lib.PC_FINVT, "f": _lib.PC_F}[op]
+        st = _lib.load().nfftgp_precond_apply(self._h, code, _ptr(V), V.shape[1], _ptr(out))
+        _lib.check(st, "nfftgp_precond_apply")
+        return out
+
+    def precond_dquad(self, W: torch.Tensor) -> np.ndarray:
+        """w_c^T dM/dtheta_j w_c, shape (P + 2, columns)."""
+        W = self._check_vec(W).contiguous()
+        out = np.zeros((self.P + 2, W.shape[1]))
+        st = _lib.load().nfftgp_precond_dquad(self._h, _ptr(W), W.shape[1], _np_ptr(out))
+        _lib.check(st, "nfftgp_precond_dquad")
+        return out
+
     def cg(self, B: torch.Tensor, tol: float, maxit: int, check_every: int = 8, raise_on=("notpd",),
-           out: torch.Tensor | None = None, history: bool = True):
+           out: torch.Tensor | None = None, history: bool = True, precond: bool = False):
         """CG on Khat X = B from zero; returns (X, iters, (alpha, beta) history, rel. residuals, status).
         Passing the same `out` again lets the library replay its captured iteration.  The
-        Lanczos history (needs maxit <= MAX_CG_HISTORY) is None with history=False."""
+        Lanczos history (needs maxit <= MAX_CG_HISTORY) is None with history=False.
+        precond=True: CG preconditioned with the attached AAFN preconditioner."""
         B = self._check_vec(B).contiguous()
         nrhs = B.shape[1]
         X = out if out is not None else torch.empty_like(B)
@@ -222,11 +271,12 @@ class AdditiveKernelPlan:
                              "pass history=False for longer solves")
         ab = np.zeros((max(maxit, 1), nrhs, 2)) if history else None
         res = np.zeros(nrhs)
-        st = _lib.load().nfftgp_cg(self._h, _ptr(B), nrhs, _ptr(X), float(tol), int(maxit), int(check_every),
-                                   _np_ptr(iters), _np_ptr(ab) if history else None, _np_ptr(res))
+        fn = _lib.load().nfftgp_pcg if precond else _lib.load().nfftgp_cg
+        st = fn(self._h, _ptr(B), nrhs, _ptr(X), float(tol), int(maxit), int(check_every),
+                _np_ptr(iters), _np_ptr(ab) if history else None, _np_ptr(res))
         if st not in (_lib.OK, _lib.E_NOCONV, _lib.E_NOTPD) or \
                 (st == _lib.E_NOTPD and "notpd" in raise_on) or (st == _lib.E_NOCONV and "noconv" in raise_on):
-            _lib.check(st, "nfftgp_cg")
+            _lib.check(st, "nfftgp_pcg" if precond else "nfftgp_cg")
         return X, iters, ab, res, st
 
 

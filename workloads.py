@@ -112,6 +112,29 @@ def c5(seed=51, n=2_000_000, nrhs=16):
                     1.0, 0.1, [64] * 7, 6, V)
 
 
+def cube6(seed=100, n=3000, ktype=MATERN12, ell=2.0, N=32, m=6):
+    """The synthetic set of the preconditioned-iteration study (Sec. 5.1): n
+    points uniform in a 6-D hypercube of side n^(1/3), two 3-D windows,
+    sigma_f^2 = 1/P, sigma_eps^2 = 0.01, right-hand side uniform in
+    [-0.5, 0.5]."""
+    g = rng(seed)
+    X = g.uniform(0.0, n ** (1.0 / 3.0), size=(n, 6))
+    V = g.uniform(-0.5, 0.5, size=(n, 1))
+    return Workload(f"cube6 n={n} 2x3D kernel={ktype} ell={ell}", X, [[0, 1, 2], [3, 4, 5]], [ktype] * 2,
+                    [ell] * 2, float(np.sqrt(0.5)), 0.1, [N] * 2, m, V)
+
+
+def unit6(seed=101, n=3000, ktype=GAUSS, ell=0.5, N=32, m=4):
+    """The synthetic regression set of the estimator-variance study (Sec. 5.1):
+    n points uniform in [0, 1]^6, y_i = sin(2 pi x_i)^T exp(x_i) + ||x_i||^2
+    + N(0, 0.01) noise, two 3-D windows."""
+    g = rng(seed)
+    X = g.uniform(0.0, 1.0, size=(n, 6))
+    y = np.sum(np.sin(2.0 * np.pi * X) * np.exp(X), axis=1) + np.sum(X * X, axis=1) + 0.1 * g.standard_normal(n)
+    return Workload(f"unit6 n={n} 2x3D kernel={ktype}", X, [[0, 1, 2], [3, 4, 5]], [ktype] * 2, [ell] * 2,
+                    1.0, 0.1, [N] * 2, m, y[:, None], y=y)
+
+
 def small(seed, n, dims, ktypes, ell, N, m, nrhs, sigma_f=1.0, sigma_eps=0.1, dist="normal",
           scale_mode=0, prec="f32"):
     """Generic small case: windows of the given dimensions over consecutive features."""
