@@ -258,7 +258,7 @@ nfftgp_status build_spread_lists(nfftgp_plan plan, Group &G, int sub_sp)
 
 // (Re)build a group's tile-interpolation work list: subproblems of up to
 // 256 * pt points of one tile (pt points per thread).
-nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt, int rows)
+nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt, int rows, bool slot = false)
 {
     // 3-D: a subproblem stages only `rows` first-axis rows of the padded tile
     // (points of first-tap rows f0..f1 read rows f0 .. f1 + 2m - 1, since the
@@ -270,6 +270,9 @@ nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt, int rows)
     const int m = plan->m;
     const bool cut = g.d == 3 && rows < g.pd;
     if (g.d != 3) rows = g.pd;
+    // 3-D slots: the lists count slots (one or two points of one cell), one per thread
+    slot = slot && g.d == 3 && plan->n > 0;
+    const int isp_s = slot ? kInterpSubPoints : isp;
     if (rows < 2 * m || rows > g.pd) return fail(NFFTGP_E_ARG, "bad interpolation row count");
     std::vector<int> iw, ib, is, ic;
     auto push = [&](int wl, int b, int start, int cnt, int f0) {
@@ -281,26 +284,27 @@ nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt, int rows)
     };
     for (int wl = 0; wl < G.nwin; ++wl) {
         const Window &w = plan->win[G.wins[wl]];
-        const std::vector<int> &bs = w.h_bin_start;
+        const std::vector<int> &bs = slot ? w.h_slot_start : w.h_bin_start;
+        const std::vector<int> &rc = slot ? w.h_row_slots : w.h_row_cnt;
         for (int b = 0; b < g.nbins; ++b) {
             const int cnt = bs[b + 1] - bs[b];
             if (cnt == 0) continue;
             if (!cut) {
-                for (int off = 0; off < cnt; off += isp) push(wl, b, bs[b] + off, std::min(isp, cnt - off), 0);
+                for (int off = 0; off < cnt; off += isp_s) push(wl, b, bs[b] + off, std::min(isp_s, cnt - off), 0);
                 continue;
             }
-            int start = bs[b], k = 0, f0 = 0;   // open subproblem: k points from row f0
+            int start = bs[b], k = 0, f0 = 0;   // open subproblem: k points (slots) from row f0
             for (int r = 0; r < g.tb; ++r) {
-                int left = w.h_row_cnt[(size_t)b * g.tb + r];
+                int left = rc[(size_t)b * g.tb + r];
                 const int f = r + 1;             // first-tap row of the points of cell row r
                 while (left > 0) {
-                    if (k > 0 && (k == isp || f - f0 + 2 * m > rows)) {
+                    if (k > 0 && (k == isp_s || f - f0 + 2 * m > rows)) {
                         push(wl, b, start, k, f0);
                         start += k;
                         k = 0;
                     }
                     if (k == 0) f0 = f;
-                    const int take = std::min(left, isp - k);
+                    const int take = std::min(left, isp_s - k);
                     k += take;
                     left -= take;
                 }
@@ -316,8 +320,10 @@ nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt, int rows)
         if (!srcv[k]->empty())
             NFFTGP_HIP_TRY(hipMemcpy(dst[k], srcv[k]->data(), srcv[k]->size() * sizeof(int), hipMemcpyHostToDevice));
     G.nisub = (int)iw.size();
-    G.interp_pt = pt;
+    G.interp_pt = slot ? 2 : pt;
     G.interp_rows = rows;
+    G.interp_slot = slot;
+    if (slot) G.interp_adj = false;
     return NFFTGP_OK;
 }
 
@@ -510,6 +516,11 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
             TRYH(hipMemcpyAsync(w.h_row_cnt.data(), rowc, w.h_row_cnt.size() * sizeof(int),
                                 hipMemcpyDeviceToHost, st));
         }
+        std::vector<int> hanchor;
+        if (d == 3 && n > 0) {
+            hanchor.resize(n);
+            TRYH(hipMemcpyAsync(hanchor.data(), w.anchor, n * sizeof(int), hipMemcpyDeviceToHost, st));
+        }
         TRYH(hipMemcpyAsync(hflags, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
         TRYH(hipStreamSynchronize(st));
         if (hflags[1]) {
@@ -518,6 +529,30 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
                                           ": a scaled point lies outside [-1/4, 1/4)^d");
         }
         w.h_bin_start = bs;
+        if (d == 3 && n > 0) {
+            // interpolation slots: consecutive points of a run of equal cells
+            // are paired (a run never crosses a tile); slots per tile and per
+            // (tile, first-axis cell row) for the work lists
+            std::vector<int> sl;
+            sl.reserve(n);
+            w.h_slot_start.assign(w.g.nbins + 1, 0);
+            w.h_row_slots.assign((size_t)w.g.nbins * w.g.tb, 0);
+            const int ng = w.g.ng, tb = w.g.tb;
+            for (int b = 0; b < w.g.nbins; ++b) {
+                w.h_slot_start[b] = (int)sl.size();
+                for (int j = bs[b]; j < bs[b + 1];) {
+                    const bool last = hanchor[j] < 0;
+                    const bool pair = !last && j + 1 < bs[b + 1];
+                    sl.push_back(pair ? (int)((unsigned)j | 0x80000000u) : j);
+                    const int a = hanchor[j] & 0x7fffffff;
+                    w.h_row_slots[(size_t)b * tb + (a / (ng * ng)) % tb] += 1;
+                    j += pair ? 2 : 1;
+                }
+            }
+            w.h_slot_start[w.g.nbins] = (int)sl.size();
+            TRYS(dalloc(plan, (void **)&w.slots, sl.size() * sizeof(int)));
+            TRYH(hipMemcpy(w.slots, sl.data(), sl.size() * sizeof(int), hipMemcpyHostToDevice));
+        }
         TRYS(dalloc(plan, &w.Dk, w.g.dcells * eb));
         TRYS(dalloc(plan, &w.Dder, w.g.dcells * eb));
         int64_t K = 1;
@@ -556,7 +591,7 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
                 icap += (cnt + kInterpSubPoints - 1) / kInterpSubPoints + (d3 && cnt > 0 ? G.g.tb : 0);
             }
             TRYS(dalloc(plan, (void **)&w.bin_sub_ptr, (w.g.nbins + 1) * sizeof(int)));
-            hd[wl] = WinDesc{w.rec, w.anchor, w.lpos, w.perm, w.bin_sub_ptr, w.Dk, w.Dder, G.wins[wl], 0};
+            hd[wl] = WinDesc{w.rec, w.anchor, w.lpos, w.perm, w.bin_sub_ptr, w.Dk, w.Dder, w.slots, G.wins[wl], 0};
         }
         G.sub_cap = (int)std::max<int64_t>(cap, 1);
         {
@@ -592,9 +627,10 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
         G.use_run_interp = iov && std::strcmp(iov, "run") == 0 && n > 0;
         const bool full = iov && std::strcmp(iov, "tilefull") == 0;
         const bool pair = iov && std::strcmp(iov, "tilepair") == 0;
+        const bool slot = iov && std::strcmp(iov, "tileslot") == 0;
         G.interp_adj = pair && G.g.d == 3;
         TRYS(build_interp_lists(plan, G, iov && (pair || std::strcmp(iov, "tile2") == 0) ? 2 : 1,
-                                full ? G.g.pd : interp_rows_rule(G.g, m)));
+                                full ? G.g.pd : interp_rows_rule(G.g, m), slot));
         {
             // run-interpolation list (built for every group, so that the
             // variant can be switched): points per wave up to kRunSubPoints,
@@ -624,7 +660,7 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
         TRYS(dalloc(plan, (void **)&G.coef_part, (size_t)coef_part_doubles(G.g, G.nwin) * sizeof(double)));
         TRYS(dalloc(plan, (void **)&G.desc, G.nwin * sizeof(WinDesc)));
         TRYH(hipMemcpy(G.desc, hd.data(), G.nwin * sizeof(WinDesc), hipMemcpyHostToDevice));
-        grid_need = std::max(grid_need, (size_t)2 * G.nwin * G.g.cells);
+        grid_need = std::max(grid_need, (size_t)G.nwin * G.g.cells);
     }
     TRYS(dalloc(plan, &plan->grid, grid_need * max_nrhs * 2 * eb));
     const size_t vec_bytes = std::max<int64_t>(n, 1) * max_nrhs * eb;
@@ -867,26 +903,31 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
         //    padded tile or the rule's row window (3-D), or runs (the pair form
         //    is not a candidate: the tuner times applies with derivative outputs,
         //    and the pair form's K-only launches, which CG makes, are slower)
-        const bool cur_run = G.use_run_interp, cur_adj = G.interp_adj;
+        const bool cur_run = G.use_run_interp, cur_adj = G.interp_adj, cur_slot = G.interp_slot;
         const int cur_pt = G.interp_pt, cur_rows = G.interp_rows;
-        bool best_run = cur_run, best_adj = cur_adj;
+        bool best_run = cur_run, best_adj = cur_adj, best_slot = cur_slot;
         int best_pt = cur_pt, best_rows = cur_rows;
-        struct Cand { bool run; int pt, rows; bool adj; };
+        struct Cand { bool run; int pt, rows; bool adj, slot; };
         std::vector<Cand> cands;
         const int rr = interp_rows_rule(G.g, plan->m);
         for (int pt : {1, 2}) {
-            cands.push_back({false, pt, rr, false});
-            if (rr != G.g.pd) cands.push_back({false, pt, G.g.pd, false});
+            cands.push_back({false, pt, rr, false, false});
+            if (rr != G.g.pd) cands.push_back({false, pt, G.g.pd, false, false});
         }
-        cands.push_back({true, cur_pt, cur_rows, cur_adj});
+        if (G.g.d == 3) {
+            // one slot (one or two points of one cell) per thread
+            cands.push_back({false, 2, rr, false, true});
+            if (rr != G.g.pd) cands.push_back({false, 2, G.g.pd, false, true});
+        }
+        cands.push_back({true, cur_pt, cur_rows, cur_adj, cur_slot});
         for (const Cand &c : cands) {
             if (stt != NFFTGP_OK) break;
             if (c.run == cur_run &&
-                (c.run || (c.pt == cur_pt && c.rows == cur_rows && c.adj == cur_adj)))
+                (c.run || (c.pt == cur_pt && c.rows == cur_rows && c.adj == cur_adj && c.slot == cur_slot)))
                 continue;
             G.use_run_interp = c.run;
             G.interp_adj = c.adj;
-            if (!c.run && (stt = build_interp_lists(plan, G, c.pt, c.rows)) != NFFTGP_OK) break;
+            if (!c.run && (stt = build_interp_lists(plan, G, c.pt, c.rows, c.slot)) != NFFTGP_OK) break;
             double t = 0.0;
             if ((stt = timed(t)) != NFFTGP_OK) break;
             if (t < best) {
@@ -895,15 +936,19 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
                 best_pt = c.pt;
                 best_rows = c.rows;
                 best_adj = c.adj;
+                best_slot = c.slot;
             }
         }
         if (stt != NFFTGP_OK) break;
         G.use_run_interp = best_run;
         G.interp_adj = best_adj;
-        if ((stt = build_interp_lists(plan, G, best_pt, best_rows)) != NFFTGP_OK) break;
+        if ((stt = build_interp_lists(plan, G, best_pt, best_rows, best_slot)) != NFFTGP_OK) break;
+        G.interp_adj = best_adj && !best_slot;
         std::string ivar = "run";
         if (!G.use_run_interp) {
-            ivar = G.interp_adj ? "tile, adjacent point pairs" : (G.interp_pt == 2 ? "tile, 2 points/thread" : "tile");
+            ivar = G.interp_slot ? "tile, same-cell point pairs"
+                                 : (G.interp_adj ? "tile, adjacent point pairs"
+                                                 : (G.interp_pt == 2 ? "tile, 2 points/thread" : "tile"));
             if (G.g.d == 3) ivar += ", " + std::to_string(G.interp_rows) + " of " + std::to_string(G.g.pd) + " rows";
         }
         char line[240];

@@ -292,8 +292,9 @@ k_fft_slab(typename Cplx<T>::type *__restrict__ data, PruneGeom pg)
 
 // MODE 0: forward transform of axis ax (reads Omega, writes F);
 // MODE 1: inverse transform of axis ax (reads F, writes Omega);
-// MODE 2: axis 0 forward, diagonal, inverse (reads Omega, writes Omega of the
-//         K block and, with DER, of the derivative block der_off batches on).
+// MODE 2: axis 0 forward, diagonal, inverse (reads Omega, writes Omega; with
+//         DER the diagonal is D + i D^der, so the kernel and derivative grids
+//         come out as the real and imaginary parts).
 // LPB lines per work-group of LPB * Q threads; the first pass reads the grid
 // and the last writes it directly.
 template <typename T, int LOGN, int LPB, int MODE, bool DER>
@@ -399,24 +400,31 @@ k_fft_pruned(typename Cplx<T>::type *__restrict__ data, PruneGeom pg, int ax, in
             fft_lines<T, LOGN, false, false>(LPB, load, keep, ybuf, twf);
         else
             fft_lines<T, LOGN, false, true>(LPB, load, keep, ybuf, twf);
-#pragma unroll
-        for (int pass = 0; pass < (DER ? 2 : 1); ++pass) {
-            auto dload = [&](int li, int k, int n1) {
-                C v = spec[li][k];
-                const T dv = dpre[pass][n1];
-                v.x *= dv;
-                v.y *= dv;
-                return v;
-            };
-            const int64_t off = pass == 0 ? 0 : der_off * pg.cells;
-            auto emit = [&](int li, int k, C v) {
-                if (s_ok[li] && cyc_has(pg.olo, pg.on, k, ng)) data[off + s_base[li] + (int64_t)k * S] = v;
-            };
-            if (S == 1)
-                fft_lines<T, LOGN, true, false>(LPB, dload, emit, ybuf, twi);
-            else
-                fft_lines<T, LOGN, true, true>(LPB, dload, emit, ybuf, twi);
-        }
+        // the spectrum of a real grid is Hermitian and D, D^der are real and
+        // even, so D G^ and D^der G^ transform back to real grids: one inverse
+        // of (D + i D^der) G^ gives the kernel grid in the real parts and the
+        // derivative grid in the imaginary parts
+        auto dload = [&](int li, int k, int n1) {
+            const C v = spec[li][k];
+            const T dv = dpre[0][n1];
+            C o;
+            if constexpr (DER) {
+                const T dd = dpre[DER ? 1 : 0][n1];
+                o.x = dv * v.x - dd * v.y;
+                o.y = dv * v.y + dd * v.x;
+            } else {
+                o.x = dv * v.x;
+                o.y = dv * v.y;
+            }
+            return o;
+        };
+        auto emit = [&](int li, int k, C v) {
+            if (s_ok[li] && cyc_has(pg.olo, pg.on, k, ng)) data[s_base[li] + (int64_t)k * S] = v;
+        };
+        if (S == 1)
+            fft_lines<T, LOGN, true, false>(LPB, dload, emit, ybuf, twi);
+        else
+            fft_lines<T, LOGN, true, true>(LPB, dload, emit, ybuf, twi);
     }
 }
 
@@ -535,7 +543,10 @@ template <typename T>
 hipError_t inv_t(const Group &G, int m, void *grid, int nrhs, bool with_der, hipStream_t s)
 {
     const PruneGeom pg = prune_geom(G.g, m);
-    const int64_t batch = (int64_t)G.nwin * nrhs * (with_der ? 2 : 1);
+    // one complex grid per window and vector: kernel and derivative grids in
+    // its real and imaginary parts
+    (void)with_der;
+    const int64_t batch = (int64_t)G.nwin * nrhs;
     if (use_slab(G)) return slab_t<T, true>(G, pg, grid, batch, s);
     for (int ax = 1; ax < G.g.d; ++ax) {
         hipError_t e = fft_dispatch<T, 1, false>(log2i(G.g.ng), grid, pg, ax, batch, G.desc, nrhs, 0, s);

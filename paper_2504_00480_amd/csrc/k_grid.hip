@@ -592,7 +592,7 @@ k_fold(const WinDesc *__restrict__ wd, const T *__restrict__ tilebuf, int nrhs, 
 // window weights are loaded once and reused for every vector.  Each window
 // writes its own block of the per-window output buffer (one owner thread per
 // entry).
-template <typename T, int D, int M, bool DER, int PT, bool ADJ = false>
+template <typename T, int D, int M, bool DER, int PT, bool ADJ = false, bool SLOT = false>
 __global__ void __launch_bounds__(256)
 k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
          const int *__restrict__ sub_bin, const int *__restrict__ sub_start,
@@ -632,11 +632,24 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     T w[PT][D][TW];
     int lin[PT], f0[PT];
     int64_t orow[PT];
+    // SLOT (d = 3, two points per thread): thread t takes slot start + t, one
+    // point or two consecutive points of one cell (then every tap read below
+    // serves both); an unpaired slot repeats its point without an output
+    int slot0 = 0;
+    if constexpr (SLOT) {
+        slot0 = (int)threadIdx.x < cnt ? win.slots[start + (int)threadIdx.x] : 0;
+    }
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
         const int k = ADJ ? 2 * (int)threadIdx.x + p : (int)threadIdx.x + 256 * p;
-        mine[p] = k < cnt;
-        const int64_t j = start + (mine[p] ? k : 0);
+        int64_t j;
+        if constexpr (SLOT) {
+            mine[p] = (int)threadIdx.x < cnt && (p == 0 || slot0 < 0);
+            j = (int64_t)(slot0 & 0x7fffffff) + (mine[p] ? p : 0);
+        } else {
+            mine[p] = k < cnt;
+            j = start + (mine[p] ? k : 0);
+        }
         rp[p] = rec + j * RS;
 #pragma unroll
         for (int q = (D == 3 ? 1 : 0); q < D; ++q)
@@ -679,7 +692,8 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     }
     for (int r = 0; r < nrhs; ++r) {
         const C *gK = grid + ((int64_t)wi * nrhs + r) * cells;
-        const C *gD = DER ? grid + ((int64_t)(nwin + wi) * nrhs + r) * cells : nullptr;
+        // the derivative grid is the imaginary part of the same grid
+        const C *gD = gK;
         if (r > 0) __syncthreads();
         if constexpr (D == 3) {
             const int pd2 = pd * pd;
@@ -697,7 +711,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                     for (int j = 0; j < NS; ++j) {
                         const bool in = ina && pin[j];
                         vK[aa][j] = in ? gK[pl + prel[j]].x : T(0);
-                        vD[aa][j] = (DER && in) ? gD[pl + prel[j]].x : T(0);
+                        vD[aa][j] = (DER && in) ? gD[pl + prel[j]].y : T(0);
                     }
                 }
 #pragma unroll
@@ -742,7 +756,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                     g = g * ng + l;
                 }
                 vK[b] = in ? gK[g].x : T(0);
-                vD[b] = (DER && in) ? gD[g].x : T(0);
+                vD[b] = (DER && in) ? gD[g].y : T(0);
             }
 #pragma unroll
             for (int b = 0; b < SB; ++b) {
@@ -766,7 +780,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             // (same first tap) each tap value read serves both; the second
             // point's rows are read again only in lanes whose cells differ
             if (mine[0]) {
-                const bool same = lin[0] == lin[1];
+                const bool same = SLOT || lin[0] == lin[1];
                 T hK[2] = {T(0), T(0)}, hD[2] = {T(0), T(0)};
 #pragma unroll 1
                 for (int aa = 0; aa < TW; ++aa) {
@@ -793,7 +807,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                             bK[cc] = aK[cc];
                             bD[cc] = aD[cc];
                         }
-                        if (!same) {
+                        if (!SLOT && !same) {
 #pragma unroll
                             for (int cc = 0; cc < TW; ++cc) {
                                 if constexpr (DER) {
@@ -968,12 +982,12 @@ k_interp_vb(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                 dst[b] = ok ? cell * S + ch * CH : -1;
                 const int vrow = r0 + ch * CH;
                 const C *gK = grid + ((int64_t)wi * nrhs + vrow) * cells + (in ? g : 0);
-                const C *gD = grid + ((int64_t)(nwin + wi) * nrhs + vrow) * cells + (in ? g : 0);
+                const C *gD = gK;   // derivative grid: imaginary parts
 #pragma unroll
                 for (int e = 0; e < CH; ++e) {
                     const bool ine = in && vrow + e < nrhs;
                     vK[b].x[e] = ine ? gK[(int64_t)e * cells].x : T(0);
-                    vD[b].x[e] = (DER && ine) ? gD[(int64_t)e * cells].x : T(0);
+                    vD[b].x[e] = (DER && ine) ? gD[(int64_t)e * cells].y : T(0);
                 }
             }
 #pragma unroll
@@ -1171,8 +1185,7 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
         __syncthreads();
         for (int r = 0; r < nrhs; ++r) {
             const typename Cplx<T>::type *gK = grid + ((int64_t)wi * nrhs + r) * cells;
-            const typename Cplx<T>::type *gD =
-                DER ? grid + ((int64_t)(nwin + wi) * nrhs + r) * cells : gK;
+            const typename Cplx<T>::type *gD = gK;   // derivative grid: imaginary parts
             T G[NG][NA], GD[NG][NA], GL[QA], GDL[QA];
             int cur = -1, fr = 0;   // fr: first tap's tile position (first-dimension weights sit rotated by it)
             for (int u = 0; u < nc; ++u) {
@@ -1190,7 +1203,7 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                         for (int k = 0; k < QA; ++k) {
                             const int64_t gi = ((int64_t)(c[0] + qL * QA + k) * ng + c[1] + i0L) * ng + c[2] + i1L;
                             GL[k] = gK[gi].x;
-                            if (DER) GDL[k] = gD[gi].x;
+                            if (DER) GDL[k] = gD[gi].y;
                         }
                     }
 #pragma unroll
@@ -1202,7 +1215,7 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                             else if (D == 2) gi = (int64_t)(c[0] + i0[g]) * ng + c[1] + i1[g];
                             else gi = c[0] + i0[g];
                             G[g][a] = gK[gi].x;
-                            if (DER) GD[g][a] = gD[gi].x;
+                            if (DER) GD[g][a] = gD[gi].y;
                         }
                 }
                 const T *rp = s_rec + u * RS;
@@ -1448,6 +1461,14 @@ hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool
         constexpr bool DR = decltype(der_tag)::value;
         constexpr int PT = decltype(pt_tag)::value;
         if constexpr (D == 3 && PT == 2) {
+            if (G.interp_slot) {
+                hipError_t e = allow_lds(k_interp<T, D, M, DR, 2, true, true>, shm);
+                if (e != hipSuccess) return e;
+                k_interp<T, D, M, DR, 2, true, true><<<(unsigned)G.nisub, 256, shm, s>>>(
+                    G.desc, G.isub_win, G.isub_bin, G.isub_start, G.isub_count, g.tb, g.nb, g.ng, G.nwin, rows,
+                    (const C *)grid, g.cells, nrhs, n, (T *)hbuf, DR ? (T *)dout : nullptr, (T)dscale);
+                return hipGetLastError();
+            }
             if (G.interp_adj) {
                 hipError_t e = allow_lds(k_interp<T, D, M, DR, 2, true>, shm);
                 if (e != hipSuccess) return e;

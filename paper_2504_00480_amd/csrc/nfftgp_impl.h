@@ -54,12 +54,16 @@ struct Window {
     int32_t *lpos = nullptr;    // per sorted point: first-tap position in its padded tile
                                 // (bits 0-19 offset, 20-26 first coordinate; bit 31 as anchor)
     int32_t *perm = nullptr;    // sorted position -> original point index
+    int32_t *slots = nullptr;   // 3-D: interpolation slots in sorted order, each one point or
+                                // two consecutive points of one cell (first point | pair << 31)
     int32_t *bin_sub_ptr = nullptr;  // tile -> spreading subproblems of its group (nbins + 1)
     void *Dk = nullptr;     // symmetrised diagonal for K_s (dcells, plan precision)
     void *Dder = nullptr;   // same for K_s^der
     // host copies used while the plan is built
     std::vector<int> h_bin_start;   // tile -> first sorted point (kept for re-tuning)
     std::vector<int> h_row_cnt;     // 3-D: points per (tile, first-axis cell row), nbins x tb
+    std::vector<int> h_slot_start;  // 3-D: tile -> first slot (nbins + 1)
+    std::vector<int> h_row_slots;   // 3-D: slots per (tile, first-axis cell row), nbins x tb
 };
 
 // Per-window data a kernel needs, in device memory (one array per group).
@@ -71,6 +75,7 @@ struct WinDesc {
     const int32_t *bin_sub_ptr;
     const void *Dk;
     const void *Dder;
+    const int32_t *slots;
     int32_t s_global;   // window index in the plan
     int32_t pad_;
 };
@@ -109,6 +114,7 @@ struct Group {
     int sub_cap = 0;             // capacity of the spreading list arrays
     int interp_pt = 1;           // points per thread of the tile interpolation (1, 2)
     bool interp_adj = false;     // 3-D, 2 points per thread: adjacent sorted points share tap reads
+    bool interp_slot = false;    // 3-D: one slot per thread (two points of one cell share every tap read)
     int interp_vb_lds = 80 << 10;   // d <= 2: LDS bytes for several vectors per staging (0: one vector)
     int interp_rows = 0;         // 3-D: first-axis rows of the padded tile staged per subproblem
     int isub_cap = 0;            // capacity of the interpolation list arrays
@@ -194,7 +200,8 @@ struct nfftgp_plan_s {
     // workspaces (owned)
     void *tilebuf = nullptr;     // spreading tiles
     size_t tile_cap = 0;         // tilebuf capacity in values per vector
-    void *grid = nullptr;        // 2 x (windows of a group) x max_nrhs x cells complex values
+    void *grid = nullptr;        // (windows of a group) x max_nrhs x cells complex values: the real
+                                 // grid before the transforms, kernel + i derivative grid after
     void *hbuf = nullptr;        // P x n x max_nrhs per-window products
     double *coef = nullptr;      // set_hyper scratch (real coefficient transforms)
     double *minb_host = nullptr; // 2 x P smallest coefficients (pinned, written by the

@@ -47,10 +47,13 @@ class AdditiveGP:
     X_test : inputs that will be predicted (their range enters the box scaling).
     dtype, device : precision and device of the plans.
     n_probes : Rademacher probes per training step.
+    precond : None, or (landmarks per window, max rank, block size) of the AAFN
+        preconditioner (Sec. 2.3; Sec. 5 trains with 10 landmarks per window):
+        training then uses the preconditioned estimator and preconditioned CG.
     """
 
     def __init__(self, X, y, windows, kernel, N, m: int, X_test=None, dtype=torch.float32,
-                 device="cuda:0", n_probes: int = 10, seed: int = 0):
+                 device="cuda:0", n_probes: int = 10, seed: int = 0, precond=None):
         self.X = np.ascontiguousarray(torch.as_tensor(X).double().cpu().numpy())
         self.y_host = np.asarray(torch.as_tensor(y).double().cpu().numpy()).reshape(-1)
         self.n, self.p = self.X.shape
@@ -79,6 +82,10 @@ class AdditiveGP:
         if self.X_test is not None:
             self.plan = AdditiveKernelPlan(self._dev(self.X), self.windows, kernel, N, self.m, max_nrhs=nb,
                                            scale=(self.c0, self.c))
+        self.precond = precond is not None
+        if self.precond:
+            kw, mr, blk = precond
+            self.plan.attach_precond(self._dev(self.X), int(kw), int(mr), int(blk))
         self.y = torch.tensor(self.y_host, dtype=dtype, device=self.device)
         # raw parameters [sigma_f, sigma_eps, ell_1..ell_P]; theta = softplus(raw)
         self.raw = np.zeros(2 + self.P)
@@ -112,7 +119,8 @@ class AdditiveGP:
         its gradient with respect to (sigma_f, sigma_eps, ell_s) in caller units."""
         th = self.theta
         est = lml_estimate(self.plan, self.y, self._probes(step), th["sigma_f"], th["ell"], th["sigma_eps"],
-                           tol=tol, maxit=maxit, check_every=max(1, maxit) if tol == 0.0 else 8)
+                           tol=tol, maxit=maxit, check_every=max(1, maxit) if tol == 0.0 else 8,
+                           precond=self.precond)
         g = np.empty(2 + self.P)
         g[0] = est["grad"]["sigma_f"]
         g[1] = est["grad"]["sigma_eps"]
@@ -124,10 +132,10 @@ class AdditiveGP:
             betas=(0.9, 0.999), eps: float = 1e-8) -> list:
         """Adam on the raw parameters (theta = softplus(raw)); fresh probes every
         step; CG stops at relative residual cg_tol or after cg_iters iterations
-        (cg_tol = 0: a fixed number of iterations, as in Sec. 5, where a
-        preconditioner makes 10 iterations enough -- without one, small noise
-        levels need converged solves for an unbiased gradient).  Returns the
-        history of (step, Z estimate, theta)."""
+        (cg_tol = 0: a fixed number of iterations, as in Sec. 5, where the
+        AAFN preconditioner makes 10 iterations enough -- without one, small
+        noise levels need converged solves for an unbiased gradient).  Returns
+        the history of (step, Z estimate, theta)."""
         m1, m2, t = self._adam
         for k in range(steps):
             ob = self.objective(step=t, tol=cg_tol, maxit=cg_iters)
@@ -147,7 +155,8 @@ class AdditiveGP:
         """alpha = Khat^-1 y at the current theta (CG to relative residual tol)."""
         th = self.theta
         self.plan.set_hyper(th["sigma_f"], th["ell"], th["sigma_eps"])
-        X, iters, _, resid, st = self.plan.cg(self.y.reshape(-1, 1).contiguous(), tol, maxit, history=False)
+        X, iters, _, resid, st = self.plan.cg(self.y.reshape(-1, 1).contiguous(), tol, maxit, history=False,
+                                              precond=self.precond)
         return X[:, 0].contiguous()
 
     def cross_apply(self, alpha: torch.Tensor, X_test=None) -> torch.Tensor:
@@ -200,7 +209,7 @@ class AdditiveGP:
             KE = up.apply(E)["KV"]
             Kc = KE[: self.n].contiguous()
             kss = KE[rows, torch.arange(jb, device=self.device)].double() - se2
-            A, _, _, _, _ = self.plan.cg(Kc, tol, maxit, history=False)
+            A, _, _, _, _ = self.plan.cg(Kc, tol, maxit, history=False, precond=self.precond)
             q = torch.tensor(self.plan.col_dots(Kc, A), dtype=torch.float64, device=self.device)
             out[j0:j0 + jb] = kss - q + (se2 if noise else 0.0)
         if up is not self._union:

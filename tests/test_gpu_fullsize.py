@@ -61,6 +61,8 @@ FULL = [
     ("C5-f32", "C5", "f32", 4, 2500, {}, False),
     ("C5-f32-R2-quad-tile2", "C5", "f32", 4, 2500,
      {"NFFTGP_SPREAD_R": "2", "NFFTGP_SPREAD_FORM": "quad", "NFFTGP_INTERP": "tile2"}, False),
+    ("C5-f32-tileslot", "C5", "f32", 4, 2500, {"NFFTGP_INTERP": "tileslot"}, False),
+    ("C4-f64-tileslot", "C4", "f64", 2, 4000, {"NFFTGP_INTERP": "tileslot"}, False),
 ]
 
 

@@ -73,14 +73,15 @@ SMALL = [
 ]
 
 
-@pytest.mark.parametrize("interp", ["tile", "tile2", "tilepair", "tilefull", "run"])
+@pytest.mark.parametrize("interp", ["tile", "tile2", "tilepair", "tileslot", "tilefull", "run"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("case", SMALL, ids=[f"case{c[0]}" for c in SMALL])
 def test_small_parity(orc, case, prec, interp, monkeypatch):
     """Every interpolation variant (per-point tile reads with one or two points
-    per thread, or two adjacent sorted points per thread sharing tap reads in
-    3-D; register-held runs of equal cells), forced through NFFTGP_INTERP at
-    plan creation."""
+    per thread, two adjacent sorted points per thread sharing tap reads in
+    3-D, one slot of one or two points of one cell per thread in 3-D;
+    register-held runs of equal cells), forced through NFFTGP_INTERP at plan
+    creation."""
     monkeypatch.setenv("NFFTGP_INTERP", interp)
     seed, n, dims, kt, ell, N, m, nrhs, dist = case
     w = workloads.small(seed, n, dims, kt, ell, N, m, nrhs, dist=dist, scale_mode=1 if dist == "box" else 0)
@@ -154,7 +155,8 @@ def test_interp_variants_agree(prec, monkeypatch):
     X = torch.tensor(w.X, dtype=dt, device="cuda:0")
     V = torch.tensor(w.V, dtype=dt, device="cuda:0")
     outs = []
-    for mode in ("tile", "tile2", "tilepair", "tilefull", "run", "tile+w2", "tile+quad", "tile+quad+w2"):
+    for mode in ("tile", "tile2", "tilepair", "tileslot", "tilefull", "run", "tile+w2", "tile+quad",
+                 "tile+quad+w2"):
         monkeypatch.setenv("NFFTGP_INTERP", mode.split("+")[0])
         monkeypatch.delenv("NFFTGP_SPREAD_W", raising=False)
         monkeypatch.delenv("NFFTGP_SPREAD_FORM", raising=False)
