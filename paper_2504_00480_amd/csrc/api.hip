@@ -617,8 +617,11 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
             const int rv = std::atoi(srv);
             G.spread_R = (rv == 1 || rv == 2 || rv == 4) ? rv : 0;
         }
-        const char *sfv = std::getenv("NFFTGP_SPREAD_FORM");   // "quad" | "run"
-        G.spread_form = !sfv ? 0 : (std::strcmp(sfv, "quad") == 0 ? 1 : (std::strcmp(sfv, "run") == 0 ? 2 : 0));
+        const char *sfv = std::getenv("NFFTGP_SPREAD_FORM");   // "quad" | "run" | "mfma"
+        G.spread_form = !sfv ? 0
+                             : (std::strcmp(sfv, "quad") == 0 ? 1
+                                                               : (std::strcmp(sfv, "run") == 0 ? 2
+                                                                                                : (std::strcmp(sfv, "mfma") == 0 ? 3 : 0)));
         const char *iov = std::getenv("NFFTGP_INTERP");
         // d <= 2: LDS bytes of the several-vector staging, NFFTGP_INTERP_VB=<bytes>
         // overrides ("0": one vector per staging)

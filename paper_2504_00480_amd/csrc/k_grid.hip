@@ -460,6 +460,227 @@ k_spread_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     }
 }
 
+// Matrix-core form of 3-D FP32 spreading.  All points of a run share the
+// cell floor(t), so the run's contribution to the (2m)^3 target cells of R
+// vectors is one dense contraction over the run's points p:
+//
+//   T[(b, c), (a, r)] = sum_p  w1_p[b] w2_p[c]  *  w0_p[a] v_p[r],
+//
+// rows (b, c) = TW^2 tap pairs of the second and third dimension, columns
+// (a, r) = first-dimension tap times vector.  It runs on
+// v_mfma_f32_16x16x4_f32, four points per step (points past the run end
+// enter with zero weight).  The first two dimensions are indexed by slot, the
+// tap's tile position modulo TW (the weight record stores the first
+// dimension that way; the second is rotated here, per run), so a tile cell's
+// slot pair does not depend on the run.  Wave w keeps column block w mod NB
+// (first-dimension slots 16/R (w mod NB) .. + 16/R - 1 times R vectors) and
+// the 3 x 16 rows of second-dimension slots 4 (w / NB) .. + 3 times all TW
+// third-dimension taps: row i = 4 q + v of its block k is second slot
+// 4 (w / NB) + q and third tap 4 k + v.  Waves therefore own disjoint slot
+// pairs, hence disjoint tile cells whatever the run, and each wave flushes a
+// run into the LDS tile after its last point with plain loads and stores and
+// no barrier (a wave's own flushes are ordered).  The LDS tile is padded (row
+// stride odd, plane stride 8 and vector stride 2 modulo 32 words) so that the
+// 32 lanes of a flush half-wave fall on distinct banks; it is written out
+// unpadded.
+template <int M, int R>
+struct SpreadMfmaShape {
+    static constexpr int TW = 2 * M;
+    static constexpr int NB = TW * R / 16;                      // column blocks
+    static constexpr int MG = TW / 4;                           // second-dimension slot groups
+    static constexpr int BPW = TW / 4;                          // row blocks per wave
+    static constexpr int NWAVE = NB * MG;
+    static_assert(TW % 4 == 0 && (TW * R) % 16 == 0 && 16 % R == 0, "block shape");
+};
+
+// Padded strides of the LDS tile (words): row, plane, vector.
+struct SpreadMfmaPad {
+    int sb, sa, sr;
+};
+
+__host__ __device__ inline SpreadMfmaPad spread_mfma_pad(int pd)
+{
+    SpreadMfmaPad q;
+    q.sb = pd | 1;
+    q.sa = pd * q.sb + ((8 - pd * q.sb) % 32 + 32) % 32;
+    q.sr = pd * q.sa + ((2 - pd * q.sa) % 32 + 32) % 32;
+    return q;
+}
+
+template <int M, int R>
+__global__ void __launch_bounds__((64 * SpreadMfmaShape<M, R>::NWAVE))
+k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
+              const int *__restrict__ sub_start, const int *__restrict__ sub_count,
+              const float *__restrict__ V, int64_t ldv, int nrhs, int pd, float *__restrict__ tilebuf)
+{
+    using f4 = __attribute__((ext_vector_type(4))) float;
+    using S = SpreadMfmaShape<M, R>;
+    constexpr int TW = S::TW, NB = S::NB, BPW = S::BPW;
+    constexpr int RS = 3 * TW;                                  // weights per point
+    constexpr int SPB = 16 / R;                                 // first-dimension slots per column block
+    constexpr int CH = 64;                                      // points staged per chunk
+    constexpr int CHP = CH + 8;                                 // + zero points read past a chunk's end
+    constexpr int NT = 64 * S::NWAVE;
+    __shared__ float s_rec[CHP * RS];
+    __shared__ float s_v[CHP * R];
+    __shared__ int s_lp[CH];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float *tiles = reinterpret_cast<float *>(smem_raw);
+    const SpreadMfmaPad pad = spread_mfma_pad(pd);
+    const int pd2 = pd * pd, pc = pd2 * pd;
+    const float inv_pd = 1.0f / (float)pd;
+    const int sq = xcd_item(blockIdx.x, gridDim.x), r0 = blockIdx.y * R;
+    const WinDesc &win = wd[sub_win[sq]];
+    const float *rec = reinterpret_cast<const float *>(win.rec);
+    const int *lpos = win.lpos;
+    const int *perm = win.perm;
+    const int start = sub_start[sq], cnt = sub_count[sq];
+    const int end = start + cnt;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < R * pad.sr; i += NT) tiles[i] = 0.0f;
+    for (int i = tid; i < (CHP - CH) * RS; i += NT) s_rec[CH * RS + i] = 0.0f;
+    for (int i = tid; i < (CHP - CH) * R; i += NT) s_v[CH * R + i] = 0.0f;
+    // operand coordinates: A[i][k] and B[k][j] sit in lane i + 16 k (resp.
+    // j + 16 k), the accumulator's element v in row 4 (lane / 16) + v
+    const int li = lane & 15, kq = lane >> 4;
+    const int nb = wave % NB, bg = wave / NB;
+    const int aslot = nb * SPB + li / R, br = li % R;           // B column: first slot, vector
+    const int bslot_a = 4 * bg + li / 4;                        // A row li: second slot
+    const int bslot_f = 4 * bg + kq;                            // accumulator rows: second slot
+    const int ac = 2 * TW + li % 4;                             // A row li, block k: third tap 4 k + li % 4
+    f4 acc[BPW];
+#pragma unroll
+    for (int k = 0; k < BPW; ++k) acc[k] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int nr = min(R, nrhs - r0);
+    constexpr int NREC = (CH * RS + NT - 1) / NT, NV = (CH * R + NT - 1) / NT;
+    float g_rec[NREC], g_v[NV];
+    int g_lp = 0;
+    auto fetch = [&](int cb) {
+        const int nc = min(CH, end - cb);
+#pragma unroll
+        for (int k = 0; k < NREC; ++k) {
+            const int i = tid + k * NT;
+            g_rec[k] = i < nc * RS ? rec[(int64_t)cb * RS + i] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const int i = tid + k * NT;
+            const int u = i / R, r = i % R;
+            g_v[k] = (i < nc * R && r < nr) ? V[(int64_t)perm[cb + u] * ldv + r0 + r] : 0.0f;
+        }
+        g_lp = tid < nc ? lpos[cb + tid] : 0;
+    };
+    if (cnt > 0) fetch(start);
+    for (int cb = start; cb < end; cb += CH) {
+        const int nc = min(CH, end - cb);
+        __syncthreads();   // tiles cleared / previous chunk consumed
+#pragma unroll
+        for (int k = 0; k < NREC; ++k) {
+            const int i = tid + k * NT;
+            if (i < CH * RS) s_rec[i] = g_rec[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const int i = tid + k * NT;
+            if (i < CH * R) s_v[i] = g_v[k];
+        }
+        if (tid < CH) s_lp[tid] = g_lp;
+        __syncthreads();
+        if (cb + CH < end) fetch(cb + CH);
+        const int my_lp = lane < nc ? s_lp[lane] : 0;
+        const bool isend = lane < nc && (my_lp < 0 || cb + lane == end - 1);
+        const unsigned long long ends = __ballot(isend);
+        int u0 = 0;
+        while (u0 < nc) {
+            const unsigned long long rest = ends >> u0;
+            const bool flush = rest != 0ull;
+            const int u1 = flush ? u0 + (int)__builtin_ctzll(rest) : nc - 1;
+            // the run's first tap is cell (a0, b0, c0) of the padded tile
+            const int lp = __builtin_amdgcn_readlane(my_lp, u0) & 0x7fffffff;
+            const int base = lp & 0xfffff, a0 = lp >> 20;
+            const int rem = base - a0 * pd2;
+            const int b0 = fdiv_small(rem, pd, inv_pd), c0 = rem - b0 * pd;
+            // second-dimension tap of the lane's A row (slot bslot_a)
+            const int ab = TW + ((bslot_a - b0) % TW + TW) % TW;
+            // operands of step u: B = w0[slot] v[r], A = w1[b] w2[c] of the
+            // lane's point u + kq, weight 0 past the run end (the reads there
+            // hit later points of the chunk or the zero padding).  Two operand
+            // sets alternate, so the reads of step u + 4 are in flight while
+            // step u's products run.
+            struct Ops {
+                float w0, v, wb, wc[BPW];
+                bool ok;
+            };
+            const float *pr = s_rec + (u0 + kq) * RS;
+            const float *pv = s_v + (u0 + kq) * R + br;
+            int pu = u0 + kq;
+            auto load = [&](Ops &o) {
+                o.w0 = pr[aslot];
+                o.v = *pv;
+                o.wb = pr[ab];
+#pragma unroll
+                for (int k = 0; k < BPW; ++k) o.wc[k] = pr[ac + 4 * k];
+                o.ok = pu <= u1;
+                pr += 4 * RS;
+                pv += 4 * R;
+                pu += 4;
+            };
+            auto step = [&](const Ops &o) {
+                const float bv = o.ok ? o.w0 * o.v : 0.0f;
+#pragma unroll
+                for (int k = 0; k < BPW; ++k)
+                    acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.wb * o.wc[k], bv, acc[k], 0, 0, 0);
+            };
+            // (scheduling barriers keep each set's reads ahead of the other
+            // set's products)
+            Ops opa, opb;
+            load(opa);
+            for (int u = u0;; u += 8) {
+                load(opb);
+                __builtin_amdgcn_sched_barrier(0);
+                step(opa);
+                __builtin_amdgcn_sched_barrier(0);
+                if (u + 4 > u1) break;
+                load(opa);
+                __builtin_amdgcn_sched_barrier(0);
+                step(opb);
+                __builtin_amdgcn_sched_barrier(0);
+                if (u + 8 > u1) break;
+            }
+            if (flush) {
+                // lane's cells: first tap (aslot - a0) mod TW, second tap
+                // (bslot_f - b0) mod TW, third taps 4 k + v; all reads first,
+                // then the writes
+                const int at = ((aslot - a0) % TW + TW) % TW;
+                const int bt = ((bslot_f - b0) % TW + TW) % TW;
+                float *tp = tiles + br * pad.sr + (a0 + at) * pad.sa + (b0 + bt) * pad.sb + c0;
+                float old[BPW][4];
+#pragma unroll
+                for (int k = 0; k < BPW; ++k)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) old[k][v] = tp[4 * k + v];
+#pragma unroll
+                for (int k = 0; k < BPW; ++k) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) tp[4 * k + v] = old[k][v] + acc[k][v];
+                    acc[k] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+                }
+            }
+            u0 = u1 + 1;
+        }
+    }
+    __syncthreads();
+    for (int r = 0; r < nr; ++r) {
+        float *out = tilebuf + ((int64_t)sq * nrhs + r0 + r) * pc;
+        for (int i = tid; i < pc; i += NT) {
+            const int a = fdiv_small(i, pd2, 1.0f / (float)pd2);
+            const int rm = i - a * pd2;
+            const int b = fdiv_small(rm, pd, inv_pd), c = rm - b * pd;
+            out[i] = tiles[r * pad.sr + a * pad.sa + b * pad.sb + c];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- fold
 // Phase 1: the subproblems of one tile are summed into the first one's slot
 // (in place, fixed order: 4 slices per cell combined through LDS).
@@ -1373,10 +1594,43 @@ hipError_t spread_launch(const Group &G, const void *V, int64_t ldv, int nrhs, v
     return hipGetLastError();
 }
 
+constexpr bool kSpreadMfmaRule = true;
+
+// Matrix-core spreading applies to FP32, d = 3, 2m = 8 or 12 and tiles whose
+// four vectors fit the LDS next to the staged points.
+constexpr size_t kSpreadMfmaLds = 148 * 1024;
+
+template <typename T, int D, int M>
+bool spread_mfma_ok(const Group &G)
+{
+    return std::is_same<T, float>::value && D == 3 && (M == 4 || M == 6) &&
+           (size_t)spread_mfma_pad(G.g.pd).sr * sizeof(float) * 4 <= kSpreadMfmaLds;
+}
+
+template <int M>
+hipError_t spread_mfma_launch(const Group &G, const void *V, int64_t ldv, int nrhs, void *tilebuf,
+                              hipStream_t s)
+{
+    constexpr int R = 4, NW = SpreadMfmaShape<M, R>::NWAVE;
+    const size_t shm = (size_t)spread_mfma_pad(G.g.pd).sr * sizeof(float) * R;
+    hipError_t e = allow_lds(k_spread_mfma<M, R>, shm);
+    if (e != hipSuccess) return e;
+    dim3 grid((unsigned)G.nsub, (unsigned)((nrhs + R - 1) / R));
+    k_spread_mfma<M, R><<<grid, 64 * NW, shm, s>>>(G.desc, G.sub_win, G.sub_start, G.sub_count,
+                                                   (const float *)V, ldv, nrhs, G.g.pd, (float *)tilebuf);
+    return hipGetLastError();
+}
+
 template <typename T, int D, int M>
 hipError_t spread_dm(const Group &G, const void *V, int64_t ldv, int nrhs, void *tilebuf,
                      hipStream_t s)
 {
+    // matrix-core form: by request (spread_form 3), or by rule for four or
+    // more vectors
+    if constexpr (std::is_same<T, float>::value && D == 3 && (M == 4 || M == 6)) {
+        if (spread_mfma_ok<T, D, M>(G) && (G.spread_form == 3 || (G.spread_form == 0 && nrhs >= 4 && kSpreadMfmaRule)))
+            return spread_mfma_launch<M>(G, V, ldv, nrhs, tilebuf, s);
+    }
     // d = 3: four waves share a tile (2m taps split four ways).  R vectors per
     // work-group share the points' weights; R tiles must fit in 64 KiB, and
     // R = 4 is taken only when it leaves no partial group of vectors (measured:

@@ -105,7 +105,8 @@ struct Group {
     int spread_R = 0;            // vectors per spreading work-group (0: rule)
     int spread_W = 0;            // 3-D: waves sharing a spreading tile (0: rule, 4; or 2)
     int spread_form = 0;         // spreading kernel: 0 rule (four-point form for one vector
-                                 // per work-group, else run-ordered), 1 four-point, 2 run-ordered
+                                 // per work-group, else run-ordered), 1 four-point, 2 run-ordered,
+                                 // 3 matrix cores (FP32, d = 3)
     // every window Gaussian: set_hyper only records theta (prm) and the next
     // apply computes the coefficients in extra work-groups of its fold launch
     bool sep = false;
