@@ -258,7 +258,8 @@ nfftgp_status build_spread_lists(nfftgp_plan plan, Group &G, int sub_sp)
 
 // (Re)build a group's tile-interpolation work list: subproblems of up to
 // 256 * pt points of one tile (pt points per thread).
-nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt, int rows, bool slot = false)
+nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt, int rows, bool slot = false,
+                                 bool blk = false)
 {
     // 3-D: a subproblem stages only `rows` first-axis rows of the padded tile
     // (points of first-tap rows f0..f1 read rows f0 .. f1 + 2m - 1, since the
@@ -270,9 +271,11 @@ nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt, int rows, b
     const int m = plan->m;
     const bool cut = g.d == 3 && rows < g.pd;
     if (g.d != 3) rows = g.pd;
-    // 3-D slots: the lists count slots (one or two points of one cell), one per thread
-    slot = slot && g.d == 3 && plan->n > 0;
-    const int isp_s = slot ? kInterpSubPoints : isp;
+    // 3-D slots: the lists count slots (one or two points of one cell), one per thread;
+    // 3-D FP32 matrix-core blocks: the lists count blocks
+    blk = blk && g.d == 3 && plan->n > 0 && plan->prec == NFFTGP_F32 && (m == 4 || m == 6);
+    slot = slot && !blk && g.d == 3 && plan->n > 0;
+    const int isp_s = blk ? kInterpSubBlocks : (slot ? kInterpSubPoints : isp);
     if (rows < 2 * m || rows > g.pd) return fail(NFFTGP_E_ARG, "bad interpolation row count");
     std::vector<int> iw, ib, is, ic;
     auto push = [&](int wl, int b, int start, int cnt, int f0) {
@@ -284,8 +287,8 @@ nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt, int rows, b
     };
     for (int wl = 0; wl < G.nwin; ++wl) {
         const Window &w = plan->win[G.wins[wl]];
-        const std::vector<int> &bs = slot ? w.h_slot_start : w.h_bin_start;
-        const std::vector<int> &rc = slot ? w.h_row_slots : w.h_row_cnt;
+        const std::vector<int> &bs = blk ? w.h_block_start : (slot ? w.h_slot_start : w.h_bin_start);
+        const std::vector<int> &rc = blk ? w.h_row_blocks : (slot ? w.h_row_slots : w.h_row_cnt);
         for (int b = 0; b < g.nbins; ++b) {
             const int cnt = bs[b + 1] - bs[b];
             if (cnt == 0) continue;
@@ -323,7 +326,8 @@ nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt, int rows, b
     G.interp_pt = slot ? 2 : pt;
     G.interp_rows = rows;
     G.interp_slot = slot;
-    if (slot) G.interp_adj = false;
+    G.interp_mfma = blk;
+    if (slot || blk) G.interp_adj = false;
     return NFFTGP_OK;
 }
 
@@ -552,6 +556,29 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
             w.h_slot_start[w.g.nbins] = (int)sl.size();
             TRYS(dalloc(plan, (void **)&w.slots, sl.size() * sizeof(int)));
             TRYH(hipMemcpy(w.slots, sl.data(), sl.size() * sizeof(int), hipMemcpyHostToDevice));
+            // matrix-core interpolation blocks: each run of equal cells cut
+            // into pieces of at most 16 points; block starts, then n
+            std::vector<int> bl;
+            bl.reserve(n / 8 + 1);
+            w.h_block_start.assign(w.g.nbins + 1, 0);
+            w.h_row_blocks.assign((size_t)w.g.nbins * w.g.tb, 0);
+            for (int b = 0; b < w.g.nbins; ++b) {
+                w.h_block_start[b] = (int)bl.size();
+                for (int j = bs[b]; j < bs[b + 1];) {
+                    int e = j;
+                    while (e < bs[b + 1] - 1 && hanchor[e] >= 0) ++e;   // e: last point of the run
+                    const int a = hanchor[j] & 0x7fffffff;
+                    for (int k = j; k <= e; k += 16) {
+                        bl.push_back(k);
+                        w.h_row_blocks[(size_t)b * tb + (a / (ng * ng)) % tb] += 1;
+                    }
+                    j = e + 1;
+                }
+            }
+            w.h_block_start[w.g.nbins] = (int)bl.size();
+            bl.push_back((int)n);
+            TRYS(dalloc(plan, (void **)&w.blocks, bl.size() * sizeof(int)));
+            TRYH(hipMemcpy(w.blocks, bl.data(), bl.size() * sizeof(int), hipMemcpyHostToDevice));
         }
         TRYS(dalloc(plan, &w.Dk, w.g.dcells * eb));
         TRYS(dalloc(plan, &w.Dder, w.g.dcells * eb));
@@ -589,9 +616,15 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
                 G.nbins_used += cnt > 0;
                 cap += (cnt + kMinSubSp - 1) / kMinSubSp;
                 icap += (cnt + kInterpSubPoints - 1) / kInterpSubPoints + (d3 && cnt > 0 ? G.g.tb : 0);
+                if (d3 && !w.h_block_start.empty()) {
+                    // the block lists (at most kInterpSubBlocks blocks per subproblem) may be longer
+                    const int nbl = w.h_block_start[b + 1] - w.h_block_start[b];
+                    icap += (nbl + kInterpSubBlocks - 1) / kInterpSubBlocks;
+                }
             }
             TRYS(dalloc(plan, (void **)&w.bin_sub_ptr, (w.g.nbins + 1) * sizeof(int)));
-            hd[wl] = WinDesc{w.rec, w.anchor, w.lpos, w.perm, w.bin_sub_ptr, w.Dk, w.Dder, w.slots, G.wins[wl], 0};
+            hd[wl] = WinDesc{w.rec,  w.anchor, w.lpos,   w.perm,        w.bin_sub_ptr, w.Dk,
+                             w.Dder, w.slots,  w.blocks, G.wins[wl], 0};
         }
         G.sub_cap = (int)std::max<int64_t>(cap, 1);
         {
@@ -607,7 +640,7 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
         }
         // interpolation variant: the per-point tile variant by default (the
         // faster one on every measured workload once its tile staging was
-        // batched); nfftgp_autotune may switch, NFFTGP_INTERP=run|tile|tile2|tilepair|tilefull
+        // batched); nfftgp_autotune may switch, NFFTGP_INTERP=run|tile|tile2|tilepair|tilefull|tileslot|mfma
         // forces (tile2: two points per thread; tilepair: two adjacent sorted points
         // per thread sharing tap reads, 3-D; tilefull: whole padded tiles staged)
         const char *swv = std::getenv("NFFTGP_SPREAD_W");   // "2": two waves per 3-D tile
@@ -631,9 +664,15 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
         const bool full = iov && std::strcmp(iov, "tilefull") == 0;
         const bool pair = iov && std::strcmp(iov, "tilepair") == 0;
         const bool slot = iov && std::strcmp(iov, "tileslot") == 0;
+        // 3-D FP32 with m = 4 or 6 and several vectors: matrix-core blocks
+        // unless another variant is forced
+        const bool blk = iov ? std::strcmp(iov, "mfma") == 0
+                             : (G.g.d == 3 && prec == NFFTGP_F32 && (m == 4 || m == 6) && max_nrhs >= 2);
+        const char *imw = std::getenv("NFFTGP_INTERP_MFMA_WAVES");   // "8" | "16"
+        G.interp_mfma_waves = imw && std::strcmp(imw, "8") == 0 ? 8 : 16;
         G.interp_adj = pair && G.g.d == 3;
         TRYS(build_interp_lists(plan, G, iov && (pair || std::strcmp(iov, "tile2") == 0) ? 2 : 1,
-                                full ? G.g.pd : interp_rows_rule(G.g, m), slot));
+                                full ? G.g.pd : interp_rows_rule(G.g, m), slot, blk));
         {
             // run-interpolation list (built for every group, so that the
             // variant can be switched): points per wave up to kRunSubPoints,
@@ -907,10 +946,11 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
         //    is not a candidate: the tuner times applies with derivative outputs,
         //    and the pair form's K-only launches, which CG makes, are slower)
         const bool cur_run = G.use_run_interp, cur_adj = G.interp_adj, cur_slot = G.interp_slot;
+        const bool cur_blk = G.interp_mfma;
         const int cur_pt = G.interp_pt, cur_rows = G.interp_rows;
-        bool best_run = cur_run, best_adj = cur_adj, best_slot = cur_slot;
+        bool best_run = cur_run, best_adj = cur_adj, best_slot = cur_slot, best_blk = cur_blk;
         int best_pt = cur_pt, best_rows = cur_rows;
-        struct Cand { bool run; int pt, rows; bool adj, slot; };
+        struct Cand { bool run; int pt, rows; bool adj, slot, blk = false; };
         std::vector<Cand> cands;
         const int rr = interp_rows_rule(G.g, plan->m);
         for (int pt : {1, 2}) {
@@ -921,16 +961,19 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
             // one slot (one or two points of one cell) per thread
             cands.push_back({false, 2, rr, false, true});
             if (rr != G.g.pd) cands.push_back({false, 2, G.g.pd, false, true});
+            // blocks of one cell on matrix cores (FP32, m = 4 or 6)
+            if (plan->prec == NFFTGP_F32 && (plan->m == 4 || plan->m == 6))
+                cands.push_back({false, 1, rr, false, false, true});
         }
-        cands.push_back({true, cur_pt, cur_rows, cur_adj, cur_slot});
+        cands.push_back({true, cur_pt, cur_rows, cur_adj, cur_slot, cur_blk});
         for (const Cand &c : cands) {
             if (stt != NFFTGP_OK) break;
-            if (c.run == cur_run &&
-                (c.run || (c.pt == cur_pt && c.rows == cur_rows && c.adj == cur_adj && c.slot == cur_slot)))
+            if (c.run == cur_run && (c.run || (c.pt == cur_pt && c.rows == cur_rows && c.adj == cur_adj &&
+                                               c.slot == cur_slot && c.blk == cur_blk)))
                 continue;
             G.use_run_interp = c.run;
             G.interp_adj = c.adj;
-            if (!c.run && (stt = build_interp_lists(plan, G, c.pt, c.rows, c.slot)) != NFFTGP_OK) break;
+            if (!c.run && (stt = build_interp_lists(plan, G, c.pt, c.rows, c.slot, c.blk)) != NFFTGP_OK) break;
             double t = 0.0;
             if ((stt = timed(t)) != NFFTGP_OK) break;
             if (t < best) {
@@ -940,18 +983,20 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
                 best_rows = c.rows;
                 best_adj = c.adj;
                 best_slot = c.slot;
+                best_blk = c.blk;
             }
         }
         if (stt != NFFTGP_OK) break;
         G.use_run_interp = best_run;
         G.interp_adj = best_adj;
-        if ((stt = build_interp_lists(plan, G, best_pt, best_rows, best_slot)) != NFFTGP_OK) break;
-        G.interp_adj = best_adj && !best_slot;
+        if ((stt = build_interp_lists(plan, G, best_pt, best_rows, best_slot, best_blk)) != NFFTGP_OK) break;
+        G.interp_adj = best_adj && !best_slot && !best_blk;
         std::string ivar = "run";
         if (!G.use_run_interp) {
-            ivar = G.interp_slot ? "tile, same-cell point pairs"
-                                 : (G.interp_adj ? "tile, adjacent point pairs"
-                                                 : (G.interp_pt == 2 ? "tile, 2 points/thread" : "tile"));
+            ivar = G.interp_mfma ? "matrix-core blocks of one cell"
+                                 : (G.interp_slot ? "tile, same-cell point pairs"
+                                                  : (G.interp_adj ? "tile, adjacent point pairs"
+                                                                  : (G.interp_pt == 2 ? "tile, 2 points/thread" : "tile")));
             if (G.g.d == 3) ivar += ", " + std::to_string(G.interp_rows) + " of " + std::to_string(G.g.pd) + " rows";
         }
         char line[240];

@@ -1117,6 +1117,174 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     }
 }
 
+// Matrix-core form of 3-D FP32 interpolation.  A block is at most 16 points
+// of one cell, so its points read the same (2m)^3 taps of the tile and
+//
+//   X[p, (a, e)] = sum_(b, c)  w1_p[b] w2_p[c]  *  G_e[a0 + a, b0 + b, c0 + c]
+//
+// is one dense product: rows p (the block's points, missing rows with zero
+// weight), reduction over the TW^2 tap pairs (b, c), four at a time on
+// v_mfma_f32_16x16x4_f32, columns (a, e) = four first-dimension taps times
+// four staged values e per cell (K and dK of two vectors with derivative
+// outputs, else K of four vectors); TW / 4 column blocks cover the TW first-
+// dimension taps.  Then h_p[e] = sum_a w0_p[a] X[p, (a, e)]: each lane
+// weights its accumulators and four lanes are summed.  A work-group of 8
+// waves takes a subproblem of at most 16 blocks of one tile; the blocks'
+// weights, output rows and first taps sit in LDS for the whole subproblem,
+// and the staged rows of the padded tile (plane stride 8 modulo 32 words:
+// the 32 lanes of a half-wave read distinct banks) hold four values per cell.
+template <int M, bool DER, int NWV>
+__global__ void __launch_bounds__((64 * NWV))
+k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
+              const int *__restrict__ sub_bin, const int *__restrict__ sub_start,
+              const int *__restrict__ sub_count, int tb, int nb, int ng, int rows,
+              const float2 *__restrict__ grid, int64_t cells, int nrhs, int64_t n,
+              float *__restrict__ hbuf, float *__restrict__ dout, float dscale)
+{
+    using f4 = __attribute__((ext_vector_type(4))) float;
+    constexpr int TW = 2 * M, RS = 3 * TW;
+    constexpr int NBK = TW / 4;                 // column blocks (four first-dimension taps each)
+    constexpr int KS = TW * TW / 4;             // reduction steps over (b, c)
+    constexpr int VPS = DER ? 2 : 4;            // vectors per staging
+    constexpr int NT = 64 * NWV;
+    constexpr int MAXP = 16 * kInterpSubBlocks;
+    __shared__ float s_w[MAXP * RS];
+    __shared__ int s_row[MAXP];
+    __shared__ int s_blk[kInterpSubBlocks + 1];
+    __shared__ int s_lp[kInterpSubBlocks];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float *tile = reinterpret_cast<float *>(smem_raw);
+    const int pd = tb + 2 * M, pd2 = pd * pd;
+    const int ps = 4 * pd2 + ((8 - 4 * pd2) % 32 + 32) % 32;   // plane stride (words)
+    const int sq = xcd_item(blockIdx.x, gridDim.x);
+    const int wi = sub_win[sq];
+    const WinDesc &win = wd[wi];
+    const float *rec = reinterpret_cast<const float *>(win.rec);
+    const int start = sub_start[sq], cnt = sub_count[sq];
+    int org[3] = {0, 0, 0};
+    const int bw = sub_bin[sq];
+    const int a0s = bw >> 24;                   // first staged row of the padded tile
+    bin_origin<3>(bw & 0xffffff, nb, tb, org);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the subproblem's points [P0, P1): weights, output rows, block starts
+    const int P0 = win.blocks[start], P1 = win.blocks[start + cnt];
+    for (int i = tid; i < (P1 - P0) * RS; i += NT) s_w[i] = rec[(int64_t)P0 * RS + i];
+    for (int i = tid; i < P1 - P0; i += NT) s_row[i] = win.perm[P0 + i];
+    if (tid <= cnt) s_blk[tid] = win.blocks[start + tid] - P0;
+    if (tid < cnt) s_lp[tid] = win.lpos[win.blocks[start + tid]];
+    // staging: thread t takes cell t of the tile's (second, third) plane
+    const bool qin = tid < pd2;
+    int prel = 0;
+    bool pin = false;
+    {
+        const int b = tid / pd, c = tid - (tid / pd) * pd;
+        const int l1 = org[1] - M + b, l2 = org[2] - M + c;
+        pin = qin && l1 >= 0 && l1 < ng && l2 >= 0 && l2 < ng;
+        prel = pin ? l1 * ng + l2 : 0;
+    }
+    const int li = lane & 15, kq = lane >> 4;
+    const int al = li >> 2, e = li & 3;         // B / accumulator column: first-dimension tap, value
+    for (int r0 = 0; r0 < nrhs; r0 += VPS) {
+        __syncthreads();   // weights staged / previous pass consumed
+        constexpr int SA = 4;
+        for (int ab = 0; ab < rows; ab += SA) {
+            f4 v4[SA];
+#pragma unroll
+            for (int aa = 0; aa < SA; ++aa) {
+                const int la = org[0] - M + a0s + ab + aa;
+                const bool in = ab + aa < rows && pin && la >= 0 && la < ng;
+                const int64_t g = (int64_t)(in ? la : 0) * ng * ng + prel;
+                f4 v = f4{0.0f, 0.0f, 0.0f, 0.0f};
+                if (DER) {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        if (in && r0 + q < nrhs) {
+                            const float2 c = grid[((int64_t)wi * nrhs + r0 + q) * cells + g];
+                            v[2 * q] = c.x;
+                            v[2 * q + 1] = c.y;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (in && r0 + q < nrhs) v[q] = grid[((int64_t)wi * nrhs + r0 + q) * cells + g].x;
+                }
+                v4[aa] = v;
+            }
+#pragma unroll
+            for (int aa = 0; aa < SA; ++aa)
+                if (ab + aa < rows && qin) *reinterpret_cast<f4 *>(tile + (ab + aa) * ps + 4 * tid) = v4[aa];
+        }
+        __syncthreads();
+        for (int k = wave; k < cnt; k += NWV) {
+            const int j0 = s_blk[k], np = s_blk[k + 1] - j0;
+            const int lp = s_lp[k];
+            const int lin = (lp & 0xfffff) - a0s * pd2;   // first tap inside the staged rows
+            const int frow = fdiv_small(lin, pd2, 1.0f / (float)pd2), rem = lin - frow * pd2;
+            // A row li: point j0 + li (rows past the block: weight 0)
+            const float *rp = s_w + (j0 + min(li, np - 1)) * RS;
+            float w1[TW], w2k[TW / 4];
+#pragma unroll
+            for (int t = 0; t < TW; ++t) w1[t] = rp[TW + t];
+#pragma unroll
+            for (int t = 0; t < TW / 4; ++t) w2k[t] = li < np ? rp[2 * TW + 4 * t + kq] : 0.0f;
+            const float *tb0 = tile + (frow + al) * ps + (rem + kq) * 4 + e;
+            f4 acc[NBK];
+#pragma unroll
+            for (int c = 0; c < NBK; ++c) acc[c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            // one second-dimension tap b per round: its TW / 4 steps times NBK
+            // column blocks; the next round's B values are read while this
+            // round's products run
+            constexpr int SPR = TW / 4;
+            float bv[2][SPR][NBK];
+            auto load_row = [&](float (&dst)[SPR][NBK], int b) {
+#pragma unroll
+                for (int t = 0; t < SPR; ++t)
+#pragma unroll
+                    for (int c = 0; c < NBK; ++c) dst[t][c] = tb0[(b * pd + 4 * t) * 4 + c * 4 * ps];
+            };
+            load_row(bv[0], 0);
+#pragma unroll
+            for (int b = 0; b < TW; ++b) {
+                if (b + 1 < TW) load_row(bv[(b + 1) & 1], b + 1);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int t = 0; t < SPR; ++t) {
+                    const float av = w1[b] * w2k[t];
+#pragma unroll
+                    for (int c = 0; c < NBK; ++c)
+                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[b & 1][t][c], acc[c], 0, 0, 0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // first dimension: lane (al, e, kq) holds X[4 kq + v][(4 c + al, e)]
+            const int L = (lp >> 20) & 0x7f;
+            float h[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float *rw = s_w + (j0 + min(4 * kq + v, np - 1)) * RS;
+                float sum = 0.0f;
+#pragma unroll
+                for (int c = 0; c < NBK; ++c) sum += rw[(L + 4 * c + al) % TW] * acc[c][v];
+                sum += __shfl_xor(sum, 4);
+                sum += __shfl_xor(sum, 8);
+                h[v] = sum;
+            }
+            if (al == 0) {
+                const int vec = r0 + (DER ? e / 2 : e);
+                const bool isd = DER && (e & 1);
+                if (vec < nrhs) {
+                    float *out = (isd ? dout : hbuf) + (int64_t)win.s_global * n * nrhs;
+                    const float sc = isd ? dscale : 1.0f;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (4 * kq + v < np) out[(int64_t)s_row[j0 + 4 * kq + v] * nrhs + vec] = sc * h[v];
+                }
+            }
+        }
+    }
+}
+
 // d <= 2 with at least 16 / sizeof(T) vectors: the tiles of up to vb vectors
 // are staged at once, cell-major (a cell's vb values, for DER then its vb
 // derivative values, then 16 bytes of padding that put neighbouring cells on
@@ -1709,6 +1877,28 @@ hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool
     // rows <= pd first-axis rows of it
     const int rows = D == 3 ? G.interp_rows : g.pd;
     if (D == 3 && (g.pd > 8 + 2 * M || rows < 2 * M || rows > g.pd)) return hipErrorInvalidValue;
+    if constexpr (std::is_same<T, float>::value && D == 3 && (M == 4 || M == 6)) {
+        if (G.interp_mfma) {
+            const int pd2 = g.pd * g.pd;
+            const int ps = 4 * pd2 + ((8 - 4 * pd2) % 32 + 32) % 32;
+            const size_t shm = (size_t)rows * ps * sizeof(float);
+            auto go = [&](auto der_tag, auto nw_tag) -> hipError_t {
+                constexpr bool DR = decltype(der_tag)::value;
+                constexpr int NW = decltype(nw_tag)::value;
+                hipError_t e = allow_lds(k_interp_mfma<M, DR, NW>, shm);
+                if (e != hipSuccess) return e;
+                k_interp_mfma<M, DR, NW><<<(unsigned)G.nisub, 64 * NW, shm, s>>>(
+                    G.desc, G.isub_win, G.isub_bin, G.isub_start, G.isub_count, g.tb, g.nb, g.ng, rows,
+                    (const float2 *)grid, g.cells, nrhs, n, (float *)hbuf, DR ? (float *)dout : nullptr,
+                    (float)dscale);
+                return hipGetLastError();
+            };
+            using w8 = std::integral_constant<int, 8>;
+            using w16 = std::integral_constant<int, 16>;
+            if (G.interp_mfma_waves == 8) return with_der ? go(std::true_type(), w8()) : go(std::false_type(), w8());
+            return with_der ? go(std::true_type(), w16()) : go(std::false_type(), w16());
+        }
+    }
     const size_t cells_staged = D == 3 ? (size_t)rows * g.pd * g.pd : (size_t)g.pc;
     size_t shm = cells_staged * sizeof(T) * (with_der ? 2 : 1);
     auto go = [&](auto der_tag, auto pt_tag) -> hipError_t {

@@ -23,6 +23,8 @@ inline double kb_beta() { return kPi * (2.0 - 1.0 / kSigma); }
 
 // Points handled by one interpolation work-group at most (one per thread).
 constexpr int kInterpSubPoints = 256;
+// 3-D matrix-core interpolation: blocks (at most 16 points of one cell) per subproblem
+constexpr int kInterpSubBlocks = 16;
 // Points per wave in run-based interpolation.
 constexpr int kRunSubPoints = 512;
 
@@ -56,6 +58,8 @@ struct Window {
     int32_t *perm = nullptr;    // sorted position -> original point index
     int32_t *slots = nullptr;   // 3-D: interpolation slots in sorted order, each one point or
                                 // two consecutive points of one cell (first point | pair << 31)
+    int32_t *blocks = nullptr;  // 3-D: first point of each block (at most 16 consecutive points
+                                // of one cell) in sorted order, then n
     int32_t *bin_sub_ptr = nullptr;  // tile -> spreading subproblems of its group (nbins + 1)
     void *Dk = nullptr;     // symmetrised diagonal for K_s (dcells, plan precision)
     void *Dder = nullptr;   // same for K_s^der
@@ -64,6 +68,8 @@ struct Window {
     std::vector<int> h_row_cnt;     // 3-D: points per (tile, first-axis cell row), nbins x tb
     std::vector<int> h_slot_start;  // 3-D: tile -> first slot (nbins + 1)
     std::vector<int> h_row_slots;   // 3-D: slots per (tile, first-axis cell row), nbins x tb
+    std::vector<int> h_block_start; // 3-D: tile -> first block (nbins + 1)
+    std::vector<int> h_row_blocks;  // 3-D: blocks per (tile, first-axis cell row), nbins x tb
 };
 
 // Per-window data a kernel needs, in device memory (one array per group).
@@ -76,6 +82,7 @@ struct WinDesc {
     const void *Dk;
     const void *Dder;
     const int32_t *slots;
+    const int32_t *blocks;
     int32_t s_global;   // window index in the plan
     int32_t pad_;
 };
@@ -116,6 +123,8 @@ struct Group {
     int interp_pt = 1;           // points per thread of the tile interpolation (1, 2)
     bool interp_adj = false;     // 3-D, 2 points per thread: adjacent sorted points share tap reads
     bool interp_slot = false;    // 3-D: one slot per thread (two points of one cell share every tap read)
+    bool interp_mfma = false;    // 3-D FP32: blocks of one cell on matrix cores (lists count blocks)
+    int interp_mfma_waves = 16;  // waves per work-group of the matrix-core interpolation (8 or 16)
     int interp_vb_lds = 80 << 10;   // d <= 2: LDS bytes for several vectors per staging (0: one vector)
     int interp_rows = 0;         // 3-D: first-axis rows of the padded tile staged per subproblem
     int isub_cap = 0;            // capacity of the interpolation list arrays
