@@ -14,10 +14,11 @@ sigma_eps = 0.1, N = 64, m = 6, 16 vectors, FP32, autotuned.  Other
 workloads: --workload C1..C4.
 
 The JSON line also carries the roofline of the dominant kernel (timed with HIP
-events on the plan's stream inside the timed region) against the FP32 vector
-peak, its LDS rate against the LDS peak and its measured HBM rate, the
-oracle's CPU throughput on a bounded sample, and the parity of the timed
-result.
+events on the plan's stream inside the timed region) against the FP32 dense
+matrix-core peak when its 3-D launches run on matrix cores (else the FP32
+vector peak, with its LDS rate), its measured HBM rate, the kernel forms the
+plan takes, the oracle's CPU throughput on a bounded sample, and the parity
+of the timed result.
 """
 from __future__ import annotations
 
@@ -300,6 +301,15 @@ def main():
     kern = {k: {"total_ms": v[0], "launches": v[1], "avg_us": (1e3 * v[0] / v[1]) if v[1] else 0.0}
             for k, v in prof_all.items() if v[1]}
     bound, work, unit = per_apply[dom]
+    # kernel forms of this apply; spreading and interpolation of the 3-D
+    # groups on matrix cores make the bound the FP32 dense MFMA peak (the
+    # d <= 2 groups, a small share of the taps, stay on the VALU)
+    forms = plan.describe(nrhs).strip().splitlines()
+    d3 = [ln for ln in forms if ln.startswith("group d=3 ")]
+    on_mfma = bool(d3) and dom in ("spread", "interp") and all(f"{dom}=mfma" in ln for ln in d3)
+    if on_mfma and prec == "f32":
+        bound = "mfma"
+    taps3 = sum(n * nrhs * (2 * w.m) ** d for d, _ in geoms if d == 3)
     dom_ms, dom_launches = prof[dom]
     work = work * args.steps / dom_launches
     avg_s = dom_ms / 1e3 / dom_launches
@@ -340,7 +350,11 @@ def main():
                 "frac": achieved / peak, "traffic": traffic,
                 "work_per_launch": work, "avg_launch_us": avg_s * 1e6,
                 "timing": f"HIP events around the {dom_launches} {dom} launches of the timed region only"}
-    if dom == "interp":
+    if bound == "mfma":
+        roofline["note"] = (f"3-D groups on v_mfma_f32_16x16x4_f32 ({100.0 * taps3 / taps:.1f} % of the taps), "
+                            "d <= 2 groups on the VALU; peak = FP32 dense matrix-core rate; work = algorithmic "
+                            "FLOPs (2 per tap, vector and output), padding of partial blocks not counted")
+    if dom == "interp" and bound != "mfma":
         # the tile kernels read one LDS value per tap, vector and grid (K and
         # dK grids with derivative outputs)
         lds_bytes = taps * eb * nout * args.steps / dom_launches
@@ -450,6 +464,7 @@ def main():
         "plan_seconds": t_plan,
         "autotune": tune,
         "workspace_bytes": plan.workspace_bytes(),
+        "kernel_forms": forms,
     }
     print(json.dumps(res))
 

@@ -341,6 +341,15 @@ nfftgp_status nfftgp_pcg(nfftgp_plan plan, const void *B_dev, int32_t nrhs, void
 /* Device bytes the plan holds. */
 nfftgp_status nfftgp_get_workspace_bytes(nfftgp_plan plan, size_t *bytes);
 
+/* The kernel forms an apply of nrhs vectors (1..max_nrhs) takes (a reporting
+ * aid for the spreading and interpolation steps of Sec. 3.1 / Appendix A):
+ * one line per window group, "group d=<d> N=<N> windows=<k>: spread=<form>
+ * ...; interp=<variant> ...", where the spreading form is "mfma" (matrix
+ * cores), "four-point" or "run" and the interpolation variant "mfma", "tile",
+ * "tile2", "tilepair", "tileslot" or "run".  Written NUL-terminated into
+ * `out` (host), truncated to len bytes.  Host work only. */
+nfftgp_status nfftgp_describe(nfftgp_plan plan, int32_t nrhs, char *out, int64_t len);
+
 /* Free the plan and everything it owns (NULL is allowed).  Synchronises. */
 void nfftgp_plan_destroy(nfftgp_plan plan);
 

@@ -27,7 +27,8 @@ SYMBOLS = ["nfftgp_plan_create", "nfftgp_plan_create_scaled", "nfftgp_set_hyper"
            "nfftgp_slq_logquad", "nfftgp_get_window_info", "nfftgp_get_workspace_bytes",
            "nfftgp_plan_destroy", "nfftgp_last_error", "nfftgp_profile", "nfftgp_profile_read",
            "nfftgp_autotune", "nfftgp_col_dots_noalloc", "nfftgp_precond_attach", "nfftgp_precond_info",
-           "nfftgp_precond_landmarks", "nfftgp_precond_apply", "nfftgp_precond_dquad", "nfftgp_pcg"]
+           "nfftgp_precond_landmarks", "nfftgp_precond_apply", "nfftgp_precond_dquad", "nfftgp_pcg",
+           "nfftgp_describe"]
 PROF_NAMES = ["fill", "spread", "fold", "fft_fwd", "diag", "fft_inv", "interp", "assemble", "coef", "cg",
               "gather", "precond"]
 PC_MINV, PC_FINVT, PC_F = 0, 1, 2
@@ -75,6 +76,8 @@ def load():
     lib.nfftgp_get_window_info.restype = ctypes.c_int
     lib.nfftgp_get_workspace_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
     lib.nfftgp_get_workspace_bytes.restype = ctypes.c_int
+    lib.nfftgp_describe.argtypes = [P, i32, ctypes.c_char_p, ctypes.c_int64]
+    lib.nfftgp_describe.restype = ctypes.c_int
     lib.nfftgp_plan_destroy.argtypes = [P]
     lib.nfftgp_plan_destroy.restype = None
     lib.nfftgp_profile.argtypes = [P, i32]

@@ -1281,6 +1281,19 @@ nfftgp_status nfftgp_get_workspace_bytes(nfftgp_plan plan, size_t *bytes)
     return NFFTGP_OK;
 }
 
+nfftgp_status nfftgp_describe(nfftgp_plan plan, int32_t nrhs, char *out, int64_t len)
+{
+    set_error("");
+    if (!plan || !out) return fail(NFFTGP_E_ARG, "NULL argument");
+    if (len < 1) return fail(NFFTGP_E_ARG, "len must be positive");
+    if (nrhs < 1 || nrhs > plan->max_nrhs) return fail(NFFTGP_E_ARG, "nrhs out of range 1..max_nrhs");
+    std::string rep;
+    for (const Group &G : plan->groups) rep += describe_group(plan->prec, G, plan->m, nrhs);
+    std::strncpy(out, rep.c_str(), (size_t)len - 1);
+    out[len - 1] = '\0';
+    return NFFTGP_OK;
+}
+
 nfftgp_status nfftgp_profile(nfftgp_plan plan, int32_t categories)
 {
     set_error("");

@@ -23,6 +23,7 @@
 #include "nfftgp_coef_sep.h"
 
 #include <cstdint>
+#include <string>
 #include <cstdlib>
 #include <type_traits>
 
@@ -1764,6 +1765,26 @@ hipError_t spread_launch(const Group &G, const void *V, int64_t ldv, int nrhs, v
 
 constexpr bool kSpreadMfmaRule = true;
 
+// Vectors per work-group of the VALU spreading forms.  d = 3: four waves
+// share a tile (2m taps split four ways).  R vectors per work-group share the
+// points' weights; R tiles must fit in 64 KiB, and R = 4 is taken only when
+// it leaves no partial group of vectors (measured: 32 vectors 4 > 2 > 1,
+// 17 vectors 2 > 1 > 4, 16 vectors of m = 6: 2 > 1)
+int spread_vectors_per_group(const Group &G, int nrhs, size_t tsize)
+{
+    const size_t tile = (size_t)G.g.pc * tsize;
+    int R = 1;
+    if (G.spread_R > 0) {
+        R = G.spread_R;
+        if (R * tile > 64 * 1024 || R > nrhs) R = (2 * tile <= 64 * 1024 && nrhs >= 2) ? 2 : 1;
+    } else if (nrhs % 4 == 0 && 4 * tile <= 64 * 1024) {
+        R = 4;
+    } else if (nrhs >= 2 && 2 * tile <= 64 * 1024) {
+        R = 2;
+    }
+    return R;
+}
+
 // Matrix-core spreading applies to FP32, d = 3, 2m = 8 or 12 and tiles whose
 // four vectors fit the LDS next to the staged points.
 constexpr size_t kSpreadMfmaLds = 148 * 1024;
@@ -1799,20 +1820,7 @@ hipError_t spread_dm(const Group &G, const void *V, int64_t ldv, int nrhs, void 
         if (spread_mfma_ok<T, D, M>(G) && (G.spread_form == 3 || (G.spread_form == 0 && nrhs >= 4 && kSpreadMfmaRule)))
             return spread_mfma_launch<M>(G, V, ldv, nrhs, tilebuf, s);
     }
-    // d = 3: four waves share a tile (2m taps split four ways).  R vectors per
-    // work-group share the points' weights; R tiles must fit in 64 KiB, and
-    // R = 4 is taken only when it leaves no partial group of vectors (measured:
-    // 32 vectors 4 > 2 > 1, 17 vectors 2 > 1 > 4, 16 vectors of m = 6: 2 > 1)
-    const size_t tile = (size_t)G.g.pc * sizeof(T);
-    int R = 1;
-    if (G.spread_R > 0) {
-        R = G.spread_R;
-        if (R * tile > 64 * 1024 || R > nrhs) R = (2 * tile <= 64 * 1024 && nrhs >= 2) ? 2 : 1;
-    } else if (nrhs % 4 == 0 && 4 * tile <= 64 * 1024) {
-        R = 4;
-    } else if (nrhs >= 2 && 2 * tile <= 64 * 1024) {
-        R = 2;
-    }
+    const int R = spread_vectors_per_group(G, nrhs, sizeof(T));
     // waves sharing a tile: 4 for d = 3 unless the group asks for 2
     auto go = [&](auto w_tag) -> hipError_t {
         constexpr int W = decltype(w_tag)::value;
@@ -2041,6 +2049,37 @@ hipError_t launch_interp(int prec, const Group &G, int m, int64_t n, int nrhs, c
     return prec == NFFTGP_F32
                ? interp_t<float>(G, m, n, nrhs, grid, with_der, hbuf, dout, dscale, s)
                : interp_t<double>(G, m, n, nrhs, grid, with_der, hbuf, dout, dscale, s);
+}
+
+std::string describe_group(int prec, const Group &G, int m, int nrhs)
+{
+    std::string sp;
+    const bool mfma_ok = prec == NFFTGP_F32 && G.g.d == 3 && (m == 4 || m == 6) &&
+                         (size_t)spread_mfma_pad(G.g.pd).sr * sizeof(float) * 4 <= kSpreadMfmaLds;
+    if (mfma_ok && (G.spread_form == 3 || (G.spread_form == 0 && nrhs >= 4 && kSpreadMfmaRule))) {
+        sp = "mfma (4 vectors per work-group)";
+    } else {
+        const int R = spread_vectors_per_group(G, nrhs, prec == NFFTGP_F32 ? 4 : 8);
+        const bool quad = G.spread_form == 1 || (G.spread_form == 0 && R == 1);
+        sp = std::string(quad ? "four-point" : "run") + " (" + std::to_string(R) + " vectors per work-group" +
+             (G.g.d == 3 ? (G.spread_W == 2 ? ", 2 waves per tile)" : ", 4 waves per tile)") : ")");
+    }
+    std::string ip;
+    if (G.use_run_interp)
+        ip = "run";
+    else if (G.interp_mfma)
+        ip = "mfma (" + std::to_string(G.interp_mfma_waves) + " waves per work-group)";
+    else if (G.interp_slot)
+        ip = "tileslot";
+    else if (G.interp_adj)
+        ip = "tilepair";
+    else
+        ip = G.interp_pt == 2 ? "tile2" : "tile";
+    if (!G.use_run_interp && G.g.d == 3)
+        ip += ", " + std::to_string(G.interp_rows) + " of " + std::to_string(G.g.pd) + " rows staged";
+    return "group d=" + std::to_string(G.g.d) + " N=" + std::to_string(G.g.N) + " windows=" +
+           std::to_string(G.nwin) + ": spread=" + sp + "; subproblem " + std::to_string(G.sub_sp) +
+           " points; interp=" + ip + "\n";
 }
 
 hipError_t launch_assemble(int prec, int64_t n, int nrhs, int P, const void *V, int64_t ldv,

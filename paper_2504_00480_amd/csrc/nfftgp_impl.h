@@ -322,6 +322,8 @@ hipError_t launch_interp(int prec, const Group &G, int m, int64_t n, int nrhs, c
 hipError_t launch_assemble(int prec, int64_t n, int nrhs, int P, const void *V, int64_t ldv,
                            const void *hbuf, double sf, double se, void *KV, void *dsf, void *dse,
                            hipStream_t s);
+// One line naming the kernel forms an apply of nrhs vectors takes for group G.
+std::string describe_group(int prec, const Group &G, int m, int nrhs);
 
 // ---------------------------------------------------------------- CG / dots
 constexpr int kDotBlocks = 120;

@@ -166,6 +166,12 @@ class AdditiveKernelPlan:
         _lib.check(_lib.load().nfftgp_get_workspace_bytes(self._h, ctypes.byref(b)), "workspace")
         return int(b.value)
 
+    def describe(self, nrhs: int = 1) -> str:
+        """The kernel forms an apply of nrhs vectors takes, one line per window group."""
+        buf = ctypes.create_string_buffer(4096)
+        _lib.check(_lib.load().nfftgp_describe(self._h, int(nrhs), buf, len(buf)), "nfftgp_describe")
+        return buf.value.decode()
+
     # ------------------------------------------------------------------
     def _check_vec(self, V: torch.Tensor):
         if V.dim() == 1:

@@ -69,6 +69,7 @@ def test_null_arguments(lib):
     P = ctypes.c_void_p
     assert lib.nfftgp_set_hyper(P(0), 1.0, P(0), 0.1) == -1
     assert lib.nfftgp_apply(P(0), P(0), 1, 1, P(0), P(0), P(0), P(0)) == -1
+    assert lib.nfftgp_describe(P(0), 1, None, 0) == -1
     lib.nfftgp_plan_destroy(P(0))
 
 

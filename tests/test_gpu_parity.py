@@ -73,15 +73,16 @@ SMALL = [
 ]
 
 
-@pytest.mark.parametrize("interp", ["tile", "tile2", "tilepair", "tileslot", "tilefull", "run"])
+@pytest.mark.parametrize("interp", ["tile", "tile2", "tilepair", "tileslot", "tilefull", "run", "mfma"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("case", SMALL, ids=[f"case{c[0]}" for c in SMALL])
 def test_small_parity(orc, case, prec, interp, monkeypatch):
     """Every interpolation variant (per-point tile reads with one or two points
     per thread, two adjacent sorted points per thread sharing tap reads in
     3-D, one slot of one or two points of one cell per thread in 3-D;
-    register-held runs of equal cells), forced through NFFTGP_INTERP at plan
-    creation."""
+    register-held runs of equal cells; blocks of one cell on matrix cores for
+    3-D FP32 windows with m = 4 or 6, the others falling back to the tile
+    form), forced through NFFTGP_INTERP at plan creation."""
     monkeypatch.setenv("NFFTGP_INTERP", interp)
     seed, n, dims, kt, ell, N, m, nrhs, dist = case
     w = workloads.small(seed, n, dims, kt, ell, N, m, nrhs, dist=dist, scale_mode=1 if dist == "box" else 0)
@@ -155,8 +156,8 @@ def test_interp_variants_agree(prec, monkeypatch):
     X = torch.tensor(w.X, dtype=dt, device="cuda:0")
     V = torch.tensor(w.V, dtype=dt, device="cuda:0")
     outs = []
-    for mode in ("tile", "tile2", "tilepair", "tileslot", "tilefull", "run", "tile+w2", "tile+quad",
-                 "tile+quad+w2"):
+    for mode in ("tile", "tile2", "tilepair", "tileslot", "tilefull", "run", "mfma", "tile+w2", "tile+quad",
+                 "tile+quad+w2", "tile+mfma", "mfma+mfma"):
         monkeypatch.setenv("NFFTGP_INTERP", mode.split("+")[0])
         monkeypatch.delenv("NFFTGP_SPREAD_W", raising=False)
         monkeypatch.delenv("NFFTGP_SPREAD_FORM", raising=False)
@@ -164,6 +165,8 @@ def test_interp_variants_agree(prec, monkeypatch):
             monkeypatch.setenv("NFFTGP_SPREAD_W", "2")   # two waves per spreading tile
         if "+quad" in mode:
             monkeypatch.setenv("NFFTGP_SPREAD_FORM", "quad")   # four-point spreading with 2 vectors
+        if "+mfma" in mode:
+            monkeypatch.setenv("NFFTGP_SPREAD_FORM", "mfma")   # matrix-core spreading (FP32, 3-D)
         plan = AdditiveKernelPlan(X, w.windows, w.ktype, w.N, w.m, max_nrhs=2)
         plan.set_hyper(1.3, w.ell, 0.2)
         outs.append({k: (v.double().cpu().numpy() if not isinstance(v, list) else
@@ -357,3 +360,30 @@ def test_set_hyper_between_applies_without_waits():
         for k in o:
             assert torch.equal(o[k], ref[name][k]), (name, k)
     assert not torch.equal(ref["a"]["KV"], ref["b"]["KV"])
+
+
+@pytest.mark.parametrize("m", [4, 6])
+def test_matrix_core_forms_parity(orc, m):
+    """The matrix-core spreading and interpolation (3-D FP32, the rule for four
+    or more vectors) against the oracle on every row, with a ragged last group
+    of vectors (6 = 4 + 2), clustered points (long runs of equal cells, blocks
+    of 16 and partial blocks) and a 2-D window beside them on the VALU forms;
+    then the forms the plan reports."""
+    w = workloads.small(17 + m, 6000, [3, 3, 2], [0, 1, 0], [0.5, 0.7, 0.4], [32, 16, 32], m, 6,
+                        dist="cluster")
+    plan, got, ref, r, pb = _run(orc, w, "f32")
+    forms = plan.describe(6).splitlines()
+    print("  " + "\n  ".join(forms), flush=True)
+    d3 = [ln for ln in forms if ln.startswith("group d=3 ")]
+    assert d3 and all("spread=mfma" in ln and "interp=mfma" in ln for ln in d3)
+    assert all("spread=mfma" not in ln for ln in forms if ln.startswith("group d=2 "))
+    tol = _tol("f32", m)
+    e_k = _rel(got["KV"][r], ref["KV"])
+    e_d = max(_rel(got["dKV_dell"][s][r], ref["dKV_dell"][s]) for s in range(pb.P))
+    e_f = _rel(got["dKV_dsf"][r], ref["dKV_dsf"])
+    print(f"  m={m}: rel err KV {e_k:.2e}  dKV/dell {e_d:.2e}  dKV/dsf {e_f:.2e}", flush=True)
+    assert e_k <= tol and e_d <= tol and e_f <= tol
+    # one vector: the VALU spreading form, matrix-core interpolation padded
+    assert "spread=mfma" not in plan.describe(1)
+    o1 = plan.apply(torch.tensor(w.V[:, :1], dtype=torch.float32, device="cuda:0"), derivs=False)
+    assert _rel(o1["KV"].double().cpu().numpy(), ref["KV"][:, :1]) <= tol
