@@ -553,41 +553,47 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
 #pragma unroll
     for (int k = 0; k < BPW; ++k) acc[k] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     const int nr = min(R, nrhs - r0);
+    // the global data of chunk c + 2 is loaded into registers while chunk c is
+    // processed (two register sets alternate)
     constexpr int NREC = (CH * RS + NT - 1) / NT, NV = (CH * R + NT - 1) / NT;
-    float g_rec[NREC], g_v[NV];
-    int g_lp = 0;
-    auto fetch = [&](int cb) {
+    struct Stage {
+        float rec[NREC], v[NV];
+        int lp;
+    };
+    auto fetch = [&](Stage &g, int cb) {
         const int nc = min(CH, end - cb);
 #pragma unroll
         for (int k = 0; k < NREC; ++k) {
             const int i = tid + k * NT;
-            g_rec[k] = i < nc * RS ? rec[(int64_t)cb * RS + i] : 0.0f;
+            g.rec[k] = i < nc * RS ? rec[(int64_t)cb * RS + i] : 0.0f;
         }
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             const int i = tid + k * NT;
             const int u = i / R, r = i % R;
-            g_v[k] = (i < nc * R && r < nr) ? V[(int64_t)perm[cb + u] * ldv + r0 + r] : 0.0f;
+            g.v[k] = (i < nc * R && r < nr) ? V[(int64_t)perm[cb + u] * ldv + r0 + r] : 0.0f;
         }
-        g_lp = tid < nc ? lpos[cb + tid] : 0;
+        g.lp = tid < nc ? lpos[cb + tid] : 0;
     };
-    if (cnt > 0) fetch(start);
-    for (int cb = start; cb < end; cb += CH) {
+    Stage ga, gb;
+    if (cnt > 0) fetch(ga, start);
+    if (cnt > CH) fetch(gb, start + CH);
+    auto chunk = [&](int cb, Stage &g) {
         const int nc = min(CH, end - cb);
         __syncthreads();   // tiles cleared / previous chunk consumed
 #pragma unroll
         for (int k = 0; k < NREC; ++k) {
             const int i = tid + k * NT;
-            if (i < CH * RS) s_rec[i] = g_rec[k];
+            if (i < CH * RS) s_rec[i] = g.rec[k];
         }
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             const int i = tid + k * NT;
-            if (i < CH * R) s_v[i] = g_v[k];
+            if (i < CH * R) s_v[i] = g.v[k];
         }
-        if (tid < CH) s_lp[tid] = g_lp;
+        if (tid < CH) s_lp[tid] = g.lp;
         __syncthreads();
-        if (cb + CH < end) fetch(cb + CH);
+        if (cb + 2 * CH < end) fetch(g, cb + 2 * CH);
         const int my_lp = lane < nc ? s_lp[lane] : 0;
         const bool isend = lane < nc && (my_lp < 0 || cb + lane == end - 1);
         const unsigned long long ends = __ballot(isend);
@@ -669,6 +675,10 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             }
             u0 = u1 + 1;
         }
+    };
+    for (int cb = start; cb < end; cb += 2 * CH) {
+        chunk(cb, ga);
+        if (cb + CH < end) chunk(cb + CH, gb);
     }
     __syncthreads();
     for (int r = 0; r < nr; ++r) {
@@ -1187,7 +1197,7 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     const int al = li >> 2, e = li & 3;         // B / accumulator column: first-dimension tap, value
     for (int r0 = 0; r0 < nrhs; r0 += VPS) {
         __syncthreads();   // weights staged / previous pass consumed
-        constexpr int SA = 4;
+        constexpr int SA = 8;
         for (int ab = 0; ab < rows; ab += SA) {
             f4 v4[SA];
 #pragma unroll
