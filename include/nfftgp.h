@@ -65,6 +65,9 @@ typedef enum {
  *           kernel of Sec. 4 (generalization to other orders); same pipeline,
  *           only the sampled kernel and its ell-derivative differ. */
 typedef enum { NFFTGP_GAUSS = 0, NFFTGP_MATERN12 = 1, NFFTGP_MATERN32 = 2 } nfftgp_kernel;
+/* Precision values: entry points take them as int32_t (any other value is
+ * rejected with NFFTGP_E_ARG), so a caller's out-of-range value never becomes
+ * an invalid enumeration value inside the library. */
 typedef enum { NFFTGP_F32 = 0, NFFTGP_F64 = 1 } nfftgp_prec;
 
 /* Scaling of each window into the box [-1/4, 1/4)^d required by Sec. 3.1.
@@ -89,7 +92,8 @@ typedef struct nfftgp_plan_s *nfftgp_plan;
 
 /* Create a plan for fixed points and windows (Sec. 2.1: the points stay fixed
  * while the hyper-parameters change).
- *   X_dev    device, n x p row-major, leading dimension ldx >= p, precision prec.
+ *   X_dev    device, n x p row-major, leading dimension ldx >= p, precision prec
+ *            (NFFTGP_F32 or NFFTGP_F64; E_ARG otherwise).
  *            Read during this call only (the plan keeps scaled, sorted copies).
  *   n        number of points, 0 <= n < 2^31.
  *   P        number of windows, 1..NFFTGP_MAX_WINDOWS.
@@ -110,7 +114,7 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out,
                                  const void *X_dev, int64_t n, int32_t p, int64_t ldx,
                                  int32_t P, const int32_t *win_ptr, const int32_t *win_idx,
                                  const int32_t *kernel, const int32_t *N, int32_t m,
-                                 nfftgp_prec prec, int32_t scale_mode, int32_t max_nrhs,
+                                 int32_t prec, int32_t scale_mode, int32_t max_nrhs,
                                  void *stream);
 
 /* As nfftgp_plan_create, with the scaling of every window into
@@ -126,7 +130,7 @@ nfftgp_status nfftgp_plan_create_scaled(nfftgp_plan *out,
                                         const void *X_dev, int64_t n, int32_t p, int64_t ldx,
                                         int32_t P, const int32_t *win_ptr, const int32_t *win_idx,
                                         const int32_t *kernel, const int32_t *N, int32_t m,
-                                        nfftgp_prec prec, const double *c0, const double *c,
+                                        int32_t prec, const double *c0, const double *c,
                                         int32_t max_nrhs, void *stream);
 
 /* Set the hyper-parameters theta = (sigma_f, ell, sigma_eps) (Sec. 1).
@@ -200,7 +204,7 @@ nfftgp_status nfftgp_col_dots(nfftgp_plan plan, const void *A_dev, int64_t lda,
  *   ncol         1..64 (E_ARG beyond: the array holds 64 columns).
  *   out_dev      device, ncol doubles: out[c] = sum_i A[i][c] B[i][c] in FP64.
  *   stream       hipStream_t to enqueue on (NULL = null stream). */
-nfftgp_status nfftgp_col_dots_noalloc(nfftgp_prec prec, const void *A_dev, int64_t lda,
+nfftgp_status nfftgp_col_dots_noalloc(int32_t prec, const void *A_dev, int64_t lda,
                                       const void *B_dev, int64_t ldb, int64_t n, int32_t ncol,
                                       double *out_dev, void *stream);
 

@@ -345,7 +345,7 @@ int interp_rows_rule(const WindowGeom &g, int m)
 nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, int32_t p,
                                int64_t ldx, int32_t P, const int32_t *win_ptr,
                                const int32_t *win_idx, const int32_t *kernel, const int32_t *N,
-                               int32_t m, nfftgp_prec prec, int32_t scale_mode,
+                               int32_t m, int32_t prec, int32_t scale_mode,
                                const double *given_c0, const double *given_c,
                                int32_t max_nrhs, void *stream)
 {
@@ -733,7 +733,7 @@ const char *nfftgp_last_error(void) { return g_err.c_str(); }
 nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n, int32_t p,
                                  int64_t ldx, int32_t P, const int32_t *win_ptr,
                                  const int32_t *win_idx, const int32_t *kernel, const int32_t *N,
-                                 int32_t m, nfftgp_prec prec, int32_t scale_mode,
+                                 int32_t m, int32_t prec, int32_t scale_mode,
                                  int32_t max_nrhs, void *stream)
 {
     set_error("");
@@ -746,7 +746,7 @@ nfftgp_status nfftgp_plan_create(nfftgp_plan *out, const void *X_dev, int64_t n,
 nfftgp_status nfftgp_plan_create_scaled(nfftgp_plan *out, const void *X_dev, int64_t n, int32_t p,
                                         int64_t ldx, int32_t P, const int32_t *win_ptr,
                                         const int32_t *win_idx, const int32_t *kernel,
-                                        const int32_t *N, int32_t m, nfftgp_prec prec,
+                                        const int32_t *N, int32_t m, int32_t prec,
                                         const double *c0, const double *c, int32_t max_nrhs,
                                         void *stream)
 {

@@ -44,7 +44,7 @@ nfftgp_status fail(nfftgp_status st, const std::string &m)
 
 }  // namespace
 
-extern "C" nfftgp_status nfftgp_col_dots_noalloc(nfftgp_prec prec, const void *A_dev, int64_t lda,
+extern "C" nfftgp_status nfftgp_col_dots_noalloc(int32_t prec, const void *A_dev, int64_t lda,
                                                  const void *B_dev, int64_t ldb, int64_t n, int32_t ncol,
                                                  double *out_dev, void *stream)
 {
