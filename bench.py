@@ -449,7 +449,7 @@ def main():
         "vs_baseline": None, "dtype": prec, "data": "synthetic",
         "config": {"workload": w.name, "n": n, "p": int(w.X.shape[1]),
                    "windows": [len(x) for x in w.windows],
-                   "kernels": [("gauss", "matern12", "matern32")[k] for k in w.ktype], "N": w.N, "m": w.m,
+                   "kernels": [("gauss", "matern12", "matern32", "mq", "imq", "sinc")[k] for k in w.ktype], "N": w.N, "m": w.m,
                    "nrhs": nrhs, "ell": w.ell, "sigma_f": w.sigma_f, "sigma_eps": w.sigma_eps,
                    "step": "set_hyper + apply with " + ("all derivative outputs" if derivs else "K only")},
         "roofline": roofline,

@@ -63,8 +63,21 @@ typedef enum {
  * MATERN12  exp(-r / ell)
  * MATERN32  (1 + sqrt(3) r / ell) exp(-sqrt(3) r / ell), the order-3/2 Matern
  *           kernel of Sec. 4 (generalization to other orders); same pipeline,
- *           only the sampled kernel and its ell-derivative differ. */
-typedef enum { NFFTGP_GAUSS = 0, NFFTGP_MATERN12 = 1, NFFTGP_MATERN32 = 2 } nfftgp_kernel;
+ *           only the sampled kernel and its ell-derivative differ.
+ * The kernels the paper names beside them for the fast summation (its software
+ * section), with the shape parameter c in the place of ell (so the "ell"
+ * derivative outputs are d/dc) and no normalisation of kappa(0):
+ * MQ        multiquadric (r^2 + c^2)^(1/2)            (not positive definite)
+ * IMQ       inverse multiquadric (r^2 + c^2)^(-1/2)
+ * SINC      sin(c r) / r, value c at r = 0 */
+typedef enum {
+    NFFTGP_GAUSS = 0,
+    NFFTGP_MATERN12 = 1,
+    NFFTGP_MATERN32 = 2,
+    NFFTGP_MQ = 3,
+    NFFTGP_IMQ = 4,
+    NFFTGP_SINC = 5
+} nfftgp_kernel;
 /* Precision values: entry points take them as int32_t (any other value is
  * rejected with NFFTGP_E_ARG), so a caller's out-of-range value never becomes
  * an invalid enumeration value inside the library. */

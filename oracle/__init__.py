@@ -44,6 +44,9 @@ _lib = None
 GAUSS = 0
 MATERN12 = 1
 MATERN32 = 2
+MQ = 3
+IMQ = 4
+SINC = 5
 
 
 def build(force: bool = True) -> str:
@@ -100,8 +103,22 @@ def kernel(ktype: int, r, ell: float):
     Matern-3/2 (1 + a) exp(-a), a = sqrt(3) r / ell,  d/d ell = 3 r^2/ell^3 * exp(-a)
     (the order-3/2 member of the Matern family that Sec. 4 names as a further
     kernel for the same method; ell is its length-scale)
+
+    The kernels the paper names for the fast summation in its software
+    section, with the shape parameter c passed as ell (derivative d/dc):
+    multiquadric sqrt(r^2 + c^2), inverse multiquadric 1/sqrt(r^2 + c^2),
+    sinc sin(c r)/r (value c at r = 0, derivative cos(c r)).
     """
     r = np.asarray(r, dtype=np.float64)
+    if ktype in (MQ, IMQ):
+        q = np.sqrt(r * r + ell * ell)
+        if ktype == MQ:
+            return q, ell / q
+        return 1.0 / q, -ell / q ** 3
+    if ktype == SINC:
+        with np.errstate(divide="ignore", invalid="ignore"):
+            v = np.where(r == 0.0, ell, np.sin(ell * r) / np.where(r == 0.0, 1.0, r))
+        return v, np.cos(ell * r)
     if ktype == GAUSS:
         e = np.exp(-(r * r) / (2.0 * ell * ell))
         return e, (r * r) / ell ** 3 * e

@@ -41,7 +41,7 @@
 
 #define ORC_PI 3.14159265358979323846264338327950288
 
-enum { ORC_GAUSS = 0, ORC_MATERN12 = 1, ORC_MATERN32 = 2 };
+enum { ORC_GAUSS = 0, ORC_MATERN12 = 1, ORC_MATERN32 = 2, ORC_MQ = 3, ORC_IMQ = 4, ORC_SINC = 5 };
 
 /* Kernel value and its derivative with respect to ell, for distance r >= 0.
  * Gaussian:   exp(-r^2/(2 ell^2)),   derivative (r^2/ell^3) exp(...)
@@ -49,9 +49,26 @@ enum { ORC_GAUSS = 0, ORC_MATERN12 = 1, ORC_MATERN32 = 2 };
  * Matern-3/2: (1 + a) exp(-a) with a = sqrt(3) r / ell,
  *             derivative (3 r^2/ell^3) exp(-a)
  * (eq. kernel_definition with unit variance, eq. def_der_additive_kernels;
- * the order-3/2 Matern kernel of Sec. 4, generalization to other orders). */
+ * the order-3/2 Matern kernel of Sec. 4, generalization to other orders).
+ * The kernels the paper names for the fast summation in its software section,
+ * with the shape parameter c in the place of ell (derivative d/dc):
+ * multiquadric sqrt(r^2 + c^2),     derivative c / sqrt(r^2 + c^2)
+ * inverse MQ   1 / sqrt(r^2 + c^2), derivative -c / (r^2 + c^2)^(3/2)
+ * sinc         sin(c r) / r (c at r = 0), derivative cos(c r) */
 void orc_kernel(int type, double r, double ell, double *val, double *dval)
 {
+    if (type == ORC_MQ || type == ORC_IMQ) {
+        double q = sqrt(r * r + ell * ell);
+        *val = type == ORC_MQ ? q : 1.0 / q;
+        *dval = type == ORC_MQ ? ell / q : -ell / (q * q * q);
+        return;
+    }
+    if (type == ORC_SINC) {
+        double x = ell * r;
+        *val = r == 0.0 ? ell : sin(x) / r;
+        *dval = cos(x);
+        return;
+    }
     if (type == ORC_GAUSS) {
         double e = exp(-(r * r) / (2.0 * ell * ell));
         *val = e;

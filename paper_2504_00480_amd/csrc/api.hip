@@ -373,7 +373,7 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
             if (seen[f]) return fail(NFFTGP_E_ARG, "windows overlap");
             seen[f] = 1;
         }
-        if (kernel[s] != NFFTGP_GAUSS && kernel[s] != NFFTGP_MATERN12 && kernel[s] != NFFTGP_MATERN32)
+        if (kernel[s] < NFFTGP_GAUSS || kernel[s] > NFFTGP_SINC)
             return fail(NFFTGP_E_ARG, "unknown kernel type");
         int Nmax = d == 3 ? 64 : 128;
         if (!is_pow2(N[s]) || N[s] < 8 || N[s] > Nmax)

@@ -32,6 +32,27 @@ __device__ double bessel_i0(double z)
 
 // Kernel and ell-derivative at distance sqrt(r2) in scaled units (converted to
 // caller units by the window's scale c).
+// Multiquadric, inverse multiquadric and sinc kernels at distance r >= 0 with
+// shape parameter c, and their derivatives in c.
+__device__ __forceinline__ void kernel_shape(int type, double r, double c, double &v, double &dv)
+{
+    if (type == NFFTGP_SINC) {
+        // sin(c r) / r = c sin(x) / x, x = c r; d/dc = cos(c r)
+        const double x = c * r;
+        v = fabs(x) < 1e-4 ? c * (1.0 - x * x / 6.0) : sin(x) / r;
+        dv = cos(x);
+    } else {
+        const double q = sqrt(r * r + c * c);
+        if (type == NFFTGP_MQ) {
+            v = q;
+            dv = c / q;
+        } else {
+            v = 1.0 / q;
+            dv = -c / (q * q * q);
+        }
+    }
+}
+
 __device__ __forceinline__ void sample_pair(const CoefParams &prm, int w, double r2, double &v,
                                             double &dv)
 {
@@ -45,6 +66,8 @@ __device__ __forceinline__ void sample_pair(const CoefParams &prm, int w, double
         const double a = 1.7320508075688772 * r / ell, e = exp(-a);
         v = (1.0 + a) * e;
         dv = 3.0 * r * r / (ell * ell * ell) * e;
+    } else if (prm.kernel[w] >= NFFTGP_MQ) {
+        kernel_shape(prm.kernel[w], r, ell, v, dv);
     } else {
         v = exp(-r / ell);
         dv = r / (ell * ell) * v;

@@ -49,6 +49,14 @@ __device__ __forceinline__ void pc_pair(const double *__restrict__ xi, const dou
             const double r = sqrt(r2), a = 1.7320508075688772 * r / l, ea = exp(-a);
             e = (1.0 + a) * ea;
             de = 3.0 * r2 / (l * l * l) * ea;
+        } else if (kp.type[s] == NFFTGP_SINC) {
+            const double r = sqrt(r2), x = l * r;
+            e = fabs(x) < 1e-4 ? l * (1.0 - x * x / 6.0) : sin(x) / r;
+            de = cos(x);
+        } else if (kp.type[s] == NFFTGP_MQ || kp.type[s] == NFFTGP_IMQ) {
+            const double q = sqrt(r2 + l * l);
+            e = kp.type[s] == NFFTGP_MQ ? q : 1.0 / q;
+            de = kp.type[s] == NFFTGP_MQ ? l / q : -l / (q * q * q);
         } else {
             const double r = sqrt(r2);
             e = exp(-r / l);

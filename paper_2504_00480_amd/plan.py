@@ -17,10 +17,14 @@ from . import _lib
 GAUSS = 0
 MATERN12 = 1
 MATERN32 = 2
+MQ = 3          # multiquadric (r^2 + c^2)^(1/2), c passed as ell
+IMQ = 4         # inverse multiquadric (r^2 + c^2)^(-1/2)
+SINC = 5        # sin(c r) / r
 SCALE_AUTO = 0
 SCALE_NONE = 1
 _KERNELS = {"gauss": GAUSS, "gaussian": GAUSS, "matern12": MATERN12, "matern": MATERN12,
-            "matern32": MATERN32}
+            "matern32": MATERN32, "mq": MQ, "multiquadric": MQ, "imq": IMQ,
+            "inverse_multiquadric": IMQ, "sinc": SINC}
 
 
 def _ptr(t: torch.Tensor | None):
@@ -38,7 +42,9 @@ class AdditiveKernelPlan:
     ----------
     X : torch.Tensor on a ROCm device, float32 or float64, n x p (row-major).
     windows : list of feature-index lists (disjoint, 1..3 features each).
-    kernel : per-window kernel ("gauss" / "matern12" / "matern32" or 0 / 1 / 2), or one for all.
+    kernel : per-window kernel ("gauss" / "matern12" / "matern32" / "mq" / "imq" / "sinc" or
+             0 .. 5), or one for all; for mq, imq and sinc the shape parameter c takes the
+             place of ell.
     N : per-window bandwidth (power of two), or one for all.
     m : window cutoff (2, 4, 6 or 8).
     scale_mode : SCALE_AUTO (scale each window into [-1/4, 1/4)^d) or SCALE_NONE.

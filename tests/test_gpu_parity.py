@@ -70,6 +70,9 @@ SMALL = [
     (10, 1500, [2, 1, 2], [1, 0, 0], [0.4, 0.3, 0.7], [64, 64, 32], 6, 36, "normal"),
     # Matern-3/2 windows (the order-3/2 kernel of Sec. 4) beside a Gaussian one
     (11, 2500, [3, 2, 1, 2], [2, 2, 2, 0], [0.7, 0.5, 0.4, 0.6], [32, 64, 64, 32], 4, 4, "normal"),
+    # inverse multiquadric, sinc and multiquadric windows (shape parameter c in
+    # the place of ell; the kernels the paper names for the fast summation)
+    (12, 2500, [3, 2, 1], [4, 5, 3], [0.5, 3.0, 0.4], [16, 32, 64], 4, 2, "normal"),
 ]
 
 

@@ -118,7 +118,7 @@ def test_matern_coefficients_are_aliased_fourier_transform(orc, ell):
     assert err < 0.02 * b.max()
 
 
-@pytest.mark.parametrize("kt", [0, 1, 2])
+@pytest.mark.parametrize("kt", [0, 1, 2, 3, 4, 5])
 def test_derivative_coefficients_finite_difference(orc, kt):
     """Sec. 3.2 eq. exact_derivative: b^der = d b / d ell (central differences)."""
     N, ell, h = 16, 0.12, 1e-5
@@ -175,6 +175,57 @@ def test_matern32_against_library(orc):
     from sklearn.gaussian_process.kernels import Matern
     np.testing.assert_allclose(orc.dense_matrix(pb, 0), Matern(length_scale=0.11, nu=1.5)(x),
                                rtol=1e-13, atol=1e-15)
+
+
+def _shape_library(kt, r, c):
+    """Library values of the kernels the paper names for the fast summation in
+    its software section: inverse multiquadric = scikit-learn's
+    RationalQuadratic(alpha = 1/2, length_scale = c) / c, multiquadric its
+    reciprocal, sinc = c numpy.sinc(c r / pi)."""
+    from sklearn.gaussian_process.kernels import RationalQuadratic
+    r = np.atleast_1d(np.asarray(r, dtype=np.float64))
+    if kt == 5:
+        return c * np.sinc(c * r / np.pi)
+    imq = RationalQuadratic(length_scale=c, alpha=0.5)(np.zeros((1, 1)), r[:, None])[0] / c
+    return imq if kt == 4 else 1.0 / imq
+
+
+@pytest.mark.parametrize("kt", [3, 4, 5])
+def test_shape_kernels_against_library(orc, kt):
+    """Multiquadric, inverse multiquadric and sinc against library values; the
+    derivative in the shape parameter against central differences of the value;
+    the C oracle's Gram matrix of a 2-D window against the library's."""
+    r = np.linspace(0.0, 4.0, 401)
+    for c in (0.05, 0.7, 3.0):
+        v, dv = orc.kernel(kt, r, c)
+        np.testing.assert_allclose(v, _shape_library(kt, r, c), rtol=1e-13, atol=1e-15 * max(1.0, c))
+        h = 1e-6 * c
+        fd = (orc.kernel(kt, r, c + h)[0] - orc.kernel(kt, r, c - h)[0]) / (2 * h)
+        np.testing.assert_allclose(dv, fd, rtol=1e-6, atol=1e-8 * max(1.0, 1.0 / c ** 2))
+    x = np.random.default_rng(8).uniform(-0.25, 0.25, size=(30, 2))
+    pb = orc.Problem(x, [[0, 1]], [kt], [0.4], 1.0, 0.0, [16], orc.SCALE_NONE)
+    dist = np.sqrt(((x[:, None, :] - x[None, :, :]) ** 2).sum(-1))
+    want = _shape_library(kt, dist.ravel(), 0.4).reshape(dist.shape)
+    np.testing.assert_allclose(orc.dense_matrix(pb, 0), want, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("kt", [3, 4, 5])
+@pytest.mark.parametrize("d,N", [(1, 64), (2, 16), (3, 8)])
+def test_shape_kernels_interpolation_property(orc, kt, d, N):
+    """The trigonometric interpolant of eq. nfftkappa reproduces the library
+    values at the grid points; sum_k b_k = kappa(0) and sum_k b^der_k =
+    d kappa(0)/dc (1, -1/c^2, 1 for the multiquadric, inverse multiquadric and
+    sinc kernels)."""
+    c = 0.3
+    b, bd = orc.coefficients(kt, d, N, c)
+    k0 = _shape_library(kt, 0.0, c)[0]
+    dk0 = {3: 1.0, 4: -1.0 / c ** 2, 5: 1.0}[kt]
+    assert abs(b.sum() - k0) <= 1e-13 * max(1.0, abs(k0))
+    assert abs(bd.sum() - dk0) <= 1e-12 * max(1.0, abs(dk0))
+    g = np.random.default_rng(1).integers(-N // 2, N // 2, size=(20, d)) / N
+    r = np.sqrt((g * g).sum(1))
+    want = _shape_library(kt, r, c)
+    np.testing.assert_allclose(orc.kappa_rf(b, g), want, atol=1e-13 * np.abs(want).max())
 
 
 def test_matern12_derivative_is_matern32_difference(orc):

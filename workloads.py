@@ -18,6 +18,9 @@ import numpy as np
 GAUSS = 0
 MATERN12 = 1
 MATERN32 = 2
+MQ = 3
+IMQ = 4
+SINC = 5
 
 
 def rng(seed: int) -> np.random.Generator:
