@@ -223,8 +223,8 @@ def main():
         Xs = torch.empty_like(B)
         timing = {}
         for mode in ("graph", "eager"):
-            if mode == "eager":
-                os.environ["NFFTGP_CG_GRAPH"] = "0"
+            if mode == "graph":
+                os.environ["NFFTGP_CG_GRAPH"] = "1"
             plan.cg(B, 0.0, args.cg_iters, check_every=args.cg_iters, raise_on=(), out=Xs)   # warm / capture
             torch.cuda.synchronize()
             t0 = time.perf_counter()

@@ -192,7 +192,11 @@ nfftgp_status nfftgp_apply(nfftgp_plan plan, const void *V_dev, int64_t ldv, int
  * frozen at its last iterate), NFFTGP_E_NOCONV if a column did not reach tol,
  * NFFTGP_OK otherwise.  Synchronises the stream every check_every iterations
  * (check_every <= 0 means 8).  Allocates no device memory: its vectors,
- * scalars and history are plan workspaces. */
+ * scalars and history are plan workspaces.  Iterations are enqueued eagerly;
+ * with the environment variable NFFTGP_CG_GRAPH=1 the check_every iterations
+ * between two checks (at most 16) are captured once into a HIP graph and
+ * replayed (bit-identical results; the graph is captured again when nrhs,
+ * X_dev, tol, sigma_f, sigma_eps or check_every change). */
 nfftgp_status nfftgp_cg(nfftgp_plan plan, const void *B_dev, int32_t nrhs, void *X_dev,
                         double tol, int32_t maxit, int32_t check_every,
                         int32_t *iters_host, double *alpha_beta_host, double *resid_host);

@@ -1075,16 +1075,21 @@ nfftgp_status nfftgp_cg(nfftgp_plan plan, const void *B_dev, int32_t nrhs, void 
         PROF_LAUNCH(plan, NFFTGP_PROF_CG, launch_cg_p(plan->prec, n, nrhs, sc, plan->cg_r, plan->cg_p, cs));
         return NFFTGP_OK;
     };
-    // The iteration is captured once into a graph and replayed (all its
-    // arguments are fixed: the iteration index lives on the device).  Not
-    // while profiling (events are per launch), not when n = 0, and not with
-    // NFFTGP_CG_GRAPH=0.
+    // With NFFTGP_CG_GRAPH=1 the iterations between two convergence checks
+    // (at most 16) are captured once into a graph and replayed (all their
+    // arguments are fixed: the iteration index lives on the device); one graph
+    // launch then covers gi iterations, and iterations left over at the end
+    // run eagerly.  By default the iterations are enqueued eagerly: replaying
+    // the graph was measured no faster (the host already runs ahead of the
+    // device).  Never while profiling (events are per launch) or when n = 0.
     const char *ge = std::getenv("NFFTGP_CG_GRAPH");
-    const bool use_graph = maxit > 0 && n > 0 && !plan->prof && !(ge && std::strcmp(ge, "0") == 0);
+    const bool use_graph = maxit > 0 && n > 0 && !plan->prof && ge && std::strcmp(ge, "1") == 0;
+    const int gi = std::max(1, std::min({check_every, maxit, 16}));
     if (use_graph) {
         const bool hit = plan->cg_exec && plan->cg_key_nrhs == nrhs && plan->cg_key_x == X_dev &&
                          plan->cg_key_hist == hist && plan->cg_key_tol == tol &&
-                         plan->cg_key_sf == plan->sigma_f && plan->cg_key_se == plan->sigma_eps;
+                         plan->cg_key_sf == plan->sigma_f && plan->cg_key_se == plan->sigma_eps &&
+                         plan->cg_key_iters == gi;
         if (!hit) {
             if (plan->cg_exec) {
                 NFFTGP_HIP_TRY(hipGraphExecDestroy(plan->cg_exec));
@@ -1095,7 +1100,8 @@ nfftgp_status nfftgp_cg(nfftgp_plan plan, const void *B_dev, int32_t nrhs, void 
             hipGraph_t graph = nullptr;
             NFFTGP_HIP_TRY(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeRelaxed));
             plan->stream = plan->cap_stream;
-            const nfftgp_status ce = iteration();
+            nfftgp_status ce = NFFTGP_OK;
+            for (int k = 0; k < gi && ce == NFFTGP_OK; ++k) ce = iteration();
             plan->stream = st;
             const hipError_t ee = hipStreamEndCapture(plan->cap_stream, &graph);
             if (ce != NFFTGP_OK) {
@@ -1112,28 +1118,31 @@ nfftgp_status nfftgp_cg(nfftgp_plan plan, const void *B_dev, int32_t nrhs, void 
             plan->cg_key_tol = tol;
             plan->cg_key_sf = plan->sigma_f;
             plan->cg_key_se = plan->sigma_eps;
+            plan->cg_key_iters = gi;
         }
     }
     std::vector<double> act(nrhs);
     int it = 0;
-    for (; it < maxit; ++it) {
-        if (use_graph) {
-            NFFTGP_HIP_TRY(hipGraphLaunch(plan->cg_exec, st));
-        } else {
-            nfftgp_status e = iteration();
-            if (e != NFFTGP_OK) return e;
-        }
-        if ((it + 1) % check_every == 0 || it + 1 == maxit) {
-            NFFTGP_HIP_TRY(hipMemcpyAsync(act.data(), sc + kActive * nrhs, nrhs * sizeof(double),
-                                          hipMemcpyDeviceToHost, st));
-            NFFTGP_HIP_TRY(hipStreamSynchronize(st));
-            bool any = false;
-            for (int c = 0; c < nrhs; ++c) any = any || act[c] != 0.0;
-            if (!any) {
+    while (it < maxit) {
+        // up to the next convergence check (or maxit): whole graph launches,
+        // then single eager iterations
+        const int stop = std::min(maxit, (it / check_every + 1) * check_every);
+        while (it < stop) {
+            if (use_graph && it + gi <= stop) {
+                NFFTGP_HIP_TRY(hipGraphLaunch(plan->cg_exec, st));
+                it += gi;
+            } else {
+                nfftgp_status e = iteration();
+                if (e != NFFTGP_OK) return e;
                 ++it;
-                break;
             }
         }
+        NFFTGP_HIP_TRY(hipMemcpyAsync(act.data(), sc + kActive * nrhs, nrhs * sizeof(double),
+                                      hipMemcpyDeviceToHost, st));
+        NFFTGP_HIP_TRY(hipStreamSynchronize(st));
+        bool any = false;
+        for (int c = 0; c < nrhs; ++c) any = any || act[c] != 0.0;
+        if (!any) break;
     }
     std::vector<double> all((size_t)kCgSlots * nrhs);
     NFFTGP_HIP_TRY(hipMemcpyAsync(all.data(), sc, all.size() * sizeof(double), hipMemcpyDeviceToHost, st));

@@ -228,6 +228,7 @@ struct nfftgp_plan_s {
     const void *cg_key_x = nullptr;
     const double *cg_key_hist = nullptr;
     double cg_key_tol = 0.0, cg_key_sf = 0.0, cg_key_se = 0.0;
+    int cg_key_iters = 0;       // iterations the captured graph holds
     nfftgp::Precond pc;          // AAFN preconditioner (nfftgp_precond_attach)
     size_t bytes = 0;
     std::vector<void *> allocs;

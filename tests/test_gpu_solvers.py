@@ -216,33 +216,42 @@ def test_indefinite_coefficients_reported(orc):
     assert abs(info["min_bder"] - bd.min()) <= 1e-10
 
 
-def test_cg_graph_replay_matches_eager(orc, monkeypatch):
-    """One CG iteration is captured as a graph and replayed; the result equals
-    the eager iteration bit for bit, also when the captured graph is replayed
-    in later calls with other work (applies, synchronisations) in between, and
-    after set_hyper changes sigma (the graph is captured again)."""
+@pytest.mark.parametrize("check_every", [8, 5, 1])
+def test_cg_graph_replay_matches_eager(orc, monkeypatch, check_every):
+    """The CG iterations between two convergence checks (check_every of them,
+    at most 16) are captured as one graph and replayed (NFFTGP_CG_GRAPH=1); the
+    result equals the eager iterations bit for bit, also when the graph is
+    replayed in later calls with other work (applies, synchronisations) in
+    between, when the iteration count is not a multiple of check_every (the
+    rest runs eagerly), and after set_hyper changes sigma (the graph is
+    captured again)."""
     w = workloads.small(25, 4000, [3, 2], [0, 1], [0.6, 0.5], [32, 32], 4, nrhs=3, sigma_eps=0.4)
     plan, pb = _setup(orc, w, dtype=torch.float32, nrhs=3)
     B = torch.tensor(w.V, dtype=torch.float32, device=DEV)
-    monkeypatch.setenv("NFFTGP_CG_GRAPH", "0")
-    Xe, ite, abe, rese, ste = plan.cg(B, 1e-5, 400)
-    monkeypatch.delenv("NFFTGP_CG_GRAPH")
+    monkeypatch.delenv("NFFTGP_CG_GRAPH", raising=False)
+    Xe, ite, abe, rese, ste = plan.cg(B, 1e-5, 400, check_every=check_every)
+    monkeypatch.setenv("NFFTGP_CG_GRAPH", "1")
     X = torch.empty_like(B)
     V = torch.randn(w.n, 3, dtype=torch.float32, device=DEV)
     for rep in range(3):
         plan.apply(V, derivs=True)          # eager work between replays
         torch.cuda.synchronize()
-        Xg, itg, abg, resg, stg = plan.cg(B, 1e-5, 400, out=X)
+        Xg, itg, abg, resg, stg = plan.cg(B, 1e-5, 400, check_every=check_every, out=X)
         torch.cuda.synchronize()
         assert stg == ste
         assert np.array_equal(itg, ite)
         assert torch.equal(Xg, Xe), rep
         assert np.array_equal(abg, abe)
-    plan.set_hyper(1.2, w.ell, 0.5)
-    monkeypatch.setenv("NFFTGP_CG_GRAPH", "0")
-    Xe2, ite2, _, _, _ = plan.cg(B, 1e-5, 400)
+    # a fixed count that is not a multiple of check_every
+    Xf, itf, _, _, _ = plan.cg(B, 0.0, 3 * check_every + 2, check_every=check_every, raise_on=(), out=X)
     monkeypatch.delenv("NFFTGP_CG_GRAPH")
-    Xg2, itg2, _, _, _ = plan.cg(B, 1e-5, 400, out=X)
+    Xf_e, itf_e, _, _, _ = plan.cg(B, 0.0, 3 * check_every + 2, check_every=check_every, raise_on=())
+    assert np.array_equal(itf, itf_e) and torch.equal(Xf, Xf_e)
+    plan.set_hyper(1.2, w.ell, 0.5)
+    Xe2, ite2, _, _, _ = plan.cg(B, 1e-5, 400, check_every=check_every)
+    monkeypatch.setenv("NFFTGP_CG_GRAPH", "1")
+    Xg2, itg2, _, _, _ = plan.cg(B, 1e-5, 400, check_every=check_every, out=X)
+    monkeypatch.delenv("NFFTGP_CG_GRAPH")
     assert np.array_equal(itg2, ite2)
     assert torch.equal(Xg2, Xe2)
 
