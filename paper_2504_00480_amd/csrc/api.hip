@@ -638,6 +638,39 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
             int32_t **id[4] = {&G.isub_win, &G.isub_bin, &G.isub_start, &G.isub_count};
             for (int k = 0; k < 4; ++k) TRYS(dalloc(plan, (void **)id[k], (size_t)G.isub_cap * sizeof(int)));
         }
+        if (!d3) {
+            // several-vector interpolation list (d <= 2): subproblems of up to
+            // vsub_sp points (rule 2048; NFFTGP_INTERP_VB_SUB=<points> overrides,
+            // a multiple of 512)
+            const char *vsv = std::getenv("NFFTGP_INTERP_VB_SUB");
+            int vsp = vsv ? std::atoi(vsv) : kInterpVbSubPoints;
+            vsp = std::max(512, std::min(1 << 16, vsp - vsp % 512));
+            G.vsub_sp = vsp;
+            int64_t vcap = 0;
+            for (int wl = 0; wl < G.nwin; ++wl) {
+                const std::vector<int> &bs = plan->win[G.wins[wl]].h_bin_start;
+                for (int b = 0; b < G.g.nbins; ++b) vcap += (bs[b + 1] - bs[b] + vsp - 1) / vsp;
+            }
+            G.vsub_cap = (int)std::max<int64_t>(vcap, 1);
+            int32_t **vd[4] = {&G.vsub_win, &G.vsub_bin, &G.vsub_start, &G.vsub_count};
+            for (int k = 0; k < 4; ++k) TRYS(dalloc(plan, (void **)vd[k], (size_t)G.vsub_cap * sizeof(int)));
+            std::vector<int> vw, vbn, vs, vc;
+            for (int wl = 0; wl < G.nwin; ++wl) {
+                const std::vector<int> &bs = plan->win[G.wins[wl]].h_bin_start;
+                for (int b = 0; b < G.g.nbins; ++b)
+                    for (int off = 0; off < bs[b + 1] - bs[b]; off += vsp) {
+                        vw.push_back(wl);
+                        vbn.push_back(b);
+                        vs.push_back(bs[b] + off);
+                        vc.push_back(std::min(vsp, bs[b + 1] - bs[b] - off));
+                    }
+            }
+            std::vector<int> *vsrc[4] = {&vw, &vbn, &vs, &vc};
+            for (int k = 0; k < 4; ++k)
+                if (!vsrc[k]->empty())
+                    TRYH(hipMemcpy(*vd[k], vsrc[k]->data(), vsrc[k]->size() * sizeof(int), hipMemcpyHostToDevice));
+            G.nvsub = (int)vw.size();
+        }
         // interpolation variant: the per-point tile variant by default (the
         // faster one on every measured workload once its tile staging was
         // batched); nfftgp_autotune may switch, NFFTGP_INTERP=run|tile|tile2|tilepair|tilefull|tileslot|mfma
@@ -914,21 +947,25 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
         }
         G.spread_R = best_R;
         if (stt != NFFTGP_OK) break;
-        // 2a) spreading form: the one the rule did not take
+        // 2a) spreading form: four-point and run-ordered, and matrix cores
+        //     (FP32, d = 3, m = 4 or 6, four or more vectors)
         {
             const int cur_F = G.spread_form;
-            G.spread_form = 1;
-            double t1 = 0.0, t2 = 0.0;
-            if ((stt = timed(t1)) != NFFTGP_OK) break;
-            G.spread_form = 2;
-            if ((stt = timed(t2)) != NFFTGP_OK) break;
-            const double tb_ = std::min(t1, t2);
-            if (tb_ < best) {
-                best = tb_;
-                G.spread_form = t1 <= t2 ? 1 : 2;
-            } else {
-                G.spread_form = cur_F;
+            std::vector<int> forms = {1, 2};
+            if (plan->prec == NFFTGP_F32 && G.g.d == 3 && (plan->m == 4 || plan->m == 6) && nrhs >= 4)
+                forms.push_back(3);
+            int best_F = cur_F;
+            for (int f : forms) {
+                G.spread_form = f;
+                double t = 0.0;
+                if ((stt = timed(t)) != NFFTGP_OK) break;
+                if (t < best) {
+                    best = t;
+                    best_F = f;
+                }
             }
+            if (stt != NFFTGP_OK) break;
+            G.spread_form = best_F;
         }
         // 2b) 3-D: waves sharing a spreading tile (4 by rule, or 2)
         if (G.g.d == 3) {
@@ -1004,7 +1041,9 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
                                           "interpolation %s; %.4f ms per apply\n",
                       G.g.d, G.g.N, G.nwin, G.sub_sp,
                       G.spread_R > 0 ? std::to_string(G.spread_R).c_str() : "rule",
-                      (std::string(G.spread_form == 1 ? ", four-point form" : (G.spread_form == 2 ? ", run form" : "")) +
+                      (std::string(G.spread_form == 1 ? ", four-point form"
+                                                      : (G.spread_form == 2 ? ", run form"
+                                                                            : (G.spread_form == 3 ? ", matrix cores" : ""))) +
                        (G.spread_W == 2 ? ", 2 waves/tile" : "")).c_str(),
                       ivar.c_str(), best);
         rep += line;

@@ -1331,23 +1331,30 @@ k_interp_vb(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     const int start = sub_start[sq], cnt = sub_count[sq];
     int org[3] = {0, 0, 0};
     bin_origin<D>(sub_bin[sq] & 0xffffff, nb, tb, org);
+    // the subproblem's points are taken 256 PT at a time (point k of a chunk
+    // by thread k mod 256): a single chunk keeps its weights in registers for
+    // every vector batch, longer subproblems reload them per batch and chunk
     bool mine[PT];
     T w[PT][D][TW];
     int lin[PT];
     int64_t orow[PT];
+    auto load_pts = [&](int pc0) {
 #pragma unroll
-    for (int p = 0; p < PT; ++p) {
-        const int k = (int)threadIdx.x + 256 * p;
-        mine[p] = k < cnt;
-        const int64_t j = start + (mine[p] ? k : 0);
-        const T *rp = rec + j * RS;
+        for (int p = 0; p < PT; ++p) {
+            const int k = pc0 + (int)threadIdx.x + 256 * p;
+            mine[p] = k < cnt;
+            const int64_t j = start + (mine[p] ? k : 0);
+            const T *rp = rec + j * RS;
 #pragma unroll
-        for (int q = 0; q < D; ++q)
+            for (int q = 0; q < D; ++q)
 #pragma unroll
-            for (int a = 0; a < TW; ++a) w[p][q][a] = rp[q * TW + a];
-        lin[p] = win.lpos[j] & 0xfffff;
-        orow[p] = (int64_t)win.perm[j] * nrhs;
-    }
+                for (int a = 0; a < TW; ++a) w[p][q][a] = rp[q * TW + a];
+            lin[p] = win.lpos[j] & 0xfffff;
+            orow[p] = (int64_t)win.perm[j] * nrhs;
+        }
+    };
+    const bool one_chunk = cnt <= 256 * PT;
+    if (one_chunk) load_pts(0);
     T *hout = hbuf + (int64_t)win.s_global * n * nrhs;
     T *dblk = DER ? dout + (int64_t)win.s_global * n * nrhs : nullptr;
     for (int r0 = 0; r0 < nrhs; r0 += vb) {
@@ -1398,6 +1405,8 @@ k_interp_vb(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             }
         }
         __syncthreads();
+        for (int pc0 = 0; pc0 < cnt; pc0 += 256 * PT) {
+        if (!one_chunk) load_pts(pc0);
 #pragma unroll
         for (int p = 0; p < PT; ++p) {
             if (!mine[p]) continue;
@@ -1460,6 +1469,7 @@ k_interp_vb(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                     }
                 }
             }
+        }
         }
     }
 }
@@ -1825,9 +1835,11 @@ hipError_t spread_dm(const Group &G, const void *V, int64_t ldv, int nrhs, void 
                      hipStream_t s)
 {
     // matrix-core form: by request (spread_form 3), or by rule for four or
-    // more vectors
+    // more vectors at 2m = 12 (at 2m = 8 the VALU run form was measured
+    // faster: C3 3-D group 1.3 vs 1.56 ms; the tuner tries both)
     if constexpr (std::is_same<T, float>::value && D == 3 && (M == 4 || M == 6)) {
-        if (spread_mfma_ok<T, D, M>(G) && (G.spread_form == 3 || (G.spread_form == 0 && nrhs >= 4 && kSpreadMfmaRule)))
+        if (spread_mfma_ok<T, D, M>(G) &&
+            (G.spread_form == 3 || (G.spread_form == 0 && nrhs >= 4 && M == 6 && kSpreadMfmaRule)))
             return spread_mfma_launch<M>(G, V, ldv, nrhs, tilebuf, s);
     }
     const int R = spread_vectors_per_group(G, nrhs, sizeof(T));
@@ -1878,8 +1890,8 @@ hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool
                 constexpr int PT = decltype(pt_tag)::value;
                 hipError_t e = allow_lds(k_interp_vb<T, D, M, DR, PT>, shm);
                 if (e != hipSuccess) return e;
-                k_interp_vb<T, D, M, DR, PT><<<(unsigned)G.nisub, 256, shm, s>>>(
-                    G.desc, G.isub_win, G.isub_bin, G.isub_start, G.isub_count, g.tb, g.nb, g.ng, G.nwin,
+                k_interp_vb<T, D, M, DR, PT><<<(unsigned)G.nvsub, 256, shm, s>>>(
+                    G.desc, G.vsub_win, G.vsub_bin, G.vsub_start, G.vsub_count, g.tb, g.nb, g.ng, G.nwin,
                     (const C *)grid, g.cells, nrhs, vb, vst, n, (T *)hbuf, DR ? (T *)dout : nullptr,
                     (T)dscale);
                 return hipGetLastError();
@@ -2066,7 +2078,7 @@ std::string describe_group(int prec, const Group &G, int m, int nrhs)
     std::string sp;
     const bool mfma_ok = prec == NFFTGP_F32 && G.g.d == 3 && (m == 4 || m == 6) &&
                          (size_t)spread_mfma_pad(G.g.pd).sr * sizeof(float) * 4 <= kSpreadMfmaLds;
-    if (mfma_ok && (G.spread_form == 3 || (G.spread_form == 0 && nrhs >= 4 && kSpreadMfmaRule))) {
+    if (mfma_ok && (G.spread_form == 3 || (G.spread_form == 0 && nrhs >= 4 && m == 6 && kSpreadMfmaRule))) {
         sp = "mfma (4 vectors per work-group)";
     } else {
         const int R = spread_vectors_per_group(G, nrhs, prec == NFFTGP_F32 ? 4 : 8);

@@ -25,6 +25,8 @@ inline double kb_beta() { return kPi * (2.0 - 1.0 / kSigma); }
 constexpr int kInterpSubPoints = 256;
 // 3-D matrix-core interpolation: blocks (at most 16 points of one cell) per subproblem
 constexpr int kInterpSubBlocks = 16;
+// d <= 2 several-vector interpolation: points per subproblem by rule
+constexpr int kInterpVbSubPoints = 2048;
 // Points per wave in run-based interpolation.
 constexpr int kRunSubPoints = 512;
 
@@ -106,6 +108,11 @@ struct Group {
     int nsub = 0;                // spreading subproblems (tile slots)
     int32_t *isub_win = nullptr, *isub_bin = nullptr, *isub_start = nullptr, *isub_count = nullptr;
     int nisub = 0;               // interpolation subproblems
+    // d <= 2: the several-vector interpolation's own list, subproblems of up to
+    // vsub_sp points of one tile (the tile is staged once per vector batch for
+    // all of them)
+    int32_t *vsub_win = nullptr, *vsub_bin = nullptr, *vsub_start = nullptr, *vsub_count = nullptr;
+    int nvsub = 0, vsub_cap = 0, vsub_sp = 0;
     int nbins_used = 0;          // tiles holding at least one point
     // tunables (rule defaults at plan creation; nfftgp_autotune may change them)
     int sub_sp = 0;              // points per spreading subproblem

@@ -366,12 +366,16 @@ def test_set_hyper_between_applies_without_waits():
 
 
 @pytest.mark.parametrize("m", [4, 6])
-def test_matrix_core_forms_parity(orc, m):
-    """The matrix-core spreading and interpolation (3-D FP32, the rule for four
-    or more vectors) against the oracle on every row, with a ragged last group
-    of vectors (6 = 4 + 2), clustered points (long runs of equal cells, blocks
-    of 16 and partial blocks) and a 2-D window beside them on the VALU forms;
-    then the forms the plan reports."""
+def test_matrix_core_forms_parity(orc, m, monkeypatch):
+    """The matrix-core spreading and interpolation (3-D FP32; the rule for four
+    or more vectors at m = 6, forced at m = 4) against the oracle on every row,
+    with a ragged last group of vectors (6 = 4 + 2), clustered points (long
+    runs of equal cells, blocks of 16 and partial blocks) and a 2-D window
+    beside them on the VALU forms; then the forms the plan reports."""
+    if m == 4:
+        monkeypatch.setenv("NFFTGP_SPREAD_FORM", "mfma")
+    else:
+        monkeypatch.delenv("NFFTGP_SPREAD_FORM", raising=False)
     w = workloads.small(17 + m, 6000, [3, 3, 2], [0, 1, 0], [0.5, 0.7, 0.4], [32, 16, 32], m, 6,
                         dist="cluster")
     plan, got, ref, r, pb = _run(orc, w, "f32")
@@ -386,7 +390,8 @@ def test_matrix_core_forms_parity(orc, m):
     e_f = _rel(got["dKV_dsf"][r], ref["dKV_dsf"])
     print(f"  m={m}: rel err KV {e_k:.2e}  dKV/dell {e_d:.2e}  dKV/dsf {e_f:.2e}", flush=True)
     assert e_k <= tol and e_d <= tol and e_f <= tol
-    # one vector: the VALU spreading form, matrix-core interpolation padded
-    assert "spread=mfma" not in plan.describe(1)
+    # one vector: the VALU spreading form (unless forced), matrix-core interpolation padded
+    if m == 6:
+        assert "spread=mfma" not in plan.describe(1)
     o1 = plan.apply(torch.tensor(w.V[:, :1], dtype=torch.float32, device="cuda:0"), derivs=False)
     assert _rel(o1["KV"].double().cpu().numpy(), ref["KV"][:, :1]) <= tol
