@@ -340,6 +340,15 @@ int interp_rows_rule(const WindowGeom &g, int m)
     return std::min(g.pd, g.tb / 2 + 2 * m - 1);
 }
 
+// Staged rows of the 3-D matrix-core interpolation by rule: one first-axis cell
+// row per subproblem (2m rows), so that the staged tile (77 KB at m = 6) lets
+// two work-groups of eight waves share a CU (measured at C5: 10.4 ms per launch
+// against 11.4 with sixteen waves and 15 rows, one work-group per CU).
+int interp_mfma_rows_rule(const WindowGeom &g, int m)
+{
+    return std::min(g.pd, 2 * m);
+}
+
 // Plan creation; given_c0 / given_c (both host, or both NULL) carry a scaling
 // chosen by the caller (nfftgp_plan_create_scaled), otherwise scale_mode rules.
 nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, int32_t p,
@@ -702,10 +711,14 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
         const bool blk = iov ? std::strcmp(iov, "mfma") == 0
                              : (G.g.d == 3 && prec == NFFTGP_F32 && (m == 4 || m == 6) && max_nrhs >= 2);
         const char *imw = std::getenv("NFFTGP_INTERP_MFMA_WAVES");   // "8" | "16"
-        G.interp_mfma_waves = imw && std::strcmp(imw, "8") == 0 ? 8 : 16;
+        G.interp_mfma_waves = imw && std::strcmp(imw, "16") == 0 ? 16 : 8;
         G.interp_adj = pair && G.g.d == 3;
+        // matrix-core blocks stage NFFTGP_INTERP_MFMA_ROWS first-axis rows
+        // (default: the rule's window)
+        const char *imr = std::getenv("NFFTGP_INTERP_MFMA_ROWS");
+        const int mrows = imr ? std::max(2 * m, std::min(G.g.pd, std::atoi(imr))) : interp_mfma_rows_rule(G.g, m);
         TRYS(build_interp_lists(plan, G, iov && (pair || std::strcmp(iov, "tile2") == 0) ? 2 : 1,
-                                full ? G.g.pd : interp_rows_rule(G.g, m), slot, blk));
+                                full ? G.g.pd : (blk ? mrows : interp_rows_rule(G.g, m)), slot, blk));
         {
             // run-interpolation list (built for every group, so that the
             // variant can be switched): points per wave up to kRunSubPoints,
@@ -999,8 +1012,11 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
             cands.push_back({false, 2, rr, false, true});
             if (rr != G.g.pd) cands.push_back({false, 2, G.g.pd, false, true});
             // blocks of one cell on matrix cores (FP32, m = 4 or 6)
-            if (plan->prec == NFFTGP_F32 && (plan->m == 4 || plan->m == 6))
-                cands.push_back({false, 1, rr, false, false, true});
+            if (plan->prec == NFFTGP_F32 && (plan->m == 4 || plan->m == 6)) {
+                const int mr = interp_mfma_rows_rule(G.g, plan->m);
+                cands.push_back({false, 1, mr, false, false, true});
+                if (rr != mr) cands.push_back({false, 1, rr, false, false, true});
+            }
         }
         cands.push_back({true, cur_pt, cur_rows, cur_adj, cur_slot, cur_blk});
         for (const Cand &c : cands) {

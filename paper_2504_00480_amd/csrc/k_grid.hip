@@ -1144,7 +1144,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
 // weights, output rows and first taps sit in LDS for the whole subproblem,
 // and the staged rows of the padded tile (plane stride 8 modulo 32 words:
 // the 32 lanes of a half-wave read distinct banks) hold four values per cell.
-template <int M, bool DER, int NWV>
+template <int M, bool DER, int NWV, bool WLDS>
 __global__ void __launch_bounds__((64 * NWV))
 k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
               const int *__restrict__ sub_bin, const int *__restrict__ sub_start,
@@ -1159,7 +1159,10 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     constexpr int VPS = DER ? 2 : 4;            // vectors per staging
     constexpr int NT = 64 * NWV;
     constexpr int MAXP = 16 * kInterpSubBlocks;
-    __shared__ float s_w[MAXP * RS];
+    // the points' weights: copied to LDS once per subproblem (WLDS), or read
+    // from the weight record (L2) per block and pass, which leaves the LDS to
+    // two work-groups per CU
+    __shared__ float s_w[WLDS ? MAXP * RS : 1];
     __shared__ int s_row[MAXP];
     __shared__ int s_blk[kInterpSubBlocks + 1];
     __shared__ int s_lp[kInterpSubBlocks];
@@ -1179,7 +1182,9 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // the subproblem's points [P0, P1): weights, output rows, block starts
     const int P0 = win.blocks[start], P1 = win.blocks[start + cnt];
-    for (int i = tid; i < (P1 - P0) * RS; i += NT) s_w[i] = rec[(int64_t)P0 * RS + i];
+    if (WLDS)
+        for (int i = tid; i < (P1 - P0) * RS; i += NT) s_w[i] = rec[(int64_t)P0 * RS + i];
+    const float *wsrc = WLDS ? s_w : rec + (int64_t)P0 * RS;
     for (int i = tid; i < P1 - P0; i += NT) s_row[i] = win.perm[P0 + i];
     if (tid <= cnt) s_blk[tid] = win.blocks[start + tid] - P0;
     if (tid < cnt) s_lp[tid] = win.lpos[win.blocks[start + tid]];
@@ -1233,7 +1238,7 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             const int lin = (lp & 0xfffff) - a0s * pd2;   // first tap inside the staged rows
             const int frow = fdiv_small(lin, pd2, 1.0f / (float)pd2), rem = lin - frow * pd2;
             // A row li: point j0 + li (rows past the block: weight 0)
-            const float *rp = s_w + (j0 + min(li, np - 1)) * RS;
+            const float *rp = wsrc + (j0 + min(li, np - 1)) * RS;
             float w1[TW], w2k[TW / 4];
 #pragma unroll
             for (int t = 0; t < TW; ++t) w1[t] = rp[TW + t];
@@ -1273,7 +1278,7 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             float h[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float *rw = s_w + (j0 + min(4 * kq + v, np - 1)) * RS;
+                const float *rw = wsrc + (j0 + min(4 * kq + v, np - 1)) * RS;
                 float sum = 0.0f;
 #pragma unroll
                 for (int c = 0; c < NBK; ++c) sum += rw[(L + 4 * c + al) % TW] * acc[c][v];
@@ -1915,9 +1920,12 @@ hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool
             auto go = [&](auto der_tag, auto nw_tag) -> hipError_t {
                 constexpr bool DR = decltype(der_tag)::value;
                 constexpr int NW = decltype(nw_tag)::value;
-                hipError_t e = allow_lds(k_interp_mfma<M, DR, NW>, shm);
+                // 16 waves keep the weights in LDS; 8 waves read them from L2
+                // so that two work-groups share a CU
+                constexpr bool WL = NW == 16;
+                hipError_t e = allow_lds(k_interp_mfma<M, DR, NW, WL>, shm);
                 if (e != hipSuccess) return e;
-                k_interp_mfma<M, DR, NW><<<(unsigned)G.nisub, 64 * NW, shm, s>>>(
+                k_interp_mfma<M, DR, NW, WL><<<(unsigned)G.nisub, 64 * NW, shm, s>>>(
                     G.desc, G.isub_win, G.isub_bin, G.isub_start, G.isub_count, g.tb, g.nb, g.ng, rows,
                     (const float2 *)grid, g.cells, nrhs, n, (float *)hbuf, DR ? (float *)dout : nullptr,
                     (float)dscale);

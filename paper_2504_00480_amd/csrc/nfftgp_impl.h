@@ -131,7 +131,8 @@ struct Group {
     bool interp_adj = false;     // 3-D, 2 points per thread: adjacent sorted points share tap reads
     bool interp_slot = false;    // 3-D: one slot per thread (two points of one cell share every tap read)
     bool interp_mfma = false;    // 3-D FP32: blocks of one cell on matrix cores (lists count blocks)
-    int interp_mfma_waves = 16;  // waves per work-group of the matrix-core interpolation (8 or 16)
+    int interp_mfma_waves = 8;   // waves per work-group of the matrix-core interpolation (8: weights
+                                 // read from L2, two work-groups per CU; 16: weights in LDS)
     int interp_vb_lds = 80 << 10;   // d <= 2: LDS bytes for several vectors per staging (0: one vector)
     int interp_rows = 0;         // 3-D: first-axis rows of the padded tile staged per subproblem
     int isub_cap = 0;            // capacity of the interpolation list arrays
