@@ -649,10 +649,17 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
         }
         if (!d3) {
             // several-vector interpolation list (d <= 2): subproblems of up to
-            // vsub_sp points (rule 2048; NFFTGP_INTERP_VB_SUB=<points> overrides,
-            // a multiple of 512)
+            // vsub_sp points (rule: from 512 doubled up to kInterpVbSubPoints
+            // while the group keeps at least 256 of them; NFFTGP_INTERP_VB_SUB=
+            // <points> overrides, a multiple of 512)
             const char *vsv = std::getenv("NFFTGP_INTERP_VB_SUB");
-            int vsp = vsv ? std::atoi(vsv) : kInterpVbSubPoints;
+            int vsp = 512;
+            if (vsv) {
+                vsp = std::atoi(vsv);
+            } else {
+                const int64_t pts = (int64_t)G.nwin * n;
+                while (vsp < kInterpVbSubPoints && pts / (2 * vsp) >= 256) vsp *= 2;
+            }
             vsp = std::max(512, std::min(1 << 16, vsp - vsp % 512));
             G.vsub_sp = vsp;
             int64_t vcap = 0;
@@ -710,6 +717,8 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
         // unless another variant is forced
         const bool blk = iov ? std::strcmp(iov, "mfma") == 0
                              : (G.g.d == 3 && prec == NFFTGP_F32 && (m == 4 || m == 6) && max_nrhs >= 2);
+        const char *smr = std::getenv("NFFTGP_SPREAD_MFMA_R");   // "2" | "4"
+        G.spread_mfma_R = smr && std::strcmp(smr, "2") == 0 ? 2 : 4;
         const char *imw = std::getenv("NFFTGP_INTERP_MFMA_WAVES");   // "8" | "16"
         G.interp_mfma_waves = imw && std::strcmp(imw, "16") == 0 ? 16 : 8;
         G.interp_adj = pair && G.g.d == 3;

@@ -487,11 +487,11 @@ k_spread_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
 template <int M, int R>
 struct SpreadMfmaShape {
     static constexpr int TW = 2 * M;
-    static constexpr int NB = TW * R / 16;                      // column blocks
+    static constexpr int NB = (TW * R + 15) / 16;               // column blocks (the last may be padded)
     static constexpr int MG = TW / 4;                           // second-dimension slot groups
     static constexpr int BPW = TW / 4;                          // row blocks per wave
     static constexpr int NWAVE = NB * MG;
-    static_assert(TW % 4 == 0 && (TW * R) % 16 == 0 && 16 % R == 0, "block shape");
+    static_assert(TW % 4 == 0 && 16 % R == 0, "block shape");
 };
 
 // Padded strides of the LDS tile (words): row, plane, vector.
@@ -545,7 +545,9 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     // j + 16 k), the accumulator's element v in row 4 (lane / 16) + v
     const int li = lane & 15, kq = lane >> 4;
     const int nb = wave % NB, bg = wave / NB;
-    const int aslot = nb * SPB + li / R, br = li % R;           // B column: first slot, vector
+    const int aslot_raw = nb * SPB + li / R, br = li % R;       // B column: first slot, vector
+    const bool colok = aslot_raw < TW;                          // columns past 2m slots pad a block
+    const int aslot = colok ? aslot_raw : 0;
     const int bslot_a = 4 * bg + li / 4;                        // A row li: second slot
     const int bslot_f = 4 * bg + kq;                            // accumulator rows: second slot
     const int ac = 2 * TW + li % 4;                             // A row li, block k: third tap 4 k + li % 4
@@ -633,7 +635,7 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                 pu += 4;
             };
             auto step = [&](const Ops &o) {
-                const float bv = o.ok ? o.w0 * o.v : 0.0f;
+                const float bv = o.ok && colok ? o.w0 * o.v : 0.0f;
 #pragma unroll
                 for (int k = 0; k < BPW; ++k)
                     acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.wb * o.wc[k], bv, acc[k], 0, 0, 0);
@@ -654,7 +656,7 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                 __builtin_amdgcn_sched_barrier(0);
                 if (u + 8 > u1) break;
             }
-            if (flush) {
+            if (flush && colok) {
                 // lane's cells: first tap (aslot - a0) mod TW, second tap
                 // (bslot_f - b0) mod TW, third taps 4 k + v; all reads first,
                 // then the writes
@@ -1821,11 +1823,11 @@ bool spread_mfma_ok(const Group &G)
            (size_t)spread_mfma_pad(G.g.pd).sr * sizeof(float) * 4 <= kSpreadMfmaLds;
 }
 
-template <int M>
+template <int M, int R>
 hipError_t spread_mfma_launch(const Group &G, const void *V, int64_t ldv, int nrhs, void *tilebuf,
                               hipStream_t s)
 {
-    constexpr int R = 4, NW = SpreadMfmaShape<M, R>::NWAVE;
+    constexpr int NW = SpreadMfmaShape<M, R>::NWAVE;
     const size_t shm = (size_t)spread_mfma_pad(G.g.pd).sr * sizeof(float) * R;
     hipError_t e = allow_lds(k_spread_mfma<M, R>, shm);
     if (e != hipSuccess) return e;
@@ -1845,7 +1847,8 @@ hipError_t spread_dm(const Group &G, const void *V, int64_t ldv, int nrhs, void 
     if constexpr (std::is_same<T, float>::value && D == 3 && (M == 4 || M == 6)) {
         if (spread_mfma_ok<T, D, M>(G) &&
             (G.spread_form == 3 || (G.spread_form == 0 && nrhs >= 4 && M == 6 && kSpreadMfmaRule)))
-            return spread_mfma_launch<M>(G, V, ldv, nrhs, tilebuf, s);
+            return G.spread_mfma_R == 2 ? spread_mfma_launch<M, 2>(G, V, ldv, nrhs, tilebuf, s)
+                                        : spread_mfma_launch<M, 4>(G, V, ldv, nrhs, tilebuf, s);
     }
     const int R = spread_vectors_per_group(G, nrhs, sizeof(T));
     // waves sharing a tile: 4 for d = 3 unless the group asks for 2

@@ -121,6 +121,8 @@ struct Group {
     int spread_form = 0;         // spreading kernel: 0 rule (four-point form for one vector
                                  // per work-group, else run-ordered), 1 four-point, 2 run-ordered,
                                  // 3 matrix cores (FP32, d = 3)
+    int spread_mfma_R = 4;       // vectors per matrix-core spreading work-group (4, or 2: two
+                                 // work-groups per CU, a padded column block)
     // every window Gaussian: set_hyper only records theta (prm) and the next
     // apply computes the coefficients in extra work-groups of its fold launch
     bool sep = false;
