@@ -386,7 +386,7 @@ k_fft_pruned(typename Cplx<T>::type *__restrict__ data, PruneGeom pg, int ax, in
 #pragma unroll
         for (int pass = 0; pass < (DER ? 2 : 1); ++pass) {
             const WinDesc &w = wd[s_win[tli]];
-            const T *D = reinterpret_cast<const T *>(pass == 0 ? w.Dk : w.Dder);
+            gmem<T> *D = (gmem<T> *)(pass == 0 ? w.Dk : w.Dder);
 #pragma unroll
             for (int n1 = 0; n1 < Sp::P; ++n1) {
                 const int k = Sp::Q * n1 + tn2;

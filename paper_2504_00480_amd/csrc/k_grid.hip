@@ -94,9 +94,9 @@ k_spread(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     for (int q = 1; q < D; ++q) pc *= pd;
     const int sq = xcd_item(blockIdx.x, gridDim.x), r0 = blockIdx.y * R;
     const WinDesc &win = wd[sub_win[sq]];
-    const T *rec = reinterpret_cast<const T *>(win.rec);
-    const int *lpos = win.lpos;
-    const int *perm = win.perm;
+    gmem<T> *rec = (gmem<T> *)win.rec;
+    gmem<int> *lpos = (gmem<int> *)win.lpos;
+    gmem<int> *perm = (gmem<int> *)win.perm;
     const int start = sub_start[sq], cnt = sub_count[sq];
     const int end = start + cnt;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -296,9 +296,9 @@ k_spread_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     for (int q = 1; q < D; ++q) pc *= pd;
     const int sq = xcd_item(blockIdx.x, gridDim.x), r0 = blockIdx.y * R;
     const WinDesc &win = wd[sub_win[sq]];
-    const T *rec = reinterpret_cast<const T *>(win.rec);
-    const int *lpos = win.lpos;
-    const int *perm = win.perm;
+    gmem<T> *rec = (gmem<T> *)win.rec;
+    gmem<int> *lpos = (gmem<int> *)win.lpos;
+    gmem<int> *perm = (gmem<int> *)win.perm;
     const int start = sub_start[sq], cnt = sub_count[sq];
     const int end = start + cnt;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -532,9 +532,9 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     const float inv_pd = 1.0f / (float)pd;
     const int sq = xcd_item(blockIdx.x, gridDim.x), r0 = blockIdx.y * R;
     const WinDesc &win = wd[sub_win[sq]];
-    const float *rec = reinterpret_cast<const float *>(win.rec);
-    const int *lpos = win.lpos;
-    const int *perm = win.perm;
+    gmem<float> *rec = (gmem<float> *)win.rec;
+    gmem<int> *lpos = (gmem<int> *)win.lpos;
+    gmem<int> *perm = (gmem<int> *)win.perm;
     const int start = sub_start[sq], cnt = sub_count[sq];
     const int end = start + cnt;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -642,9 +642,11 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             };
             // (scheduling barriers keep each set's reads ahead of the other
             // set's products)
+            // (four steps per loop iteration: the loop header's conservative
+            // LDS wait comes once per four steps)
             Ops opa, opb;
             load(opa);
-            for (int u = u0;; u += 8) {
+            for (int u = u0;; u += 16) {
                 load(opb);
                 __builtin_amdgcn_sched_barrier(0);
                 step(opa);
@@ -655,6 +657,16 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                 step(opb);
                 __builtin_amdgcn_sched_barrier(0);
                 if (u + 8 > u1) break;
+                load(opb);
+                __builtin_amdgcn_sched_barrier(0);
+                step(opa);
+                __builtin_amdgcn_sched_barrier(0);
+                if (u + 12 > u1) break;
+                load(opa);
+                __builtin_amdgcn_sched_barrier(0);
+                step(opb);
+                __builtin_amdgcn_sched_barrier(0);
+                if (u + 16 > u1) break;
             }
             if (flush && colok) {
                 // lane's cells: first tap (aslot - a0) mod TW, second tap
@@ -705,7 +717,7 @@ k_fold_bins(const WinDesc *__restrict__ wd, const int *__restrict__ fb, T *__res
 {
     __shared__ T part[4][64];
     const int wb = fb[blockIdx.y], r = blockIdx.z;
-    const int *bsp = wd[wb / nbins].bin_sub_ptr;
+    gmem<int> *bsp = (gmem<int> *)wd[wb / nbins].bin_sub_ptr;
     const int bin = wb % nbins;
     const int s0 = bsp[bin], s1 = bsp[bin + 1];
     if (s1 - s0 < 2) return;
@@ -763,7 +775,7 @@ k_fold(const WinDesc *__restrict__ wd, const T *__restrict__ tilebuf, int nrhs, 
     const int w = wr / nrhs, r = wr % nrhs;
     int rem = ci;
     const float inv_on = 1.0f / (float)on;
-    const int *bsp = wd[w].bin_sub_ptr;
+    gmem<int> *bsp = (gmem<int> *)wd[w].bin_sub_ptr;
     int l[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     int64_t cell = 0, cstride = 1;
     for (int q = D - 1; q >= 0; --q) {
@@ -849,7 +861,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     const int sq = xcd_item(blockIdx.x, gridDim.x);
     const int wi = sub_win[sq];
     const WinDesc &win = wd[wi];
-    const T *rec = reinterpret_cast<const T *>(win.rec);
+    gmem<T> *rec = (gmem<T> *)win.rec;
     const int start = sub_start[sq], cnt = sub_count[sq];
     // 3-D: only first-axis rows a0 .. a0 + rows - 1 of the padded tile are
     // staged (a0 in bits 24-31 of the tile index)
@@ -862,7 +874,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     // first dimension's weights are re-read inside its (rolled) loop so that
     // no register array is indexed by a loop variable
     bool mine[PT];
-    const T *rp[PT];
+    gmem<T> *rp[PT];
     T w[PT][D][TW];
     int lin[PT], f0[PT];
     int64_t orow[PT];
@@ -871,7 +883,7 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     // serves both); an unpaired slot repeats its point without an output
     int slot0 = 0;
     if constexpr (SLOT) {
-        slot0 = (int)threadIdx.x < cnt ? win.slots[start + (int)threadIdx.x] : 0;
+        slot0 = (int)threadIdx.x < cnt ? ((gmem<int> *)win.slots)[start + (int)threadIdx.x] : 0;
     }
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
@@ -889,10 +901,10 @@ k_interp(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
         for (int q = (D == 3 ? 1 : 0); q < D; ++q)
 #pragma unroll
             for (int a = 0; a < TW; ++a) w[p][q][a] = rp[p][q * TW + a];
-        const int lpj = win.lpos[j];
+        const int lpj = ((gmem<int> *)win.lpos)[j];
         lin[p] = (lpj & 0xfffff) - a0 * pd * pd * (D == 3);   // first tap inside the staged rows
         f0[p] = (lpj >> 20) & 0x7f;                         // first-dimension weights sit rotated by it
-        orow[p] = (int64_t)win.perm[j] * nrhs;
+        orow[p] = (int64_t)((gmem<int> *)win.perm)[j] * nrhs;
     }
     T *hout = hbuf + (int64_t)win.s_global * n * nrhs;
     T *dblk = DER ? dout + (int64_t)win.s_global * n * nrhs : nullptr;
@@ -1175,7 +1187,10 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     const int sq = xcd_item(blockIdx.x, gridDim.x);
     const int wi = sub_win[sq];
     const WinDesc &win = wd[wi];
-    const float *rec = reinterpret_cast<const float *>(win.rec);
+    gmem<float> *rec = (gmem<float> *)win.rec;
+    gmem<int> *blocks = (gmem<int> *)win.blocks;
+    gmem<int> *lposg = (gmem<int> *)win.lpos;
+    gmem<int> *permg = (gmem<int> *)win.perm;
     const int start = sub_start[sq], cnt = sub_count[sq];
     int org[3] = {0, 0, 0};
     const int bw = sub_bin[sq];
@@ -1183,13 +1198,19 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     bin_origin<3>(bw & 0xffffff, nb, tb, org);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // the subproblem's points [P0, P1): weights, output rows, block starts
-    const int P0 = win.blocks[start], P1 = win.blocks[start + cnt];
+    const int P0 = blocks[start], P1 = blocks[start + cnt];
     if (WLDS)
         for (int i = tid; i < (P1 - P0) * RS; i += NT) s_w[i] = rec[(int64_t)P0 * RS + i];
-    const float *wsrc = WLDS ? s_w : rec + (int64_t)P0 * RS;
-    for (int i = tid; i < P1 - P0; i += NT) s_row[i] = win.perm[P0 + i];
-    if (tid <= cnt) s_blk[tid] = win.blocks[start + tid] - P0;
-    if (tid < cnt) s_lp[tid] = win.lpos[win.blocks[start + tid]];
+    // weight idx of the subproblem's points (local point index x RS + slot)
+    auto wread = [&](int idx) -> float {
+        if constexpr (WLDS)
+            return s_w[idx];
+        else
+            return rec[(int64_t)P0 * RS + idx];
+    };
+    for (int i = tid; i < P1 - P0; i += NT) s_row[i] = permg[P0 + i];
+    if (tid <= cnt) s_blk[tid] = blocks[start + tid] - P0;
+    if (tid < cnt) s_lp[tid] = lposg[blocks[start + tid]];
     // staging: thread t takes cell t of the tile's (second, third) plane
     const bool qin = tid < pd2;
     int prel = 0;
@@ -1240,12 +1261,12 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             const int lin = (lp & 0xfffff) - a0s * pd2;   // first tap inside the staged rows
             const int frow = fdiv_small(lin, pd2, 1.0f / (float)pd2), rem = lin - frow * pd2;
             // A row li: point j0 + li (rows past the block: weight 0)
-            const float *rp = wsrc + (j0 + min(li, np - 1)) * RS;
+            const int rb = (j0 + min(li, np - 1)) * RS;
             float w1[TW], w2k[TW / 4];
 #pragma unroll
-            for (int t = 0; t < TW; ++t) w1[t] = rp[TW + t];
+            for (int t = 0; t < TW; ++t) w1[t] = wread(rb + TW + t);
 #pragma unroll
-            for (int t = 0; t < TW / 4; ++t) w2k[t] = li < np ? rp[2 * TW + 4 * t + kq] : 0.0f;
+            for (int t = 0; t < TW / 4; ++t) w2k[t] = li < np ? wread(rb + 2 * TW + 4 * t + kq) : 0.0f;
             const float *tb0 = tile + (frow + al) * ps + (rem + kq) * 4 + e;
             f4 acc[NBK];
 #pragma unroll
@@ -1280,10 +1301,10 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             float h[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float *rw = wsrc + (j0 + min(4 * kq + v, np - 1)) * RS;
+                const int wb = (j0 + min(4 * kq + v, np - 1)) * RS;
                 float sum = 0.0f;
 #pragma unroll
-                for (int c = 0; c < NBK; ++c) sum += rw[(L + 4 * c + al) % TW] * acc[c][v];
+                for (int c = 0; c < NBK; ++c) sum += wread(wb + (L + 4 * c + al) % TW) * acc[c][v];
                 sum += __shfl_xor(sum, 4);
                 sum += __shfl_xor(sum, 8);
                 h[v] = sum;
@@ -1334,7 +1355,7 @@ k_interp_vb(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     const int sq = xcd_item(blockIdx.x, gridDim.x);
     const int wi = sub_win[sq];
     const WinDesc &win = wd[wi];
-    const T *rec = reinterpret_cast<const T *>(win.rec);
+    gmem<T> *rec = (gmem<T> *)win.rec;
     const int start = sub_start[sq], cnt = sub_count[sq];
     int org[3] = {0, 0, 0};
     bin_origin<D>(sub_bin[sq] & 0xffffff, nb, tb, org);
@@ -1351,13 +1372,13 @@ k_interp_vb(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             const int k = pc0 + (int)threadIdx.x + 256 * p;
             mine[p] = k < cnt;
             const int64_t j = start + (mine[p] ? k : 0);
-            const T *rp = rec + j * RS;
+            gmem<T> *rp = rec + j * RS;
 #pragma unroll
             for (int q = 0; q < D; ++q)
 #pragma unroll
                 for (int a = 0; a < TW; ++a) w[p][q][a] = rp[q * TW + a];
-            lin[p] = win.lpos[j] & 0xfffff;
-            orow[p] = (int64_t)win.perm[j] * nrhs;
+            lin[p] = ((gmem<int> *)win.lpos)[j] & 0xfffff;
+            orow[p] = (int64_t)((gmem<int> *)win.perm)[j] * nrhs;
         }
     };
     const bool one_chunk = cnt <= 256 * PT;
@@ -1557,7 +1578,7 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     const int sblk = xcd_item(blockIdx.x, gridDim.x);
     const int wi = sub_win[sblk];
     const WinDesc &win = wd[wi];
-    const T *rec = reinterpret_cast<const T *>(win.rec);
+    gmem<T> *rec = (gmem<T> *)win.rec;
     const int start = sub_start[sblk], cnt = sub_count[sblk];
     const int end = start + cnt;
     // 3-D windows with 16 items past the last full group of 64 (m = 2, 6):
@@ -1592,8 +1613,8 @@ k_interp_run(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                 const int i = lane + 64 * k;
                 v[k] = i < nc * RS ? rec[(int64_t)cb * RS + i] : T(0);
             }
-            const int an = lane < nc ? win.anchor[cb + lane] & 0x7fffffff : 0;
-            const int pm = lane < nc ? win.perm[cb + lane] : 0;
+            const int an = lane < nc ? ((gmem<int> *)win.anchor)[cb + lane] & 0x7fffffff : 0;
+            const int pm = lane < nc ? ((gmem<int> *)win.perm)[cb + lane] : 0;
 #pragma unroll
             for (int k = 0; k < RS; ++k) s_rec[lane + 64 * k] = v[k];
             s_an[lane] = an;

@@ -16,6 +16,14 @@ __device__ __forceinline__ int fdiv_small(int i, int d, float inv_d)
     return q;
 }
 
+// Device arrays reached through pointers stored in a descriptor: the compiler
+// cannot tell such generic pointers from LDS ones, and loads through generic
+// pointers are FLAT instructions, which also count in the LDS wait counter, so
+// one global load in flight (a prefetch) turns every LDS wait into a full
+// wait.  Kernels read these arrays through global-address-space pointers.
+template <typename T>
+using gmem = const __attribute__((address_space(1))) T;
+
 // The dispatcher deals work-groups round-robin over the 8 XCDs (work-group b
 // runs on XCD b % 8), and each XCD has its own L2.  Work lists are ordered in
 // space (by tile), so giving every XCD one contiguous range of the list keeps
