@@ -546,7 +546,7 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     const int li = lane & 15, kq = lane >> 4;
     const int nb = wave % NB, bg = wave / NB;
     const int aslot_raw = nb * SPB + li / R, br = li % R;       // B column: first slot, vector
-    const bool colok = aslot_raw < TW;                          // columns past 2m slots pad a block
+    const bool colok = (TW * R) % 16 == 0 || aslot_raw < TW;    // columns past 2m slots pad a block
     const int aslot = colok ? aslot_raw : 0;
     const int bslot_a = 4 * bg + li / 4;                        // A row li: second slot
     const int bslot_f = 4 * bg + kq;                            // accumulator rows: second slot
@@ -555,47 +555,66 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
 #pragma unroll
     for (int k = 0; k < BPW; ++k) acc[k] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     const int nr = min(R, nrhs - r0);
-    // the global data of chunk c + 2 is loaded into registers while chunk c is
-    // processed (two register sets alternate)
+    // The global data of chunk c + 2 is loaded into registers while chunk c is
+    // processed (two register sets alternate), and the sorted-order index of
+    // the vector row a thread gathers for it is loaded one chunk earlier still,
+    // so no load waits on another load issued in the same chunk.  Every load is
+    // issued on every path, at an index clamped into the subproblem (values
+    // past its end are masked when staged): the number of loads in flight is
+    // then the same on all paths and each wait covers only the loads it needs.
     constexpr int NREC = (CH * RS + NT - 1) / NT, NV = (CH * R + NT - 1) / NT;
     struct Stage {
         float rec[NREC], v[NV];
         int lp;
     };
-    auto fetch = [&](Stage &g, int cb) {
-        const int nc = min(CH, end - cb);
+    // (chunk bases at or past the end read the subproblem's last point)
+    const int rc = min(tid % R, nr - 1) + r0;                   // vector column this thread gathers
+    auto prefetch_rows = [&](int (&pi)[NV], int cb) {
+        const int cx = min(cb, end - 1), last = end - 1 - cx;
+        gmem<int> *pb = perm + cx;
 #pragma unroll
-        for (int k = 0; k < NREC; ++k) {
-            const int i = tid + k * NT;
-            g.rec[k] = i < nc * RS ? rec[(int64_t)cb * RS + i] : 0.0f;
-        }
+        for (int k = 0; k < NV; ++k) pi[k] = pb[min(min((tid + k * NT) / R, CH - 1), last)];
+    };
+    auto fetch = [&](Stage &g, int cb, const int (&pi)[NV]) {
+        const int cx = min(cb, end - 1), last = end - 1 - cx;
+        gmem<float> *rb = rec + (int64_t)cx * RS;
+        const int rlast = (last + 1) * RS - 1;
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            const int i = tid + k * NT;
-            const int u = i / R, r = i % R;
-            g.v[k] = (i < nc * R && r < nr) ? V[(int64_t)perm[cb + u] * ldv + r0 + r] : 0.0f;
-        }
-        g.lp = tid < nc ? lpos[cb + tid] : 0;
+        for (int k = 0; k < NREC; ++k) g.rec[k] = rb[min(tid + k * NT, rlast)];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) g.v[k] = V[(int64_t)pi[k] * ldv + rc];
+        g.lp = lpos[cx + min(tid, last)];
     };
     Stage ga, gb;
-    if (cnt > 0) fetch(ga, start);
-    if (cnt > CH) fetch(gb, start + CH);
+    int pq[NV], pn[NV];
+    if (cnt > 0) {
+        // (issued in the loop's order: the index for chunk 2 before the
+        // fetch of chunk 1, so the wait counts at the loop header agree)
+        prefetch_rows(pn, start);
+        fetch(ga, start, pn);
+        prefetch_rows(pn, start + CH);
+        prefetch_rows(pq, start + 2 * CH);
+        fetch(gb, start + CH, pn);
+    }
     auto chunk = [&](int cb, Stage &g) {
-        const int nc = min(CH, end - cb);
+        const int nc = min(CH, end - cb);                      // <= 0 for the empty last chunk of an odd count
         __syncthreads();   // tiles cleared / previous chunk consumed
 #pragma unroll
         for (int k = 0; k < NREC; ++k) {
             const int i = tid + k * NT;
-            if (i < CH * RS) s_rec[i] = g.rec[k];
+            if (i < CH * RS) s_rec[i] = i < nc * RS ? g.rec[k] : 0.0f;
         }
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             const int i = tid + k * NT;
-            if (i < CH * R) s_v[i] = g.v[k];
+            if (i < CH * R) s_v[i] = (i < nc * R && i % R < nr) ? g.v[k] : 0.0f;
         }
-        if (tid < CH) s_lp[tid] = g.lp;
+        if (tid < CH) s_lp[tid] = tid < nc ? g.lp : 0;
         __syncthreads();
-        if (cb + 2 * CH < end) fetch(g, cb + 2 * CH);
+        prefetch_rows(pn, cb + 3 * CH);
+        fetch(g, cb + 2 * CH, pq);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) pq[k] = pn[k];
         const int my_lp = lane < nc ? s_lp[lane] : 0;
         const bool isend = lane < nc && (my_lp < 0 || cb + lane == end - 1);
         const unsigned long long ends = __ballot(isend);
@@ -610,7 +629,9 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             const int rem = base - a0 * pd2;
             const int b0 = fdiv_small(rem, pd, inv_pd), c0 = rem - b0 * pd;
             // second-dimension tap of the lane's A row (slot bslot_a)
-            const int ab = TW + ((bslot_a - b0) % TW + TW) % TW;
+            const int a0m = a0 % TW, b0m = b0 % TW;
+            const int abt = bslot_a - b0m;
+            const int ab = TW + (abt < 0 ? abt + TW : abt);
             // operands of step u: B = w0[slot] v[r], A = w1[b] w2[c] of the
             // lane's point u + kq, weight 0 past the run end (the reads there
             // hit later points of the chunk or the zero padding).  Two operand
@@ -618,62 +639,86 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             // step u's products run.
             struct Ops {
                 float w0, v, wb, wc[BPW];
-                bool ok;
             };
             const float *pr = s_rec + (u0 + kq) * RS;
             const float *pv = s_v + (u0 + kq) * R + br;
-            int pu = u0 + kq;
             auto load = [&](Ops &o) {
                 o.w0 = pr[aslot];
                 o.v = *pv;
                 o.wb = pr[ab];
 #pragma unroll
                 for (int k = 0; k < BPW; ++k) o.wc[k] = pr[ac + 4 * k];
-                o.ok = pu <= u1;
                 pr += 4 * RS;
                 pv += 4 * R;
-                pu += 4;
             };
-            auto step = [&](const Ops &o) {
-                const float bv = o.ok && colok ? o.w0 * o.v : 0.0f;
+            // lim = points of the step that belong to the run (4 but for a
+            // run's last step)
+            auto step = [&](const Ops &o, int lim) {
+                const float bv = colok && kq < lim ? o.w0 * o.v : 0.0f;
+#pragma unroll
+                for (int k = 0; k < BPW; ++k)
+                    acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.wb * o.wc[k], bv, acc[k], 0, 0, 0);
+            };
+            auto step_full = [&](const Ops &o) {
+                const float bv = colok ? o.w0 * o.v : 0.0f;
 #pragma unroll
                 for (int k = 0; k < BPW; ++k)
                     acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.wb * o.wc[k], bv, acc[k], 0, 0, 0);
             };
             // (scheduling barriers keep each set's reads ahead of the other
-            // set's products)
-            // (four steps per loop iteration: the loop header's conservative
-            // LDS wait comes once per four steps)
+            // set's products).  Whole groups of four full steps run in a loop
+            // with one exit and no masking; the last 0-3 full steps and the
+            // run's partial step follow it.
+            const int np = u1 - u0 + 1, nfull = np >> 2, tail = np & 3;
             Ops opa, opb;
             load(opa);
-            for (int u = u0;; u += 16) {
+            int st = 0;
+            for (; st + 4 <= nfull; st += 4) {
                 load(opb);
                 __builtin_amdgcn_sched_barrier(0);
-                step(opa);
+                step_full(opa);
                 __builtin_amdgcn_sched_barrier(0);
-                if (u + 4 > u1) break;
                 load(opa);
                 __builtin_amdgcn_sched_barrier(0);
-                step(opb);
+                step_full(opb);
                 __builtin_amdgcn_sched_barrier(0);
-                if (u + 8 > u1) break;
                 load(opb);
                 __builtin_amdgcn_sched_barrier(0);
-                step(opa);
+                step_full(opa);
                 __builtin_amdgcn_sched_barrier(0);
-                if (u + 12 > u1) break;
                 load(opa);
                 __builtin_amdgcn_sched_barrier(0);
-                step(opb);
+                step_full(opb);
                 __builtin_amdgcn_sched_barrier(0);
-                if (u + 16 > u1) break;
+            }
+            const int nrest = nfull - st + (tail > 0);         // 0..4 steps left
+            const int llim = tail > 0 ? tail : 4;
+            if (nrest > 0) {
+                if (nrest > 1) load(opb);
+                __builtin_amdgcn_sched_barrier(0);
+                step(opa, nrest == 1 ? llim : 4);
+                __builtin_amdgcn_sched_barrier(0);
+                if (nrest > 1) {
+                    if (nrest > 2) load(opa);
+                    __builtin_amdgcn_sched_barrier(0);
+                    step(opb, nrest == 2 ? llim : 4);
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (nrest > 2) {
+                        if (nrest > 3) load(opb);
+                        __builtin_amdgcn_sched_barrier(0);
+                        step(opa, nrest == 3 ? llim : 4);
+                        __builtin_amdgcn_sched_barrier(0);
+                        if (nrest > 3) step(opb, llim);
+                    }
+                }
             }
             if (flush && colok) {
                 // lane's cells: first tap (aslot - a0) mod TW, second tap
                 // (bslot_f - b0) mod TW, third taps 4 k + v; all reads first,
                 // then the writes
-                const int at = ((aslot - a0) % TW + TW) % TW;
-                const int bt = ((bslot_f - b0) % TW + TW) % TW;
+                const int at0 = aslot - a0m, bt0 = bslot_f - b0m;
+                const int at = at0 < 0 ? at0 + TW : at0;
+                const int bt = bt0 < 0 ? bt0 + TW : bt0;
                 float *tp = tiles + br * pad.sr + (a0 + at) * pad.sa + (b0 + bt) * pad.sb + c0;
                 float old[BPW][4];
 #pragma unroll
@@ -692,16 +737,34 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     };
     for (int cb = start; cb < end; cb += 2 * CH) {
         chunk(cb, ga);
-        if (cb + CH < end) chunk(cb + CH, gb);
+        chunk(cb + CH, gb);
     }
     __syncthreads();
-    for (int r = 0; r < nr; ++r) {
-        float *out = tilebuf + ((int64_t)sq * nrhs + r0 + r) * pc;
+    // cell i = (a, b, c) advances by NT per iteration: (a, b, c) and the padded
+    // offset are stepped with carries instead of divided out per cell
+    {
+        float *out = tilebuf + ((int64_t)sq * nrhs + r0) * pc;
+        const int da = NT / pd2, db = (NT - da * pd2) / pd, dc = NT - da * pd2 - db * pd;
+        const int a = fdiv_small(tid, pd2, 1.0f / (float)pd2), rm = tid - a * pd2;
+        int b = fdiv_small(rm, pd, inv_pd), c = rm - b * pd;
+        int off = a * pad.sa + b * pad.sb + c;
+        const int doff = da * pad.sa + db * pad.sb + dc;
         for (int i = tid; i < pc; i += NT) {
-            const int a = fdiv_small(i, pd2, 1.0f / (float)pd2);
-            const int rm = i - a * pd2;
-            const int b = fdiv_small(rm, pd, inv_pd), c = rm - b * pd;
-            out[i] = tiles[r * pad.sr + a * pad.sa + b * pad.sb + c];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (r < nr) out[(int64_t)r * pc + i] = tiles[r * pad.sr + off];
+            off += doff;
+            c += dc;
+            b += db;
+            if (c >= pd) {
+                c -= pd;
+                ++b;
+                off += pad.sb - pd;
+            }
+            if (b >= pd) {
+                b -= pd;
+                off += pad.sa - pd * pad.sb;
+            }
         }
     }
 }
