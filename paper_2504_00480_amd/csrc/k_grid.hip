@@ -653,17 +653,25 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             };
             // lim = points of the step that belong to the run (4 but for a
             // run's last step)
+            // (a step's operand products are formed before its matrix
+            // products issue, so no product waits on the vector unit)
             auto step = [&](const Ops &o, int lim) {
                 const float bv = colok && kq < lim ? o.w0 * o.v : 0.0f;
+                float av[BPW];
 #pragma unroll
-                for (int k = 0; k < BPW; ++k)
-                    acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.wb * o.wc[k], bv, acc[k], 0, 0, 0);
+                for (int k = 0; k < BPW; ++k) av[k] = o.wb * o.wc[k];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k < BPW; ++k) acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[k], bv, acc[k], 0, 0, 0);
             };
             auto step_full = [&](const Ops &o) {
                 const float bv = colok ? o.w0 * o.v : 0.0f;
+                float av[BPW];
 #pragma unroll
-                for (int k = 0; k < BPW; ++k)
-                    acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.wb * o.wc[k], bv, acc[k], 0, 0, 0);
+                for (int k = 0; k < BPW; ++k) av[k] = o.wb * o.wc[k];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k < BPW; ++k) acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[k], bv, acc[k], 0, 0, 0);
             };
             // (scheduling barriers keep each set's reads ahead of the other
             // set's products).  Whole groups of four full steps run in a loop
