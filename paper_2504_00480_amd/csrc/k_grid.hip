@@ -654,15 +654,18 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             // lim = points of the step that belong to the run (4 but for a
             // run's last step)
             // (a step's operand products are formed before its matrix
-            // products issue, so no product waits on the vector unit)
+            // products issue, so no product waits on the vector unit; the
+            // products issue at raised wave priority)
             auto step = [&](const Ops &o, int lim) {
                 const float bv = colok && kq < lim ? o.w0 * o.v : 0.0f;
                 float av[BPW];
 #pragma unroll
                 for (int k = 0; k < BPW; ++k) av[k] = o.wb * o.wc[k];
                 __builtin_amdgcn_sched_barrier(0);
+                __builtin_amdgcn_s_setprio(1);
 #pragma unroll
                 for (int k = 0; k < BPW; ++k) acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[k], bv, acc[k], 0, 0, 0);
+                __builtin_amdgcn_s_setprio(0);
             };
             auto step_full = [&](const Ops &o) {
                 const float bv = colok ? o.w0 * o.v : 0.0f;
@@ -670,8 +673,10 @@ k_spread_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
 #pragma unroll
                 for (int k = 0; k < BPW; ++k) av[k] = o.wb * o.wc[k];
                 __builtin_amdgcn_sched_barrier(0);
+                __builtin_amdgcn_s_setprio(1);
 #pragma unroll
                 for (int k = 0; k < BPW; ++k) acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[k], bv, acc[k], 0, 0, 0);
+                __builtin_amdgcn_s_setprio(0);
             };
             // (scheduling barriers keep each set's reads ahead of the other
             // set's products).  Whole groups of four full steps run in a loop
@@ -1358,6 +1363,9 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             for (int b = 0; b < TW; ++b) {
                 if (b + 1 < TW) load_row(bv[(b + 1) & 1], b + 1);
                 __builtin_amdgcn_sched_barrier(0);
+                // (waves issuing matrix products run at raised priority, so
+                // they are picked before waves that are staging)
+                __builtin_amdgcn_s_setprio(1);
 #pragma unroll
                 for (int t = 0; t < SPR; ++t) {
                     const float av = w1[b] * w2k[t];
@@ -1365,6 +1373,7 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                     for (int c = 0; c < NBK; ++c)
                         acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[b & 1][t][c], acc[c], 0, 0, 0);
                 }
+                __builtin_amdgcn_s_setprio(0);
                 __builtin_amdgcn_sched_barrier(0);
             }
             // first dimension: lane (al, e, kq) holds X[4 kq + v][(4 c + al, e)]
