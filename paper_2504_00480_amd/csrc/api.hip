@@ -275,7 +275,7 @@ nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt, int rows, b
     // 3-D FP32 matrix-core blocks: the lists count blocks
     blk = blk && g.d == 3 && plan->n > 0 && plan->prec == NFFTGP_F32 && (m == 4 || m == 6);
     slot = slot && !blk && g.d == 3 && plan->n > 0;
-    const int isp_s = blk ? kInterpSubBlocks : (slot ? kInterpSubPoints : isp);
+    const int isp_s = blk ? G.interp_sub_blocks : (slot ? kInterpSubPoints : isp);
     if (rows < 2 * m || rows > g.pd) return fail(NFFTGP_E_ARG, "bad interpolation row count");
     std::vector<int> iw, ib, is, ic;
     auto push = [&](int wl, int b, int start, int cnt, int f0) {
@@ -628,7 +628,7 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
                 if (d3 && !w.h_block_start.empty()) {
                     // the block lists (at most kInterpSubBlocks blocks per subproblem) may be longer
                     const int nbl = w.h_block_start[b + 1] - w.h_block_start[b];
-                    icap += (nbl + kInterpSubBlocks - 1) / kInterpSubBlocks;
+                    icap += (nbl + kInterpSubBlocksLds - 1) / kInterpSubBlocksLds;
                 }
             }
             TRYS(dalloc(plan, (void **)&w.bin_sub_ptr, (w.g.nbins + 1) * sizeof(int)));
@@ -721,6 +721,15 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
         G.spread_mfma_R = smr && std::strcmp(smr, "2") == 0 ? 2 : 4;
         const char *imw = std::getenv("NFFTGP_INTERP_MFMA_WAVES");   // "8" | "16"
         G.interp_mfma_waves = imw && std::strcmp(imw, "16") == 0 ? 16 : 8;
+        // blocks per subproblem (NFFTGP_INTERP_SUB_BLOCKS, default the
+        // kernel form's maximum): more blocks share one staging of the tile
+        // rows per vector pass; measured at C5 (n = 2e6, m = 6, 16 vectors),
+        // 3-D interpolation per launch: 16 blocks 10.20 ms, 32 blocks 9.71 ms
+        {
+            const char *isb = std::getenv("NFFTGP_INTERP_SUB_BLOCKS");
+            const int cap = G.interp_mfma_waves == 16 ? kInterpSubBlocksLds : kInterpSubBlocks;
+            G.interp_sub_blocks = isb ? std::max(1, std::min(cap, std::atoi(isb))) : cap;
+        }
         G.interp_adj = pair && G.g.d == 3;
         // matrix-core blocks stage NFFTGP_INTERP_MFMA_ROWS first-axis rows
         // (default: the rule's window)

@@ -1248,14 +1248,15 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     constexpr int KS = TW * TW / 4;             // reduction steps over (b, c)
     constexpr int VPS = DER ? 2 : 4;            // vectors per staging
     constexpr int NT = 64 * NWV;
-    constexpr int MAXP = 16 * kInterpSubBlocks;
+    constexpr int MB = WLDS ? kInterpSubBlocksLds : kInterpSubBlocks;   // blocks per subproblem, at most
+    constexpr int MAXP = 16 * MB;
     // the points' weights: copied to LDS once per subproblem (WLDS), or read
     // from the weight record (L2) per block and pass, which leaves the LDS to
     // two work-groups per CU
     __shared__ float s_w[WLDS ? MAXP * RS : 1];
     __shared__ int s_row[MAXP];
-    __shared__ int s_blk[kInterpSubBlocks + 1];
-    __shared__ int s_lp[kInterpSubBlocks];
+    __shared__ int s_blk[MB + 1];
+    __shared__ int s_lp[MB];
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float *tile = reinterpret_cast<float *>(smem_raw);
     const int pd = tb + 2 * M, pd2 = pd * pd;

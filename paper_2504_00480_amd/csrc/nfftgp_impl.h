@@ -23,8 +23,11 @@ inline double kb_beta() { return kPi * (2.0 - 1.0 / kSigma); }
 
 // Points handled by one interpolation work-group at most (one per thread).
 constexpr int kInterpSubPoints = 256;
-// 3-D matrix-core interpolation: blocks (at most 16 points of one cell) per subproblem
-constexpr int kInterpSubBlocks = 16;
+// 3-D matrix-core interpolation: blocks (at most 16 points of one cell) per
+// subproblem, at most (the kernel form that keeps the points' weights in LDS
+// takes at most kInterpSubBlocksLds)
+constexpr int kInterpSubBlocks = 32;
+constexpr int kInterpSubBlocksLds = 16;
 // d <= 2 several-vector interpolation: points per subproblem by rule
 constexpr int kInterpVbSubPoints = 2048;
 // Points per wave in run-based interpolation.
@@ -133,6 +136,7 @@ struct Group {
     bool interp_adj = false;     // 3-D, 2 points per thread: adjacent sorted points share tap reads
     bool interp_slot = false;    // 3-D: one slot per thread (two points of one cell share every tap read)
     bool interp_mfma = false;    // 3-D FP32: blocks of one cell on matrix cores (lists count blocks)
+    int interp_sub_blocks = kInterpSubBlocksLds;   // blocks per matrix-core interpolation subproblem
     int interp_mfma_waves = 8;   // waves per work-group of the matrix-core interpolation (8: weights
                                  // read from L2, two work-groups per CU; 16: weights in LDS)
     int interp_vb_lds = 80 << 10;   // d <= 2: LDS bytes for several vectors per staging (0: one vector)
