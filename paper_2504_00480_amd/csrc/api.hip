@@ -719,6 +719,8 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
                              : (G.g.d == 3 && prec == NFFTGP_F32 && (m == 4 || m == 6) && max_nrhs >= 2);
         const char *smr = std::getenv("NFFTGP_SPREAD_MFMA_R");   // "2" | "4"
         G.spread_mfma_R = smr && std::strcmp(smr, "2") == 0 ? 2 : 4;
+        const char *ffm = std::getenv("NFFTGP_FOLD");   // "cells" | "tiles"
+        G.fold_form = ffm ? (std::strcmp(ffm, "tiles") == 0 ? 2 : (std::strcmp(ffm, "cells") == 0 ? 1 : 0)) : 0;
         const char *imw = std::getenv("NFFTGP_INTERP_MFMA_WAVES");   // "8" | "16"
         G.interp_mfma_waves = imw && std::strcmp(imw, "16") == 0 ? 16 : 8;
         // blocks per subproblem (NFFTGP_INTERP_SUB_BLOCKS, default the

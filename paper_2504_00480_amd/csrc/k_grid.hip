@@ -2112,6 +2112,91 @@ hipError_t interp_t(const Group &G, int m, int64_t n, int nrhs, const void *grid
     }
 }
 
+// 3-D fold by tiles: work-group (tile of the occupied box, window and
+// vector) reads the first subproblem of the 27 tiles around its tile once,
+// then each cell of the tile sums the covering tiles' values (a cell of tile
+// b is covered by tiles b - 1, b, b + 1 per axis at most, since m <= tb), in
+// increasing tile order as k_fold does, so the sums agree bit for bit.
+// Cells outside the occupied box are not written, as in k_fold.  Rows
+// blockIdx.y >= nwr: the group's separable coefficients, as in k_fold.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fold_tiles(const WinDesc *__restrict__ wd, const T *__restrict__ tilebuf, int nrhs, int tb, int nb,
+             int ng, int m, int pd, int pc, int64_t cells, int olo, int on, int t0, int nt,
+             typename Cplx<T>::type *__restrict__ grid, int nwr, int coef_blocks, int coef_nper, int cd,
+             int cN, CoefParams prm, const double *__restrict__ cinv2, const double *__restrict__ cw,
+             double *__restrict__ cpart)
+{
+    if ((int)blockIdx.y >= nwr) {
+        __shared__ double lds[4 * kCoefMaxH + 256];
+        const int cb = ((int)blockIdx.y - nwr) * (int)gridDim.x + (int)blockIdx.x;
+        if (cb >= coef_blocks) return;
+        const int blk = cb % coef_nper, aw = cb / coef_nper;
+        coef_sep_block<T>(cd, cN, prm, cinv2, cw, wd, cpart, blk, coef_nper, aw % 2, aw / 2, lds);
+        return;
+    }
+    __shared__ int s_first[27];
+    const int wr = blockIdx.y;
+    const int w = wr / nrhs, r = wr % nrhs;
+    const int ti = xcd_item(blockIdx.x, gridDim.x);
+    const int b0 = t0 + ti / (nt * nt), b1 = t0 + (ti / nt) % nt, b2 = t0 + ti % nt;
+    if (threadIdx.x < 27) {
+        const int c0 = b0 + (int)threadIdx.x / 9 - 1, c1 = b1 + ((int)threadIdx.x / 3) % 3 - 1,
+                  c2 = b2 + (int)threadIdx.x % 3 - 1;
+        int s0 = -1;
+        if (c0 >= 0 && c0 < nb && c1 >= 0 && c1 < nb && c2 >= 0 && c2 < nb) {
+            gmem<int> *bsp = (gmem<int> *)wd[w].bin_sub_ptr;
+            const int bin = (c0 * nb + c1) * nb + c2;
+            if (bsp[bin + 1] > bsp[bin]) s0 = bsp[bin];
+        }
+        s_first[threadIdx.x] = s0;
+    }
+    __syncthreads();
+    const int sh = __ffs(tb) - 1;   // tb is a power of two
+    const T *tr = tilebuf + (int64_t)r * pc;
+    for (int q = threadIdx.x; q < tb * tb * tb; q += 256) {
+        const int x = q >> (2 * sh), y = (q >> sh) & (tb - 1), z = q & (tb - 1);
+        const int l0 = b0 * tb + x, l1 = b1 * tb + y, l2 = b2 * tb + z;
+        if (l0 < olo || l0 >= olo + on || l1 < olo || l1 >= olo + on || l2 < olo || l2 >= olo + on) continue;
+        T sum = T(0);
+#pragma unroll
+        for (int u0 = 0; u0 < 3; ++u0) {
+            const int i0 = x - (u0 - 1) * tb + m;
+            if (i0 < 0 || i0 >= pd) continue;
+#pragma unroll
+            for (int u1 = 0; u1 < 3; ++u1) {
+                const int i1 = y - (u1 - 1) * tb + m;
+                if (i1 < 0 || i1 >= pd) continue;
+#pragma unroll
+                for (int u2 = 0; u2 < 3; ++u2) {
+                    const int i2 = z - (u2 - 1) * tb + m;
+                    const int s0 = s_first[(u0 * 3 + u1) * 3 + u2];
+                    if (i2 < 0 || i2 >= pd || s0 < 0) continue;
+                    sum += tr[(int64_t)s0 * nrhs * pc + (i0 * pd + i1) * pd + i2];
+                }
+            }
+        }
+        typename Cplx<T>::type o;
+        o.x = sum;
+        o.y = T(0);
+        grid[(int64_t)wr * cells + ((int64_t)l0 * ng + l1) * ng + l2] = o;
+    }
+}
+
+// 3-D fold by tiles of the occupied box (k_fold_tiles) when cells have up to
+// 27 covering tiles (m > tb / 2) and there are many window-vector rows; per
+// cell (k_fold) otherwise: at m = 4 every cell has 8 covering tiles and the
+// per-cell form's longer contiguous runs win.  Fold per launch, tiles vs
+// cells: n = 2e6, m = 6, 6 windows x 16 vectors 0.73 vs 0.89 ms; n = 5e5,
+// m = 4, 32 vectors 68 vs 57 us; n = 1e5, m = 4, 3 windows x 1 vector 21 vs
+// 17 us.  G.fold_form 1 / 2 forces cells / tiles.
+bool fold_by_tiles(const Group &G, int m, int nrhs)
+{
+    if (G.g.d != 3) return false;
+    if (G.fold_form != 0) return G.fold_form == 2;
+    return 2 * m > G.g.tb && G.nwin * nrhs >= 32;
+}
+
 template <typename T>
 hipError_t fold_t(const Group &G, int m, int nrhs, void *tilebuf, void *grid, bool with_coef, hipStream_t s)
 {
@@ -2138,10 +2223,19 @@ hipError_t fold_t(const Group &G, int m, int nrhs, void *tilebuf, void *grid, bo
     k_fold<T, DD><<<fgrid, 256, 0, s>>>(G.desc, (const T *)tilebuf, nrhs, g.tb, g.nb, g.ng, m, g.pd, \
                                         g.pc, g.cells, olo, on, (int)ocells, (C *)grid, nwr,      \
                                         coef_blocks, nper, g.d, g.N, G.prm, G.cinv2, G.cw, G.coef_part);
-    switch (g.d) {
+    switch (fold_by_tiles(G, m, nrhs) ? 4 : g.d) {
     case 1: NFFTGP_FOLD(1) break;
     case 2: NFFTGP_FOLD(2) break;
     case 3: NFFTGP_FOLD(3) break;
+    case 4: {
+        const int t0 = olo / g.tb, nt = (olo + on - 1) / g.tb - t0 + 1;
+        const int tx = nt * nt * nt;
+        const dim3 tgrid((unsigned)tx, (unsigned)(nwr + (coef_blocks + tx - 1) / tx));
+        k_fold_tiles<T><<<tgrid, 256, 0, s>>>(G.desc, (const T *)tilebuf, nrhs, g.tb, g.nb, g.ng, m, g.pd, g.pc,
+                                              g.cells, olo, on, t0, nt, (C *)grid, nwr, coef_blocks, nper, g.d,
+                                              g.N, G.prm, G.cinv2, G.cw, G.coef_part);
+        break;
+    }
     default: return hipErrorInvalidValue;
     }
 #undef NFFTGP_FOLD
@@ -2214,7 +2308,7 @@ std::string describe_group(int prec, const Group &G, int m, int nrhs)
         ip += ", " + std::to_string(G.interp_rows) + " of " + std::to_string(G.g.pd) + " rows staged";
     return "group d=" + std::to_string(G.g.d) + " N=" + std::to_string(G.g.N) + " windows=" +
            std::to_string(G.nwin) + ": spread=" + sp + "; subproblem " + std::to_string(G.sub_sp) +
-           " points; interp=" + ip + "\n";
+           " points; interp=" + ip + "; fold=" + (fold_by_tiles(G, m, nrhs) ? "tiles" : "cells") + "\n";
 }
 
 hipError_t launch_assemble(int prec, int64_t n, int nrhs, int P, const void *V, int64_t ldv,

@@ -137,6 +137,7 @@ struct Group {
     bool interp_slot = false;    // 3-D: one slot per thread (two points of one cell share every tap read)
     bool interp_mfma = false;    // 3-D FP32: blocks of one cell on matrix cores (lists count blocks)
     int interp_sub_blocks = kInterpSubBlocksLds;   // blocks per matrix-core interpolation subproblem
+    int fold_form = 0;           // 3-D fold: 0 by rule, 1 per cell, 2 by tiles
     int interp_mfma_waves = 8;   // waves per work-group of the matrix-core interpolation (8: weights
                                  // read from L2, two work-groups per CU; 16: weights in LDS)
     int interp_vb_lds = 80 << 10;   // d <= 2: LDS bytes for several vectors per staging (0: one vector)

@@ -395,3 +395,25 @@ def test_matrix_core_forms_parity(orc, m, monkeypatch):
         assert "spread=mfma" not in plan.describe(1)
     o1 = plan.apply(torch.tensor(w.V[:, :1], dtype=torch.float32, device="cuda:0"), derivs=False)
     assert _rel(o1["KV"].double().cpu().numpy(), ref["KV"][:, :1]) <= tol
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("m", [4, 6])
+def test_fold_by_tiles_parity(orc, m, prec, monkeypatch):
+    """The 3-D fold by tiles of the occupied box (forced here; the rule takes it
+    at m = 6 with many window-vector rows) against the oracle: clustered points
+    (tiles with several subproblems, so the per-tile sums run first), two 3-D
+    windows of different bandwidth and a 2-D window beside them."""
+    monkeypatch.setenv("NFFTGP_FOLD", "tiles")
+    w = workloads.small(29 + m, 6000, [3, 3, 2], [0, 1, 0], [0.5, 0.7, 0.4], [32, 16, 32], m, 3,
+                        dist="cluster")
+    plan, got, ref, r, pb = _run(orc, w, prec)
+    forms = plan.describe(3).splitlines()
+    print("  " + "\n  ".join(forms), flush=True)
+    assert all("fold=tiles" in ln for ln in forms if ln.startswith("group d=3 "))
+    assert all("fold=cells" in ln for ln in forms if ln.startswith("group d=2 "))
+    tol = _tol(prec, m)
+    e_k = _rel(got["KV"][r], ref["KV"])
+    e_d = max(_rel(got["dKV_dell"][s][r], ref["dKV_dell"][s]) for s in range(pb.P))
+    print(f"  m={m} {prec}: rel err KV {e_k:.2e}  dKV/dell {e_d:.2e}", flush=True)
+    assert e_k <= tol and e_d <= tol
+
