@@ -1302,7 +1302,7 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     const int al = li >> 2, e = li & 3;         // B / accumulator column: first-dimension tap, value
     for (int r0 = 0; r0 < nrhs; r0 += VPS) {
         __syncthreads();   // weights staged / previous pass consumed
-        constexpr int SA = 8;
+        constexpr int SA = 12;
         for (int ab = 0; ab < rows; ab += SA) {
             f4 v4[SA];
 #pragma unroll
