@@ -1344,6 +1344,18 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
             for (int t = 0; t < TW; ++t) w1[t] = wread(rb + TW + t);
 #pragma unroll
             for (int t = 0; t < TW / 4; ++t) w2k[t] = li < np ? wread(rb + 2 * TW + 4 * t + kq) : 0.0f;
+            // first-dimension weights of the epilogue, loaded now so that their
+            // latency overlaps the products: lane (al, e, kq) weights its
+            // accumulator element v of block c with w0 of point 4 kq + v at
+            // tap 4 c + al (slot (L + 4 c + al) mod TW of the rotated record)
+            const int L = (lp >> 20) & 0x7f;
+            float w0e[4][NBK];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int wb = (j0 + min(4 * kq + v, np - 1)) * RS;
+#pragma unroll
+                for (int c = 0; c < NBK; ++c) w0e[v][c] = wread(wb + (L + 4 * c + al) % TW);
+            }
             const float *tb0 = tile + (frow + al) * ps + (rem + kq) * 4 + e;
             f4 acc[NBK];
 #pragma unroll
@@ -1378,14 +1390,12 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
                 __builtin_amdgcn_sched_barrier(0);
             }
             // first dimension: lane (al, e, kq) holds X[4 kq + v][(4 c + al, e)]
-            const int L = (lp >> 20) & 0x7f;
             float h[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int wb = (j0 + min(4 * kq + v, np - 1)) * RS;
                 float sum = 0.0f;
 #pragma unroll
-                for (int c = 0; c < NBK; ++c) sum += wread(wb + (L + 4 * c + al) % TW) * acc[c][v];
+                for (int c = 0; c < NBK; ++c) sum += w0e[v][c] * acc[c][v];
                 sum += __shfl_xor(sum, 4);
                 sum += __shfl_xor(sum, 8);
                 h[v] = sum;
