@@ -128,6 +128,37 @@ def test_deterministic(orc):
         assert torch.equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("dist", ["normal", "cluster"])
+def test_deterministic_matrix_core(orc, dist):
+    """Matrix-core spreading and interpolation (a 3-D window at m = 6 with 64
+    vectors: sixteen four-vector groups over 128-point subproblems with many
+    short runs, beside a 2-D window) give bit-identical outputs on repeated
+    applies and match the oracle. The spreading adds runs to its LDS tile
+    without barriers, each wave owning fixed cells; a flush race between waves
+    would show here as run-to-run differences."""
+    from paper_2504_00480_amd import AdditiveKernelPlan
+    w = workloads.small(51, 1500, [2, 3], [0, 1], [0.5, 0.9], [32, 16], 6, 64, dist=dist)
+    X = torch.tensor(w.X, dtype=torch.float32, device="cuda:0")
+    V = torch.tensor(w.V, dtype=torch.float32, device="cuda:0")
+    plan = AdditiveKernelPlan(X, w.windows, w.ktype, w.N, w.m, max_nrhs=64)
+    d3 = [ln for ln in plan.describe(64).splitlines() if ln.startswith("group d=3 ")]
+    assert d3 and "spread=mfma" in d3[0] and "interp=mfma" in d3[0], d3
+    plan.set_hyper(1.0, w.ell, 0.1)
+    outs = []
+    for _ in range(3):
+        o = plan.apply(V, derivs=True)
+        torch.cuda.synchronize()
+        outs.append({k: v.clone() for k, v in o.items()})
+    for o in outs[1:]:
+        for k in o:
+            assert torch.equal(o[k], outs[0][k]), k
+    pb = orc.Problem(w.X, w.windows, w.ktype, w.ell, 1.0, 0.1, w.N)
+    ref = orc.rf_apply(pb, w.V, derivs=False)
+    e = _rel(outs[0]["KV"].double().cpu().numpy(), ref["KV"])
+    print(f"  {dist}: rel err KV {e:.2e}", flush=True)
+    assert e <= _tol("f32", 6)
+
+
 def test_derivative_matches_finite_difference(orc):
     """dKhat/d ell V equals the central difference of Khat V in ell (eq. exact_derivative)."""
     from paper_2504_00480_amd import AdditiveKernelPlan
