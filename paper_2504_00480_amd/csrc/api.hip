@@ -272,8 +272,8 @@ nfftgp_status build_interp_lists(nfftgp_plan plan, Group &G, int pt, int rows, b
     const bool cut = g.d == 3 && rows < g.pd;
     if (g.d != 3) rows = g.pd;
     // 3-D slots: the lists count slots (one or two points of one cell), one per thread;
-    // 3-D FP32 matrix-core blocks: the lists count blocks
-    blk = blk && g.d == 3 && plan->n > 0 && plan->prec == NFFTGP_F32 && (m == 4 || m == 6);
+    // 3-D and 2-D FP32 matrix-core blocks: the lists count blocks
+    blk = blk && (g.d == 3 || g.d == 2) && plan->n > 0 && plan->prec == NFFTGP_F32 && (m == 4 || m == 6);
     slot = slot && !blk && g.d == 3 && plan->n > 0;
     const int isp_s = blk ? G.interp_sub_blocks : (slot ? kInterpSubPoints : isp);
     if (rows < 2 * m || rows > g.pd) return fail(NFFTGP_E_ARG, "bad interpolation row count");
@@ -530,7 +530,7 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
                                 hipMemcpyDeviceToHost, st));
         }
         std::vector<int> hanchor;
-        if (d == 3 && n > 0) {
+        if ((d == 3 || d == 2) && n > 0) {
             hanchor.resize(n);
             TRYH(hipMemcpyAsync(hanchor.data(), w.anchor, n * sizeof(int), hipMemcpyDeviceToHost, st));
         }
@@ -542,7 +542,9 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
                                           ": a scaled point lies outside [-1/4, 1/4)^d");
         }
         w.h_bin_start = bs;
-        if (d == 3 && n > 0) {
+        if ((d == 3 || d == 2) && n > 0) {
+            const int ng = w.g.ng, tb = w.g.tb;
+            if (d == 3) {
             // interpolation slots: consecutive points of a run of equal cells
             // are paired (a run never crosses a tile); slots per tile and per
             // (tile, first-axis cell row) for the work lists
@@ -550,7 +552,6 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
             sl.reserve(n);
             w.h_slot_start.assign(w.g.nbins + 1, 0);
             w.h_row_slots.assign((size_t)w.g.nbins * w.g.tb, 0);
-            const int ng = w.g.ng, tb = w.g.tb;
             for (int b = 0; b < w.g.nbins; ++b) {
                 w.h_slot_start[b] = (int)sl.size();
                 for (int j = bs[b]; j < bs[b + 1];) {
@@ -565,8 +566,10 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
             w.h_slot_start[w.g.nbins] = (int)sl.size();
             TRYS(dalloc(plan, (void **)&w.slots, sl.size() * sizeof(int)));
             TRYH(hipMemcpy(w.slots, sl.data(), sl.size() * sizeof(int), hipMemcpyHostToDevice));
-            // matrix-core interpolation blocks: each run of equal cells cut
-            // into pieces of at most 16 points; block starts, then n
+            }
+            // matrix-core interpolation blocks (3-D and 2-D windows): each run
+            // of equal cells cut into pieces of at most 16 points; block
+            // starts, then n (the per-row counts serve the 3-D lists)
             std::vector<int> bl;
             bl.reserve(n / 8 + 1);
             w.h_block_start.assign(w.g.nbins + 1, 0);
@@ -579,7 +582,7 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
                     const int a = hanchor[j] & 0x7fffffff;
                     for (int k = j; k <= e; k += 16) {
                         bl.push_back(k);
-                        w.h_row_blocks[(size_t)b * tb + (a / (ng * ng)) % tb] += 1;
+                        if (d == 3) w.h_row_blocks[(size_t)b * tb + (a / (ng * ng)) % tb] += 1;
                     }
                     j = e + 1;
                 }
@@ -625,7 +628,7 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
                 G.nbins_used += cnt > 0;
                 cap += (cnt + kMinSubSp - 1) / kMinSubSp;
                 icap += (cnt + kInterpSubPoints - 1) / kInterpSubPoints + (d3 && cnt > 0 ? G.g.tb : 0);
-                if (d3 && !w.h_block_start.empty()) {
+                if (!w.h_block_start.empty()) {
                     // the block lists (at most kInterpSubBlocks blocks per subproblem) may be longer
                     const int nbl = w.h_block_start[b + 1] - w.h_block_start[b];
                     icap += (nbl + kInterpSubBlocksLds - 1) / kInterpSubBlocksLds;

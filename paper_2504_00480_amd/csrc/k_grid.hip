@@ -1415,6 +1415,156 @@ k_interp_mfma(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
     }
 }
 
+// 2-D FP32 interpolation on matrix cores: the 3-D kernel's block contraction
+// with one reduction dimension.  A block of at most 16 points of one cell
+// reads the same taps, so X[p, (a, e)] = sum_b w1_p[b] G_e[a0 + a, b0 + b] is
+// a product of the points' second-dimension weights (rows = points, the
+// reduction over b four taps per v_mfma_f32_16x16x4_f32 step) and the staged
+// tile (columns = four first-dimension taps times the four values e staged
+// per cell: K and dK of two vectors, or K of four); the epilogue weights the
+// columns with w0_p[a] and sums four lanes, as in 3-D.  A work-group of four
+// waves takes a subproblem of blocks of one tile and stages the whole padded
+// tile per pass (row stride = 8 modulo 32 words: the lanes of a half-wave
+// read distinct banks).  The 2-D weight record is not rotated.
+template <int M, bool DER>
+__global__ void __launch_bounds__(256)
+k_interp_mfma2(const WinDesc *__restrict__ wd, const int *__restrict__ sub_win,
+               const int *__restrict__ sub_bin, const int *__restrict__ sub_start,
+               const int *__restrict__ sub_count, int tb, int nb, int ng,
+               const float2 *__restrict__ grid, int64_t cells, int nrhs, int64_t n,
+               float *__restrict__ hbuf, float *__restrict__ dout, float dscale)
+{
+    using f4 = __attribute__((ext_vector_type(4))) float;
+    constexpr int TW = 2 * M, RS = 2 * TW;
+    constexpr int NBK = TW / 4;                 // column blocks (four first-dimension taps each)
+    constexpr int KS = TW / 4;                  // reduction steps over b
+    constexpr int NV = kInterp2Values;          // values staged per cell and pass
+    constexpr int NG = NV / 4;                  // value groups of four (one MFMA column set each)
+    constexpr int VPS = DER ? NV / 2 : NV;      // vectors per pass
+    constexpr int CS = NV + 4;                  // cell stride (words): adjacent cells on other banks
+    constexpr int NWV = 4, NT = 64 * NWV;
+    constexpr int MB = kInterpSubBlocks, MAXP = 16 * MB;
+    __shared__ int s_row[MAXP];
+    __shared__ int s_blk[MB + 1];
+    __shared__ int s_lp[MB];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float *tile = reinterpret_cast<float *>(smem_raw);
+    const int pd = tb + 2 * M;
+    const int rstr = pd * CS + ((8 - pd * CS) % 32 + 32) % 32;   // row stride (words)
+    const int sq = xcd_item(blockIdx.x, gridDim.x);
+    const int wi = sub_win[sq];
+    const WinDesc &win = wd[wi];
+    gmem<float> *rec = (gmem<float> *)win.rec;
+    gmem<int> *blocks = (gmem<int> *)win.blocks;
+    gmem<int> *lposg = (gmem<int> *)win.lpos;
+    gmem<int> *permg = (gmem<int> *)win.perm;
+    const int start = sub_start[sq], cnt = sub_count[sq];
+    int org[3] = {0, 0, 0};
+    bin_origin<2>(sub_bin[sq] & 0xffffff, nb, tb, org);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int P0 = blocks[start], P1 = blocks[start + cnt];
+    for (int i = tid; i < P1 - P0; i += NT) s_row[i] = permg[P0 + i];
+    if (tid <= cnt) s_blk[tid] = blocks[start + tid] - P0;
+    if (tid < cnt) s_lp[tid] = lposg[blocks[start + tid]];
+    const int li = lane & 15, kq = lane >> 4;
+    const int al = li >> 2, e = li & 3;         // B / accumulator column: first-dimension tap, value
+    const int pc = pd * pd;
+    const float inv_ng = 1.0f / (float)NG, inv_pd = 1.0f / (float)pd;
+    for (int r0 = 0; r0 < nrhs; r0 += VPS) {
+        __syncthreads();   // block lists staged / previous pass consumed
+        // unit u = (cell, value group); a value group holds K and dK of two
+        // vectors (DER) or K of four
+        for (int u = tid; u < pc * NG; u += NT) {
+            const int c = fdiv_small(u, NG, inv_ng), gq = u - c * NG;
+            const int a = fdiv_small(c, pd, inv_pd), b = c - a * pd;
+            const int l0 = org[0] - M + a, l1 = org[1] - M + b;
+            const bool in = l0 >= 0 && l0 < ng && l1 >= 0 && l1 < ng;
+            const int64_t g = in ? (int64_t)l0 * ng + l1 : 0;
+            f4 v = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            if (DER) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int vec = r0 + 2 * gq + q;
+                    if (in && vec < nrhs) {
+                        const float2 z = grid[((int64_t)wi * nrhs + vec) * cells + g];
+                        v[2 * q] = z.x;
+                        v[2 * q + 1] = z.y;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int vec = r0 + 4 * gq + q;
+                    if (in && vec < nrhs) v[q] = grid[((int64_t)wi * nrhs + vec) * cells + g].x;
+                }
+            }
+            *reinterpret_cast<f4 *>(tile + a * rstr + b * CS + 4 * gq) = v;
+        }
+        __syncthreads();
+        for (int k = wave; k < cnt; k += NWV) {
+            const int j0 = s_blk[k], np = s_blk[k + 1] - j0;
+            const int lp = s_lp[k];
+            const int L0 = (lp >> 20) & 0x7f, L1 = (lp & 0xfffff) - L0 * pd;   // first tap in the tile
+            // A row li: point j0 + li (rows past the block: weight 0), taps 4 t + kq
+            const int64_t rb = (int64_t)(P0 + j0 + min(li, np - 1)) * RS;
+            float w1k[KS];
+#pragma unroll
+            for (int t = 0; t < KS; ++t) w1k[t] = li < np ? rec[rb + TW + 4 * t + kq] : 0.0f;
+            // epilogue weights: w0 of point 4 kq + v at tap 4 c + al
+            float w0e[4][NBK];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t wb = (int64_t)(P0 + j0 + min(4 * kq + v, np - 1)) * RS;
+#pragma unroll
+                for (int c = 0; c < NBK; ++c) w0e[v][c] = rec[wb + 4 * c + al];
+            }
+            int orow[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) orow[v] = 4 * kq + v < np ? s_row[j0 + 4 * kq + v] : -1;
+            const float *tb0 = tile + (L0 + al) * rstr + (L1 + kq) * CS + e;
+            for (int gq = 0; gq < NG; ++gq) {
+                f4 acc[NBK];
+#pragma unroll
+                for (int c = 0; c < NBK; ++c) acc[c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+                float bv[KS][NBK];
+#pragma unroll
+                for (int t = 0; t < KS; ++t)
+#pragma unroll
+                    for (int c = 0; c < NBK; ++c) bv[t][c] = tb0[4 * c * rstr + 4 * t * CS + 4 * gq];
+                __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+                for (int t = 0; t < KS; ++t)
+#pragma unroll
+                    for (int c = 0; c < NBK; ++c)
+                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(w1k[t], bv[t][c], acc[c], 0, 0, 0);
+                __builtin_amdgcn_s_setprio(0);
+                // first dimension: lane (al, e, kq) holds X[4 kq + v][(4 c + al, e)]
+                float h[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    float sum = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < NBK; ++c) sum += w0e[v][c] * acc[c][v];
+                    sum += __shfl_xor(sum, 4);
+                    sum += __shfl_xor(sum, 8);
+                    h[v] = sum;
+                }
+                if (al == 0) {
+                    const int vec = r0 + (DER ? 2 * gq + e / 2 : 4 * gq + e);
+                    const bool isd = DER && (e & 1);
+                    if (vec < nrhs) {
+                        float *out = (isd ? dout : hbuf) + (int64_t)win.s_global * n * nrhs;
+                        const float sc = isd ? dscale : 1.0f;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (orow[v] >= 0) out[(int64_t)orow[v] * nrhs + vec] = sc * h[v];
+                    }
+                }
+            }
+        }
+    }
+}
+
 // d <= 2 with at least 16 / sizeof(T) vectors: the tiles of up to vb vectors
 // are staged at once, cell-major (a cell's vb values, for DER then its vb
 // derivative values, then 16 bytes of padding that put neighbouring cells on
@@ -1995,6 +2145,24 @@ hipError_t interp_dm(const Group &G, int64_t n, int nrhs, const void *grid, bool
                 nrhs, n, (T *)hbuf, nullptr, (T)dscale);
         return hipGetLastError();
     }
+    if constexpr (std::is_same<T, float>::value && D == 2 && (M == 4 || M == 6)) {
+        if (G.interp_mfma) {
+            constexpr int CS = kInterp2Values + 4;
+            const int rstr = g.pd * CS + ((8 - g.pd * CS) % 32 + 32) % 32;
+            const size_t shm = (size_t)g.pd * rstr * sizeof(float);
+            auto go = [&](auto der_tag) -> hipError_t {
+                constexpr bool DR = decltype(der_tag)::value;
+                hipError_t e = allow_lds(k_interp_mfma2<M, DR>, shm);
+                if (e != hipSuccess) return e;
+                k_interp_mfma2<M, DR><<<(unsigned)G.nisub, 256, shm, s>>>(
+                    G.desc, G.isub_win, G.isub_bin, G.isub_start, G.isub_count, g.tb, g.nb, g.ng,
+                    (const float2 *)grid, g.cells, nrhs, n, (float *)hbuf, DR ? (float *)dout : nullptr,
+                    (float)dscale);
+                return hipGetLastError();
+            };
+            return with_der ? go(std::true_type()) : go(std::false_type());
+        }
+    }
     if constexpr (D <= 2) {
         // several vectors per staging from 16 bytes of vectors on; 16-byte
         // output stores when the output rows are 16-byte aligned
@@ -2307,7 +2475,7 @@ std::string describe_group(int prec, const Group &G, int m, int nrhs)
     if (G.use_run_interp)
         ip = "run";
     else if (G.interp_mfma)
-        ip = "mfma (" + std::to_string(G.interp_mfma_waves) + " waves per work-group)";
+        ip = "mfma (" + std::to_string(G.g.d == 2 ? 4 : G.interp_mfma_waves) + " waves per work-group)";
     else if (G.interp_slot)
         ip = "tileslot";
     else if (G.interp_adj)

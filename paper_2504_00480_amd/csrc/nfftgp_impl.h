@@ -28,6 +28,9 @@ constexpr int kInterpSubPoints = 256;
 // takes at most kInterpSubBlocksLds)
 constexpr int kInterpSubBlocks = 32;
 constexpr int kInterpSubBlocksLds = 16;
+// 2-D matrix-core interpolation: values staged per cell and pass (K and dK of
+// half as many vectors with derivative outputs)
+constexpr int kInterp2Values = 16;
 // d <= 2 several-vector interpolation: points per subproblem by rule
 constexpr int kInterpVbSubPoints = 2048;
 // Points per wave in run-based interpolation.
