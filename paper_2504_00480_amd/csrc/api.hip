@@ -716,10 +716,13 @@ nfftgp_status plan_create_impl(nfftgp_plan *out, const void *X_dev, int64_t n, i
         const bool full = iov && std::strcmp(iov, "tilefull") == 0;
         const bool pair = iov && std::strcmp(iov, "tilepair") == 0;
         const bool slot = iov && std::strcmp(iov, "tileslot") == 0;
-        // 3-D FP32 with m = 4 or 6 and several vectors: matrix-core blocks
-        // unless another variant is forced
+        // 3-D and 2-D FP32 with m = 4 or 6 and several vectors: matrix-core
+        // blocks unless another variant is forced (2-D: measured C3 4.28 ->
+        // 4.21 ms, C4 1.45 -> 1.43 ms, C5 36.13 -> 36.05 ms per step; the tuner
+        // also times the tile forms)
         const bool blk = iov ? std::strcmp(iov, "mfma") == 0
-                             : (G.g.d == 3 && prec == NFFTGP_F32 && (m == 4 || m == 6) && max_nrhs >= 2);
+                             : ((G.g.d == 3 || G.g.d == 2) && prec == NFFTGP_F32 && (m == 4 || m == 6) &&
+                                max_nrhs >= 2);
         const char *smr = std::getenv("NFFTGP_SPREAD_MFMA_R");   // "2" | "4"
         G.spread_mfma_R = smr && std::strcmp(smr, "2") == 0 ? 2 : 4;
         const char *ffm = std::getenv("NFFTGP_FOLD");   // "cells" | "tiles"
@@ -1041,6 +1044,9 @@ nfftgp_status nfftgp_autotune(nfftgp_plan plan, int32_t nrhs, int32_t with_deriv
                 if (rr != mr) cands.push_back({false, 1, rr, false, false, true});
             }
         }
+        // 2-D: blocks of one cell on matrix cores (FP32, m = 4 or 6)
+        if (G.g.d == 2 && plan->prec == NFFTGP_F32 && (plan->m == 4 || plan->m == 6))
+            cands.push_back({false, 1, G.g.pd, false, false, true});
         cands.push_back({true, cur_pt, cur_rows, cur_adj, cur_slot, cur_blk});
         for (const Cand &c : cands) {
             if (stt != NFFTGP_OK) break;
